@@ -1,0 +1,334 @@
+"""FP64 CPU oracle of the independent-ensemble bootstrap particle filter.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The
+product library (``paper_1407_8071_amd``) never imports, links or runs it,
+and it imports nothing from the product library.
+
+The arithmetic lives in ``pf_oracle.c`` (plain C, FP64, single thread); this
+module builds it with gcc, loads it with ctypes and wraps each step of
+Algorithm 1 (Sec. 2.3) with numpy arrays.  Particle arrays here are
+``[N, dx]`` float64 (particle-major).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KINDS = {"ou1d": 0, "lorenz63": 1, "fhn": 2}
+P_INIT, P_PROP, P_RESAMPLE, P_TRUTH_INIT, P_TRUTH_NOISE, P_OBS_NOISE, P_TRAIN, P_CONFIG = range(1, 9)
+TRUTH_STREAM = 0xFFFFFFFF
+
+
+def build(force: bool = True) -> str:
+    """Compile pf_oracle.c into liboracle.so (plain gcc -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+             "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int), ("dx", C.c_int), ("J", C.c_int), ("S", C.c_int),
+        ("h", C.c_double), ("p", C.c_double * 4), ("sd", C.c_double * 2),
+        ("dy", C.c_int), ("obs_idx", C.POINTER(C.c_int)), ("obs_var", C.c_double),
+        ("prior_mean", C.POINTER(C.c_double)), ("prior_sd", C.POINTER(C.c_double)),
+    ]
+
+
+_lib = None
+
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_U32 = C.POINTER(C.c_uint32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        M = C.POINTER(_Model)
+        sig = {
+            "or_key": (None, [C.c_uint64, _U32]),
+            "or_philox4x32_10": (None, [_U32, _U32, _U32]),
+            "or_u01": (C.c_double, [C.c_uint32]),
+            "or_normals4": (None, [_U32, _U32, _D]),
+            "or_philox_stream": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, _U32]),
+            "or_normal_stream": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, _D]),
+            "or_drift": (None, [M, _D, _D]),
+            "or_laplacian": (None, [C.c_int, _D, _D]),
+            "or_step_noise": (None, [M, _U32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _D]),
+            "or_em_step": (None, [M, _D, _D, _D]),
+            "or_prior_draw": (None, [M, _U32, C.c_uint32, C.c_uint32, C.c_uint32, _D]),
+            "or_loglik": (C.c_double, [M, _D, _D]),
+            "or_init": (None, [M, C.c_uint64, C.c_uint32, C.c_int, _D]),
+            "or_propagate": (None, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D]),
+            "or_weights": (None, [M, C.c_int, _D, _D, _D]),
+            "or_normalise": (C.c_int, [C.c_int, _D, _D, _D, _D]),
+            "or_cdf": (None, [C.c_int, _D, C.c_double, C.c_int, _D]),
+            "or_sorted_uniforms": (None, [C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D]),
+            "or_ancestors": (None, [C.c_int, _D, _D, _I32]),
+            "or_gather": (None, [C.c_int, C.c_int, _D, _I32, _D]),
+            "or_mean": (None, [C.c_int, C.c_int, _D, _D]),
+            "or_weighted_mean": (None, [C.c_int, C.c_int, _D, _D, C.c_double, _D]),
+            "or_filter_interval": (C.c_int, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D, _D,
+                                             _D, _D, _I32, _D, _D, _D]),
+            "or_run_ensemble": (None, [M, C.c_uint64, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D, _D]),
+            "or_simulate": (None, [M, C.c_uint64, C.c_int, _D, _D]),
+            "or_kalman_ou": (C.c_double, [M, C.c_int, _D, _D, _D]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _i32(a):
+    return a.ctypes.data_as(_I32) if a is not None else None
+
+
+def _u32(a):
+    return a.ctypes.data_as(_U32) if a is not None else None
+
+
+class Model:
+    """A state-space model (tau_0, tau_t, g_t) of Sec. 2.2 for the oracle.
+
+    ``spec`` is a plain dict: kind ('ou1d' | 'lorenz63' | 'fhn'), dx, J, S, h,
+    params (4 numbers), noise_sd (2), obs_idx, obs_var, prior_mean, prior_sd.
+    """
+
+    def __init__(self, spec: dict):
+        self.spec = dict(spec)
+        self.kind = spec["kind"]
+        self.dx = int(spec["dx"])
+        self.J = int(spec.get("J", 0))
+        self.S = int(spec["S"])
+        self.obs_idx = np.ascontiguousarray(spec["obs_idx"], dtype=np.int32)
+        self.dy = int(self.obs_idx.size)
+        self.prior_mean = np.ascontiguousarray(spec["prior_mean"], dtype=np.float64)
+        self.prior_sd = np.ascontiguousarray(spec["prior_sd"], dtype=np.float64)
+        assert self.prior_mean.size == self.dx and self.prior_sd.size == self.dx
+        p = list(spec["params"]) + [0.0] * (4 - len(spec["params"]))
+        sd = list(spec["noise_sd"]) + [0.0] * (2 - len(spec["noise_sd"]))
+        self.c = _Model(
+            KINDS[self.kind], self.dx, self.J, self.S, float(spec["h"]),
+            (C.c_double * 4)(*p), (C.c_double * 2)(*sd), self.dy,
+            self.obs_idx.ctypes.data_as(C.POINTER(C.c_int)), float(spec["obs_var"]),
+            _d(self.prior_mean), _d(self.prior_sd))
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+# ---------------------------------------------------------------- RNG ---------
+def key(seed: int) -> np.ndarray:
+    k = np.zeros(2, np.uint32)
+    lib().or_key(C.c_uint64(seed), _u32(k))
+    return k
+
+
+def philox(ctr, k) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    kk = np.ascontiguousarray(k, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_u32(c), _u32(kk), _u32(out))
+    return out
+
+
+def u01(x: int) -> float:
+    return lib().or_u01(C.c_uint32(x))
+
+
+def normals4(ctr, k) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    kk = np.ascontiguousarray(k, dtype=np.uint32)
+    z = np.zeros(4)
+    lib().or_normals4(_u32(c), _u32(kk), _d(z))
+    return z
+
+
+def philox_stream(seed, c1, c2, c3, n) -> np.ndarray:
+    out = np.zeros(n, np.uint32)
+    lib().or_philox_stream(C.c_uint64(seed), c1, c2, c3, n, _u32(out))
+    return out
+
+
+def normal_stream(seed, c1, c2, c3, n) -> np.ndarray:
+    out = np.zeros(n)
+    lib().or_normal_stream(C.c_uint64(seed), c1, c2, c3, n, _d(out))
+    return out
+
+
+# ---------------------------------------------------------------- model -------
+def drift(m: Model, x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    f = np.zeros(m.dx)
+    lib().or_drift(m.ref, _d(x), _d(f))
+    return f
+
+
+def laplacian(v) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    J = v.shape[0]
+    out = np.zeros_like(v)
+    lib().or_laplacian(J, _d(v), _d(out))
+    return out
+
+
+def step_noise(m: Model, seed, purpose, c0, c1, n) -> np.ndarray:
+    z = np.zeros(m.dx)
+    lib().or_step_noise(m.ref, _u32(key(seed)), purpose, c0, c1, n, _d(z))
+    return z
+
+
+def em_step(m: Model, x, z) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    xo = np.zeros(m.dx)
+    lib().or_em_step(m.ref, _d(x), _d(z), _d(xo))
+    return xo
+
+
+def loglik(m: Model, x, y) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return lib().or_loglik(m.ref, _d(x), _d(y))
+
+
+# ---------------------------------------------------------------- filter ------
+def init(m: Model, seed, filt, N) -> np.ndarray:
+    X = np.zeros((N, m.dx))
+    lib().or_init(m.ref, C.c_uint64(seed), filt, N, _d(X))
+    return X
+
+
+def propagate(m: Model, seed, filt, t, X) -> np.ndarray:
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    lib().or_propagate(m.ref, C.c_uint64(seed), filt, X.shape[0], t, _d(X))
+    return X
+
+
+def weights(m: Model, X, y) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    lw = np.zeros(X.shape[0])
+    lib().or_weights(m.ref, X.shape[0], _d(X), _d(y), _d(lw))
+    return lw
+
+
+def normalise(lw):
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    mx, W, s2 = C.c_double(), C.c_double(), C.c_double()
+    deg = lib().or_normalise(lw.size, _d(lw), C.byref(mx), C.byref(W), C.byref(s2))
+    return mx.value, W.value, s2.value, bool(deg)
+
+
+def cdf(lw, mx, degenerate=False) -> np.ndarray:
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    out = np.zeros(lw.size)
+    lib().or_cdf(lw.size, _d(lw), mx, int(degenerate), _d(out))
+    return out
+
+
+def sorted_uniforms(seed, filt, t, N) -> np.ndarray:
+    U = np.zeros(N)
+    lib().or_sorted_uniforms(C.c_uint64(seed), filt, t, N, _d(U))
+    return U
+
+
+def ancestors(Cdf, U) -> np.ndarray:
+    Cdf = np.ascontiguousarray(Cdf, dtype=np.float64)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    A = np.zeros(Cdf.size, np.int32)
+    lib().or_ancestors(Cdf.size, _d(Cdf), _d(U), _i32(A))
+    return A
+
+
+def resample(seed, filt, t, lw):
+    """Normalise + CDF + sorted uniforms + ancestor search (steps 2a-2b)."""
+    mx, W, s2, deg = normalise(lw)
+    Cdf = cdf(lw, mx, deg)
+    U = sorted_uniforms(seed, filt, t, len(lw))
+    return ancestors(Cdf, U), Cdf, U, (mx, W, s2, deg)
+
+
+def mean(X) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = np.zeros(X.shape[1])
+    lib().or_mean(X.shape[0], X.shape[1], _d(X), _d(out))
+    return out
+
+
+def weighted_mean(X, lw, mx) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    out = np.zeros(X.shape[1])
+    lib().or_weighted_mean(X.shape[0], X.shape[1], _d(X), _d(lw), mx, _d(out))
+    return out
+
+
+def filter_interval(m: Model, seed, filt, t, X, y, logZ=0.0):
+    """One full interval of Algorithm 1 for one filter.  Returns a dict."""
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    N = X.shape[0]
+    lz = C.c_double(logZ)
+    lw = np.zeros(N)
+    A = np.zeros(N, np.int32)
+    mp = np.zeros(m.dx)
+    mw = np.zeros(m.dx)
+    ess = C.c_double()
+    deg = lib().or_filter_interval(m.ref, C.c_uint64(seed), filt, N, t, _d(X), _d(y), C.byref(lz),
+                                   _d(lw), _i32(A), _d(mp), _d(mw), C.byref(ess))
+    return dict(X=X, lw=lw, A=A, mean_post=mp, mean_w=mw, logZ=lz.value, ess=ess.value,
+                degenerate=bool(deg))
+
+
+def run_ensemble(m: Model, seed, M, N, y):
+    """Definition 3 over y[T, dy]: returns est[T,dx], est_w[T,dx], logZ[M], ess[T]."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    T = y.shape[0]
+    est = np.zeros((T, m.dx))
+    est_w = np.zeros((T, m.dx))
+    logZ = np.zeros(M)
+    ess = np.zeros(T)
+    lib().or_run_ensemble(m.ref, C.c_uint64(seed), M, N, T, _d(y), _d(est), _d(est_w), _d(logZ),
+                          _d(ess))
+    return est, est_w, logZ, ess
+
+
+def simulate(m: Model, seed, T):
+    """Truth x_true[T+1, dx] and observations y[T, dy] from the truth stream."""
+    xt = np.zeros((T + 1, m.dx))
+    y = np.zeros((T, m.dy))
+    lib().or_simulate(m.ref, C.c_uint64(seed), T, _d(xt), _d(y))
+    return xt, y
+
+
+def kalman_ou(m: Model, y):
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(-1))
+    mean_ = np.zeros(y.size)
+    var_ = np.zeros(y.size)
+    ll = lib().or_kalman_ou(m.ref, y.size, _d(y), _d(mean_), _d(var_))
+    return mean_, var_, ll

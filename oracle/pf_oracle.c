@@ -1,0 +1,483 @@
+/*
+ * pf_oracle.c -- FP64 single-threaded reference of the independent-ensemble
+ * bootstrap particle filter.  TEST INFRASTRUCTURE ONLY (see pf_oracle.h).
+ *
+ * Every function follows the paper's definition step by step, in the paper's
+ * order; nothing is blocked, fused or reordered.
+ *
+ * Random-number layout (the one contract the GPU side implements again on its
+ * own):
+ *   key      = (low 32 bits of seed, high 32 bits of seed XOR 0x14078071)
+ *   counter  = (c0, c1, c2, c3) with c3 = purpose << 24 | sub-block
+ *   uniform  u = (2*(x >> 9) + 1) * 2^-24, exactly representable in FP32
+ *   normals  Box-Muller on (u0,u1) -> z0 = r cos(2 pi u1), z1 = r sin(2 pi u1)
+ *            with r = sqrt(-2 ln u0); (u2,u3) -> z2, z3 likewise
+ *   Euler noise of a particle (c0 = particle, c1 = filter), step n:
+ *     vector models of dimension d: c2 = n/4, component c of step n uses
+ *       normal l = (n%4)*d + c, i.e. sub-block l/4, lane l%4;
+ *     grid model: c2 = n, sub-block p = node/2; lanes 0,1 are the (v, w)
+ *       noise of node 2p and lanes 2,3 those of node 2p+1 (nodes row-major);
+ *   prior draw: state index s uses c2 = 0, sub-block s/4, lane s%4;
+ *   resampling: exponential E_j (j = 0..N) uses c0 = j/4, c1 = filter,
+ *     c2 = t, sub-block 0, lane j%4;
+ *   truth path: c0 = 0, c1 = 0xFFFFFFFF, purposes TRUTH_INIT / TRUTH_NOISE;
+ *   observation noise of y_t component k: c0 = 0, c1 = 0xFFFFFFFF, c2 = t,
+ *     sub-block k/4, lane k%4.
+ */
+#include "pf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11): two 32x32->64 multiplications per
+   round with the published multipliers, the Weyl key schedule with the
+   published increments, ten rounds. */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void or_key(uint64_t seed, uint32_t key[2]) {
+  key[0] = (uint32_t)seed;
+  key[1] = (uint32_t)(seed >> 32) ^ 0x14078071u;
+}
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += PHILOX_W0;
+    k1 += PHILOX_W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+double or_u01(uint32_t x) {
+  return (double)(2u * (x >> 9) + 1u) * 0x1p-24;
+}
+
+void or_normals4(const uint32_t ctr[4], const uint32_t key[2], double z[4]) {
+  uint32_t r[4];
+  or_philox4x32_10(ctr, key, r);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int k = 0; k < 4; k += 2) {
+    double u0 = or_u01(r[k]);
+    double u1 = or_u01(r[k + 1]);
+    double rad = sqrt(-2.0 * log(u0));
+    z[k] = rad * cos(two_pi * u1);
+    z[k + 1] = rad * sin(two_pi * u1);
+  }
+}
+
+static void make_ctr(uint32_t c[4], uint32_t c0, uint32_t c1, uint32_t c2,
+                     uint32_t purpose, uint32_t sub) {
+  c[0] = c0; c[1] = c1; c[2] = c2; c[3] = (purpose << 24) | (sub & 0xFFFFFFu);
+}
+
+void or_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                      int64_t n, uint32_t *out) {
+  uint32_t key[2], ctr[4], r[4];
+  or_key(seed, key);
+  for (int64_t i = 0; i < n; i += 4) {
+    ctr[0] = (uint32_t)(i / 4); ctr[1] = c1; ctr[2] = c2; ctr[3] = c3;
+    or_philox4x32_10(ctr, key, r);
+    for (int l = 0; l < 4 && i + l < n; ++l) out[i + l] = r[l];
+  }
+}
+
+void or_normal_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                      int64_t n, double *out) {
+  uint32_t key[2], ctr[4];
+  double z[4];
+  or_key(seed, key);
+  for (int64_t i = 0; i < n; i += 4) {
+    ctr[0] = (uint32_t)(i / 4); ctr[1] = c1; ctr[2] = c2; ctr[3] = c3;
+    or_normals4(ctr, key, z);
+    for (int l = 0; l < 4 && i + l < n; ++l) out[i + l] = z[l];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Models. */
+
+/* Discrete Laplacian with the truncated neighbourhoods of Sec. 5.2: every
+   node is coupled to its up/down/left/right neighbours that exist in the
+   grid (two at corners, three on sides, four inside):
+   lap_ij = sum_{nbr} (v_nbr - v_ij). */
+void or_laplacian(int J, const double *v, double *lap) {
+  for (int i = 0; i < J; ++i) {
+    for (int j = 0; j < J; ++j) {
+      double c = v[i * J + j];
+      double acc = 0.0;
+      if (i > 0) acc += v[(i - 1) * J + j] - c;
+      if (i < J - 1) acc += v[(i + 1) * J + j] - c;
+      if (j > 0) acc += v[i * J + j - 1] - c;
+      if (j < J - 1) acc += v[i * J + j + 1] - c;
+      lap[i * J + j] = acc;
+    }
+  }
+}
+
+void or_drift(const or_model *m, const double *x, double *f) {
+  if (m->kind == OR_OU1D) {
+    f[0] = -m->p[0] * x[0];
+  } else if (m->kind == OR_LORENZ63) {
+    /* eqs. (eqDiscreteLorenz-1..3): s(x2 - x1), r x1 - x2 - x1 x3,
+       x1 x2 - b x3 */
+    double s = m->p[0], r = m->p[1], b = m->p[2];
+    f[0] = s * (x[1] - x[0]);
+    f[1] = r * x[0] - x[1] - x[0] * x[2];
+    f[2] = x[0] * x[1] - b * x[2];
+  } else {
+    /* FitzHugh-Nagumo grid: v plane x[0..J*J), w plane x[J*J..2J*J).
+       f_v = v (v - a)(1 - v) - w + D lap(v), f_w = eps (v - gam w). */
+    int J = m->J, nn = J * J;
+    double a = m->p[0], D = m->p[1], eps = m->p[2], gam = m->p[3];
+    const double *v = x, *w = x + nn;
+    double *lap = (double *)malloc(sizeof(double) * (size_t)nn);
+    or_laplacian(J, v, lap);
+    for (int k = 0; k < nn; ++k) {
+      f[k] = v[k] * (v[k] - a) * (1.0 - v[k]) - w[k] + D * lap[k];
+      f[nn + k] = eps * (v[k] - gam * w[k]);
+    }
+    free(lap);
+  }
+}
+
+void or_step_noise(const or_model *m, const uint32_t key[2], uint32_t purpose,
+                   uint32_t c0, uint32_t c1, uint32_t n, double *z) {
+  uint32_t ctr[4];
+  double q[4];
+  if (m->kind == OR_FHN) {
+    int nn = m->J * m->J;
+    for (int p = 0; 2 * p < nn; ++p) {
+      make_ctr(ctr, c0, c1, n, purpose, (uint32_t)p);
+      or_normals4(ctr, key, q);
+      z[2 * p] = q[0];
+      z[nn + 2 * p] = q[1];
+      if (2 * p + 1 < nn) {
+        z[2 * p + 1] = q[2];
+        z[nn + 2 * p + 1] = q[3];
+      }
+    }
+  } else {
+    int d = m->dx;
+    uint32_t r = n % 4u;
+    for (int c = 0; c < d; ++c) {
+      uint32_t l = r * (uint32_t)d + (uint32_t)c;
+      make_ctr(ctr, c0, c1, n / 4u, purpose, l / 4u);
+      or_normals4(ctr, key, q);
+      z[c] = q[l % 4u];
+    }
+  }
+}
+
+/* Euler-Maruyama: x' = x + h f(x) + sd sqrt(h) z (drift first, then the
+   deterministic update, then the noise). */
+void or_em_step(const or_model *m, const double *x, const double *z, double *xo) {
+  int d = m->dx;
+  double *f = (double *)malloc(sizeof(double) * (size_t)d);
+  or_drift(m, x, f);
+  double sq0 = m->sd[0] * sqrt(m->h);
+  double sq1 = m->sd[1] * sqrt(m->h);
+  int half = (m->kind == OR_FHN) ? m->J * m->J : d;
+  for (int k = 0; k < d; ++k) {
+    double sq = (k < half) ? sq0 : sq1;
+    xo[k] = (x[k] + m->h * f[k]) + sq * z[k];
+  }
+  free(f);
+}
+
+void or_prior_draw(const or_model *m, const uint32_t key[2], uint32_t purpose,
+                   uint32_t c0, uint32_t c1, double *x) {
+  uint32_t ctr[4];
+  double q[4];
+  for (int s = 0; s < m->dx; s += 4) {
+    make_ctr(ctr, c0, c1, 0u, purpose, (uint32_t)(s / 4));
+    or_normals4(ctr, key, q);
+    for (int l = 0; l < 4 && s + l < m->dx; ++l)
+      x[s + l] = m->prior_mean[s + l] + m->prior_sd[s + l] * q[l];
+  }
+}
+
+/* log g_t^{y}(x) up to the additive constant: -(1/(2 sigma^2)) sum (y-Hx)^2
+   (eqObservLorenz likelihood, eqObservFHN likelihood).  A NaN state gives
+   -inf (the particle can never be selected). */
+double or_loglik(const or_model *m, const double *x, const double *y) {
+  double acc = 0.0;
+  for (int k = 0; k < m->dy; ++k) {
+    double r = y[k] - x[m->obs_idx[k]];
+    acc += r * r;
+  }
+  double lw = -acc / (2.0 * m->obs_var);
+  if (isnan(lw)) lw = -INFINITY;
+  return lw;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1, one filter. */
+
+/* Step 1: x_0^(i) ~ tau_0, i = 1..N. */
+void or_init(const or_model *m, uint64_t seed, uint32_t filter, int N, double *X) {
+  uint32_t key[2];
+  or_key(seed, key);
+  for (int i = 0; i < N; ++i)
+    or_prior_draw(m, key, OR_P_INIT, (uint32_t)i, filter, X + (size_t)i * m->dx);
+}
+
+/* Step 2(a), sampling: xbar_t^(i) ~ tau_t(.|x_{t-1}^(i)), realised as S
+   Euler-Maruyama steps n = (t-1)S .. tS-1 (Sec. 4.1). */
+void or_propagate(const or_model *m, uint64_t seed, uint32_t filter, int N,
+                  int t, double *X) {
+  uint32_t key[2];
+  or_key(seed, key);
+  int d = m->dx;
+  double *z = (double *)malloc(sizeof(double) * (size_t)d);
+  double *xn = (double *)malloc(sizeof(double) * (size_t)d);
+  for (int i = 0; i < N; ++i) {
+    double *x = X + (size_t)i * d;
+    for (int s = 0; s < m->S; ++s) {
+      uint32_t n = (uint32_t)((t - 1) * m->S + s);
+      or_step_noise(m, key, OR_P_PROP, (uint32_t)i, filter, n, z);
+      or_em_step(m, x, z, xn);
+      memcpy(x, xn, sizeof(double) * (size_t)d);
+    }
+  }
+  free(z);
+  free(xn);
+}
+
+/* Step 2(a), weighting: log g_t^{y_t}(xbar_t^(i)). */
+void or_weights(const or_model *m, int N, const double *X, const double *y,
+                double *lw) {
+  for (int i = 0; i < N; ++i) lw[i] = or_loglik(m, X + (size_t)i * m->dx, y);
+}
+
+/* Step 2(a), normalisation: w^(i) = g(xbar^(i)) / sum_k g(xbar^(k)), carried
+   as mx = max lw and W = sum exp(lw - mx) (sequential, index order).  If no
+   weight is positive the weights are taken as uniform and 1 is returned. */
+int or_normalise(int N, const double *lw, double *mx, double *W, double *sumw2) {
+  double m = -INFINITY;
+  for (int i = 0; i < N; ++i)
+    if (lw[i] > m) m = lw[i];
+  if (!(m > -INFINITY) || isnan(m) || isinf(m)) {
+    *mx = -INFINITY;
+    *W = (double)N;
+    *sumw2 = (double)N;
+    return 1;
+  }
+  double s = 0.0, s2 = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double w = exp(lw[i] - m);
+    s += w;
+    s2 += w * w;
+  }
+  *mx = m;
+  *W = s;
+  *sumw2 = s2;
+  return 0;
+}
+
+/* Cumulative weights C_i = sum_{j<=i} exp(lw_j - mx) (uniform if degenerate). */
+void or_cdf(int N, const double *lw, double mx, int degenerate, double *C) {
+  double acc = 0.0;
+  for (int i = 0; i < N; ++i) {
+    acc += degenerate ? 1.0 : exp(lw[i] - mx);
+    C[i] = acc;
+  }
+}
+
+/* Sorted uniforms by exponential spacings (Devroye 1986, Ch. V.3):
+   E_j = -ln u_j, j = 0..N; S_k = sum_{j<=k} E_j; U_k = S_k / S_N for
+   k = 0..N-1 are the order statistics of N independent U(0,1). */
+void or_sorted_uniforms(uint64_t seed, uint32_t filter, int t, int N, double *U) {
+  uint32_t key[2], ctr[4], r[4];
+  or_key(seed, key);
+  double *S = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+  double acc = 0.0;
+  for (int j = 0; j <= N; ++j) {
+    if (j % 4 == 0) {
+      make_ctr(ctr, (uint32_t)(j / 4), filter, (uint32_t)t, OR_P_RESAMPLE, 0u);
+      or_philox4x32_10(ctr, key, r);
+    }
+    acc += -log(or_u01(r[j % 4]));
+    S[j] = acc;
+  }
+  for (int k = 0; k < N; ++k) U[k] = S[k] / S[N];
+  free(S);
+}
+
+/* Step 2(b), multinomial selection: ancestor a_k = min{ i : C_i > U_k C_{N-1} }
+   for the ascending U, found with one forward pointer over C. */
+void or_ancestors(int N, const double *C, const double *U, int32_t *A) {
+  int i = 0;
+  double total = C[N - 1];
+  for (int k = 0; k < N; ++k) {
+    double v = U[k] * total;
+    while (i < N - 1 && C[i] <= v) ++i;
+    A[k] = i;
+  }
+}
+
+void or_gather(int N, int dx, const double *X, const int32_t *A, double *Xo) {
+  for (int k = 0; k < N; ++k)
+    memcpy(Xo + (size_t)k * dx, X + (size_t)A[k] * dx, sizeof(double) * (size_t)dx);
+}
+
+/* (f, pi_t^N) with f the identity: (1/N) sum_i x_t^(i). */
+void or_mean(int N, int dx, const double *X, double *mean) {
+  for (int c = 0; c < dx; ++c) mean[c] = 0.0;
+  for (int i = 0; i < N; ++i)
+    for (int c = 0; c < dx; ++c) mean[c] += X[(size_t)i * dx + c];
+  for (int c = 0; c < dx; ++c) mean[c] /= (double)N;
+}
+
+/* sum_i w^(i) xbar^(i): the weighted (pre-resampling) estimate. */
+void or_weighted_mean(int N, int dx, const double *X, const double *lw,
+                      double mx, double *mean) {
+  double W = 0.0;
+  for (int c = 0; c < dx; ++c) mean[c] = 0.0;
+  int degenerate = !(mx > -INFINITY);
+  for (int i = 0; i < N; ++i) {
+    double w = degenerate ? 1.0 : exp(lw[i] - mx);
+    W += w;
+    for (int c = 0; c < dx; ++c) mean[c] += w * X[(size_t)i * dx + c];
+  }
+  for (int c = 0; c < dx; ++c) mean[c] /= W;
+}
+
+int or_filter_interval(const or_model *m, uint64_t seed, uint32_t filter, int N,
+                       int t, double *X, const double *y, double *logZ,
+                       double *lw_out, int32_t *A_out, double *mean_post,
+                       double *mean_w, double *ess) {
+  int d = m->dx;
+  double *lw = (double *)malloc(sizeof(double) * (size_t)N);
+  double *C = (double *)malloc(sizeof(double) * (size_t)N);
+  double *U = (double *)malloc(sizeof(double) * (size_t)N);
+  int32_t *A = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  double *Xo = (double *)malloc(sizeof(double) * (size_t)N * d);
+  double mx, W, s2;
+
+  or_propagate(m, seed, filter, N, t, X);
+  or_weights(m, N, X, y, lw);
+  int deg = or_normalise(N, lw, &mx, &W, &s2);
+  if (logZ) {
+    const double two_pi = 6.283185307179586476925286766559;
+    if (deg)
+      *logZ = -INFINITY;
+    else
+      *logZ += mx + log(W / (double)N) - 0.5 * m->dy * log(two_pi * m->obs_var);
+  }
+  if (ess) *ess = W * W / s2;
+  if (mean_w) or_weighted_mean(N, d, X, lw, mx, mean_w);
+  or_cdf(N, lw, mx, deg, C);
+  or_sorted_uniforms(seed, filter, t, N, U);
+  or_ancestors(N, C, U, A);
+  or_gather(N, d, X, A, Xo);
+  memcpy(X, Xo, sizeof(double) * (size_t)N * d);
+  if (mean_post) or_mean(N, d, X, mean_post);
+  if (lw_out) memcpy(lw_out, lw, sizeof(double) * (size_t)N);
+  if (A_out) memcpy(A_out, A, sizeof(int32_t) * (size_t)N);
+  free(lw); free(C); free(U); free(A); free(Xo);
+  return deg;
+}
+
+/* Definition 3: M independent filters on the same y_{1:T}, averaged with
+   equal weights 1/M. */
+void or_run_ensemble(const or_model *m, uint64_t seed, int M, int N, int T,
+                     const double *y, double *est, double *est_w,
+                     double *logZ, double *ess) {
+  int d = m->dx;
+  double *X = (double *)malloc(sizeof(double) * (size_t)N * d);
+  double *mp = (double *)malloc(sizeof(double) * (size_t)d);
+  double *mw = (double *)malloc(sizeof(double) * (size_t)d);
+  if (est) memset(est, 0, sizeof(double) * (size_t)T * d);
+  if (est_w) memset(est_w, 0, sizeof(double) * (size_t)T * d);
+  if (ess) memset(ess, 0, sizeof(double) * (size_t)T);
+  for (int f = 0; f < M; ++f) {
+    double lz = 0.0;
+    or_init(m, seed, (uint32_t)f, N, X);
+    for (int t = 1; t <= T; ++t) {
+      double e;
+      or_filter_interval(m, seed, (uint32_t)f, N, t, X, y + (size_t)(t - 1) * m->dy,
+                         &lz, NULL, NULL, mp, mw, &e);
+      for (int c = 0; c < d; ++c) {
+        if (est) est[(size_t)(t - 1) * d + c] += mp[c] / (double)M;
+        if (est_w) est_w[(size_t)(t - 1) * d + c] += mw[c] / (double)M;
+      }
+      if (ess) ess[t - 1] += e / (double)M;
+    }
+    if (logZ) logZ[f] = lz;
+  }
+  free(X); free(mp); free(mw);
+}
+
+void or_simulate(const or_model *m, uint64_t seed, int T, double *x_true,
+                 double *y) {
+  uint32_t key[2], ctr[4];
+  double q[4];
+  int d = m->dx;
+  or_key(seed, key);
+  double *x = (double *)malloc(sizeof(double) * (size_t)d);
+  double *z = (double *)malloc(sizeof(double) * (size_t)d);
+  double *xn = (double *)malloc(sizeof(double) * (size_t)d);
+  or_prior_draw(m, key, OR_P_TRUTH_INIT, 0u, OR_TRUTH_STREAM, x);
+  memcpy(x_true, x, sizeof(double) * (size_t)d);
+  double sy = sqrt(m->obs_var);
+  for (int t = 1; t <= T; ++t) {
+    for (int s = 0; s < m->S; ++s) {
+      uint32_t n = (uint32_t)((t - 1) * m->S + s);
+      or_step_noise(m, key, OR_P_TRUTH_NOISE, 0u, OR_TRUTH_STREAM, n, z);
+      or_em_step(m, x, z, xn);
+      memcpy(x, xn, sizeof(double) * (size_t)d);
+    }
+    memcpy(x_true + (size_t)t * d, x, sizeof(double) * (size_t)d);
+    for (int k = 0; k < m->dy; k += 4) {
+      make_ctr(ctr, 0u, OR_TRUTH_STREAM, (uint32_t)t, OR_P_OBS_NOISE, (uint32_t)(k / 4));
+      or_normals4(ctr, key, q);
+      for (int l = 0; l < 4 && k + l < m->dy; ++l)
+        y[(size_t)(t - 1) * m->dy + k + l] = x[m->obs_idx[k + l]] + sy * q[l];
+    }
+  }
+  free(x); free(z); free(xn);
+}
+
+/* Exact filter for x_{n+1} = (1 - theta h) x_n + sd sqrt(h) z observed as
+   y_t = x_{tS} + N(0, obs_var): the interval transition is
+   x_{tS} = a x_{(t-1)S} + N(0, q) with a = (1-theta h)^S and
+   q = sd^2 h sum_{i<S} (1-theta h)^{2i}. */
+double or_kalman_ou(const or_model *m, int T, const double *y, double *mean,
+                    double *var) {
+  double phi = 1.0 - m->p[0] * m->h;
+  double a = 1.0, q = 0.0;
+  for (int i = 0; i < m->S; ++i) {
+    q += m->sd[0] * m->sd[0] * m->h * a * a;
+    a *= phi;
+  }
+  double mu = m->prior_mean[0], P = m->prior_sd[0] * m->prior_sd[0];
+  double R = m->obs_var, ll = 0.0;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int t = 0; t < T; ++t) {
+    double mp = a * mu, Pp = a * a * P + q;
+    double Sv = Pp + R;
+    double r = y[t] - mp;
+    ll += -0.5 * (log(two_pi * Sv) + r * r / Sv);
+    double K = Pp / Sv;
+    mu = mp + K * r;
+    P = (1.0 - K) * Pp;
+    if (mean) mean[t] = mu;
+    if (var) var[t] = P;
+  }
+  return ll;
+}

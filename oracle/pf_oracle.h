@@ -1,0 +1,142 @@
+/*
+ * pf_oracle.h -- plain, slow, single-threaded FP64 reference of the
+ * independent-ensemble bootstrap particle filter (Crisan, Miguez, Rios,
+ * arXiv 1407.8071).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the HIP path: the Philox
+ * generator, Box-Muller, the model drifts, the resampler and the estimators
+ * are written here a second time, from their published definitions.
+ *
+ * What is computed, and where the paper defines it:
+ *   - state-space model (tau_0, tau_t, g_t): Sec. 2.2, eqs. (eqPrior),
+ *     (eqKernel) and the conditional observation density g_t;
+ *   - bootstrap filter: Sec. 2.3, Algorithm 1 (initialise from tau_0; per
+ *     observation draw from tau_t, weight by g_t and normalise, resample
+ *     multinomially);
+ *   - normalising-constant estimate G_t^N: Sec. 2.3, eq. (eqGtN);
+ *   - estimators (f, xi_t^N), (f, pi_t^N): Sec. 2.3 (sample averages);
+ *   - ensemble measure pi_t^{MxN} = (1/M) sum_m pi_t^{m,N}: Sec. 3.3,
+ *     Definition 3;
+ *   - stochastic Lorenz 63 under Euler-Maruyama: Sec. 4.1,
+ *     eqs. (eqDiscreteLorenz-1..3) and (eqObservLorenz);
+ *   - FitzHugh-Nagumo grid: Sec. 5.1, eqs. (eqUd), (eqVd) with the
+ *     neighbourhoods of Sec. 5.2 (classical reaction term, see DESIGN
+ *     readings), observations eq. (eqObservFHN);
+ *   - 1-D Ornstein-Uhlenbeck test model and its exact Kalman filter: the
+ *     linear-Gaussian special case of Sec. 2.2 in which the recursion
+ *     (eqRecursiveFormula1) has a closed form.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC'11), keyed and countered as described in
+ * the comments of pf_oracle.c; uniforms u = (2*(x>>9)+1) * 2^-24 in (0,1);
+ * normals by the Box-Muller transform; exponential variates -ln u.
+ */
+#ifndef PF_ORACLE_H
+#define PF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_OU1D = 0, OR_LORENZ63 = 1, OR_FHN = 2 };
+
+/* Counter "purpose" tags (top byte of counter word 3). */
+enum {
+  OR_P_INIT = 1, OR_P_PROP = 2, OR_P_RESAMPLE = 3, OR_P_TRUTH_INIT = 4,
+  OR_P_TRUTH_NOISE = 5, OR_P_OBS_NOISE = 6, OR_P_TRAIN = 7, OR_P_CONFIG = 8
+};
+
+#define OR_TRUTH_STREAM 0xFFFFFFFFu
+
+typedef struct {
+  int kind;                 /* OR_OU1D, OR_LORENZ63, OR_FHN                    */
+  int dx;                   /* state dimension (FHN: 2*J*J, v plane then w)    */
+  int J;                    /* grid side (FHN only)                            */
+  int S;                    /* Euler-Maruyama steps per observation interval  */
+  double h;                 /* Euler step                                      */
+  double p[4];              /* OU: theta | L63: s, r, b | FHN: a, D, eps, gam  */
+  double sd[2];             /* diffusion coefficient per variable class        */
+  int dy;                   /* observation dimension                           */
+  const int *obs_idx;       /* [dy] observed state indices (H is a selection)  */
+  double obs_var;           /* observation noise variance                      */
+  const double *prior_mean; /* [dx]                                            */
+  const double *prior_sd;   /* [dx]                                            */
+} or_model;
+
+/* ---- random numbers ---------------------------------------------------- */
+void or_key(uint64_t seed, uint32_t key[2]);
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double or_u01(uint32_t x);
+void or_normals4(const uint32_t ctr[4], const uint32_t key[2], double z[4]);
+/* bulk helpers for statistical tests: n words / normals from counters
+   (c0 = i/4 for i in [0,n), c1, c2, c3 fixed), lane i%4. */
+void or_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                      int64_t n, uint32_t *out);
+void or_normal_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                      int64_t n, double *out);
+
+/* ---- model ------------------------------------------------------------- */
+void or_drift(const or_model *m, const double *x, double *f);
+void or_laplacian(int J, const double *v, double *lap);
+/* normals of Euler step n for (c0, c1) under `purpose`: z[dx] */
+void or_step_noise(const or_model *m, const uint32_t key[2], uint32_t purpose,
+                   uint32_t c0, uint32_t c1, uint32_t n, double *z);
+void or_em_step(const or_model *m, const double *x, const double *z, double *xo);
+void or_prior_draw(const or_model *m, const uint32_t key[2], uint32_t purpose,
+                   uint32_t c0, uint32_t c1, double *x);
+double or_loglik(const or_model *m, const double *x, const double *y);
+
+/* ---- filter steps (one filter, N particles, X is [N][dx]) -------------- */
+void or_init(const or_model *m, uint64_t seed, uint32_t filter, int N, double *X);
+void or_propagate(const or_model *m, uint64_t seed, uint32_t filter, int N,
+                  int t, double *X);
+void or_weights(const or_model *m, int N, const double *X, const double *y,
+                double *lw);
+/* returns mx, W = sum exp(lw-mx), sumw2 = sum exp(2(lw-mx)); degenerate flag */
+int or_normalise(int N, const double *lw, double *mx, double *W, double *sumw2);
+void or_cdf(int N, const double *lw, double mx, int degenerate, double *C);
+void or_sorted_uniforms(uint64_t seed, uint32_t filter, int t, int N, double *U);
+void or_ancestors(int N, const double *C, const double *U, int32_t *A);
+void or_gather(int N, int dx, const double *X, const int32_t *A, double *Xo);
+void or_mean(int N, int dx, const double *X, double *mean);
+void or_weighted_mean(int N, int dx, const double *X, const double *lw,
+                      double mx, double *mean);
+
+/* One observation interval of one filter: propagate, weight, normalise,
+   resample, estimate.  X [N][dx] is updated in place (post-resampling).
+   Outputs (any may be NULL): lw[N], A[N], mean_post[dx], mean_w[dx].
+   logZ is incremented by log of the interval's factor of G_t^N including the
+   Gaussian normalising constant.  Returns 1 if the weights were degenerate. */
+int or_filter_interval(const or_model *m, uint64_t seed, uint32_t filter, int N,
+                       int t, double *X, const double *y, double *logZ,
+                       double *lw, int32_t *A, double *mean_post,
+                       double *mean_w, double *ess);
+
+/* Whole ensemble run over T observations y[T][dy].  est[T][dx] receives the
+   ensemble (equal-weight) post-resampling mean, est_w[T][dx] the ensemble of
+   weighted pre-resampling means, logZ[M] the final log-evidence per filter,
+   ess[T] the mean ESS over filters.  Filter m uses Philox counter word 1 = m
+   and the given seed.  Any output may be NULL. */
+void or_run_ensemble(const or_model *m, uint64_t seed, int M, int N, int T,
+                     const double *y, double *est, double *est_w,
+                     double *logZ, double *ess);
+
+/* Truth trajectory x_true[(T+1)][dx] (row 0 = x_0) and observations
+   y[T][dy], from the truth stream of `seed`. */
+void or_simulate(const or_model *m, uint64_t seed, int T, double *x_true,
+                 double *y);
+
+/* Exact Kalman filter for the OU test model observed every S steps:
+   mean[T], var[T] of the filtering distributions and the log marginal
+   likelihood log p(y_{1:T}). */
+double or_kalman_ou(const or_model *m, int T, const double *y, double *mean,
+                    double *var);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
