@@ -1,0 +1,196 @@
+/*
+ * pf.h -- C ABI of the MI355X (gfx950) independent-ensemble particle filter.
+ *
+ * The library runs M fully independent bootstrap particle filters of N
+ * particles each (Crisan, Miguez, Rios, arXiv 1407.8071, Sec. 3.1 and
+ * Definition 3) through one observation interval per call, entirely in
+ * hand-written HIP kernels, and averages them into a single estimator.
+ * Several ensembles, each with its own model, M, N and seed, can share one
+ * context (a batch).
+ *
+ * Conventions for every entry point:
+ *   - Pointers prefixed d_ are device pointers (HBM), h_ host pointers.
+ *   - The library never allocates device memory: the caller passes one
+ *     workspace (pf_workspace_bytes) and owns every buffer it passes in.
+ *     Host descriptor arrays are copied during pf_init and may be freed
+ *     afterwards.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  All
+ *     device work is enqueued asynchronously on it; a call returns once the
+ *     work is enqueued.  Device faults surface at the next call that
+ *     synchronises (pf_sync) or as PF_ERR_DEVICE from a later launch.
+ *   - No function throws across the ABI.  Argument and call-order errors
+ *     return a status before anything is enqueued; pf_last_error() gives a
+ *     human-readable reason for the last failure on the calling thread.
+ *   - One context is driven by one host thread at a time.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pf_status {
+  PF_OK = 0,
+  PF_ERR_INVALID_ARG = 1, /* bad descriptor, size, index or NULL pointer    */
+  PF_ERR_UNSUPPORTED = 2, /* valid request this build does not implement    */
+  PF_ERR_WORKSPACE = 3,   /* workspace too small or misaligned              */
+  PF_ERR_DEVICE = 4,      /* a HIP runtime call failed                      */
+  PF_ERR_STATE = 5        /* call out of order (e.g. step before init)      */
+} pf_status;
+
+/* State-space models (tau_0, tau_t, g_t) of Sec. 2.2. */
+typedef enum pf_model_kind {
+  /* x' = x - theta h x + sd sqrt(h) z, observed directly: the linear-Gaussian
+     special case with a closed-form optimal filter (test model). */
+  PF_MODEL_OU1D = 0,
+  /* Stochastic Lorenz 63 under Euler-Maruyama, Sec. 4.1,
+     eqs. (eqDiscreteLorenz-1..3); params = (s, r, b). */
+  PF_MODEL_LORENZ63 = 1,
+  /* FitzHugh-Nagumo network on a J x J grid, Sec. 5.1 eqs. (eqUd), (eqVd),
+     classical reaction v(v-a)(1-v) - w + D lap(v), recovery eps (v - gam w),
+     additive noise on both variables; lap is the 5-point Laplacian over the
+     truncated neighbourhoods of Sec. 5.2 (no flux).
+     params = (a, D, eps, gam). */
+  PF_MODEL_FHN = 2
+} pf_model_kind;
+
+typedef struct pf_model_desc {
+  int32_t kind;          /* pf_model_kind                                   */
+  int32_t state_dim;     /* d_x: 1 (OU), 3 (Lorenz), 2*J*J (FH-N)            */
+  int32_t grid_j;        /* J for FH-N, else 0                              */
+  int32_t steps_per_obs; /* S Euler-Maruyama steps per observation interval */
+  double h;              /* Euler step                                      */
+  double params[4];      /* see pf_model_kind                               */
+  double noise_sd[2];    /* diffusion per variable class (v, w for FH-N);
+                            the per-step noise is noise_sd * sqrt(h) * z    */
+  int32_t obs_dim;       /* d_y                                             */
+  const int32_t *h_obs_index; /* [obs_dim] observed state indices (H is a
+                            selection); FH-N v of node (i,j) is i*J + j     */
+  double obs_var;        /* Gaussian observation noise variance (eqObservLorenz,
+                            eqObservFHN)                                    */
+  const double *h_prior_mean; /* [state_dim] tau_0 = N(mean, diag(sd^2))    */
+  const double *h_prior_sd;   /* [state_dim]                                */
+} pf_model_desc;
+
+/* One ensemble of M independent filters with N particles each, on model
+   `model` (index into the model array), seeded by `seed`.  Filter m of the
+   ensemble draws its random numbers from Philox4x32-10 counter word 1 = m. */
+typedef struct pf_ensemble_desc {
+  int32_t model;
+  int32_t M;
+  int32_t N;
+  uint32_t flags; /* reserved, must be 0 */
+  uint64_t seed;
+} pf_ensemble_desc;
+
+/* Context options (pf_init `options`). */
+#define PF_OPT_PLAIN 0u /* one kernel per method step (reference path)     */
+#define PF_OPT_FUSED 1u /* one persistent fused kernel per interval        */
+
+/* Stages for pf_run_stages (bit mask). */
+#define PF_STAGE_PROPAGATE 1u /* Algorithm 1 step 2(a): draw from tau_t        */
+#define PF_STAGE_WEIGHT 2u    /* step 2(a): log g_t^{y_t}                      */
+#define PF_STAGE_RESAMPLE 4u  /* steps 2(a)-(b): normalise, CDF, sorted
+                                 uniforms, ancestor search                     */
+#define PF_STAGE_GATHER 8u    /* step 2(b): x_t^(k) = xbar_t^(a_k)             */
+#define PF_STAGE_ESTIMATE 16u /* (f, pi_t^N), (f, pi_t^{MxN}) for f = identity */
+#define PF_STAGE_ALL 31u
+
+typedef struct pf_ctx pf_ctx; /* opaque; the library owns only this host struct */
+
+/* Bytes of device workspace pf_init needs for these descriptors. */
+pf_status pf_workspace_bytes(const pf_model_desc *h_models, int32_t n_models,
+                             const pf_ensemble_desc *h_ens, int32_t n_ens,
+                             uint32_t options, size_t *out_bytes);
+
+/* Validate the descriptors, lay the workspace out (d_workspace must be
+   256-byte aligned and at least pf_workspace_bytes long; the caller keeps it
+   alive until pf_destroy), upload model constants and draw every filter's
+   initial particles x_0 ~ tau_0 (Algorithm 1, step 1).  The next pf_step
+   processes interval t = 1. */
+pf_status pf_init(const pf_model_desc *h_models, int32_t n_models,
+                  const pf_ensemble_desc *h_ens, int32_t n_ens, uint32_t options,
+                  void *d_workspace, size_t workspace_bytes, void *stream,
+                  pf_ctx **out_ctx);
+
+/* One observation interval t for every ensemble (Algorithm 1, step 2):
+   S Euler-Maruyama steps per particle, Gaussian log-likelihood weighting,
+   normalisation with the update of log G_t^N (eqGtN), multinomial resampling
+   and the estimators.  d_y: float32, the observations y_t of every ensemble
+   concatenated in ensemble order (obs_dim of its model each).  Advances t. */
+pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream);
+
+/* Run selected stages (PF_STAGE_*) of the current interval on the plain path
+   without advancing t: the per-step hooks of the parity tests.  The fused
+   context runs them on its plain kernels too. */
+pf_status pf_run_stages(pf_ctx *ctx, uint32_t stages, const float *d_y, void *stream);
+
+/* Estimates after the last completed interval.  Any pointer may be NULL.
+   d_mean:   float64 [sum_e state_dim(e)]: ensemble average (Definition 3) of
+             the post-resampling filter means (f, pi_t^{m,N}), f = identity.
+   d_mean_w: float64 [sum_e state_dim(e)]: ensemble average of the weighted
+             pre-resampling means sum_i w_t^(i) xbar_t^(i).
+   d_logZ:   float64 [sum_e M(e)]: log G_t^N per filter including the Gaussian
+             normalising constant, so that exp(d_logZ) is unbiased for
+             p(y_{1:t}) (Lemma 2); -inf once a filter degenerated.
+   d_filter_mean: float64 [sum_e M(e)*state_dim(e)]: per-filter means. */
+pf_status pf_estimate(pf_ctx *ctx, double *d_mean, double *d_mean_w, double *d_logZ,
+                      double *d_filter_mean, void *stream);
+
+/* Test hooks.  Particle layouts: vector models (OU, Lorenz) float32
+   [M][state_dim][N]; grid model (FH-N) float32 [M][N][state_dim]. */
+pf_status pf_set_particles(pf_ctx *ctx, int32_t ens, const float *d_x, void *stream);
+/* post-resampling particles x_t (materialised by a gather if needed) */
+pf_status pf_get_particles(pf_ctx *ctx, int32_t ens, float *d_x, void *stream);
+/* pre-resampling particles xbar_t of the current interval (get / overwrite) */
+pf_status pf_get_predicted(pf_ctx *ctx, int32_t ens, float *d_x, void *stream);
+pf_status pf_set_predicted(pf_ctx *ctx, int32_t ens, const float *d_x, void *stream);
+/* log-weights float32 [M][N] of the current interval */
+pf_status pf_get_logweights(pf_ctx *ctx, int32_t ens, float *d_lw, void *stream);
+pf_status pf_set_logweights(pf_ctx *ctx, int32_t ens, const float *d_lw, void *stream);
+/* ancestors int32 [M][N] of the current interval, ascending per filter */
+pf_status pf_get_ancestors(pf_ctx *ctx, int32_t ens, int32_t *d_a, void *stream);
+/* per-filter float64 [M][4]: max log-weight, sum exp(lw - max),
+   sum exp(2(lw - max)), degenerate flag (1.0 if no weight was positive) */
+pf_status pf_get_filter_stats(pf_ctx *ctx, int32_t ens, double *d_stats, void *stream);
+/* Set the interval index t that the next pf_step / pf_run_stages processes. */
+pf_status pf_set_interval(pf_ctx *ctx, int32_t t);
+pf_status pf_get_interval(const pf_ctx *ctx, int32_t *out_t);
+
+/* Truth path and observations from the model of ensemble `ens` on the
+   dedicated truth stream of `seed`: d_x_true float32 [(T+1)][state_dim]
+   (row 0 is x_0 ~ tau_0), d_y float32 [T][obs_dim].  Synthetic-data helper
+   for benchmarks; runs on the GPU. */
+pf_status pf_simulate(pf_ctx *ctx, int32_t ens, uint64_t seed, int32_t T,
+                      float *d_x_true, float *d_y, void *stream);
+
+/* Random-number hook: for i in [0, n), word/normal i comes from the Philox4x32-10
+   call with counter (i/4, c1, c2, c3) and key(seed), lane i%4.  d_bits uint32
+   [n] and d_z float32 [n] (Box-Muller normals); either may be NULL. */
+pf_status pf_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                           int64_t n, uint32_t *d_bits, float *d_z, void *stream);
+
+/* Timing of the dominant kernel (the propagation kernel on the plain path,
+   the fused interval kernel on the fused path).  While enabled, every
+   pf_step records a pair of HIP events around that kernel on the stream it
+   is launched on (at most 65536 pairs are kept).  pf_read_profile waits for
+   them, returns the summed duration in milliseconds and the number of
+   launches, and clears the record. */
+pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable);
+pf_status pf_read_profile(pf_ctx *ctx, double *out_ms, int64_t *out_launches);
+
+/* Block until all work of the context's last stream is done; reports an
+   asynchronous device error as PF_ERR_DEVICE. */
+pf_status pf_sync(pf_ctx *ctx);
+void pf_destroy(pf_ctx *ctx);
+const char *pf_status_str(pf_status s);
+const char *pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H */

@@ -76,6 +76,7 @@ def lib():
             "or_loglik": (C.c_double, [M, _D, _D]),
             "or_init": (None, [M, C.c_uint64, C.c_uint32, C.c_int, _D]),
             "or_propagate": (None, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D]),
+            "or_propagate_particle": (None, [M, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int, _D]),
             "or_weights": (None, [M, C.c_int, _D, _D, _D]),
             "or_normalise": (C.c_int, [C.c_int, _D, _D, _D, _D]),
             "or_cdf": (None, [C.c_int, _D, C.c_double, C.c_int, _D]),
@@ -227,6 +228,13 @@ def propagate(m: Model, seed, filt, t, X) -> np.ndarray:
     X = np.array(X, dtype=np.float64, order="C", copy=True)
     lib().or_propagate(m.ref, C.c_uint64(seed), filt, X.shape[0], t, _d(X))
     return X
+
+
+def propagate_particle(m: Model, seed, filt, index, t, x) -> np.ndarray:
+    """Interval t of one particle with Philox counter word 0 = index."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    lib().or_propagate_particle(m.ref, C.c_uint64(seed), filt, index, t, _d(x))
+    return x
 
 
 def weights(m: Model, X, y) -> np.ndarray:

@@ -258,6 +258,25 @@ void or_propagate(const or_model *m, uint64_t seed, uint32_t filter, int N,
   free(xn);
 }
 
+/* The same draw for one particle of index `index` (Philox counter word 0),
+   so that a sample of a large filter can be checked particle by particle. */
+void or_propagate_particle(const or_model *m, uint64_t seed, uint32_t filter,
+                           uint32_t index, int t, double *x) {
+  uint32_t key[2];
+  or_key(seed, key);
+  int d = m->dx;
+  double *z = (double *)malloc(sizeof(double) * (size_t)d);
+  double *xn = (double *)malloc(sizeof(double) * (size_t)d);
+  for (int s = 0; s < m->S; ++s) {
+    uint32_t n = (uint32_t)((t - 1) * m->S + s);
+    or_step_noise(m, key, OR_P_PROP, index, filter, n, z);
+    or_em_step(m, x, z, xn);
+    memcpy(x, xn, sizeof(double) * (size_t)d);
+  }
+  free(z);
+  free(xn);
+}
+
 /* Step 2(a), weighting: log g_t^{y_t}(xbar_t^(i)). */
 void or_weights(const or_model *m, int N, const double *X, const double *y,
                 double *lw) {

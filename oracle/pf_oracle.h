@@ -94,6 +94,8 @@ double or_loglik(const or_model *m, const double *x, const double *y);
 void or_init(const or_model *m, uint64_t seed, uint32_t filter, int N, double *X);
 void or_propagate(const or_model *m, uint64_t seed, uint32_t filter, int N,
                   int t, double *X);
+void or_propagate_particle(const or_model *m, uint64_t seed, uint32_t filter,
+                           uint32_t index, int t, double *x);
 void or_weights(const or_model *m, int N, const double *X, const double *y,
                 double *lw);
 /* returns mx, W = sum exp(lw-mx), sumw2 = sum exp(2(lw-mx)); degenerate flag */

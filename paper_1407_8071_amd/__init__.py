@@ -1,0 +1,287 @@
+"""MI355X-native independent-ensemble particle filter (arXiv 1407.8071).
+
+Thin ctypes binding over ``libpf.so`` (the C ABI of ``include/pf.h``).  This
+module only marshals arguments: every step of the filter runs in the HIP
+kernels of the shared library.  PyTorch provides device memory (the
+workspace and all tensors) and the current HIP stream.  If ``libpf.so`` is
+missing the import of the binding fails loudly; there is no CPU fallback.
+
+Model dictionaries (see ``PFModel``): kind ('ou1d' | 'lorenz63' | 'fhn'), dx,
+J, S, h, params, noise_sd, obs_idx, obs_var, prior_mean, prior_sd.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpf.so")
+
+KIND = {"ou1d": 0, "lorenz63": 1, "fhn": 2}
+OPT_PLAIN, OPT_FUSED = 0, 1
+STAGE_PROPAGATE, STAGE_WEIGHT, STAGE_RESAMPLE, STAGE_GATHER, STAGE_ESTIMATE = 1, 2, 4, 8, 16
+STAGE_ALL = 31
+
+
+class PFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pf status {status}: {msg}")
+        self.status = status
+
+
+class _ModelDesc(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("state_dim", C.c_int32), ("grid_j", C.c_int32),
+        ("steps_per_obs", C.c_int32), ("h", C.c_double), ("params", C.c_double * 4),
+        ("noise_sd", C.c_double * 2), ("obs_dim", C.c_int32),
+        ("h_obs_index", C.POINTER(C.c_int32)), ("obs_var", C.c_double),
+        ("h_prior_mean", C.POINTER(C.c_double)), ("h_prior_sd", C.POINTER(C.c_double)),
+    ]
+
+
+class _EnsDesc(C.Structure):
+    _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32),
+                ("flags", C.c_uint32), ("seed", C.c_uint64)]
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def lib():
+    """Load libpf.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1407_8071_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    i32, u32, u64, i64 = C.c_int32, C.c_uint32, C.c_uint64, C.c_int64
+    MD, ED = C.POINTER(_ModelDesc), C.POINTER(_EnsDesc)
+    sigs = {
+        "pf_workspace_bytes": [MD, i32, ED, i32, u32, C.POINTER(C.c_size_t)],
+        "pf_init": [MD, i32, ED, i32, u32, _VP, C.c_size_t, _VP, C.POINTER(_VP)],
+        "pf_step": [_VP, _VP, _VP],
+        "pf_run_stages": [_VP, u32, _VP, _VP],
+        "pf_estimate": [_VP, _VP, _VP, _VP, _VP, _VP],
+        "pf_set_particles": [_VP, i32, _VP, _VP],
+        "pf_get_particles": [_VP, i32, _VP, _VP],
+        "pf_get_predicted": [_VP, i32, _VP, _VP],
+        "pf_set_predicted": [_VP, i32, _VP, _VP],
+        "pf_get_logweights": [_VP, i32, _VP, _VP],
+        "pf_set_logweights": [_VP, i32, _VP, _VP],
+        "pf_get_ancestors": [_VP, i32, _VP, _VP],
+        "pf_get_filter_stats": [_VP, i32, _VP, _VP],
+        "pf_set_interval": [_VP, i32],
+        "pf_get_interval": [_VP, C.POINTER(i32)],
+        "pf_simulate": [_VP, i32, u64, i32, _VP, _VP, _VP],
+        "pf_philox_stream": [u64, u32, u32, u32, i64, _VP, _VP, _VP],
+        "pf_sync": [_VP],
+        "pf_set_profiling": [_VP, i32],
+        "pf_read_profile": [_VP, C.POINTER(C.c_double), C.POINTER(i64)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.pf_destroy.argtypes = [_VP]
+    L.pf_destroy.restype = None
+    L.pf_status_str.argtypes = [C.c_int]
+    L.pf_status_str.restype = C.c_char_p
+    L.pf_last_error.argtypes = []
+    L.pf_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise PFError(status, lib().pf_last_error().decode())
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class PFModel:
+    """Marshals a model dictionary into a pf_model_desc (keeps arrays alive)."""
+
+    def __init__(self, spec: dict):
+        self.spec = dict(spec)
+        self.dx = int(spec["dx"])
+        self.obs_idx = np.ascontiguousarray(spec["obs_idx"], dtype=np.int32)
+        self.dy = int(self.obs_idx.size)
+        self.prior_mean = np.ascontiguousarray(spec["prior_mean"], dtype=np.float64)
+        self.prior_sd = np.ascontiguousarray(spec["prior_sd"], dtype=np.float64)
+        p = list(spec["params"]) + [0.0] * (4 - len(spec["params"]))
+        sd = list(spec["noise_sd"]) + [0.0] * (2 - len(spec["noise_sd"]))
+        self.desc = _ModelDesc(
+            KIND[spec["kind"]], self.dx, int(spec.get("J", 0)), int(spec["S"]),
+            float(spec["h"]), (C.c_double * 4)(*p), (C.c_double * 2)(*sd), self.dy,
+            self.obs_idx.ctypes.data_as(C.POINTER(C.c_int32)), float(spec["obs_var"]),
+            self.prior_mean.ctypes.data_as(C.POINTER(C.c_double)),
+            self.prior_sd.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+class ParticleFilter:
+    """A context of one or more ensembles of independent bootstrap filters.
+
+    ``ensembles`` is a list of (model_index, M, N, seed).  ``fused`` selects
+    the persistent fused interval kernel instead of one kernel per step.
+    """
+
+    def __init__(self, models, ensembles, fused: bool = False, stream=None):
+        import torch
+        self.models = [m if isinstance(m, PFModel) else PFModel(m) for m in models]
+        self.ens = [tuple(e) for e in ensembles]
+        nm, ne = len(self.models), len(self.ens)
+        self._md = (_ModelDesc * nm)(*[m.desc for m in self.models])
+        self._ed = (_EnsDesc * ne)(*[_EnsDesc(int(mi), int(M), int(N), 0, int(seed))
+                                     for (mi, M, N, seed) in self.ens])
+        self.options = OPT_FUSED if fused else OPT_PLAIN
+        nbytes = C.c_size_t()
+        _check(lib().pf_workspace_bytes(self._md, nm, self._ed, ne, self.options,
+                                        C.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self.workspace = torch.empty(max(1, nbytes.value) + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        self._ws = C.c_void_p((base + 255) // 256 * 256)
+        ctx = C.c_void_p()
+        _check(lib().pf_init(self._md, nm, self._ed, ne, self.options, self._ws,
+                             nbytes.value, _stream(stream), C.byref(ctx)))
+        self._ctx = ctx
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                lib().pf_destroy(ctx)
+            except Exception:
+                pass
+            self._ctx = None
+
+    # ---- shapes ------------------------------------------------------------
+    def dims(self, e: int):
+        mi, M, N, _ = self.ens[e]
+        return self.models[mi], M, N
+
+    def particle_shape(self, e: int):
+        m, M, N = self.dims(e)
+        if m.spec["kind"] == "fhn":
+            return (M, N, m.dx)
+        return (M, m.dx, N)
+
+    # ---- the filter --------------------------------------------------------
+    def step(self, y, stream=None):
+        _check(lib().pf_step(self._ctx, _ptr(y), _stream(stream)))
+
+    def run_stages(self, stages: int, y=None, stream=None):
+        _check(lib().pf_run_stages(self._ctx, stages, _ptr(y), _stream(stream)))
+
+    def estimate(self, stream=None):
+        import torch
+        dx = sum(self.models[mi].dx for (mi, _, _, _) in self.ens)
+        nM = sum(M for (_, M, _, _) in self.ens)
+        nF = sum(M * self.models[mi].dx for (mi, M, _, _) in self.ens)
+        mean = torch.empty(dx, dtype=torch.float64, device="cuda")
+        mean_w = torch.empty(dx, dtype=torch.float64, device="cuda")
+        logZ = torch.empty(nM, dtype=torch.float64, device="cuda")
+        fmean = torch.empty(nF, dtype=torch.float64, device="cuda")
+        _check(lib().pf_estimate(self._ctx, _ptr(mean), _ptr(mean_w), _ptr(logZ), _ptr(fmean),
+                                 _stream(stream)))
+        return mean, mean_w, logZ, fmean
+
+    # ---- hooks -------------------------------------------------------------
+    def set_particles(self, e: int, x, stream=None):
+        import torch
+        assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+        assert tuple(x.shape) == self.particle_shape(e)
+        _check(lib().pf_set_particles(self._ctx, e, _ptr(x), _stream(stream)))
+
+    def _get(self, fn, e, shape, dtype, stream):
+        import torch
+        out = torch.empty(shape, dtype=dtype, device="cuda")
+        _check(fn(self._ctx, e, _ptr(out), _stream(stream)))
+        return out
+
+    def get_particles(self, e: int, stream=None):
+        import torch
+        return self._get(lib().pf_get_particles, e, self.particle_shape(e), torch.float32, stream)
+
+    def get_predicted(self, e: int, stream=None):
+        import torch
+        return self._get(lib().pf_get_predicted, e, self.particle_shape(e), torch.float32, stream)
+
+    def set_predicted(self, e: int, x, stream=None):
+        import torch
+        assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+        assert tuple(x.shape) == self.particle_shape(e)
+        _check(lib().pf_set_predicted(self._ctx, e, _ptr(x), _stream(stream)))
+
+    def get_logweights(self, e: int, stream=None):
+        import torch
+        _, M, N = self.dims(e)
+        return self._get(lib().pf_get_logweights, e, (M, N), torch.float32, stream)
+
+    def set_logweights(self, e: int, lw, stream=None):
+        import torch
+        _, M, N = self.dims(e)
+        assert lw.dtype == torch.float32 and lw.is_cuda and tuple(lw.shape) == (M, N)
+        _check(lib().pf_set_logweights(self._ctx, e, _ptr(lw.contiguous()), _stream(stream)))
+
+    def get_ancestors(self, e: int, stream=None):
+        import torch
+        _, M, N = self.dims(e)
+        return self._get(lib().pf_get_ancestors, e, (M, N), torch.int32, stream)
+
+    def get_filter_stats(self, e: int, stream=None):
+        import torch
+        _, M, _ = self.dims(e)
+        return self._get(lib().pf_get_filter_stats, e, (M, 4), torch.float64, stream)
+
+    def set_interval(self, t: int):
+        _check(lib().pf_set_interval(self._ctx, t))
+
+    def interval(self) -> int:
+        t = C.c_int32()
+        _check(lib().pf_get_interval(self._ctx, C.byref(t)))
+        return t.value
+
+    def simulate(self, e: int, seed: int, T: int, stream=None):
+        import torch
+        m, _, _ = self.dims(e)
+        xt = torch.empty((T + 1, m.dx), dtype=torch.float32, device="cuda")
+        y = torch.empty((T, m.dy), dtype=torch.float32, device="cuda")
+        _check(lib().pf_simulate(self._ctx, e, seed, T, _ptr(xt), _ptr(y), _stream(stream)))
+        return xt, y
+
+    def sync(self):
+        _check(lib().pf_sync(self._ctx))
+
+    def set_profiling(self, enable: bool):
+        _check(lib().pf_set_profiling(self._ctx, 1 if enable else 0))
+
+    def read_profile(self):
+        """(summed milliseconds, launches) of the dominant kernel since the last read."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().pf_read_profile(self._ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+def philox_stream(seed: int, c1: int, c2: int, c3: int, n: int, stream=None):
+    """Philox words and Box-Muller normals from the device generator."""
+    import torch
+    bits = torch.empty(n, dtype=torch.int32, device="cuda")
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(lib().pf_philox_stream(seed, c1, c2, c3, n, _ptr(bits), _ptr(z), _stream(stream)))
+    return bits, z

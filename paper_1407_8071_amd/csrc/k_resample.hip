@@ -1,0 +1,297 @@
+// k_resample.hip -- normalisation, cumulative weights, sorted uniforms and the
+// ancestor search of multinomial resampling (Algorithm 1, steps 2(a)-(b)),
+// tiled so that one filter of any N spreads over ceil(N / 4096) workgroups.
+//
+// Each filter's N log-weights are cut into tiles of 4096 (256 threads x 16
+// consecutive elements).  The CDF is held in two levels: a tile-local
+// inclusive scan Cl (FP64) and per-tile offsets coff, with coff[q+1] =
+// coff[q] + Cl[last of tile q], so C_i = coff[tile(i)] + Cl[i] agrees exactly
+// with the offsets at every tile boundary.  The exponential spacings use the
+// same two-level layout (Sl, soff).  Uniforms come from exponential spacings:
+// E_j = -ln u_j (j = 0..N), S_k = sum_{j<=k} E_j, U_k = S_k / S_N, which are
+// the order statistics of N uniforms, so the ancestors come out ascending.
+#include "pf_internal.h"
+
+namespace pfk {
+namespace {
+
+__device__ __forceinline__ float sane_lw(float v) { return (v == v) ? v : -INFINITY; }
+
+// Tile maximum of the log-weights.
+__global__ void __launch_bounds__(TILE_THREADS)
+k_tile_max(int N, int T, const float *__restrict__ lw, double *__restrict__ tile) {
+  __shared__ float sh[TILE_THREADS / 64];
+  const int m = blockIdx.y, q = blockIdx.x;
+  float v = -INFINITY;
+  for (int e = 0; e < TILE_PER_THREAD; ++e) {
+    const int i = q * TILE + e * TILE_THREADS + threadIdx.x;
+    if (i < N) v = fmaxf(v, sane_lw(lw[(size_t)m * N + i]));
+  }
+  v = block_max(v, sh);
+  if (threadIdx.x == 0) tile[((size_t)m * T + q) * TREC + 0] = (double)v;
+}
+
+// mx of a filter from its tile maxima (exact, order-free).
+__device__ __forceinline__ double filter_max(const double *__restrict__ tile, int m, int T,
+                                             float *sh) {
+  float v = -INFINITY;
+  for (int q = threadIdx.x; q < T; q += blockDim.x)
+    v = fmaxf(v, (float)tile[((size_t)m * T + q) * TREC + 0]);
+  return (double)block_max(v, sh);
+}
+
+// Tile-local inclusive scan of w_i = exp(lw_i - mx) in FP64 (w = 1 for every
+// particle when no weight is positive).  Thread t owns the 16 consecutive
+// elements [16t, 16t+16) of the tile.
+__global__ void __launch_bounds__(TILE_THREADS)
+k_cdf_tiles(int N, int T, const float *__restrict__ lw, double *__restrict__ tile,
+            double *__restrict__ Cl) {
+  __shared__ float shf[TILE_THREADS / 64];
+  __shared__ double shd[TILE_THREADS / 64];
+  const int m = blockIdx.y, q = blockIdx.x;
+  const double mx = filter_max(tile, m, T, shf);
+  const bool deg = !(mx > -INFINITY);
+  const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
+  double w[TILE_PER_THREAD];
+  double run = 0.0, sq = 0.0;
+#pragma unroll
+  for (int e = 0; e < TILE_PER_THREAD; ++e) {
+    const int i = base + e;
+    double we = 0.0;
+    if (i < N) we = deg ? 1.0 : exp((double)sane_lw(lw[(size_t)m * N + i]) - mx);
+    run += we;
+    sq += we * we;
+    w[e] = run;
+  }
+  double tot;
+  const double off = block_exscan(run, shd, &tot);
+  const int last = min(N - 1, q * TILE + TILE - 1);
+#pragma unroll
+  for (int e = 0; e < TILE_PER_THREAD; ++e) {
+    const int i = base + e;
+    if (i < N) {
+      const double c = off + w[e];
+      Cl[(size_t)m * N + i] = c;
+      if (i == last) tile[((size_t)m * T + q) * TREC + 1] = c;
+    }
+  }
+  const double s2 = block_sum(sq, shd);
+  if (threadIdx.x == 0) tile[((size_t)m * T + q) * TREC + 2] = s2;
+}
+
+// Tile-local inclusive sums of the exponential variates E_j; the last tile
+// also adds E_N to its total.
+__global__ void __launch_bounds__(TILE_THREADS)
+k_uniform_tiles(Key key, int N, int T, int t, double *__restrict__ tile, double *__restrict__ Sl) {
+  __shared__ double shd[TILE_THREADS / 64];
+  const int m = blockIdx.y, q = blockIdx.x;
+  const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
+  double s[TILE_PER_THREAD];
+  double run = 0.0;
+#pragma unroll
+  for (int g = 0; g < TILE_PER_THREAD / 4; ++g) {
+    const int j0 = base + 4 * g;
+    uint4 r = make_uint4(0, 0, 0, 0);
+    if (j0 < N) r = philox((uint32_t)(j0 >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
+    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if (j0 + l < N) run += -log(u01d(rw[l]));
+      s[4 * g + l] = run;
+    }
+  }
+  double tot;
+  const double off = block_exscan(run, shd, &tot);
+  const int last = min(N - 1, q * TILE + TILE - 1);
+#pragma unroll
+  for (int e = 0; e < TILE_PER_THREAD; ++e) {
+    const int j = base + e;
+    if (j < N) {
+      const double c = off + s[e];
+      Sl[(size_t)m * N + j] = c;
+      if (j == last) {
+        double tail = 0.0;
+        if (q == T - 1) {
+          const uint4 r = philox((uint32_t)(N >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
+          const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+          tail = -log(u01d(rw[N & 3]));
+        }
+        tile[((size_t)m * T + q) * TREC + 3] = c + tail;
+      }
+    }
+  }
+}
+
+// Per filter: tile offsets of the CDF and of the exponential sums (sequential
+// in tile order), the normaliser, ESS and the log G_t^N update of (eqGtN):
+// log G += mx + log(W / N) - (d_y/2) log(2 pi sigma^2).
+__global__ void k_filter_reduce(int N, int T, double lognorm, const double *__restrict__ tile,
+                                double *__restrict__ coff, double *__restrict__ soff,
+                                double *__restrict__ fstat) {
+  const int m = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double mx = -INFINITY, c = 0.0, s = 0.0, s2 = 0.0;
+  coff[(size_t)m * (T + 1)] = 0.0;
+  soff[(size_t)m * (T + 1)] = 0.0;
+  for (int q = 0; q < T; ++q) {
+    const double *r = tile + ((size_t)m * T + q) * TREC;
+    mx = fmax(mx, r[0]);
+    c += r[1];
+    s += r[3];
+    s2 += r[2];
+    coff[(size_t)m * (T + 1) + q + 1] = c;
+    soff[(size_t)m * (T + 1) + q + 1] = s;
+  }
+  double *f = fstat + (size_t)m * FREC;
+  const bool deg = !(mx > -INFINITY);
+  f[0] = mx;
+  f[1] = c;
+  f[2] = s2;
+  f[3] = deg ? 1.0 : 0.0;
+  f[4] = s;
+  f[5] = deg ? -INFINITY : f[5] + mx + log(c / (double)N) + lognorm;
+  f[6] = c * c / s2;
+}
+
+struct Cdf2 {
+  const double *Cl, *coff;
+  int N;
+  __device__ __forceinline__ double at(int i) const { return coff[i / TILE] + Cl[i]; }
+};
+
+// Smallest i in [lo, N-1] with C(i) > v, given C(lo - 1) <= v: exponential
+// search from lo, then bisection.  The answer is clamped to N - 1.
+__device__ __forceinline__ int gallop(const Cdf2 &c, int lo, double v) {
+  const int hi_max = c.N - 1;
+  if (lo >= hi_max) return hi_max;
+  if (c.at(lo) > v) return lo;
+  int step = 1, known_le = lo, hi = lo;
+  while (true) {
+    hi = known_le + step;
+    if (hi >= hi_max) {
+      hi = hi_max;
+      break;
+    }
+    if (c.at(hi) > v) break;
+    known_le = hi;
+    step <<= 1;
+  }
+  int a = known_le + 1, b = hi;  // answer in [a, b]
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (c.at(mid) > v)
+      b = mid;
+    else
+      a = mid + 1;
+  }
+  return a;
+}
+
+// Ancestor a_k = min{ i : C_i > U_k C_{N-1} } for the 16 consecutive k of
+// each thread: bisection for the first, exponential search onward.
+__global__ void __launch_bounds__(TILE_THREADS)
+k_ancestors(int N, int T, const double *__restrict__ Cl, const double *__restrict__ coff,
+            const double *__restrict__ Sl, const double *__restrict__ soff,
+            const double *__restrict__ fstat, int32_t *__restrict__ A) {
+  const int m = blockIdx.y, q = blockIdx.x;
+  const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
+  if (base >= N) return;
+  const double W = fstat[(size_t)m * FREC + 1];
+  const double SN = fstat[(size_t)m * FREC + 4];
+  const double so = soff[(size_t)m * (T + 1) + q];
+  const Cdf2 c{Cl + (size_t)m * N, coff + (size_t)m * (T + 1), N};
+  int i = 0;
+  // first target: full bisection
+  {
+    const double v = ((so + Sl[(size_t)m * N + base]) / SN) * W;
+    int a = 0, b = N - 1;
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if (c.at(mid) > v)
+        b = mid;
+      else
+        a = mid + 1;
+    }
+    i = a;
+    A[(size_t)m * N + base] = i;
+  }
+  for (int e = 1; e < TILE_PER_THREAD; ++e) {
+    const int k = base + e;
+    if (k >= N) break;
+    const double v = ((so + Sl[(size_t)m * N + k]) / SN) * W;
+    i = gallop(c, i, v);
+    A[(size_t)m * N + k] = i;
+  }
+}
+
+// Per-filter means from the tile partial sums, then the equal-weight
+// ensemble average of Definition 3 (fixed summation order).
+__global__ void k_filter_means(int N, int T, int dx, const double *__restrict__ mpart,
+                               const double *__restrict__ wpart, const double *__restrict__ fstat,
+                               double *__restrict__ fmean, double *__restrict__ fmeanw) {
+  const int m = blockIdx.x;
+  const double W = fstat[(size_t)m * FREC + 1];
+  for (int c = threadIdx.x; c < dx; c += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < T; ++q) {
+      a += mpart[((size_t)m * T + q) * dx + c];
+      b += wpart[((size_t)m * T + q) * dx + c];
+    }
+    fmean[(size_t)m * dx + c] = a / (double)N;
+    fmeanw[(size_t)m * dx + c] = b / W;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_ensemble_mean(int M, int dx, const double *__restrict__ fmean, const double *__restrict__ fmeanw,
+                double *__restrict__ emean) {
+  __shared__ double sh[4];
+  if (dx <= 64) {
+    // few components: the workgroup reduces over filters for each component
+    for (int c = 0; c < dx; ++c) {
+      double a = 0.0, b = 0.0;
+      for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        a += fmean[(size_t)m * dx + c];
+        b += fmeanw[(size_t)m * dx + c];
+      }
+      a = block_sum(a, sh);
+      b = block_sum(b, sh);
+      if (threadIdx.x == 0) {
+        emean[c] = a / (double)M;
+        emean[dx + c] = b / (double)M;
+      }
+    }
+  } else {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= dx) return;
+    double a = 0.0, b = 0.0;
+    for (int m = 0; m < M; ++m) {
+      a += fmean[(size_t)m * dx + c];
+      b += fmeanw[(size_t)m * dx + c];
+    }
+    emean[c] = a / (double)M;
+    emean[dx + c] = b / (double)M;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s) {
+  const dim3 g((unsigned)e.T, (unsigned)e.M);
+  k_tile_max<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile);
+  k_cdf_tiles<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile, e.Cl);
+  k_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, e.tile, e.Sl);
+  k_filter_reduce<<<e.M, 64, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
+  k_ancestors<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_means(const EnsDev &e, hipStream_t s) {
+  const int dx = e.md.dx;
+  k_filter_means<<<e.M, 256, 0, s>>>(e.N, e.T, dx, e.mpart, e.wpart, e.fstat, e.fmean, e.fmeanw);
+  const unsigned g = dx <= 64 ? 1u : (unsigned)((dx + 255) / 256);
+  k_ensemble_mean<<<g, 256, 0, s>>>(e.M, dx, e.fmean, e.fmeanw, e.emean);
+  return hipGetLastError();
+}
+
+}  // namespace pfk

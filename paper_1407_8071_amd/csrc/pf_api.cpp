@@ -1,0 +1,547 @@
+// pf_api.cpp -- the C ABI of include/pf.h: descriptor validation, workspace
+// layout, and the per-interval orchestration of the gfx950 kernels.
+#include "pf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pf_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pf_status fail(pf_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+pf_status dev(hipError_t e, const char *what) {
+  if (e == hipSuccess) return PF_OK;
+  return fail(PF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PF_TRY(expr)                  \
+  do {                                \
+    pf_status _s = (expr);            \
+    if (_s != PF_OK) return _s;       \
+  } while (0)
+#define PF_HIP(expr) PF_TRY(dev((expr), #expr))
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Host-side record of one ensemble.
+struct Ens {
+  pf_ensemble_desc d;
+  int dx, dy, T;
+  bool grid;
+  std::vector<int32_t> obs_idx;
+  std::vector<float> prior_mean, prior_sd;
+  pfk::EnsDev dev;
+  int cur = 0;           // buffer holding the particles entering the next interval
+  bool pending = false;  // X[cur] still needs the gather through A
+  int xbar = 1;          // buffer holding xbar of the current interval
+};
+
+// Offsets of every array of one ensemble inside the workspace.
+struct Layout {
+  size_t obs, pmean, psd, X0, X1, lw, A, Cl, Sl, tile, coff, soff, fstat, mpart, wpart, fmean,
+      fmeanw, emean, end;
+};
+
+Layout layout_of(size_t base, int M, int N, int dx, int dy, int T) {
+  Layout L{};
+  size_t o = base;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t MN = (size_t)M * N;
+  L.obs = take(sizeof(int32_t) * (size_t)dy);
+  L.pmean = take(sizeof(float) * (size_t)dx);
+  L.psd = take(sizeof(float) * (size_t)dx);
+  L.X0 = take(sizeof(float) * MN * dx);
+  L.X1 = take(sizeof(float) * MN * dx);
+  L.lw = take(sizeof(float) * MN);
+  L.A = take(sizeof(int32_t) * MN);
+  L.Cl = take(sizeof(double) * MN);
+  L.Sl = take(sizeof(double) * MN);
+  L.tile = take(sizeof(double) * (size_t)M * T * pfk::TREC);
+  L.coff = take(sizeof(double) * (size_t)M * (T + 1));
+  L.soff = take(sizeof(double) * (size_t)M * (T + 1));
+  L.fstat = take(sizeof(double) * (size_t)M * pfk::FREC);
+  L.mpart = take(sizeof(double) * (size_t)M * T * dx);
+  L.wpart = take(sizeof(double) * (size_t)M * T * dx);
+  L.fmean = take(sizeof(double) * (size_t)M * dx);
+  L.fmeanw = take(sizeof(double) * (size_t)M * dx);
+  L.emean = take(sizeof(double) * 2 * (size_t)dx);
+  L.end = o;
+  return L;
+}
+
+pf_status check_model(const pf_model_desc &m, int idx) {
+  if (m.kind == PF_MODEL_OU1D) {
+    if (m.state_dim != 1) return fail(PF_ERR_INVALID_ARG, "model %d: OU needs state_dim 1", idx);
+  } else if (m.kind == PF_MODEL_LORENZ63) {
+    if (m.state_dim != 3) return fail(PF_ERR_INVALID_ARG, "model %d: Lorenz needs state_dim 3", idx);
+  } else if (m.kind == PF_MODEL_FHN) {
+    if (m.grid_j < 2 || m.grid_j > 64 || m.state_dim != 2 * m.grid_j * m.grid_j)
+      return fail(PF_ERR_INVALID_ARG, "model %d: FH-N needs 2 <= J <= 64 and state_dim 2*J*J", idx);
+    return fail(PF_ERR_UNSUPPORTED, "model %d: FH-N grid model not in this build", idx);
+  } else {
+    return fail(PF_ERR_INVALID_ARG, "model %d: unknown kind %d", idx, m.kind);
+  }
+  if (m.steps_per_obs < 1 || m.steps_per_obs > (1 << 20))
+    return fail(PF_ERR_INVALID_ARG, "model %d: steps_per_obs out of range", idx);
+  if (!(m.h > 0.0) || !std::isfinite(m.h)) return fail(PF_ERR_INVALID_ARG, "model %d: h <= 0", idx);
+  if (m.obs_dim < 1 || m.obs_dim > m.state_dim || !m.h_obs_index)
+    return fail(PF_ERR_INVALID_ARG, "model %d: bad obs_dim / obs_index", idx);
+  for (int k = 0; k < m.obs_dim; ++k)
+    if (m.h_obs_index[k] < 0 || m.h_obs_index[k] >= m.state_dim)
+      return fail(PF_ERR_INVALID_ARG, "model %d: obs_index[%d] out of range", idx, k);
+  if (!(m.obs_var > 0.0) || !std::isfinite(m.obs_var))
+    return fail(PF_ERR_INVALID_ARG, "model %d: obs_var must be > 0", idx);
+  if (!m.h_prior_mean || !m.h_prior_sd)
+    return fail(PF_ERR_INVALID_ARG, "model %d: prior arrays missing", idx);
+  for (int k = 0; k < 2; ++k)
+    if (!(m.noise_sd[k] >= 0.0)) return fail(PF_ERR_INVALID_ARG, "model %d: noise_sd < 0", idx);
+  return PF_OK;
+}
+
+pf_status check_all(const pf_model_desc *models, int n_models, const pf_ensemble_desc *ens,
+                    int n_ens) {
+  if (!models || n_models < 1) return fail(PF_ERR_INVALID_ARG, "no models");
+  if (!ens || n_ens < 1) return fail(PF_ERR_INVALID_ARG, "no ensembles");
+  for (int i = 0; i < n_models; ++i) PF_TRY(check_model(models[i], i));
+  for (int e = 0; e < n_ens; ++e) {
+    const pf_ensemble_desc &d = ens[e];
+    if (d.model < 0 || d.model >= n_models)
+      return fail(PF_ERR_INVALID_ARG, "ensemble %d: model index %d out of range", e, d.model);
+    if (d.M < 1 || d.N < 1 || d.N > (1 << 26) || (int64_t)d.M * d.N > (int64_t)1 << 30)
+      return fail(PF_ERR_INVALID_ARG, "ensemble %d: bad M=%d N=%d", e, d.M, d.N);
+    if (d.M > 65535) return fail(PF_ERR_INVALID_ARG, "ensemble %d: M > 65535", e);
+    if (d.flags != 0) return fail(PF_ERR_INVALID_ARG, "ensemble %d: flags must be 0", e);
+  }
+  return PF_OK;
+}
+
+size_t total_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int n_ens) {
+  size_t o = 0;
+  for (int e = 0; e < n_ens; ++e) {
+    const pf_model_desc &m = models[ens[e].model];
+    const int T = (ens[e].N + pfk::TILE - 1) / pfk::TILE;
+    o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T).end;
+  }
+  return o;
+}
+
+}  // namespace
+
+struct pf_ctx {
+  std::vector<Ens> ens;
+  uint32_t options = 0;
+  int t = 1;  // interval processed by the next step
+  hipStream_t last_stream = nullptr;
+  int device = 0;
+  // event pairs around the dominant kernel while profiling is enabled
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  size_t ev_used = 0;
+  ~pf_ctx() {
+    for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+constexpr size_t MAX_EVENT_PAIRS = 65536;
+
+// Records the start event of a profiled launch; returns the pair index or -1.
+long prof_begin(pf_ctx *ctx, hipStream_t s) {
+  if (!ctx->profiling || ctx->ev_used >= MAX_EVENT_PAIRS) return -1;
+  if (ctx->ev_used == ctx->ev_start.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return -1;
+    }
+    ctx->ev_start.push_back(a);
+    ctx->ev_stop.push_back(b);
+  }
+  const size_t i = ctx->ev_used++;
+  if (hipEventRecord(ctx->ev_start[i], s) != hipSuccess) return -1;
+  return (long)i;
+}
+
+void prof_end(pf_ctx *ctx, long i, hipStream_t s) {
+  if (i >= 0) (void)hipEventRecord(ctx->ev_stop[(size_t)i], s);
+}
+
+pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t s) {
+  size_t yoff = 0;
+  const int t = ctx->t;
+  for (Ens &E : ctx->ens) {
+    pfk::EnsDev &D = E.dev;
+    const float *y = d_y ? d_y + yoff : nullptr;
+    yoff += (size_t)E.dy;
+    if (stages & PF_STAGE_PROPAGATE) {
+      const int32_t *anc = E.pending ? D.A : nullptr;
+      const int out = 1 - E.cur;
+      const long ev = prof_begin(ctx, s);
+      PF_HIP(pfk::launch_vec_propagate(D, t, D.X[E.cur], anc, D.X[out], nullptr, nullptr, s));
+      prof_end(ctx, ev, s);
+      E.xbar = out;
+      E.pending = false;
+    }
+    if (stages & PF_STAGE_WEIGHT) {
+      if (!y) return fail(PF_ERR_INVALID_ARG, "weighting needs observations");
+      PF_HIP(pfk::launch_vec_loglik(D, D.X[E.xbar], y, s));
+    }
+    if (stages & PF_STAGE_RESAMPLE) PF_HIP(pfk::launch_resample(D, t, s));
+    if (stages & PF_STAGE_GATHER) {
+      const int out = 1 - E.xbar;
+      PF_HIP(pfk::launch_vec_gather(D, D.X[E.xbar], D.X[out], s));
+      E.cur = out;
+      E.pending = false;
+    }
+    if (stages & PF_STAGE_ESTIMATE)
+      PF_HIP(pfk::launch_vec_estimate(D, D.X[E.cur], D.X[E.xbar], s));
+  }
+  ctx->last_stream = s;
+  return PF_OK;
+}
+
+Ens *get_ens(pf_ctx *ctx, int32_t e) {
+  if (!ctx || e < 0 || e >= (int32_t)ctx->ens.size()) return nullptr;
+  return &ctx->ens[(size_t)e];
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_workspace_bytes(const pf_model_desc *h_models, int32_t n_models,
+                             const pf_ensemble_desc *h_ens, int32_t n_ens, uint32_t options,
+                             size_t *out_bytes) {
+  if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
+  if (options > PF_OPT_FUSED) return fail(PF_ERR_INVALID_ARG, "unknown options");
+  PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
+  *out_bytes = total_bytes(h_models, h_ens, n_ens);
+  return PF_OK;
+}
+
+pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ensemble_desc *h_ens,
+                  int32_t n_ens, uint32_t options, void *d_workspace, size_t workspace_bytes,
+                  void *stream, pf_ctx **out_ctx) {
+  if (!out_ctx) return fail(PF_ERR_INVALID_ARG, "out_ctx is NULL");
+  *out_ctx = nullptr;
+  if (options > PF_OPT_FUSED) return fail(PF_ERR_INVALID_ARG, "unknown options");
+  PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
+  const size_t need = total_bytes(h_models, h_ens, n_ens);
+  if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0)
+    return fail(PF_ERR_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+  if (workspace_bytes < need)
+    return fail(PF_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  if (options & PF_OPT_FUSED) return fail(PF_ERR_UNSUPPORTED, "fused path not in this build");
+
+  hipStream_t s = (hipStream_t)stream;
+  int device = 0;
+  PF_HIP(hipGetDevice(&device));
+  pf_ctx *ctx = new pf_ctx();
+  ctx->options = options;
+  ctx->device = device;
+  char *ws = (char *)d_workspace;
+  size_t base = 0;
+  ctx->ens.resize((size_t)n_ens);
+  for (int e = 0; e < n_ens; ++e) {
+    Ens &E = ctx->ens[(size_t)e];
+    E.d = h_ens[e];
+    const pf_model_desc &m = h_models[E.d.model];
+    E.dx = m.state_dim;
+    E.dy = m.obs_dim;
+    E.grid = m.kind == PF_MODEL_FHN;
+    E.T = (E.d.N + pfk::TILE - 1) / pfk::TILE;
+    E.obs_idx.assign(m.h_obs_index, m.h_obs_index + m.obs_dim);
+    E.prior_mean.resize((size_t)E.dx);
+    E.prior_sd.resize((size_t)E.dx);
+    for (int k = 0; k < E.dx; ++k) {
+      E.prior_mean[(size_t)k] = (float)m.h_prior_mean[k];
+      E.prior_sd[(size_t)k] = (float)m.h_prior_sd[k];
+    }
+    const Layout L = layout_of(base, E.d.M, E.d.N, E.dx, E.dy, E.T);
+    base = L.end;
+    pfk::EnsDev &D = E.dev;
+    pfk::ModelDev &md = D.md;
+    md.kind = m.kind;
+    md.dx = E.dx;
+    md.J = m.grid_j;
+    md.S = m.steps_per_obs;
+    md.dy = E.dy;
+    md.h = (float)m.h;
+    md.p0 = (float)m.params[0];
+    md.p1 = (float)m.params[1];
+    md.p2 = (float)m.params[2];
+    md.p3 = (float)m.params[3];
+    md.sq0 = (float)(m.noise_sd[0] * std::sqrt(m.h));
+    md.sq1 = (float)(m.noise_sd[1] * std::sqrt(m.h));
+    md.inv2var = (float)(1.0 / (2.0 * m.obs_var));
+    md.obs_sd = (float)std::sqrt(m.obs_var);
+    md.obs_idx = (const int32_t *)(ws + L.obs);
+    md.prior_mean = (const float *)(ws + L.pmean);
+    md.prior_sd = (const float *)(ws + L.psd);
+    D.key = pfk::make_key(E.d.seed);
+    D.M = E.d.M;
+    D.N = E.d.N;
+    D.T = E.T;
+    D.lognorm = -0.5 * m.obs_dim * std::log(2.0 * M_PI * m.obs_var);
+    D.X[0] = (float *)(ws + L.X0);
+    D.X[1] = (float *)(ws + L.X1);
+    D.lw = (float *)(ws + L.lw);
+    D.A = (int32_t *)(ws + L.A);
+    D.Cl = (double *)(ws + L.Cl);
+    D.Sl = (double *)(ws + L.Sl);
+    D.tile = (double *)(ws + L.tile);
+    D.coff = (double *)(ws + L.coff);
+    D.soff = (double *)(ws + L.soff);
+    D.fstat = (double *)(ws + L.fstat);
+    D.mpart = (double *)(ws + L.mpart);
+    D.wpart = (double *)(ws + L.wpart);
+    D.fmean = (double *)(ws + L.fmean);
+    D.fmeanw = (double *)(ws + L.fmeanw);
+    D.emean = (double *)(ws + L.emean);
+    pf_status st = PF_OK;
+#define INIT_TRY(expr)                                  \
+  do {                                                  \
+    st = dev((expr), #expr);                            \
+    if (st != PF_OK) {                                  \
+      delete ctx;                                       \
+      return st;                                        \
+    }                                                   \
+  } while (0)
+    INIT_TRY(hipMemcpyAsync((void *)md.obs_idx, E.obs_idx.data(), sizeof(int32_t) * E.dy,
+                            hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync((void *)md.prior_mean, E.prior_mean.data(), sizeof(float) * E.dx,
+                            hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync((void *)md.prior_sd, E.prior_sd.data(), sizeof(float) * E.dx,
+                            hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemsetAsync(D.fstat, 0, sizeof(double) * (size_t)E.d.M * pfk::FREC, s));
+    INIT_TRY(hipMemsetAsync(D.emean, 0, sizeof(double) * 2 * (size_t)E.dx, s));
+    INIT_TRY(pfk::launch_vec_init(D, D.X[0], s));
+    E.cur = 0;
+    E.xbar = 1;
+    E.pending = false;
+  }
+  // the host copies above must stay valid until the uploads ran
+  {
+    pf_status st = dev(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st != PF_OK) {
+      delete ctx;
+      return st;
+    }
+  }
+  ctx->t = 1;
+  ctx->last_stream = s;
+  *out_ctx = ctx;
+  return PF_OK;
+}
+
+pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream) {
+  if (!ctx) return fail(PF_ERR_STATE, "pf_step before pf_init");
+  if (!d_y) return fail(PF_ERR_INVALID_ARG, "d_y is NULL");
+  PF_TRY(stage_run(ctx, PF_STAGE_ALL, d_y, (hipStream_t)stream));
+  ctx->t += 1;
+  return PF_OK;
+}
+
+pf_status pf_run_stages(pf_ctx *ctx, uint32_t stages, const float *d_y, void *stream) {
+  if (!ctx) return fail(PF_ERR_STATE, "pf_run_stages before pf_init");
+  if (stages & ~PF_STAGE_ALL) return fail(PF_ERR_INVALID_ARG, "unknown stage bits");
+  return stage_run(ctx, stages, d_y, (hipStream_t)stream);
+}
+
+pf_status pf_estimate(pf_ctx *ctx, double *d_mean, double *d_mean_w, double *d_logZ,
+                      double *d_filter_mean, void *stream) {
+  if (!ctx) return fail(PF_ERR_STATE, "pf_estimate before pf_init");
+  hipStream_t s = (hipStream_t)stream;
+  size_t xo = 0, mo = 0, fo = 0;
+  for (Ens &E : ctx->ens) {
+    const pfk::EnsDev &D = E.dev;
+    if (d_mean)
+      PF_HIP(hipMemcpyAsync(d_mean + xo, D.emean, sizeof(double) * E.dx, hipMemcpyDeviceToDevice, s));
+    if (d_mean_w)
+      PF_HIP(hipMemcpyAsync(d_mean_w + xo, D.emean + E.dx, sizeof(double) * E.dx,
+                            hipMemcpyDeviceToDevice, s));
+    if (d_logZ)
+      PF_HIP(hipMemcpy2DAsync(d_logZ + mo, sizeof(double), D.fstat + 5, sizeof(double) * pfk::FREC,
+                              sizeof(double), (size_t)E.d.M, hipMemcpyDeviceToDevice, s));
+    if (d_filter_mean)
+      PF_HIP(hipMemcpyAsync(d_filter_mean + fo, D.fmean, sizeof(double) * (size_t)E.d.M * E.dx,
+                            hipMemcpyDeviceToDevice, s));
+    xo += (size_t)E.dx;
+    mo += (size_t)E.d.M;
+    fo += (size_t)E.d.M * E.dx;
+  }
+  ctx->last_stream = s;
+  return PF_OK;
+}
+
+pf_status pf_set_particles(pf_ctx *ctx, int32_t ens, const float *d_x, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
+  PF_HIP(hipMemcpyAsync(E->dev.X[E->cur], d_x, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  E->pending = false;
+  return PF_OK;
+}
+
+pf_status pf_get_particles(pf_ctx *ctx, int32_t ens, float *d_x, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  hipStream_t s = (hipStream_t)stream;
+  if (E->pending) {
+    PF_HIP(pfk::launch_vec_gather(E->dev, E->dev.X[E->cur], d_x, s));
+  } else {
+    const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
+    PF_HIP(hipMemcpyAsync(d_x, E->dev.X[E->cur], bytes, hipMemcpyDeviceToDevice, s));
+  }
+  return PF_OK;
+}
+
+pf_status pf_get_predicted(pf_ctx *ctx, int32_t ens, float *d_x, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
+  PF_HIP(hipMemcpyAsync(d_x, E->dev.X[E->xbar], bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_set_predicted(pf_ctx *ctx, int32_t ens, const float *d_x, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
+  if (E->xbar == E->cur) E->xbar = 1 - E->cur;
+  PF_HIP(hipMemcpyAsync(E->dev.X[E->xbar], d_x, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_get_logweights(pf_ctx *ctx, int32_t ens, float *d_lw, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_lw) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  PF_HIP(hipMemcpyAsync(d_lw, E->dev.lw, sizeof(float) * (size_t)E->d.M * E->d.N,
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_set_logweights(pf_ctx *ctx, int32_t ens, const float *d_lw, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_lw) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  PF_HIP(hipMemcpyAsync(E->dev.lw, d_lw, sizeof(float) * (size_t)E->d.M * E->d.N,
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_get_ancestors(pf_ctx *ctx, int32_t ens, int32_t *d_a, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_a) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  PF_HIP(hipMemcpyAsync(d_a, E->dev.A, sizeof(int32_t) * (size_t)E->d.M * E->d.N,
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_get_filter_stats(pf_ctx *ctx, int32_t ens, double *d_stats, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_stats) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  PF_HIP(hipMemcpy2DAsync(d_stats, 4 * sizeof(double), E->dev.fstat, sizeof(double) * pfk::FREC,
+                          4 * sizeof(double), (size_t)E->d.M, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_set_interval(pf_ctx *ctx, int32_t t) {
+  if (!ctx) return fail(PF_ERR_STATE, "no context");
+  if (t < 1) return fail(PF_ERR_INVALID_ARG, "interval index starts at 1");
+  ctx->t = t;
+  return PF_OK;
+}
+
+pf_status pf_get_interval(const pf_ctx *ctx, int32_t *out_t) {
+  if (!ctx || !out_t) return fail(PF_ERR_INVALID_ARG, "NULL argument");
+  *out_t = ctx->t;
+  return PF_OK;
+}
+
+pf_status pf_simulate(pf_ctx *ctx, int32_t ens, uint64_t seed, int32_t T, float *d_x_true,
+                      float *d_y, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_x_true || !d_y || T < 1) return fail(PF_ERR_INVALID_ARG, "bad simulate arguments");
+  PF_HIP(pfk::launch_vec_simulate(E->dev, seed, T, d_x_true, d_y, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                           uint32_t *d_bits, float *d_z, void *stream) {
+  if (n < 0 || n > ((int64_t)1 << 32)) return fail(PF_ERR_INVALID_ARG, "n out of range");
+  PF_HIP(pfk::launch_philox_stream(seed, c1, c2, c3, n, d_bits, d_z, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_set_profiling(pf_ctx *ctx, int32_t enable) {
+  if (!ctx) return fail(PF_ERR_STATE, "no context");
+  ctx->profiling = enable != 0;
+  return PF_OK;
+}
+
+pf_status pf_read_profile(pf_ctx *ctx, double *out_ms, int64_t *out_launches) {
+  if (!ctx || !out_ms || !out_launches) return fail(PF_ERR_INVALID_ARG, "NULL argument");
+  double total = 0.0;
+  for (size_t i = 0; i < ctx->ev_used; ++i) {
+    PF_HIP(hipEventSynchronize(ctx->ev_stop[i]));
+    float ms = 0.f;
+    PF_HIP(hipEventElapsedTime(&ms, ctx->ev_start[i], ctx->ev_stop[i]));
+    total += (double)ms;
+  }
+  *out_ms = total;
+  *out_launches = (int64_t)ctx->ev_used;
+  ctx->ev_used = 0;
+  return PF_OK;
+}
+
+pf_status pf_sync(pf_ctx *ctx) {
+  if (!ctx) return fail(PF_ERR_STATE, "no context");
+  PF_HIP(hipStreamSynchronize(ctx->last_stream));
+  PF_HIP(hipGetLastError());
+  return PF_OK;
+}
+
+void pf_destroy(pf_ctx *ctx) { delete ctx; }
+
+const char *pf_status_str(pf_status s) {
+  switch (s) {
+    case PF_OK: return "ok";
+    case PF_ERR_INVALID_ARG: return "invalid argument";
+    case PF_ERR_UNSUPPORTED: return "unsupported";
+    case PF_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case PF_ERR_DEVICE: return "device error";
+    case PF_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char *pf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// pf_device.h -- device primitives shared by the gfx950 kernels: the
+// Philox4x32-10 counter-based generator, the uniform and Box-Muller maps,
+// wave64 / workgroup reductions and scans, and the device-side model record.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+// ---------------------------------------------------------------------------
+// Random numbers.  Philox4x32-10 (Salmon et al., SC'11): per round two 32x32
+// -> 64-bit products of counter words 0 and 2 with the published multipliers,
+// the Weyl key schedule, ten rounds.  The counter layout that every kernel
+// uses: (c0, c1, c2, purpose << 24 | sub-block), key = (seed_lo, seed_hi ^
+// 0x14078071).
+enum : uint32_t {
+  P_INIT = 1, P_PROP = 2, P_RESAMPLE = 3, P_TRUTH_INIT = 4,
+  P_TRUTH_NOISE = 5, P_OBS_NOISE = 6, P_TRAIN = 7
+};
+constexpr uint32_t TRUTH_STREAM = 0xFFFFFFFFu;
+
+struct Key {
+  uint32_t k0, k1;
+};
+
+__host__ __device__ inline Key make_key(uint64_t seed) {
+  return Key{(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x14078071u};
+}
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        Key key) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// u = (2 (x >> 9) + 1) 2^-24 in (0, 1): the integer has at most 24
+// significant bits, so the float is exact.
+__device__ __forceinline__ float u01f(uint32_t x) {
+  return (float)((x >> 9) * 2u + 1u) * 0x1p-24f;
+}
+__device__ __forceinline__ double u01d(uint32_t x) {
+  return (double)((x >> 9) * 2u + 1u) * 0x1p-24;
+}
+
+// Box-Muller pair: r = sqrt(-2 ln u0), (r cos 2 pi u1, r sin 2 pi u1).  The
+// hardware log2 and sine/cosine take the argument in revolutions, which is
+// exactly what u1 is.
+__device__ __forceinline__ float2 box_muller(uint32_t a, uint32_t b) {
+  const float u0 = u01f(a);
+  const float u1 = u01f(b);
+  const float r = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+  return make_float2(r * __builtin_amdgcn_cosf(u1), r * __builtin_amdgcn_sinf(u1));
+}
+
+__device__ __forceinline__ void normals4(uint4 w, float z[4]) {
+  const float2 a = box_muller(w.x, w.y);
+  const float2 b = box_muller(w.z, w.w);
+  z[0] = a.x; z[1] = a.y; z[2] = b.x; z[3] = b.y;
+}
+
+// ---------------------------------------------------------------------------
+// Model record handed to kernels by value.
+struct ModelDev {
+  int32_t kind;      // 0 OU, 1 Lorenz 63, 2 FH-N
+  int32_t dx, J, S, dy;
+  float h;
+  float p0, p1, p2, p3;   // model parameters
+  float sq0, sq1;         // noise_sd * sqrt(h) per variable class
+  float inv2var;          // 1 / (2 obs_var)
+  float obs_sd;           // sqrt(obs_var)
+  const int32_t *obs_idx; // [dy]
+  const float *prior_mean, *prior_sd; // [dx]
+};
+
+// ---------------------------------------------------------------------------
+// Wave64 and workgroup reductions / scans.
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// inclusive scan across the 64 lanes
+__device__ __forceinline__ double wave_scan(double v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Workgroup max over blockDim.x threads (multiple of 64, <= 1024).
+__device__ __forceinline__ float block_max(float v, float *sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  float r = sh[0];
+  for (int i = 1; i < nw; ++i) r = fmaxf(r, sh[i]);
+  return r;
+}
+// Workgroup sum in a fixed order (deterministic).
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
+  return r;
+}
+// Workgroup exclusive scan; returns the exclusive prefix of this thread and
+// the total in *tot.
+__device__ __forceinline__ double block_exscan(double v, double *sh, double *tot) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const double inc = wave_scan(v);
+  double exc = __shfl_up(inc, 1, 64);
+  if (lane == 0) exc = 0.0;
+  __syncthreads();
+  if (lane == 63) sh[wid] = inc;
+  __syncthreads();
+  double off = 0.0, all = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < wid) off += sh[i];
+    all += sh[i];
+  }
+  *tot = all;
+  return off + exc;
+}
+
+}  // namespace pfk

