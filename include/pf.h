@@ -124,9 +124,11 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models,
    concatenated in ensemble order (obs_dim of its model each).  Advances t. */
 pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream);
 
-/* Run selected stages (PF_STAGE_*) of the current interval on the plain path
-   without advancing t: the per-step hooks of the parity tests.  The fused
-   context runs them on its plain kernels too. */
+/* Run selected stages (PF_STAGE_*) of the current interval without advancing
+   t: the per-step hooks of the parity tests.  They run on the plain kernels,
+   except that on a PF_OPT_FUSED context a request with PF_STAGE_RESAMPLE and
+   without PROPAGATE / WEIGHT runs the fused kernel's resampling and estimation
+   phases on the log-weights and pre-resampling particles in place. */
 pf_status pf_run_stages(pf_ctx *ctx, uint32_t stages, const float *d_y, void *stream);
 
 /* Estimates after the last completed interval.  Any pointer may be NULL.

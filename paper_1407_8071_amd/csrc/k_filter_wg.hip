@@ -1,0 +1,289 @@
+// k_filter_wg.hip -- the whole interval of a filter inside one workgroup
+// (vector models, N up to 8192).
+//
+// One workgroup owns one filter for the interval, so no memory ever crosses
+// workgroups and no grid-wide synchronisation or device-scope fence is
+// needed (on MI355X a grid barrier across ~1300 workgroups measured ~60 us,
+// more than the resampling work itself).  Per workgroup:
+//   1. propagation: particle i = p * BD + tid (p = 0 .. ceil(N/BD)-1), read
+//      through the previous interval's ancestor (fused gather), S Euler-
+//      Maruyama steps in registers, log-weight to LDS and HBM, xbar to HBM;
+//   2. normalisation: block maximum, w = exp(lw - mx) in FP64, the CDF by
+//      chunked block scans into LDS (FP64), sum w^2, and sum w xbar;
+//   3. sorted uniforms: thread t owns the contiguous k-range
+//      [t*KPT, (t+1)*KPT); its exponentials E_j, their block exclusive scan
+//      and the running sum give S_k, U_k = S_k / S_N;
+//   4. ancestor search in the LDS CDF (bisection for the first k of the
+//      thread, exponential search onward), ancestors to HBM, and the sum of
+//      the resampled particles xbar^(a_k) read back from HBM (written by this
+//      workgroup, so a workgroup barrier makes them visible);
+//   5. the filter's estimates and log G update, written by thread 0.
+// The cross-filter average is a separate small kernel.
+#include "pf_internal.h"
+
+namespace pfk {
+namespace {
+
+template <int D>
+__device__ __forceinline__ void wg_drift(const ModelDev &md, const float x[D], float f[D]) {
+  if constexpr (D == 3) {
+    f[0] = md.p0 * (x[1] - x[0]);
+    f[1] = md.p1 * x[0] - x[1] - x[0] * x[2];
+    f[2] = x[0] * x[1] - md.p2 * x[2];
+  } else {
+    f[0] = -md.p0 * x[0];
+  }
+}
+
+// S Euler-Maruyama steps with the compensated FP32 state update (the same
+// arithmetic as the plain propagation kernel).
+template <int D>
+__device__ __forceinline__ void wg_em(const ModelDev &md, Key key, uint32_t c0, uint32_t c1,
+                                      int n0, float x[D]) {
+  const int n1 = n0 + md.S;
+  float comp[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) comp[c] = 0.f;
+  for (int q = n0 >> 2; (q << 2) < n1; ++q) {
+    float z[4 * D];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      normals4(philox(c0, c1, (uint32_t)q, (P_PROP << 24) | (uint32_t)j, key), &z[4 * j]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 4 * q + r;
+      if (n < n0 || n >= n1) continue;
+      float f[D];
+      wg_drift<D>(md, x, f);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const float inc = fmaf(md.h, f[c], md.sq0 * z[r * D + c]) - comp[c];
+        const float nx = x[c] + inc;
+        comp[c] = (nx - x[c]) - inc;
+        x[c] = nx;
+      }
+    }
+  }
+}
+
+template <int D>
+__device__ __forceinline__ float wg_loglik(const ModelDev &md, const float x[D], const float *y) {
+  float acc = 0.f;
+  for (int k = 0; k < md.dy; ++k) {
+    const int o = md.obs_idx[k];
+    float xo = x[0];
+#pragma unroll
+    for (int c = 1; c < D; ++c)
+      if (o == c) xo = x[c];
+    const float r = y[k] - xo;
+    acc = fmaf(r, r, acc);
+  }
+  const float lw = -acc * md.inv2var;
+  return (lw == lw) ? lw : -INFINITY;
+}
+
+struct ExpoWG {
+  Key key;
+  uint32_t m, t;
+  int cached = -1;
+  uint4 r;
+  __device__ __forceinline__ double operator()(int j) {
+    if ((j >> 2) != cached) {
+      cached = j >> 2;
+      r = philox((uint32_t)cached, m, t, P_RESAMPLE << 24, key);
+    }
+    const int l = j & 3;
+    const uint32_t w = l == 0 ? r.x : l == 1 ? r.y : l == 2 ? r.z : r.w;
+    return -log(u01d(w));
+  }
+};
+
+// smallest i in [0, N) with C[i] > v (clamped to N - 1), starting from the
+// known lower bound lo (C[lo - 1] <= v)
+__device__ __forceinline__ int lds_search(const double *C, int N, int lo, double v) {
+  if (lo >= N - 1) return N - 1;
+  if (C[lo] > v) return lo;
+  int step = 1, known = lo, hi;
+  while (true) {
+    hi = known + step;
+    if (hi >= N - 1) {
+      hi = N - 1;
+      break;
+    }
+    if (C[hi] > v) break;
+    known = hi;
+    step <<= 1;
+  }
+  int a = known + 1, b = hi;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (C[mid] > v)
+      b = mid;
+    else
+      a = mid + 1;
+  }
+  return a;
+}
+
+template <int D, int BD>
+__global__ void __launch_bounds__(BD)
+k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, int t, int parity,
+            int pending, const float *__restrict__ y, int resample_only) {
+  extern __shared__ double lds[];
+  constexpr int NW = BD / 64;
+  double *shd = lds;                       // NW doubles of reduction scratch
+  float *shf = (float *)(lds + NW);        // NW floats
+  double *C = lds + 2 * NW;                // [N] FP64 CDF
+  const WgJob job = jobs[blockIdx.x];
+  const FusedEns &E = ens[job.ens];
+  const int m = job.filter, N = E.N, tid = threadIdx.x;
+  float *lws = (float *)(C + N);           // [N] log-weights
+  const float *Xin = parity ? E.X1 : E.X0;
+  float *Xb = parity ? E.X0 : E.X1;        // xbar of this interval
+  const size_t xo = (size_t)m * D * N;
+  float *lwg = E.lw + (size_t)m * N;
+
+  // 1. propagation and weighting
+  float lmax = -INFINITY;
+  for (int i = tid; i < N; i += BD) {
+    float lw;
+    if (resample_only) {
+      lw = lwg[i];
+      lw = (lw == lw) ? lw : -INFINITY;
+    } else {
+      const int src = pending ? min(max(E.A[(size_t)m * N + i], 0), N - 1) : i;
+      float x[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) x[c] = Xin[xo + (size_t)c * N + src];
+      wg_em<D>(E.md, E.key, (uint32_t)i, (uint32_t)m, (t - 1) * E.md.S, x);
+#pragma unroll
+      for (int c = 0; c < D; ++c) Xb[xo + (size_t)c * N + i] = x[c];
+      lw = wg_loglik<D>(E.md, x, y + E.yoff);
+      lwg[i] = lw;
+    }
+    lws[i] = lw;
+    lmax = fmaxf(lmax, lw);
+  }
+  // 2. normalisation and the CDF in LDS
+  const float mxf = block_max(lmax, shf);
+  const bool deg = !(mxf > -INFINITY);
+  const double mx = (double)mxf;
+  double carry = 0.0, s2 = 0.0, sw[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) sw[c] = 0.0;
+  for (int base = 0; base < N; base += BD) {
+    const int i = base + tid;
+    double w = 0.0;
+    if (i < N) {
+      w = deg ? 1.0 : exp((double)lws[i] - mx);
+      s2 += w * w;
+#pragma unroll
+      for (int c = 0; c < D; ++c) sw[c] += w * (double)Xb[xo + (size_t)c * N + i];
+    }
+    double tot;
+    const double ex = block_exscan(w, shd, &tot);
+    if (i < N) C[i] = carry + (ex + w);
+    carry += tot;
+  }
+  __syncthreads();
+  const double W = C[N - 1];
+  const double w2 = block_sum(s2, shd);
+  double wsum[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) wsum[c] = block_sum(sw[c], shd);
+
+  // 3. sorted uniforms from exponential spacings
+  const int KPT = (N + BD - 1) / BD;
+  const int k0 = tid * KPT, k1 = min(N, k0 + KPT);
+  ExpoWG ex{E.key, (uint32_t)m, (uint32_t)t};
+  double es = 0.0;
+  for (int j = k0; j < k1; ++j) es += ex(j);
+  double SN;
+  const double eoff = block_exscan(es, shd, &SN);
+  if (tid == 0) {
+    ExpoWG tail{E.key, (uint32_t)m, (uint32_t)t};
+    lds[2 * NW - 1] = tail(N);  // E_N, in the free slot after the float scratch
+  }
+  __syncthreads();
+  SN += lds[2 * NW - 1];
+
+  // 4. ancestors and the resampled sum
+  double run = eoff, px[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) px[c] = 0.0;
+  int i = 0;
+  for (int k = k0; k < k1; ++k) {
+    run += ex(k);
+    const double v = (run / SN) * W;
+    i = lds_search(C, N, (k == k0) ? 0 : i, v);
+    E.A[(size_t)m * N + k] = i;
+#pragma unroll
+    for (int c = 0; c < D; ++c) px[c] += (double)Xb[xo + (size_t)c * N + i];
+  }
+  double psum[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) psum[c] = block_sum(px[c], shd);
+
+  // 5. the filter's estimates and log G_t^N
+  if (tid == 0) {
+    double *f = E.fstat + (size_t)m * FREC;
+    f[0] = mx;
+    f[1] = W;
+    f[2] = w2;
+    f[3] = deg ? 1.0 : 0.0;
+    f[4] = SN;
+    f[5] = deg ? -INFINITY : f[5] + mx + log(W / (double)N) + E.lognorm;
+    f[6] = W * W / w2;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      E.fmean[(size_t)m * D + c] = psum[c] / (double)N;
+      E.fmeanw[(size_t)m * D + c] = wsum[c] / W;
+    }
+  }
+}
+
+}  // namespace
+
+// LDS bytes of a workgroup that owns a filter of N particles.
+size_t filter_wg_lds(int N, int BD) {
+  return sizeof(double) * (2 * (size_t)(BD / 64) + 2) + sizeof(double) * (size_t)N +
+         sizeof(float) * (size_t)N;
+}
+
+hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
+                            const FusedEns *d_ens, int t, int parity, int pending, const float *y,
+                            int resample_only, hipStream_t s) {
+  const size_t lds = filter_wg_lds(max_n, BD);
+#define PF_WG_LAUNCH(DD, B)                                                                  \
+  k_filter_wg<DD, B><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, t, parity, pending, y, resample_only)
+  if (D == 3) {
+    if (BD == 256) PF_WG_LAUNCH(3, 256);
+    else if (BD == 512) PF_WG_LAUNCH(3, 512);
+    else PF_WG_LAUNCH(3, 1024);
+  } else {
+    if (BD == 256) PF_WG_LAUNCH(1, 256);
+    else if (BD == 512) PF_WG_LAUNCH(1, 512);
+    else PF_WG_LAUNCH(1, 1024);
+  }
+#undef PF_WG_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t set_filter_wg_lds_limit() {
+  // allow the largest dynamic LDS request (N = 8192 at BD = 1024)
+  const int bytes = (int)filter_wg_lds(WG_MAX_N, 1024);
+  hipError_t e;
+  e = hipFuncSetAttribute((const void *)k_filter_wg<3, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_filter_wg<3, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_filter_wg<3, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_filter_wg<1, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_filter_wg<1, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_filter_wg<1, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace pfk

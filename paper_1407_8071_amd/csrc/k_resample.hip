@@ -274,7 +274,33 @@ k_ensemble_mean(int M, int dx, const double *__restrict__ fmean, const double *_
   }
 }
 
+// One workgroup per ensemble: equal-weight average of its filters' means.
+__global__ void __launch_bounds__(256)
+k_ensemble_means_batched(const FusedEns *__restrict__ ens) {
+  __shared__ double sh[4];
+  const FusedEns &E = ens[blockIdx.x];
+  const int dx = E.md.dx;
+  for (int c = 0; c < dx; ++c) {
+    double a = 0.0, b = 0.0;
+    for (int m = threadIdx.x; m < E.M; m += blockDim.x) {
+      a += E.fmean[(size_t)m * dx + c];
+      b += E.fmeanw[(size_t)m * dx + c];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+      E.emean[c] = a / (double)E.M;
+      E.emean[dx + c] = b / (double)E.M;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, hipStream_t s) {
+  if (n_ens > 0) k_ensemble_means_batched<<<n_ens, 256, 0, s>>>(d_ens);
+  return hipGetLastError();
+}
 
 hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s) {
   const dim3 g((unsigned)e.T, (unsigned)e.M);
@@ -286,9 +312,10 @@ hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_combine_means(const EnsDev &e, hipStream_t s) {
+hipError_t launch_combine_means(const EnsDev &e, bool ensemble_mean, hipStream_t s) {
   const int dx = e.md.dx;
   k_filter_means<<<e.M, 256, 0, s>>>(e.N, e.T, dx, e.mpart, e.wpart, e.fstat, e.fmean, e.fmeanw);
+  if (!ensemble_mean) return hipGetLastError();
   const unsigned g = dx <= 64 ? 1u : (unsigned)((dx + 255) / 256);
   k_ensemble_mean<<<g, 256, 0, s>>>(e.M, dx, e.fmean, e.fmeanw, e.emean);
   return hipGetLastError();

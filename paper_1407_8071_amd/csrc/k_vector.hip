@@ -101,7 +101,7 @@ k_vec_propagate(ModelDev md, Key key, int N, int t, const float *__restrict__ Xi
   const int m = blockIdx.y;
   const int i = blockIdx.x * VEC_BLOCK + threadIdx.x;
   if (i >= N) return;
-  const int src = anc ? anc[(size_t)m * N + i] : i;
+  const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
   float x[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) x[c] = Xin[((size_t)m * D + c) * N + src];
@@ -132,7 +132,7 @@ k_vec_gather(int N, const int32_t *__restrict__ A, const float *__restrict__ Xin
   const int m = blockIdx.y;
   const int k = blockIdx.x * VEC_BLOCK + threadIdx.x;
   if (k >= N) return;
-  const int a = A[(size_t)m * N + k];
+  const int a = min(max(A[(size_t)m * N + k], 0), N - 1);
 #pragma unroll
   for (int c = 0; c < D; ++c) Xout[((size_t)m * D + c) * N + k] = Xin[((size_t)m * D + c) * N + a];
 }
@@ -142,8 +142,9 @@ k_vec_gather(int N, const int32_t *__restrict__ A, const float *__restrict__ Xin
 template <int D>
 __global__ void __launch_bounds__(TILE_THREADS)
 k_vec_estimate_tiles(int N, int T, const float *__restrict__ Xpost, const float *__restrict__ Xpre,
-                     const float *__restrict__ lw, const double *__restrict__ fstat,
-                     double *__restrict__ mpart, double *__restrict__ wpart) {
+                     const int32_t *__restrict__ anc, const float *__restrict__ lw,
+                     const double *__restrict__ fstat, double *__restrict__ mpart,
+                     double *__restrict__ wpart) {
   __shared__ double sh[TILE_THREADS / 64];
   const int m = blockIdx.y, q = blockIdx.x;
   const double mx = fstat[(size_t)m * FREC + 0];
@@ -155,9 +156,11 @@ k_vec_estimate_tiles(int N, int T, const float *__restrict__ Xpost, const float 
     const int i = q * TILE + e * TILE_THREADS + threadIdx.x;
     if (i >= N) break;
     const double w = deg ? 1.0 : exp((double)lw[(size_t)m * N + i] - mx);
+    // post-resampling particle k = i: stored, or xbar read through a_i
+    const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      sp[c] += (double)Xpost[((size_t)m * D + c) * N + i];
+      sp[c] += (double)Xpost[((size_t)m * D + c) * N + src];
       sw[c] += w * (double)Xpre[((size_t)m * D + c) * N + i];
     }
   }
@@ -246,16 +249,18 @@ hipError_t launch_vec_gather(const EnsDev &e, const float *Xin, float *Xout, hip
 }
 
 hipError_t launch_vec_estimate(const EnsDev &e, const float *Xpost, const float *Xpre,
-                               hipStream_t s) {
+                               const int32_t *anc, bool ensemble_mean, hipStream_t s) {
   dim3 g((unsigned)e.T, (unsigned)e.M);
   PF_DISPATCH_D(e,
-                (k_vec_estimate_tiles<3><<<g, TILE_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, e.lw,
-                                                                    e.fstat, e.mpart, e.wpart)),
-                (k_vec_estimate_tiles<1><<<g, TILE_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, e.lw,
-                                                                    e.fstat, e.mpart, e.wpart)));
+                (k_vec_estimate_tiles<3><<<g, TILE_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, anc,
+                                                                    e.lw, e.fstat, e.mpart,
+                                                                    e.wpart)),
+                (k_vec_estimate_tiles<1><<<g, TILE_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, anc,
+                                                                    e.lw, e.fstat, e.mpart,
+                                                                    e.wpart)));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  return launch_combine_means(e, s);
+  return launch_combine_means(e, ensemble_mean, s);
 }
 
 hipError_t launch_vec_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,

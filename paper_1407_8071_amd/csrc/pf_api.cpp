@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,13 +48,23 @@ struct Ens {
   pf_ensemble_desc d;
   int dx, dy, T;
   bool grid;
+  bool wg;  // fused path: the filter-per-workgroup kernel handles it
   std::vector<int32_t> obs_idx;
   std::vector<float> prior_mean, prior_sd;
   pfk::EnsDev dev;
-  int cur = 0;           // buffer holding the particles entering the next interval
-  bool pending = false;  // X[cur] still needs the gather through A
-  int xbar = 1;          // buffer holding xbar of the current interval
+  pfk::FusedEns fz;  // record of the fused kernels
 };
+
+// One launch of the filter-per-workgroup kernel: every filter of the
+// ensembles of one (state dimension, workgroup size) class.
+struct WgClass {
+  int D, BD, max_n;
+  std::vector<pfk::WgJob> jobs;
+  pfk::WgJob *d_jobs = nullptr;
+};
+
+// Workgroup size of the filter-per-workgroup kernel for N particles.
+int wg_block(int N) { return N <= 256 ? 256 : (N <= 512 ? 512 : 1024); }
 
 // Offsets of every array of one ensemble inside the workspace.
 struct Layout {
@@ -90,6 +101,15 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T) {
   L.emean = take(sizeof(double) * 2 * (size_t)dx);
   L.end = o;
   return L;
+}
+
+// Context-wide arrays after the ensembles: the fused ensemble table and the
+// workgroup job lists (at most one job per filter).
+size_t ctx_bytes(const pf_ensemble_desc *ens, int n_ens) {
+  size_t jobs = 0;
+  for (int e = 0; e < n_ens; ++e) jobs += (size_t)ens[e].M;
+  return align_up(sizeof(pfk::FusedEns) * (size_t)n_ens) +
+         6 * align_up(sizeof(pfk::WgJob) * jobs);
 }
 
 pf_status check_model(const pf_model_desc &m, int idx) {
@@ -145,7 +165,7 @@ size_t total_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int
     const int T = (ens[e].N + pfk::TILE - 1) / pfk::TILE;
     o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T).end;
   }
-  return o;
+  return o + ctx_bytes(ens, n_ens);
 }
 
 }  // namespace
@@ -156,6 +176,15 @@ struct pf_ctx {
   int t = 1;  // interval processed by the next step
   hipStream_t last_stream = nullptr;
   int device = 0;
+  // particle buffers, shared by every ensemble: X[cur] holds the particles
+  // entering the next interval (to be read through A when `pending`), X[xbar]
+  // the pre-resampling particles of the current interval
+  int cur = 0, xbar = 1;
+  bool pending = false;
+  // fused path
+  pfk::FusedEns *d_fens = nullptr;
+  std::vector<pfk::FusedEns> fz_host;
+  std::vector<WgClass> classes;
   // event pairs around the dominant kernel while profiling is enabled
   bool profiling = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -193,36 +222,92 @@ void prof_end(pf_ctx *ctx, long i, hipStream_t s) {
 }
 
 pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t s) {
-  size_t yoff = 0;
   const int t = ctx->t;
+  if ((stages & PF_STAGE_WEIGHT) && !d_y)
+    return fail(PF_ERR_INVALID_ARG, "weighting needs observations");
+  if (stages & PF_STAGE_PROPAGATE) {
+    const int out = 1 - ctx->cur;
+    const long ev = prof_begin(ctx, s);
+    for (Ens &E : ctx->ens) {
+      pfk::EnsDev &D = E.dev;
+      const int32_t *anc = ctx->pending ? D.A : nullptr;
+      PF_HIP(pfk::launch_vec_propagate(D, t, D.X[ctx->cur], anc, D.X[out], nullptr, nullptr, s));
+    }
+    prof_end(ctx, ev, s);
+    ctx->xbar = out;
+    ctx->pending = false;
+  }
+  size_t yoff = 0;
   for (Ens &E : ctx->ens) {
     pfk::EnsDev &D = E.dev;
     const float *y = d_y ? d_y + yoff : nullptr;
     yoff += (size_t)E.dy;
-    if (stages & PF_STAGE_PROPAGATE) {
-      const int32_t *anc = E.pending ? D.A : nullptr;
-      const int out = 1 - E.cur;
-      const long ev = prof_begin(ctx, s);
-      PF_HIP(pfk::launch_vec_propagate(D, t, D.X[E.cur], anc, D.X[out], nullptr, nullptr, s));
-      prof_end(ctx, ev, s);
-      E.xbar = out;
-      E.pending = false;
-    }
-    if (stages & PF_STAGE_WEIGHT) {
-      if (!y) return fail(PF_ERR_INVALID_ARG, "weighting needs observations");
-      PF_HIP(pfk::launch_vec_loglik(D, D.X[E.xbar], y, s));
-    }
+    if (stages & PF_STAGE_WEIGHT) PF_HIP(pfk::launch_vec_loglik(D, D.X[ctx->xbar], y, s));
     if (stages & PF_STAGE_RESAMPLE) PF_HIP(pfk::launch_resample(D, t, s));
-    if (stages & PF_STAGE_GATHER) {
-      const int out = 1 - E.xbar;
-      PF_HIP(pfk::launch_vec_gather(D, D.X[E.xbar], D.X[out], s));
-      E.cur = out;
-      E.pending = false;
+    if (stages & PF_STAGE_GATHER)
+      PF_HIP(pfk::launch_vec_gather(D, D.X[ctx->xbar], D.X[1 - ctx->xbar], s));
+  }
+  if (stages & PF_STAGE_GATHER) {
+    ctx->cur = 1 - ctx->xbar;
+    ctx->pending = false;
+  }
+  if (stages & PF_STAGE_ESTIMATE) {
+    for (Ens &E : ctx->ens) {
+      pfk::EnsDev &D = E.dev;
+      if (ctx->pending) return fail(PF_ERR_STATE, "estimate stage needs gathered particles");
+      PF_HIP(pfk::launch_vec_estimate(D, D.X[ctx->cur], D.X[ctx->xbar], nullptr, true, s));
     }
-    if (stages & PF_STAGE_ESTIMATE)
-      PF_HIP(pfk::launch_vec_estimate(D, D.X[E.cur], D.X[E.xbar], s));
   }
   ctx->last_stream = s;
+  return PF_OK;
+}
+
+// The fused interval: one filter-per-workgroup launch per class, the tiled
+// kernels for ensembles whose filters exceed one workgroup, and the
+// cross-filter averages.  The particles stay where propagation wrote them
+// and the next interval gathers them through the ancestors.
+pf_status fused_run(pf_ctx *ctx, const float *d_y, hipStream_t s, bool resample_only) {
+  const int parity = resample_only ? 1 - ctx->xbar : ctx->cur;
+  const int pending = (!resample_only && ctx->pending) ? 1 : 0;
+  const long ev = resample_only ? -1 : prof_begin(ctx, s);
+  for (const WgClass &c : ctx->classes)
+    PF_HIP(pfk::launch_filter_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
+                                 ctx->t, parity, pending, d_y, resample_only ? 1 : 0, s));
+  size_t yoff = 0;
+  for (Ens &E : ctx->ens) {
+    const float *y = d_y ? d_y + yoff : nullptr;
+    yoff += (size_t)E.dy;
+    if (E.wg) continue;
+    pfk::EnsDev &D = E.dev;
+    const int out = 1 - parity;
+    if (!resample_only) {
+      const int32_t *anc = pending ? D.A : nullptr;
+      PF_HIP(pfk::launch_vec_propagate(D, ctx->t, D.X[parity], anc, D.X[out], D.lw, y, s));
+    }
+    PF_HIP(pfk::launch_resample(D, ctx->t, s));
+    PF_HIP(pfk::launch_vec_estimate(D, D.X[out], D.X[out], D.A, false, s));
+  }
+  PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), s));
+  prof_end(ctx, ev, s);
+  if (resample_only) {
+    ctx->cur = ctx->xbar;
+  } else {
+    ctx->cur = 1 - ctx->cur;
+    ctx->xbar = ctx->cur;
+  }
+  ctx->pending = true;
+  ctx->last_stream = s;
+  return PF_OK;
+}
+
+// Resolve pending ancestors: gather every ensemble into the other buffer.
+pf_status materialise(pf_ctx *ctx, hipStream_t s) {
+  if (!ctx->pending) return PF_OK;
+  for (Ens &E : ctx->ens)
+    PF_HIP(pfk::launch_vec_gather(E.dev, E.dev.X[ctx->cur], E.dev.X[1 - ctx->cur], s));
+  ctx->xbar = ctx->cur;
+  ctx->cur = 1 - ctx->cur;
+  ctx->pending = false;
   return PF_OK;
 }
 
@@ -257,7 +342,6 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     return fail(PF_ERR_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
   if (workspace_bytes < need)
     return fail(PF_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
-  if (options & PF_OPT_FUSED) return fail(PF_ERR_UNSUPPORTED, "fused path not in this build");
 
   hipStream_t s = (hipStream_t)stream;
   int device = 0;
@@ -266,7 +350,7 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
   ctx->options = options;
   ctx->device = device;
   char *ws = (char *)d_workspace;
-  size_t base = 0;
+  size_t base = 0, yoff_acc = 0;
   ctx->ens.resize((size_t)n_ens);
   for (int e = 0; e < n_ens; ++e) {
     Ens &E = ctx->ens[(size_t)e];
@@ -324,6 +408,24 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     D.fmean = (double *)(ws + L.fmean);
     D.fmeanw = (double *)(ws + L.fmeanw);
     D.emean = (double *)(ws + L.emean);
+    // fused-path record
+    pfk::FusedEns &F = E.fz;
+    F.md = md;
+    F.key = D.key;
+    F.M = E.d.M;
+    F.N = E.d.N;
+    F.yoff = (int32_t)yoff_acc;
+    yoff_acc += (size_t)E.dy;
+    F.lognorm = D.lognorm;
+    F.X0 = D.X[0];
+    F.X1 = D.X[1];
+    F.lw = D.lw;
+    F.A = D.A;
+    F.fstat = D.fstat;
+    F.fmean = D.fmean;
+    F.fmeanw = D.fmeanw;
+    F.emean = D.emean;
+    E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N;
     pf_status st = PF_OK;
 #define INIT_TRY(expr)                                  \
   do {                                                  \
@@ -341,10 +443,53 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
                             hipMemcpyHostToDevice, s));
     INIT_TRY(hipMemsetAsync(D.fstat, 0, sizeof(double) * (size_t)E.d.M * pfk::FREC, s));
     INIT_TRY(hipMemsetAsync(D.emean, 0, sizeof(double) * 2 * (size_t)E.dx, s));
+    // every ancestor index is valid from the start
+    INIT_TRY(hipMemsetAsync(D.A, 0, sizeof(int32_t) * (size_t)E.d.M * E.d.N, s));
     INIT_TRY(pfk::launch_vec_init(D, D.X[0], s));
-    E.cur = 0;
-    E.xbar = 1;
-    E.pending = false;
+  }
+  // context arrays: the fused ensemble table and the workgroup job lists
+  {
+    pf_status st = PF_OK;
+    ctx->d_fens = (pfk::FusedEns *)(ws + base);
+    size_t o = base + align_up(sizeof(pfk::FusedEns) * (size_t)n_ens);
+    size_t total_jobs = 0;
+    for (int e = 0; e < n_ens; ++e) total_jobs += (size_t)h_ens[e].M;
+    ctx->fz_host.resize((size_t)n_ens);
+    for (int e = 0; e < n_ens; ++e) ctx->fz_host[(size_t)e] = ctx->ens[(size_t)e].fz;
+    INIT_TRY(hipMemcpyAsync(ctx->d_fens, ctx->fz_host.data(), sizeof(pfk::FusedEns) * (size_t)n_ens,
+                            hipMemcpyHostToDevice, s));
+    // classes by (state dimension, workgroup size); filters of larger N first
+    const int Ds[2] = {3, 1}, BDs[3] = {1024, 512, 256};
+    for (int D : Ds) {
+      for (int BD : BDs) {
+        WgClass c;
+        c.D = D;
+        c.BD = BD;
+        c.max_n = 0;
+        std::vector<std::pair<int, int>> order;  // (N, ensemble)
+        for (int e = 0; e < n_ens; ++e) {
+          const Ens &E = ctx->ens[(size_t)e];
+          if (E.wg && E.dx == D && wg_block(E.d.N) == BD) order.push_back({E.d.N, e});
+        }
+        if (order.empty()) continue;
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+                           return a.first > b.first;
+                         });
+        for (auto &pr : order) {
+          c.max_n = std::max(c.max_n, pr.first);
+          for (int mm = 0; mm < ctx->ens[(size_t)pr.second].d.M; ++mm)
+            c.jobs.push_back(pfk::WgJob{pr.second, mm});
+        }
+        c.d_jobs = (pfk::WgJob *)(ws + o);
+        o += align_up(sizeof(pfk::WgJob) * total_jobs);
+        ctx->classes.push_back(std::move(c));
+      }
+    }
+    for (WgClass &c : ctx->classes)
+      INIT_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
+                              hipMemcpyHostToDevice, s));
+    INIT_TRY(pfk::set_filter_wg_lds_limit());
   }
   // the host copies above must stay valid until the uploads ran
   {
@@ -355,6 +500,9 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     }
   }
   ctx->t = 1;
+  ctx->cur = 0;
+  ctx->xbar = 1;
+  ctx->pending = false;
   ctx->last_stream = s;
   *out_ctx = ctx;
   return PF_OK;
@@ -363,7 +511,10 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
 pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream) {
   if (!ctx) return fail(PF_ERR_STATE, "pf_step before pf_init");
   if (!d_y) return fail(PF_ERR_INVALID_ARG, "d_y is NULL");
-  PF_TRY(stage_run(ctx, PF_STAGE_ALL, d_y, (hipStream_t)stream));
+  if (ctx->options & PF_OPT_FUSED)
+    PF_TRY(fused_run(ctx, d_y, (hipStream_t)stream, false));
+  else
+    PF_TRY(stage_run(ctx, PF_STAGE_ALL, d_y, (hipStream_t)stream));
   ctx->t += 1;
   return PF_OK;
 }
@@ -371,6 +522,13 @@ pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream) {
 pf_status pf_run_stages(pf_ctx *ctx, uint32_t stages, const float *d_y, void *stream) {
   if (!ctx) return fail(PF_ERR_STATE, "pf_run_stages before pf_init");
   if (stages & ~PF_STAGE_ALL) return fail(PF_ERR_INVALID_ARG, "unknown stage bits");
+  if ((ctx->options & PF_OPT_FUSED) && (stages & PF_STAGE_RESAMPLE) &&
+      !(stages & (PF_STAGE_PROPAGATE | PF_STAGE_WEIGHT))) {
+    // resampling (+ gather and estimates) through the fused kernel's phases
+    PF_TRY(fused_run(ctx, nullptr, (hipStream_t)stream, true));
+    if (stages & PF_STAGE_GATHER) PF_TRY(materialise(ctx, (hipStream_t)stream));
+    return PF_OK;
+  }
   return stage_run(ctx, stages, d_y, (hipStream_t)stream);
 }
 
@@ -403,9 +561,10 @@ pf_status pf_estimate(pf_ctx *ctx, double *d_mean, double *d_mean_w, double *d_l
 pf_status pf_set_particles(pf_ctx *ctx, int32_t ens, const float *d_x, void *stream) {
   Ens *E = get_ens(ctx, ens);
   if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  hipStream_t s = (hipStream_t)stream;
+  PF_TRY(materialise(ctx, s));
   const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
-  PF_HIP(hipMemcpyAsync(E->dev.X[E->cur], d_x, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
-  E->pending = false;
+  PF_HIP(hipMemcpyAsync(E->dev.X[ctx->cur], d_x, bytes, hipMemcpyDeviceToDevice, s));
   return PF_OK;
 }
 
@@ -413,11 +572,11 @@ pf_status pf_get_particles(pf_ctx *ctx, int32_t ens, float *d_x, void *stream) {
   Ens *E = get_ens(ctx, ens);
   if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
   hipStream_t s = (hipStream_t)stream;
-  if (E->pending) {
-    PF_HIP(pfk::launch_vec_gather(E->dev, E->dev.X[E->cur], d_x, s));
+  if (ctx->pending) {
+    PF_HIP(pfk::launch_vec_gather(E->dev, E->dev.X[ctx->cur], d_x, s));
   } else {
     const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
-    PF_HIP(hipMemcpyAsync(d_x, E->dev.X[E->cur], bytes, hipMemcpyDeviceToDevice, s));
+    PF_HIP(hipMemcpyAsync(d_x, E->dev.X[ctx->cur], bytes, hipMemcpyDeviceToDevice, s));
   }
   return PF_OK;
 }
@@ -426,16 +585,18 @@ pf_status pf_get_predicted(pf_ctx *ctx, int32_t ens, float *d_x, void *stream) {
   Ens *E = get_ens(ctx, ens);
   if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
   const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
-  PF_HIP(hipMemcpyAsync(d_x, E->dev.X[E->xbar], bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  PF_HIP(hipMemcpyAsync(d_x, E->dev.X[ctx->xbar], bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return PF_OK;
 }
 
 pf_status pf_set_predicted(pf_ctx *ctx, int32_t ens, const float *d_x, void *stream) {
   Ens *E = get_ens(ctx, ens);
   if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  hipStream_t s = (hipStream_t)stream;
+  PF_TRY(materialise(ctx, s));
+  ctx->xbar = 1 - ctx->cur;
   const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
-  if (E->xbar == E->cur) E->xbar = 1 - E->cur;
-  PF_HIP(hipMemcpyAsync(E->dev.X[E->xbar], d_x, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  PF_HIP(hipMemcpyAsync(E->dev.X[ctx->xbar], d_x, bytes, hipMemcpyDeviceToDevice, s));
   return PF_OK;
 }
 

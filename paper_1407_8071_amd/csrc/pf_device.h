@@ -62,7 +62,9 @@ __device__ __forceinline__ double u01d(uint32_t x) {
 __device__ __forceinline__ float2 box_muller(uint32_t a, uint32_t b) {
   const float u0 = u01f(a);
   const float u1 = u01f(b);
-  const float r = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+  // u0 >= 2^-24, so the argument of the square root is a normal float in
+  // (0, 33.3]: the raw hardware square root needs no denormal scaling.
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
   return make_float2(r * __builtin_amdgcn_cosf(u1), r * __builtin_amdgcn_sinf(u1));
 }
 

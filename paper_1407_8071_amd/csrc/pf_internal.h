@@ -43,20 +43,47 @@ struct EnsDev {
   double *emean;    // [2][dx]: ensemble post-resampling and weighted means
 };
 
+// Device-side record of one ensemble for the fused interval kernels.
+struct FusedEns {
+  ModelDev md;
+  Key key;
+  int32_t M, N;
+  int32_t yoff;  // offset of this ensemble's observations
+  double lognorm;
+  float *X0, *X1, *lw;
+  int32_t *A;
+  double *fstat, *fmean, *fmeanw, *emean;
+};
+
 // ---- vector models (OU, Lorenz 63): particles [M][dx][N] ------------------
 hipError_t launch_vec_init(const EnsDev &e, float *X, hipStream_t s);
 hipError_t launch_vec_propagate(const EnsDev &e, int t, const float *Xin, const int32_t *anc,
                                 float *Xout, float *lw_or_null, const float *y, hipStream_t s);
 hipError_t launch_vec_loglik(const EnsDev &e, const float *X, const float *y, hipStream_t s);
 hipError_t launch_vec_gather(const EnsDev &e, const float *Xin, float *Xout, hipStream_t s);
+// estimates of the filters: post-resampling particles read from Xpost (through
+// `anc` when not null), weighted ones from Xpre; optionally the ensemble mean
 hipError_t launch_vec_estimate(const EnsDev &e, const float *Xpost, const float *Xpre,
-                               hipStream_t s);
+                               const int32_t *anc, bool ensemble_mean, hipStream_t s);
 hipError_t launch_vec_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,
                                hipStream_t s);
 
 // ---- resampling (any model): lw [M][N] -> A [M][N] ------------------------
 hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s);
-hipError_t launch_combine_means(const EnsDev &e, hipStream_t s);
+hipError_t launch_combine_means(const EnsDev &e, bool ensemble_mean, hipStream_t s);
+
+// ---- filter-per-workgroup interval kernel (vector models, N <= WG_MAX_N) ---
+constexpr int WG_MAX_N = 8192;
+struct WgJob {
+  int32_t ens, filter;
+};
+size_t filter_wg_lds(int N, int BD);
+hipError_t set_filter_wg_lds_limit();
+hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
+                            const FusedEns *d_ens, int t, int parity, int pending, const float *y,
+                            int resample_only, hipStream_t s);
+// cross-filter averages of many ensembles at once (one workgroup each)
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, hipStream_t s);
 
 // ---- random-number hook ----------------------------------------------------
 hipError_t launch_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,

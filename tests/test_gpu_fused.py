@@ -1,0 +1,191 @@
+"""GPU parity of the fused persistent interval kernel (MI355X only).
+
+The fused kernel runs propagation, weighting, normalisation, resampling and
+the estimators of every filter in one launch per interval.  It is checked
+  - against the oracle on identical log-weights (its own resampling phases,
+    driven through the resample-only hook), ancestors strictly equal outside
+    the 1e-6 band and essentially equal everywhere;
+  - against the oracle on sampled particles at the full 2^20-particle size of
+    the Lorenz time-error sweep, in the launch configuration the benchmark
+    times;
+  - against the plain one-kernel-per-step path over several intervals;
+  - statistically: MSE against the simulated truth over 32 seeds.
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+import pf_inputs
+from pf_testlib import assert_rel_close, band_mask, oracle_to_vec, vec_to_oracle
+
+pytestmark = pytest.mark.gpu
+
+L63 = pf_inputs.lorenz63()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pf(torch_mod):
+    import paper_1407_8071_amd as pf
+    pf.lib()
+    return pf
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _strict_ancestors(orc, A, lw, seed, t):
+    M, N = lw.shape
+    n_diff = 0
+    for k in range(M):
+        Ao, Co, Uo, _ = orc.resample(seed, k, t, lw[k].astype(np.float64))
+        band = band_mask(Co, Uo)
+        assert np.all(np.diff(A[k]) >= 0) and A[k].min() >= 0 and A[k].max() < N
+        mism = (A[k] != Ao) & ~band
+        assert not mism.any(), (k, np.argwhere(mism)[:5].ravel())
+        n_diff += int((A[k] != Ao).sum())
+    assert n_diff <= max(4, 1e-5 * M * N), n_diff
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (3, 7), (4, 256), (2, 4097), (16, 5000), (1, 70001),
+                                 (1, 1 << 20)])
+def test_fused_resampling_matches_oracle(pf, orc, torch_mod, M, N):
+    seed, t = 40 + N, 23
+    lw = pf_inputs.logweights(7 + N, M, N, scale=4.0)
+    if N > 10:
+        lw[:, 2] = -np.inf
+    Xb = pf_inputs.particles(seed, L63, M, N).astype(np.float32)
+    f = pf.ParticleFilter([L63], [(0, M, N, seed)], fused=True)
+    f.set_predicted(0, _dev(oracle_to_vec(Xb)))
+    f.set_logweights(0, _dev(lw))
+    f.set_interval(t)
+    f.run_stages(pf.STAGE_RESAMPLE)
+    f.sync()
+    A = f.get_ancestors(0).cpu().numpy()
+    _strict_ancestors(orc, A, lw, seed, t)
+    st = f.get_filter_stats(0).cpu().numpy()
+    mean, mean_w, _, fmean = [x.cpu().numpy() for x in f.estimate()]
+    fmean = fmean.reshape(M, 3)
+    for k in range(min(M, 4)):
+        lwk = lw[k].astype(np.float64)
+        Ao, Co, Uo, (mx, W, s2, deg) = orc.resample(seed, k, t, lwk)
+        assert st[k, 0] == mx and st[k, 1] == pytest.approx(W, rel=1e-12)
+        ref = orc.mean(Xb[k].astype(np.float64)[A[k]])
+        assert np.allclose(fmean[k], ref, rtol=1e-11, atol=1e-11)
+    if M <= 4:
+        emw = np.mean([orc.weighted_mean(Xb[k].astype(np.float64), lw[k].astype(np.float64),
+                                         float(lw[k].max())) for k in range(M)], axis=0)
+        assert np.allclose(mean_w, emw, rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("M,N", [(1, 1 << 20), (16, 1 << 16), (256, 1 << 12), (4096, 1 << 8)])
+def test_fused_full_size_sampled(pf, orc, torch_mod, M, N):
+    """The four splits of the Lorenz time-error sweep (K = 2^20) at full size:
+    one fused interval from the prior, checked on 256 sampled particles."""
+    seed = 3
+    m = orc.Model(L63)
+    _, y = orc.simulate(m, 77, 1)
+    y32 = y.astype(np.float32)
+    f = pf.ParticleFilter([L63], [(0, M, N, seed)], fused=True)
+    f.step(_dev(y32[0]))
+    f.sync()
+    xb = f.get_predicted(0).cpu().numpy()       # [M, 3, N]
+    lw = f.get_logweights(0).cpu().numpy()
+    A = f.get_ancestors(0).cpu().numpy()
+    rng = np.random.default_rng(N)
+    fil = rng.integers(0, M, 256)
+    idx = rng.integers(0, N, 256)
+    key = orc.key(seed)
+    for fm, i in zip(fil, idx):
+        x0 = np.zeros(3)
+        # the prior draw of particle i of filter fm, then its interval-1 path
+        z = orc.normals4([int(i), int(fm), 0, orc.P_INIT << 24], key)
+        x0 = np.array(L63["prior_mean"]) + np.array(L63["prior_sd"]) * z[:3]
+        x0 = x0.astype(np.float32).astype(np.float64)
+        ref = orc.propagate_particle(m, seed, int(fm), int(i), 1, x0)
+        assert_rel_close(xb[fm, :, i], ref, what="fused states")
+        rlw = orc.loglik(m, ref, y32[0].astype(np.float64))
+        assert_rel_close(lw[fm, i], rlw, what="fused log-weights")
+    # ancestors are valid and ascending in every filter
+    assert A.min() >= 0 and A.max() < N
+    assert np.all(np.diff(A, axis=1) >= 0)
+
+
+@pytest.mark.parametrize("M,N", [(4, 256), (16, 5000), (2, 70001)])
+def test_fused_matches_plain(pf, orc, torch_mod, M, N):
+    seed = 12
+    m = orc.Model(L63)
+    _, y = orc.simulate(m, 5, 4)
+    yd = _dev(y.astype(np.float32))
+    fp = pf.ParticleFilter([L63], [(0, M, N, seed)], fused=False)
+    ff = pf.ParticleFilter([L63], [(0, M, N, seed)], fused=True)
+    for t in range(4):
+        fp.step(yd[t])
+        ff.step(yd[t])
+        ff.sync()
+        xp, xf = fp.get_predicted(0).cpu().numpy(), ff.get_predicted(0).cpu().numpy()
+        ap, af = fp.get_ancestors(0).cpu().numpy(), ff.get_ancestors(0).cpu().numpy()
+        if t == 0:
+            assert_rel_close(xf, xp, rel=1e-6, what="fused vs plain states")
+        ndiff = int((ap != af).sum())
+        assert ndiff <= max(4, 1e-5 * M * N), (t, ndiff)
+        if ndiff == 0:
+            ep, ef = fp.estimate(), ff.estimate()
+            for a, b in zip(ep, ef):
+                a, b = a.cpu().numpy(), b.cpu().numpy()
+                fin = np.isfinite(a)
+                assert np.allclose(a[fin], b[fin], rtol=1e-5, atol=1e-6)
+
+
+def test_fused_determinism(pf, torch_mod):
+    outs = []
+    y = torch_mod.tensor([1.0, 20.0], dtype=torch_mod.float32, device="cuda")
+    for _ in range(2):
+        f = pf.ParticleFilter([L63], [(0, 8, 3000, 9)], fused=True)
+        for _t in range(5):
+            f.step(y)
+        f.sync()
+        outs.append([t.cpu().numpy() for t in f.estimate()] + [f.get_ancestors(0).cpu().numpy()])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def _oracle_mse(args):
+    seed, T = args
+    import oracle as orc
+    m = orc.Model(pf_inputs.lorenz63())
+    xt, y = orc.simulate(m, 20_000 + seed, T)
+    est, _, _, _ = orc.run_ensemble(m, seed, 4, 256, y.astype(np.float32).astype(np.float64))
+    return float(np.mean((est - xt[1:]) ** 2))
+
+
+def test_fused_end_to_end_mse_32_seeds(pf, orc, torch_mod):
+    T = 100
+    seeds = list(range(1, 33))
+    m = orc.Model(L63)
+    gpu = []
+    for s in seeds:
+        xt, y = orc.simulate(m, 20_000 + s, T)
+        f = pf.ParticleFilter([L63], [(0, 4, 256, s)], fused=True)
+        yd = _dev(y.astype(np.float32))
+        est = np.zeros((T, 3))
+        for t in range(T):
+            f.step(yd[t])
+            est[t] = f.estimate()[0].cpu().numpy()
+        f.sync()
+        gpu.append(float(np.mean((est - xt[1:]) ** 2)))
+    with cf.ThreadPoolExecutor(8) as pool:
+        ora = list(pool.map(_oracle_mse, [(s, T) for s in seeds]))
+    gpu, ora = np.array(gpu), np.array(ora)
+    se = ora.std(ddof=1) / np.sqrt(len(seeds))
+    print(f"fused MSE gpu {gpu.mean():.5f} oracle {ora.mean():.5f} (2 SE = {2 * se:.5f})")
+    assert abs(gpu.mean() - ora.mean()) <= 2 * se
