@@ -242,7 +242,120 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, in
   }
 }
 
+// Resampling of one filter per workgroup from its log-weights alone (models
+// whose particles are too large to keep in a workgroup): normalisation, the
+// LDS CDF, the sorted uniforms, the ancestors, their offspring counts n_i
+// (for the post-resampling estimate sum_i n_i xbar_i / N), and log G.
+template <int BD>
+__global__ void __launch_bounds__(BD)
+k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, int t,
+              int32_t *const *__restrict__ counts) {
+  extern __shared__ double lds[];
+  constexpr int NW = BD / 64;
+  double *shd = lds;
+  float *shf = (float *)(lds + NW);
+  double *C = lds + 2 * NW;
+  const WgJob job = jobs[blockIdx.x];
+  const FusedEns &E = ens[job.ens];
+  const int m = job.filter, N = E.N, tid = threadIdx.x;
+  int *cnt = (int *)(C + N);  // [N] offspring counts
+  const float *lwg = E.lw + (size_t)m * N;
+  float lmax = -INFINITY;
+  for (int i = tid; i < N; i += BD) {
+    float lw = lwg[i];
+    lw = (lw == lw) ? lw : -INFINITY;
+    lmax = fmaxf(lmax, lw);
+    cnt[i] = 0;
+  }
+  const float mxf = block_max(lmax, shf);
+  const bool deg = !(mxf > -INFINITY);
+  const double mx = (double)mxf;
+  double carry = 0.0, s2 = 0.0;
+  for (int base = 0; base < N; base += BD) {
+    const int i = base + tid;
+    double w = 0.0;
+    if (i < N) {
+      const float lw = lwg[i];
+      w = deg ? 1.0 : exp((double)((lw == lw) ? lw : -INFINITY) - mx);
+      s2 += w * w;
+    }
+    double tot;
+    const double ex = block_exscan(w, shd, &tot);
+    if (i < N) C[i] = carry + (ex + w);
+    carry += tot;
+  }
+  __syncthreads();
+  const double W = C[N - 1];
+  const double w2 = block_sum(s2, shd);
+  const int KPT = (N + BD - 1) / BD;
+  const int k0 = tid * KPT, k1 = min(N, k0 + KPT);
+  ExpoWG ex{E.key, (uint32_t)m, (uint32_t)t};
+  double es = 0.0;
+  for (int j = k0; j < k1; ++j) es += ex(j);
+  double SN;
+  const double eoff = block_exscan(es, shd, &SN);
+  if (tid == 0) {
+    ExpoWG tail{E.key, (uint32_t)m, (uint32_t)t};
+    lds[2 * NW - 1] = tail(N);
+  }
+  __syncthreads();
+  SN += lds[2 * NW - 1];
+  double run = eoff;
+  int i = 0;
+  for (int k = k0; k < k1; ++k) {
+    run += ex(k);
+    const double v = (run / SN) * W;
+    i = lds_search(C, N, (k == k0) ? 0 : i, v);
+    E.A[(size_t)m * N + k] = i;
+    atomicAdd(cnt + i, 1);
+  }
+  __syncthreads();
+  int32_t *cg = counts[job.ens] + (size_t)m * N;
+  for (int j = tid; j < N; j += BD) cg[j] = cnt[j];
+  if (tid == 0) {
+    double *f = E.fstat + (size_t)m * FREC;
+    f[0] = mx;
+    f[1] = W;
+    f[2] = w2;
+    f[3] = deg ? 1.0 : 0.0;
+    f[4] = SN;
+    f[5] = deg ? -INFINITY : f[5] + mx + log(W / (double)N) + E.lognorm;
+    f[6] = W * W / w2;
+  }
+}
+
+// Offspring counts n_i = #{k : a_k = i} of every filter from its ancestors.
+__global__ void __launch_bounds__(256)
+k_offspring_counts(int N, const int32_t *__restrict__ A, int32_t *__restrict__ cnt) {
+  const int m = blockIdx.y;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  atomicAdd(cnt + (size_t)m * N + min(max(A[(size_t)m * N + k], 0), N - 1), 1);
+}
+
 }  // namespace
+
+hipError_t launch_resample_wg(int BD, const WgJob *d_jobs, int n_jobs, int max_n,
+                              const FusedEns *d_ens, int t, int32_t *const *d_counts,
+                              hipStream_t s) {
+  const size_t lds = sizeof(double) * (2 * (size_t)(BD / 64) + 2) +
+                     sizeof(double) * (size_t)max_n + sizeof(int) * (size_t)max_n;
+  if (BD == 256)
+    k_resample_wg<256><<<n_jobs, 256, lds, s>>>(d_jobs, d_ens, t, d_counts);
+  else if (BD == 512)
+    k_resample_wg<512><<<n_jobs, 512, lds, s>>>(d_jobs, d_ens, t, d_counts);
+  else
+    k_resample_wg<1024><<<n_jobs, 1024, lds, s>>>(d_jobs, d_ens, t, d_counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_offspring_counts(const EnsDev &e, int32_t *cnt, hipStream_t s) {
+  hipError_t err = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)e.M * e.N, s);
+  if (err != hipSuccess) return err;
+  dim3 g((unsigned)((e.N + 255) / 256), (unsigned)e.M);
+  k_offspring_counts<<<g, 256, 0, s>>>(e.N, e.A, cnt);
+  return hipGetLastError();
+}
 
 // LDS bytes of a workgroup that owns a filter of N particles.
 size_t filter_wg_lds(int N, int BD) {
@@ -282,6 +395,12 @@ hipError_t set_filter_wg_lds_limit() {
   e = hipFuncSetAttribute((const void *)k_filter_wg<1, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_filter_wg<1, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_resample_wg<256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_resample_wg<512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_resample_wg<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void *)k_filter_wg<1, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }

@@ -1,0 +1,471 @@
+// k_grid.hip -- kernels of the FitzHugh-Nagumo grid model (J x J nodes, two
+// variables per node, particle-major state [M][N][2][J][J]: the v plane then
+// the w plane of each particle, contiguous).
+//
+// A workgroup owns one particle at a time.  Thread t handles the float4
+// slots s = t, t + blockDim, ... of the particle (nodes 4s .. 4s+3 in row-major
+// order): v and w of its nodes live in registers, and the v plane is staged
+// in LDS because the 5-point Laplacian reads the neighbours' v.
+//   - k_grid_steps: every Euler step of the interval with the plane resident
+//     in LDS (temporal blocking: the state crosses HBM once per interval);
+//     the first read goes through the ancestor index (fused gather) and the
+//     last step also produces the log-weight (fused weighting).
+//   - k_grid_stream_step: one Euler step per launch, state read from and
+//     written to HBM (16 bytes per node-step).
+// Both share grid_euler(): drift v(v-a)(1-v) - w + D lap(v), eps (v - gam w),
+// Euler-Maruyama with compensated FP32 sums, the noise of nodes 2p, 2p+1 from
+// the Philox call of node pair p at step n.
+#include <algorithm>
+
+#include "pf_internal.h"
+
+namespace pfk {
+namespace {
+
+constexpr int GB = 256;  // workgroup size of the element-wise grid kernels
+// The stepping kernels run 64 * ceil(slots / (64 * SPT)) threads with SPT
+// float4 slots each (slots = J*J/4); J <= 64 needs at most 1024 slots.
+
+struct Slot4 {
+  float4 v, w, cv, cw;  // state of 4 nodes and the compensation terms
+};
+
+__device__ __forceinline__ float get(const float4 &a, int e) {
+  return e == 0 ? a.x : e == 1 ? a.y : e == 2 ? a.z : a.w;
+}
+__device__ __forceinline__ void set(float4 &a, int e, float x) {
+  if (e == 0) a.x = x; else if (e == 1) a.y = x; else if (e == 2) a.z = x; else a.w = x;
+}
+
+// One Euler-Maruyama step of the 4 nodes of slot s (nodes 4s .. 4s+3), reading
+// neighbour v values from the LDS plane vs.  Returns the new state in S.
+__device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t purpose,
+                                           uint32_t c0, uint32_t c1, uint32_t n, int s,
+                                           const float *vs, Slot4 &S) {
+  const int J = md.J;
+  const uint4 ra = philox(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s), key);
+  const uint4 rb = philox(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s + 1), key);
+  float za[4], zb[4];
+  normals4(ra, za);
+  normals4(rb, zb);
+  // node 4s+e: pair 2s + e/2; lanes (0,1) for the even node, (2,3) the odd
+  const float zv[4] = {za[0], za[2], zb[0], zb[2]};
+  const float zw[4] = {za[1], za[3], zb[1], zb[3]};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = 4 * s + e;
+    const int i = k / J, j = k - i * J;
+    const float c = get(S.v, e), w = get(S.w, e);
+    float lap = 0.f;
+    if (i > 0) lap += vs[k - J] - c;
+    if (i < J - 1) lap += vs[k + J] - c;
+    if (j > 0) lap += vs[k - 1] - c;
+    if (j < J - 1) lap += vs[k + 1] - c;
+    const float fv = c * (c - md.p0) * (1.f - c) - w + md.p1 * lap;
+    const float fw = md.p2 * (c - md.p3 * w);
+    const float iv = fmaf(md.h, fv, md.sq0 * zv[e]) - get(S.cv, e);
+    const float nv = c + iv;
+    set(S.cv, e, (nv - c) - iv);
+    set(S.v, e, nv);
+    const float iw = fmaf(md.h, fw, md.sq1 * zw[e]) - get(S.cw, e);
+    const float nw = w + iw;
+    set(S.cw, e, (nw - w) - iw);
+    set(S.w, e, nw);
+  }
+}
+
+// -(1/(2 sigma^2)) sum_k (y_k - v[obs_k])^2 from the LDS plane (workgroup sum)
+__device__ __forceinline__ float grid_loglik(const ModelDev &md, const float *vs, const float *y,
+                                             float *shf) {
+  float acc = 0.f;
+  for (int k = threadIdx.x; k < md.dy; k += blockDim.x) {
+    const float r = y[k] - vs[md.obs_idx[k]];
+    acc = fmaf(r, r, acc);
+  }
+  // block sum in FP32 (fixed order over waves)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) shf[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  float tot = 0.f;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += shf[i];
+  const float lw = -tot * md.inv2var;
+  return (lw == lw) ? lw : -INFINITY;
+}
+
+// Interval of S steps per particle with the v plane resident in LDS.
+template <int SPT>
+__global__ void __launch_bounds__(1024)
+k_grid_steps(ModelDev md, Key key, int M, int N, int t, const float *__restrict__ Xin,
+             const int32_t *__restrict__ anc, float *__restrict__ Xout, float *__restrict__ lw,
+             const float *__restrict__ y) {
+  extern __shared__ float vs[];  // [J*J] v plane, then 8 floats of scratch
+  const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
+  float *shf = vs + nn;
+  for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
+    const int m = p / N, i = p - m * N;
+    const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
+    const float4 *in = (const float4 *)(Xin + ((size_t)m * N + src) * dx);
+    Slot4 S[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = threadIdx.x + q * blockDim.x;
+      if (s < slots) {
+        S[q].v = in[s];
+        S[q].w = in[slots + s];
+        S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
+        *(float4 *)(vs + 4 * s) = S[q].v;
+      }
+    }
+    __syncthreads();
+    const int n0 = (t - 1) * md.S;
+    for (int st = 0; st < md.S; ++st) {
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int s = threadIdx.x + q * blockDim.x;
+        if (s < slots) grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), s, vs, S[q]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int s = threadIdx.x + q * blockDim.x;
+        if (s < slots) *(float4 *)(vs + 4 * s) = S[q].v;
+      }
+      __syncthreads();
+    }
+    float4 *out = (float4 *)(Xout + ((size_t)m * N + i) * dx);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = threadIdx.x + q * blockDim.x;
+      if (s < slots) {
+        out[s] = S[q].v;
+        out[slots + s] = S[q].w;
+      }
+    }
+    if (lw) {
+      const float l = grid_loglik(md, vs, y, shf);
+      if (threadIdx.x == 0) lw[(size_t)m * N + i] = l;
+    }
+    __syncthreads();
+  }
+}
+
+// One Euler step n of every particle, state through HBM.
+template <int SPT>
+__global__ void __launch_bounds__(1024)
+k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
+                   const int32_t *__restrict__ anc, float *Xout,
+                   float *__restrict__ lw, const float *__restrict__ y) {
+  // Xin may equal Xout (in-place step): each workgroup reads its whole
+  // particle before the barrier and writes it after.
+  extern __shared__ float vs[];
+  const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
+  float *shf = vs + nn;
+  for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
+    const int m = p / N, i = p - m * N;
+    const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
+    const float4 *in = (const float4 *)(Xin + ((size_t)m * N + src) * dx);
+    Slot4 S[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = threadIdx.x + q * blockDim.x;
+      if (s < slots) {
+        S[q].v = in[s];
+        S[q].w = in[slots + s];
+        S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
+        *(float4 *)(vs + 4 * s) = S[q].v;
+      }
+    }
+    __syncthreads();
+    float4 *out = (float4 *)(Xout + ((size_t)m * N + i) * dx);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = threadIdx.x + q * blockDim.x;
+      if (s < slots) {
+        grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)n, s, vs, S[q]);
+        out[s] = S[q].v;
+        out[slots + s] = S[q].w;
+      }
+    }
+    if (lw) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int s = threadIdx.x + q * blockDim.x;
+        if (s < slots) *(float4 *)(vs + 4 * s) = S[q].v;
+      }
+      __syncthreads();
+      const float l = grid_loglik(md, vs, y, shf);
+      if (threadIdx.x == 0) lw[(size_t)m * N + i] = l;
+    }
+    __syncthreads();
+  }
+}
+
+// Prior draw: state index s of particle i uses Philox (i, m, 0, INIT | s/4).
+__global__ void __launch_bounds__(GB)
+k_grid_init(ModelDev md, Key key, int N, float *__restrict__ X) {
+  const int dx = md.dx, p = blockIdx.x;  // p = m * N + i
+  const int m = p / N, i = p - m * N;
+  float *x = X + (size_t)p * dx;
+  for (int g = threadIdx.x; 4 * g < dx; g += GB) {  // group of 4 states
+    float z[4];
+    normals4(philox((uint32_t)i, (uint32_t)m, 0u, (P_INIT << 24) | (uint32_t)g, key), z);
+    for (int l = 0; l < 4 && 4 * g + l < dx; ++l)
+      x[4 * g + l] = md.prior_mean[4 * g + l] + md.prior_sd[4 * g + l] * z[l];
+  }
+}
+
+// log-weights of every particle from its stored state (plain path).
+__global__ void __launch_bounds__(GB)
+k_grid_loglik(ModelDev md, int M, int N, const float *__restrict__ X, const float *__restrict__ y,
+              float *__restrict__ lw) {
+  const int p = blockIdx.x * GB + threadIdx.x;
+  if (p >= M * N) return;
+  const float *v = X + (size_t)p * md.dx;
+  float acc = 0.f;
+  for (int k = 0; k < md.dy; ++k) {
+    const float r = y[k] - v[md.obs_idx[k]];
+    acc = fmaf(r, r, acc);
+  }
+  const float l = -acc * md.inv2var;
+  lw[p] = (l == l) ? l : -INFINITY;
+}
+
+// x'[m][k] = xbar[m][a_k]: float4 block copies.
+__global__ void __launch_bounds__(GB)
+k_grid_gather(int N, int dx4, const int32_t *__restrict__ A, const float4 *__restrict__ Xin,
+              float4 *__restrict__ Xout) {
+  const int p = blockIdx.x;  // m * N + k
+  const int m = p / N;
+  const int a = min(max(A[p], 0), N - 1);
+  const float4 *src = Xin + ((size_t)m * N + a) * dx4;
+  float4 *dst = Xout + (size_t)p * dx4;
+  for (int g = threadIdx.x; g < dx4; g += GB) dst[g] = src[g];
+}
+
+// Partial sums over a chunk of particles of one filter, per state element:
+// post-resampling sum_i n_i xbar_i (n_i offspring counts) and weighted
+// sum_i w_i xbar_i, both in FP64.  Grid: (state groups, chunks, M).
+constexpr int EST_CHUNK = 32;
+__global__ void __launch_bounds__(GB)
+k_grid_estimate_part(int N, int dx4, const float4 *__restrict__ Xb,
+                     const int32_t *__restrict__ cnt, const float *__restrict__ lw,
+                     const double *__restrict__ fstat, double *__restrict__ part) {
+  const int g = blockIdx.x * GB + threadIdx.x;
+  const int ch = blockIdx.y, m = blockIdx.z;
+  const int nch = gridDim.y;
+  if (g >= dx4) return;
+  const double mx = fstat[(size_t)m * FREC + 0];
+  const bool deg = fstat[(size_t)m * FREC + 3] != 0.0;
+  double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
+  const int i0 = ch * EST_CHUNK, i1 = min(N, i0 + EST_CHUNK);
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
+    const float4 x = Xb[((size_t)m * N + i) * dx4 + g];
+    const double n = (double)cnt[(size_t)m * N + i];
+    const double w = deg ? 1.0 : exp((double)lw[(size_t)m * N + i] - mx);
+    pv[0] += n * x.x; pv[1] += n * x.y; pv[2] += n * x.z; pv[3] += n * x.w;
+    wv[0] += w * x.x; wv[1] += w * x.y; wv[2] += w * x.z; wv[3] += w * x.w;
+  }
+  double *o = part + (((size_t)m * nch + ch) * 2) * (size_t)dx4 * 4;
+  for (int l = 0; l < 4; ++l) {
+    o[(size_t)g * 4 + l] = pv[l];
+    o[(size_t)dx4 * 4 + (size_t)g * 4 + l] = wv[l];
+  }
+}
+
+// Filter means from the chunk partials, then the ensemble means (one thread
+// per state element, fixed summation order).
+__global__ void __launch_bounds__(GB)
+k_grid_estimate_fold(int M, int N, int dx, int nch, const double *__restrict__ part,
+                     const double *__restrict__ fstat, double *__restrict__ fmean,
+                     double *__restrict__ fmeanw, double *__restrict__ emean) {
+  const int c = blockIdx.x * GB + threadIdx.x;
+  if (c >= dx) return;
+  double ea = 0.0, eb = 0.0;
+  for (int m = 0; m < M; ++m) {
+    double a = 0.0, b = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const double *o = part + (((size_t)m * nch + ch) * 2) * (size_t)dx;
+      a += o[c];
+      b += o[(size_t)dx + c];
+    }
+    const double W = fstat[(size_t)m * FREC + 1];
+    a /= (double)N;
+    b /= W;
+    fmean[(size_t)m * dx + c] = a;
+    fmeanw[(size_t)m * dx + c] = b;
+    ea += a;
+    eb += b;
+  }
+  emean[c] = ea / (double)M;
+  emean[dx + c] = eb / (double)M;
+}
+
+// Truth path on the truth stream: one workgroup, T intervals of S steps.
+template <int SPT>
+__global__ void __launch_bounds__(1024)
+k_grid_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *__restrict__ y) {
+  extern __shared__ float vs[];
+  const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
+  Slot4 S[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int s = threadIdx.x + q * blockDim.x;
+    if (s < slots) {
+      float z[4], v[4], w[4];
+      // state index of v at node 4s+l is 4s+l, of w is nn + 4s+l
+      normals4(philox(0u, TRUTH_STREAM, 0u, (P_TRUTH_INIT << 24) | (uint32_t)s, key), z);
+      for (int l = 0; l < 4; ++l) v[l] = md.prior_mean[4 * s + l] + md.prior_sd[4 * s + l] * z[l];
+      normals4(philox(0u, TRUTH_STREAM, 0u, (P_TRUTH_INIT << 24) | (uint32_t)(slots + s), key), z);
+      for (int l = 0; l < 4; ++l)
+        w[l] = md.prior_mean[nn + 4 * s + l] + md.prior_sd[nn + 4 * s + l] * z[l];
+      S[q].v = make_float4(v[0], v[1], v[2], v[3]);
+      S[q].w = make_float4(w[0], w[1], w[2], w[3]);
+      S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
+      *(float4 *)(vs + 4 * s) = S[q].v;
+      ((float4 *)xtrue)[s] = S[q].v;
+      ((float4 *)xtrue)[slots + s] = S[q].w;
+    }
+  }
+  __syncthreads();
+  for (int t = 1; t <= T; ++t) {
+    for (int st = 0; st < md.S; ++st) {
+      const uint32_t n = (uint32_t)((t - 1) * md.S + st);
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int s = threadIdx.x + q * blockDim.x;
+        if (s < slots) grid_euler(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, n, s, vs, S[q]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int s = threadIdx.x + q * blockDim.x;
+        if (s < slots) *(float4 *)(vs + 4 * s) = S[q].v;
+      }
+      __syncthreads();
+    }
+    float4 *xt = (float4 *)(xtrue + (size_t)t * dx);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = threadIdx.x + q * blockDim.x;
+      if (s < slots) {
+        xt[s] = S[q].v;
+        xt[slots + s] = S[q].w;
+      }
+    }
+    for (int k4 = threadIdx.x; 4 * k4 < md.dy; k4 += GB) {
+      float z[4];
+      normals4(philox(0u, TRUTH_STREAM, (uint32_t)t, (P_OBS_NOISE << 24) | (uint32_t)k4, key), z);
+      for (int l = 0; l < 4 && 4 * k4 + l < md.dy; ++l)
+        y[(size_t)(t - 1) * md.dy + 4 * k4 + l] = vs[md.obs_idx[4 * k4 + l]] + md.obs_sd * z[l];
+    }
+    __syncthreads();
+  }
+}
+
+size_t grid_lds(const ModelDev &md) { return sizeof(float) * ((size_t)md.J * md.J + 16); }
+
+}  // namespace
+
+namespace {
+// slots per thread and threads per workgroup of the stepping kernels
+void grid_shape(const ModelDev &md, int *spt, int *threads) {
+  const int slots = md.J * md.J / 4;
+  int k = 1;
+  while (k < 4 && 64 * ((slots + 64 * k - 1) / (64 * k)) > 1024) k <<= 1;
+  *spt = k;
+  *threads = 64 * ((slots + 64 * k - 1) / (64 * k));
+}
+}  // namespace
+
+int grid_resident_blocks(const ModelDev &md) {
+  int dev = 0, per_cu = 0, spt, threads;
+  grid_shape(md, &spt, &threads);
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
+  hipError_t e = spt == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<1>, threads, grid_lds(md))
+               : spt == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<2>, threads, grid_lds(md))
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<4>, threads, grid_lds(md));
+  if (e != hipSuccess) return 1024;
+  return std::max(1, per_cu) * prop.multiProcessorCount;
+}
+
+hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s) {
+  k_grid_init<<<e.M * e.N, GB, 0, s>>>(e.md, e.key, e.N, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_steps(const EnsDev &e, int t, const float *Xin, const int32_t *anc,
+                             float *Xout, float *lw, const float *y, int blocks, hipStream_t s) {
+  int spt, threads;
+  grid_shape(e.md, &spt, &threads);
+  const int g = std::min(blocks, e.M * e.N);
+  const size_t lds = grid_lds(e.md);
+  if (spt == 1)
+    k_grid_steps<1><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, t, Xin, anc, Xout, lw, y);
+  else if (spt == 2)
+    k_grid_steps<2><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, t, Xin, anc, Xout, lw, y);
+  else
+    k_grid_steps<4><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, t, Xin, anc, Xout, lw, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_stream_step(const EnsDev &e, int n, const float *Xin, const int32_t *anc,
+                                   float *Xout, float *lw, const float *y, int blocks,
+                                   hipStream_t s) {
+  int spt, threads;
+  grid_shape(e.md, &spt, &threads);
+  const int g = std::min(blocks, e.M * e.N);
+  const size_t lds = grid_lds(e.md);
+  if (spt == 1)
+    k_grid_stream_step<1><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, n, Xin, anc, Xout, lw, y);
+  else if (spt == 2)
+    k_grid_stream_step<2><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, n, Xin, anc, Xout, lw, y);
+  else
+    k_grid_stream_step<4><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, n, Xin, anc, Xout, lw, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_loglik(const EnsDev &e, const float *X, const float *y, hipStream_t s) {
+  const int total = e.M * e.N;
+  k_grid_loglik<<<(total + GB - 1) / GB, GB, 0, s>>>(e.md, e.M, e.N, X, y, e.lw);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_gather(const EnsDev &e, const float *Xin, float *Xout, hipStream_t s) {
+  const int dx4 = e.md.dx / 4;
+  k_grid_gather<<<e.M * e.N, GB, 0, s>>>(e.N, dx4, e.A, (const float4 *)Xin, (float4 *)Xout);
+  return hipGetLastError();
+}
+
+int grid_est_chunks(int N) { return (N + EST_CHUNK - 1) / EST_CHUNK; }
+
+hipError_t launch_grid_estimate(const EnsDev &e, const float *Xb, const int32_t *cnt,
+                                double *part, hipStream_t s) {
+  const int dx4 = e.md.dx / 4, nch = grid_est_chunks(e.N);
+  dim3 g((unsigned)((dx4 + GB - 1) / GB), (unsigned)nch, (unsigned)e.M);
+  k_grid_estimate_part<<<g, GB, 0, s>>>(e.N, dx4, (const float4 *)Xb, cnt, e.lw, e.fstat, part);
+  k_grid_estimate_fold<<<(e.md.dx + GB - 1) / GB, GB, 0, s>>>(e.M, e.N, e.md.dx, nch, part,
+                                                               e.fstat, e.fmean, e.fmeanw, e.emean);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,
+                                hipStream_t s) {
+  int spt, threads;
+  grid_shape(e.md, &spt, &threads);
+  const size_t lds = grid_lds(e.md);
+  if (spt == 1)
+    k_grid_simulate<1><<<1, threads, lds, s>>>(e.md, make_key(seed), T, xtrue, y);
+  else if (spt == 2)
+    k_grid_simulate<2><<<1, threads, lds, s>>>(e.md, make_key(seed), T, xtrue, y);
+  else
+    k_grid_simulate<4><<<1, threads, lds, s>>>(e.md, make_key(seed), T, xtrue, y);
+  return hipGetLastError();
+}
+
+}  // namespace pfk

@@ -279,6 +279,7 @@ __global__ void __launch_bounds__(256)
 k_ensemble_means_batched(const FusedEns *__restrict__ ens) {
   __shared__ double sh[4];
   const FusedEns &E = ens[blockIdx.x];
+  if (E.md.kind == 2) return;  // grid model: folded by its own estimator
   const int dx = E.md.dx;
   for (int c = 0; c < dx; ++c) {
     double a = 0.0, b = 0.0;

@@ -53,12 +53,15 @@ struct Ens {
   std::vector<float> prior_mean, prior_sd;
   pfk::EnsDev dev;
   pfk::FusedEns fz;  // record of the fused kernels
+  int blocks = 1024;       // grid model: resident workgroups of the stepping kernels
+  int32_t *cnt = nullptr;  // grid model: offspring counts [M][N]
+  double *gpart = nullptr; // grid model: estimator partial sums
 };
 
 // One launch of the filter-per-workgroup kernel: every filter of the
 // ensembles of one (state dimension, workgroup size) class.
 struct WgClass {
-  int D, BD, max_n;
+  int D, BD, max_n;  // D = 0: grid-model resampling class
   std::vector<pfk::WgJob> jobs;
   pfk::WgJob *d_jobs = nullptr;
 };
@@ -69,10 +72,10 @@ int wg_block(int N) { return N <= 256 ? 256 : (N <= 512 ? 512 : 1024); }
 // Offsets of every array of one ensemble inside the workspace.
 struct Layout {
   size_t obs, pmean, psd, X0, X1, lw, A, Cl, Sl, tile, coff, soff, fstat, mpart, wpart, fmean,
-      fmeanw, emean, end;
+      fmeanw, emean, cnt, gpart, end;
 };
 
-Layout layout_of(size_t base, int M, int N, int dx, int dy, int T) {
+Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid) {
   Layout L{};
   size_t o = base;
   auto take = [&](size_t bytes) {
@@ -99,6 +102,9 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T) {
   L.fmean = take(sizeof(double) * (size_t)M * dx);
   L.fmeanw = take(sizeof(double) * (size_t)M * dx);
   L.emean = take(sizeof(double) * 2 * (size_t)dx);
+  // grid model: offspring counts and the chunk partial sums of its estimator
+  L.cnt = take(grid ? sizeof(int32_t) * MN : 0);
+  L.gpart = take(grid ? sizeof(double) * (size_t)M * pfk::grid_est_chunks(N) * 2 * dx : 0);
   L.end = o;
   return L;
 }
@@ -109,7 +115,7 @@ size_t ctx_bytes(const pf_ensemble_desc *ens, int n_ens) {
   size_t jobs = 0;
   for (int e = 0; e < n_ens; ++e) jobs += (size_t)ens[e].M;
   return align_up(sizeof(pfk::FusedEns) * (size_t)n_ens) +
-         6 * align_up(sizeof(pfk::WgJob) * jobs);
+         align_up(sizeof(int32_t *) * (size_t)n_ens) + 9 * align_up(sizeof(pfk::WgJob) * jobs);
 }
 
 pf_status check_model(const pf_model_desc &m, int idx) {
@@ -118,9 +124,9 @@ pf_status check_model(const pf_model_desc &m, int idx) {
   } else if (m.kind == PF_MODEL_LORENZ63) {
     if (m.state_dim != 3) return fail(PF_ERR_INVALID_ARG, "model %d: Lorenz needs state_dim 3", idx);
   } else if (m.kind == PF_MODEL_FHN) {
-    if (m.grid_j < 2 || m.grid_j > 64 || m.state_dim != 2 * m.grid_j * m.grid_j)
-      return fail(PF_ERR_INVALID_ARG, "model %d: FH-N needs 2 <= J <= 64 and state_dim 2*J*J", idx);
-    return fail(PF_ERR_UNSUPPORTED, "model %d: FH-N grid model not in this build", idx);
+    if (m.grid_j < 2 || m.grid_j > 64 || (m.grid_j & 1) || m.state_dim != 2 * m.grid_j * m.grid_j)
+      return fail(PF_ERR_INVALID_ARG,
+                  "model %d: FH-N needs an even J in [2, 64] and state_dim 2*J*J", idx);
   } else {
     return fail(PF_ERR_INVALID_ARG, "model %d: unknown kind %d", idx, m.kind);
   }
@@ -158,12 +164,19 @@ pf_status check_all(const pf_model_desc *models, int n_models, const pf_ensemble
   return PF_OK;
 }
 
+pf_status check_fused(const pf_model_desc *models, const pf_ensemble_desc *ens, int n_ens) {
+  for (int e = 0; e < n_ens; ++e)
+    if (models[ens[e].model].kind == PF_MODEL_FHN && ens[e].N > pfk::WG_MAX_N)
+      return fail(PF_ERR_UNSUPPORTED, "fused path: FH-N ensemble %d has N > %d", e, pfk::WG_MAX_N);
+  return PF_OK;
+}
+
 size_t total_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int n_ens) {
   size_t o = 0;
   for (int e = 0; e < n_ens; ++e) {
     const pf_model_desc &m = models[ens[e].model];
     const int T = (ens[e].N + pfk::TILE - 1) / pfk::TILE;
-    o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T).end;
+    o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T, m.kind == PF_MODEL_FHN).end;
   }
   return o + ctx_bytes(ens, n_ens);
 }
@@ -184,7 +197,10 @@ struct pf_ctx {
   // fused path
   pfk::FusedEns *d_fens = nullptr;
   std::vector<pfk::FusedEns> fz_host;
-  std::vector<WgClass> classes;
+  std::vector<WgClass> classes;       // filter-per-workgroup launches (vector models)
+  std::vector<WgClass> grid_classes;  // per-filter resampling launches (grid model)
+  int32_t **d_counts = nullptr;       // [n_ens] device pointers to offspring counts
+  std::vector<int32_t *> counts_host;
   // event pairs around the dominant kernel while profiling is enabled
   bool profiling = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -221,19 +237,39 @@ void prof_end(pf_ctx *ctx, long i, hipStream_t s) {
   if (i >= 0) (void)hipEventRecord(ctx->ev_stop[(size_t)i], s);
 }
 
+// gather x' = xbar[A] of one ensemble from buffer `from` into buffer `to`
+hipError_t gather(const Ens &E, int from, int to, hipStream_t s) {
+  const pfk::EnsDev &D = E.dev;
+  return E.grid ? pfk::launch_grid_gather(D, D.X[from], D.X[to], s)
+                : pfk::launch_vec_gather(D, D.X[from], D.X[to], s);
+}
+
 pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t s) {
   const int t = ctx->t;
   if ((stages & PF_STAGE_WEIGHT) && !d_y)
     return fail(PF_ERR_INVALID_ARG, "weighting needs observations");
   if (stages & PF_STAGE_PROPAGATE) {
     const int out = 1 - ctx->cur;
-    const long ev = prof_begin(ctx, s);
     for (Ens &E : ctx->ens) {
       pfk::EnsDev &D = E.dev;
       const int32_t *anc = ctx->pending ? D.A : nullptr;
-      PF_HIP(pfk::launch_vec_propagate(D, t, D.X[ctx->cur], anc, D.X[out], nullptr, nullptr, s));
+      if (!E.grid) {
+        const long ev = prof_begin(ctx, s);
+        PF_HIP(pfk::launch_vec_propagate(D, t, D.X[ctx->cur], anc, D.X[out], nullptr, nullptr, s));
+        prof_end(ctx, ev, s);
+      } else {
+        // one streaming launch per Euler step: the first reads through the
+        // ancestors into the other buffer, the rest update it in place
+        for (int st = 0; st < D.md.S; ++st) {
+          const long ev = prof_begin(ctx, s);
+          PF_HIP(pfk::launch_grid_stream_step(D, (t - 1) * D.md.S + st,
+                                              st == 0 ? D.X[ctx->cur] : D.X[out],
+                                              st == 0 ? anc : nullptr, D.X[out], nullptr, nullptr,
+                                              E.blocks, s));
+          prof_end(ctx, ev, s);
+        }
+      }
     }
-    prof_end(ctx, ev, s);
     ctx->xbar = out;
     ctx->pending = false;
   }
@@ -242,10 +278,14 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
     pfk::EnsDev &D = E.dev;
     const float *y = d_y ? d_y + yoff : nullptr;
     yoff += (size_t)E.dy;
-    if (stages & PF_STAGE_WEIGHT) PF_HIP(pfk::launch_vec_loglik(D, D.X[ctx->xbar], y, s));
+    if (stages & PF_STAGE_WEIGHT) {
+      if (E.grid)
+        PF_HIP(pfk::launch_grid_loglik(D, D.X[ctx->xbar], y, s));
+      else
+        PF_HIP(pfk::launch_vec_loglik(D, D.X[ctx->xbar], y, s));
+    }
     if (stages & PF_STAGE_RESAMPLE) PF_HIP(pfk::launch_resample(D, t, s));
-    if (stages & PF_STAGE_GATHER)
-      PF_HIP(pfk::launch_vec_gather(D, D.X[ctx->xbar], D.X[1 - ctx->xbar], s));
+    if (stages & PF_STAGE_GATHER) PF_HIP(gather(E, ctx->xbar, 1 - ctx->xbar, s));
   }
   if (stages & PF_STAGE_GATHER) {
     ctx->cur = 1 - ctx->xbar;
@@ -254,8 +294,14 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
   if (stages & PF_STAGE_ESTIMATE) {
     for (Ens &E : ctx->ens) {
       pfk::EnsDev &D = E.dev;
-      if (ctx->pending) return fail(PF_ERR_STATE, "estimate stage needs gathered particles");
-      PF_HIP(pfk::launch_vec_estimate(D, D.X[ctx->cur], D.X[ctx->xbar], nullptr, true, s));
+      if (E.grid) {
+        // sum_i n_i xbar_i / N with the offspring counts n_i of the ancestors
+        PF_HIP(pfk::launch_offspring_counts(D, E.cnt, s));
+        PF_HIP(pfk::launch_grid_estimate(D, D.X[ctx->xbar], E.cnt, E.gpart, s));
+      } else {
+        if (ctx->pending) return fail(PF_ERR_STATE, "estimate stage needs gathered particles");
+        PF_HIP(pfk::launch_vec_estimate(D, D.X[ctx->cur], D.X[ctx->xbar], nullptr, true, s));
+      }
     }
   }
   ctx->last_stream = s;
@@ -273,11 +319,33 @@ pf_status fused_run(pf_ctx *ctx, const float *d_y, hipStream_t s, bool resample_
   for (const WgClass &c : ctx->classes)
     PF_HIP(pfk::launch_filter_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
                                  ctx->t, parity, pending, d_y, resample_only ? 1 : 0, s));
+  // grid model: the interval's steps with the plane in LDS, then per-filter
+  // resampling from the log-weights, then the one-pass estimator
+  bool any_grid = false;
+  size_t yo = 0;
+  for (Ens &E : ctx->ens) {
+    const float *y = d_y ? d_y + yo : nullptr;
+    yo += (size_t)E.dy;
+    if (!E.grid) continue;
+    any_grid = true;
+    if (!resample_only) {
+      pfk::EnsDev &D = E.dev;
+      PF_HIP(pfk::launch_grid_steps(D, ctx->t, D.X[parity], pending ? D.A : nullptr,
+                                    D.X[1 - parity], D.lw, y, E.blocks, s));
+    }
+  }
+  if (any_grid) {
+    for (const WgClass &c : ctx->grid_classes)
+      PF_HIP(pfk::launch_resample_wg(c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
+                                     ctx->t, ctx->d_counts, s));
+    for (Ens &E : ctx->ens)
+      if (E.grid) PF_HIP(pfk::launch_grid_estimate(E.dev, E.dev.X[1 - parity], E.cnt, E.gpart, s));
+  }
   size_t yoff = 0;
   for (Ens &E : ctx->ens) {
     const float *y = d_y ? d_y + yoff : nullptr;
     yoff += (size_t)E.dy;
-    if (E.wg) continue;
+    if (E.wg || E.grid) continue;
     pfk::EnsDev &D = E.dev;
     const int out = 1 - parity;
     if (!resample_only) {
@@ -303,8 +371,7 @@ pf_status fused_run(pf_ctx *ctx, const float *d_y, hipStream_t s, bool resample_
 // Resolve pending ancestors: gather every ensemble into the other buffer.
 pf_status materialise(pf_ctx *ctx, hipStream_t s) {
   if (!ctx->pending) return PF_OK;
-  for (Ens &E : ctx->ens)
-    PF_HIP(pfk::launch_vec_gather(E.dev, E.dev.X[ctx->cur], E.dev.X[1 - ctx->cur], s));
+  for (Ens &E : ctx->ens) PF_HIP(gather(E, ctx->cur, 1 - ctx->cur, s));
   ctx->xbar = ctx->cur;
   ctx->cur = 1 - ctx->cur;
   ctx->pending = false;
@@ -326,6 +393,7 @@ pf_status pf_workspace_bytes(const pf_model_desc *h_models, int32_t n_models,
   if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
   if (options > PF_OPT_FUSED) return fail(PF_ERR_INVALID_ARG, "unknown options");
   PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
+  if (options & PF_OPT_FUSED) PF_TRY(check_fused(h_models, h_ens, n_ens));
   *out_bytes = total_bytes(h_models, h_ens, n_ens);
   return PF_OK;
 }
@@ -337,6 +405,7 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
   *out_ctx = nullptr;
   if (options > PF_OPT_FUSED) return fail(PF_ERR_INVALID_ARG, "unknown options");
   PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
+  if (options & PF_OPT_FUSED) PF_TRY(check_fused(h_models, h_ens, n_ens));
   const size_t need = total_bytes(h_models, h_ens, n_ens);
   if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0)
     return fail(PF_ERR_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
@@ -367,7 +436,7 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
       E.prior_mean[(size_t)k] = (float)m.h_prior_mean[k];
       E.prior_sd[(size_t)k] = (float)m.h_prior_sd[k];
     }
-    const Layout L = layout_of(base, E.d.M, E.d.N, E.dx, E.dy, E.T);
+    const Layout L = layout_of(base, E.d.M, E.d.N, E.dx, E.dy, E.T, E.grid);
     base = L.end;
     pfk::EnsDev &D = E.dev;
     pfk::ModelDev &md = D.md;
@@ -426,6 +495,11 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     F.fmeanw = D.fmeanw;
     F.emean = D.emean;
     E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N;
+    if (E.grid) {
+      E.cnt = (int32_t *)(ws + L.cnt);
+      E.gpart = (double *)(ws + L.gpart);
+      E.blocks = pfk::grid_resident_blocks(md);
+    }
     pf_status st = PF_OK;
 #define INIT_TRY(expr)                                  \
   do {                                                  \
@@ -445,13 +519,22 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     INIT_TRY(hipMemsetAsync(D.emean, 0, sizeof(double) * 2 * (size_t)E.dx, s));
     // every ancestor index is valid from the start
     INIT_TRY(hipMemsetAsync(D.A, 0, sizeof(int32_t) * (size_t)E.d.M * E.d.N, s));
-    INIT_TRY(pfk::launch_vec_init(D, D.X[0], s));
+    if (E.grid)
+      INIT_TRY(pfk::launch_grid_init(D, D.X[0], s));
+    else
+      INIT_TRY(pfk::launch_vec_init(D, D.X[0], s));
   }
   // context arrays: the fused ensemble table and the workgroup job lists
   {
     pf_status st = PF_OK;
     ctx->d_fens = (pfk::FusedEns *)(ws + base);
     size_t o = base + align_up(sizeof(pfk::FusedEns) * (size_t)n_ens);
+    ctx->d_counts = (int32_t **)(ws + o);
+    o += align_up(sizeof(int32_t *) * (size_t)n_ens);
+    ctx->counts_host.resize((size_t)n_ens);
+    for (int e = 0; e < n_ens; ++e) ctx->counts_host[(size_t)e] = ctx->ens[(size_t)e].cnt;
+    INIT_TRY(hipMemcpyAsync(ctx->d_counts, ctx->counts_host.data(), sizeof(int32_t *) * (size_t)n_ens,
+                            hipMemcpyHostToDevice, s));
     size_t total_jobs = 0;
     for (int e = 0; e < n_ens; ++e) total_jobs += (size_t)h_ens[e].M;
     ctx->fz_host.resize((size_t)n_ens);
@@ -486,7 +569,27 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
         ctx->classes.push_back(std::move(c));
       }
     }
+    // grid-model resampling classes by workgroup size
+    for (int BD : BDs) {
+      WgClass c;
+      c.D = 0;
+      c.BD = BD;
+      c.max_n = 0;
+      for (int e = 0; e < n_ens; ++e) {
+        const Ens &E = ctx->ens[(size_t)e];
+        if (!E.grid || wg_block(E.d.N) != BD || E.d.N > pfk::WG_MAX_N) continue;
+        c.max_n = std::max(c.max_n, E.d.N);
+        for (int mm = 0; mm < E.d.M; ++mm) c.jobs.push_back(pfk::WgJob{e, mm});
+      }
+      if (c.jobs.empty()) continue;
+      c.d_jobs = (pfk::WgJob *)(ws + o);
+      o += align_up(sizeof(pfk::WgJob) * total_jobs);
+      ctx->grid_classes.push_back(std::move(c));
+    }
     for (WgClass &c : ctx->classes)
+      INIT_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
+                              hipMemcpyHostToDevice, s));
+    for (WgClass &c : ctx->grid_classes)
       INIT_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
                               hipMemcpyHostToDevice, s));
     INIT_TRY(pfk::set_filter_wg_lds_limit());
@@ -573,7 +676,10 @@ pf_status pf_get_particles(pf_ctx *ctx, int32_t ens, float *d_x, void *stream) {
   if (!E || !d_x) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
   hipStream_t s = (hipStream_t)stream;
   if (ctx->pending) {
-    PF_HIP(pfk::launch_vec_gather(E->dev, E->dev.X[ctx->cur], d_x, s));
+    if (E->grid)
+      PF_HIP(pfk::launch_grid_gather(E->dev, E->dev.X[ctx->cur], d_x, s));
+    else
+      PF_HIP(pfk::launch_vec_gather(E->dev, E->dev.X[ctx->cur], d_x, s));
   } else {
     const size_t bytes = sizeof(float) * (size_t)E->d.M * E->d.N * E->dx;
     PF_HIP(hipMemcpyAsync(d_x, E->dev.X[ctx->cur], bytes, hipMemcpyDeviceToDevice, s));
@@ -650,7 +756,10 @@ pf_status pf_simulate(pf_ctx *ctx, int32_t ens, uint64_t seed, int32_t T, float 
                       float *d_y, void *stream) {
   Ens *E = get_ens(ctx, ens);
   if (!E || !d_x_true || !d_y || T < 1) return fail(PF_ERR_INVALID_ARG, "bad simulate arguments");
-  PF_HIP(pfk::launch_vec_simulate(E->dev, seed, T, d_x_true, d_y, (hipStream_t)stream));
+  if (E->grid)
+    PF_HIP(pfk::launch_grid_simulate(E->dev, seed, T, d_x_true, d_y, (hipStream_t)stream));
+  else
+    PF_HIP(pfk::launch_vec_simulate(E->dev, seed, T, d_x_true, d_y, (hipStream_t)stream));
   return PF_OK;
 }
 

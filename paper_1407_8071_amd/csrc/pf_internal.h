@@ -82,6 +82,29 @@ hipError_t set_filter_wg_lds_limit();
 hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                             const FusedEns *d_ens, int t, int parity, int pending, const float *y,
                             int resample_only, hipStream_t s);
+// resampling of each job's filter from its log-weights; offspring counts to
+// d_counts[ensemble] (an array of per-ensemble device pointers)
+hipError_t launch_resample_wg(int BD, const WgJob *d_jobs, int n_jobs, int max_n,
+                              const FusedEns *d_ens, int t, int32_t *const *d_counts,
+                              hipStream_t s);
+hipError_t launch_offspring_counts(const EnsDev &e, int32_t *cnt, hipStream_t s);
+
+// ---- grid model (FH-N): particles [M][N][2][J][J] ---------------------------
+int grid_resident_blocks(const ModelDev &md);
+hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s);
+hipError_t launch_grid_steps(const EnsDev &e, int t, const float *Xin, const int32_t *anc,
+                             float *Xout, float *lw, const float *y, int blocks, hipStream_t s);
+hipError_t launch_grid_stream_step(const EnsDev &e, int n, const float *Xin, const int32_t *anc,
+                                   float *Xout, float *lw, const float *y, int blocks,
+                                   hipStream_t s);
+hipError_t launch_grid_loglik(const EnsDev &e, const float *X, const float *y, hipStream_t s);
+hipError_t launch_grid_gather(const EnsDev &e, const float *Xin, float *Xout, hipStream_t s);
+int grid_est_chunks(int N);
+hipError_t launch_grid_estimate(const EnsDev &e, const float *Xb, const int32_t *cnt,
+                                double *part, hipStream_t s);
+hipError_t launch_grid_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,
+                                hipStream_t s);
+
 // cross-filter averages of many ensembles at once (one workgroup each)
 hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, hipStream_t s);
 
