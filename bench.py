@@ -28,19 +28,32 @@ sys.path.insert(0, ROOT)
 import pf_inputs  # noqa: E402
 
 # ---------------------------------------------------------------------------
-# Roofline constants (MI355X: 256 CUs x 64 lanes x 2.4 GHz).
-VALU_SLOTS_PER_S = 256 * 64 * 2.4e9   # full-rate VALU lane-operations per second
+# Roofline constants of one MI355X (256 CUs, 2.4 GHz).
+#   HBM3E peak 8 TB/s.
+#   VALU: a full-rate 32-bit instruction (FP32 FMA/add/mul, bit ops) issues
+#   for 128 lanes per CU per clock, i.e. 7.86e13 lane-ops/s, which is the
+#   published 157.3 TFLOP/s FP32 at 2 FLOP per FMA.  Work is counted in
+#   full-rate issue slots and reported in FMA-equivalent FLOP (2 per slot);
+#   half-rate instructions (32x32-bit integer multiply, v_mad_u64_u32, FP64
+#   FMA, int->float conversion) take 2 slots, transcendentals (log2, sqrt,
+#   sin, cos, exp) take 4 -- the rates measured on the device.
 HBM_PEAK_GBS = 8000.0
+VALU_SLOTS_PER_S = 256 * 128 * 2.4e9
+FLOP_PER_SLOT = 2.0
 
-# Algorithmic VALU work of one Lorenz 63 particle-step, in full-rate lane-op
-# slots (a quarter-rate instruction -- 32-bit integer multiply, transcendental
-# -- occupies four):
-#   Philox4x32-10, 3 calls per 4 steps: 10 rounds x (2 wide products x 4
-#     + 2 three-input XORs) = 100 per call                        -> 75.0
-#   Box-Muller, 1.5 pairs per step: 2 x 3 for the uniforms, log2, sqrt,
-#     sin, cos (4 each), 3 multiplies                              -> 37.5
-#   drift (8) and Euler update (6 FMAs)                            -> 14.0
-L63_SLOTS_PER_PARTICLE_STEP = 126.5
+# Algorithmic VALU slots of one Philox4x32-10 call (10 rounds x (2 wide
+# products x 2 + 4 XORs)) and of one Box-Muller pair (2 uniforms x 5, log2,
+# sqrt, sin, cos x 4, 3 multiplies).
+PHILOX_SLOTS = 80.0
+BOXMULLER_SLOTS = 29.0
+# Lorenz 63 particle-step: 3 Philox calls per 4 steps, 1.5 Box-Muller pairs,
+# drift (7) and the Euler update (2 FMAs per component).
+L63_SLOTS_PER_PARTICLE_STEP = 0.75 * PHILOX_SLOTS + 1.5 * BOXMULLER_SLOTS + 7 + 6
+# FH-N node-step: one Philox call per 2 nodes, one Box-Muller pair, the
+# 4-neighbour Laplacian (7), reaction and recovery drifts (8), 2 x 2 FMAs.
+FHN_SLOTS_PER_NODE_STEP = 0.5 * PHILOX_SLOTS + BOXMULLER_SLOTS + 7 + 8 + 4
+# FH-N streaming Euler step: every node's v and w read and written once.
+FHN_BYTES_PER_NODE_STEP = 16.0
 
 
 def parse():
@@ -49,7 +62,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="l63_sweep_M256", choices=sorted(pf_inputs.WORKLOADS))
-    ap.add_argument("--path", default="plain", choices=["plain", "fused"])
+    ap.add_argument("--path", default="fused", choices=["plain", "fused"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables it)")
     return ap.parse_args()
@@ -89,6 +102,7 @@ def cpu_baseline(spec, M, N, y_host, target_s):
     wall = time.perf_counter() - t0
     steps = n_filters * intervals * N * spec["S"]
     return {"value": steps / wall, "unit": "particle-steps/s", "cores": n_filters,
+            "wall_s": wall,
             "kind": "oracle",
             "sample": f"{n_filters} filters x N={N} x {intervals} intervals "
                       f"({steps:.3g} particle-steps, FP64, one filter per core)"}
@@ -105,8 +119,7 @@ def main():
 
     factory, M, N, T_cfg = pf_inputs.WORKLOADS[a.workload]
     spec = factory()
-    if spec["kind"] != "lorenz63":
-        raise SystemExit("this bench times the Lorenz workloads")
+    grid = spec["kind"] == "fhn"
     torch.cuda.set_device(0)
     f = pf.ParticleFilter([spec], [(0, M, N, 1)], fused=(a.path == "fused"))
     T = a.warmup + a.steps
@@ -131,20 +144,34 @@ def main():
     ms = e0.elapsed_time(e1)
     f.set_profiling(False)
     k_ms, k_n = f.read_profile()
+    f.sync()
     est = f.estimate()[0].cpu().numpy()
     assert np.all(np.isfinite(est)), "non-finite estimate"
 
     S = spec["S"]
+    nodes = spec["J"] ** 2 if grid else 1
     psteps = M * N * S * a.steps
     ms_per_step = ms / a.steps
     value = psteps / (ms / 1e3)
     k_avg_s = (k_ms / max(k_n, 1)) / 1e3
-    slots = L63_SLOTS_PER_PARTICLE_STEP * M * N * S
-    achieved = slots / k_avg_s
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12,
-                "unit": "TOP/s", "frac": achieved / VALU_SLOTS_PER_S, "traffic": None,
-                "kernel": "k_vec_propagate" if a.path == "plain" else "k_fused_interval",
-                "kernel_avg_us": k_avg_s * 1e6, "launches": k_n}
+    if grid and a.path == "plain":
+        # dominant kernel: one streaming Euler step of every particle per launch
+        nbytes = FHN_BYTES_PER_NODE_STEP * M * N * nodes
+        achieved = nbytes / k_avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "k_grid_stream_step", "algorithmic_bytes_per_launch": nbytes}
+    else:
+        # dominant kernel: S Euler steps of every particle per launch, VALU-bound
+        per = FHN_SLOTS_PER_NODE_STEP * nodes if grid else L63_SLOTS_PER_PARTICLE_STEP
+        slots = per * M * N * S
+        achieved = slots * FLOP_PER_SLOT / k_avg_s / 1e12
+        peak = VALU_SLOTS_PER_S * FLOP_PER_SLOT / 1e12
+        kname = ("k_grid_steps" if grid else "k_filter_wg") if a.path == "fused" else "k_vec_propagate"
+        roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": None, "kernel": kname,
+                    "algorithmic_slots_per_launch": slots}
+    roofline.update({"kernel_avg_us": k_avg_s * 1e6, "launches": k_n})
     cpu = None
     if a.cpu_seconds > 0:
         cpu = cpu_baseline(spec, M, N, y.double().cpu().numpy(), a.cpu_seconds)
@@ -153,8 +180,8 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (GPU-simulated truth and observations)",
-        "config": {"workload": a.workload, "model": "lorenz63", "M": M, "N": N, "S": S,
-                   "path": a.path, "wall_s": wall},
+        "config": {"workload": a.workload, "model": spec["kind"], "M": M, "N": N, "S": S,
+                   "nodes_per_particle": nodes, "path": a.path, "wall_s": wall},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -242,78 +242,152 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, in
   }
 }
 
-// Resampling of one filter per workgroup from its log-weights alone (models
-// whose particles are too large to keep in a workgroup): normalisation, the
-// LDS CDF, the sorted uniforms, the ancestors, their offspring counts n_i
-// (for the post-resampling estimate sum_i n_i xbar_i / N), and log G.
-template <int BD>
+// Resampling of one filter per workgroup from its log-weights: normalisation,
+// the LDS CDF, the sorted uniforms, the ancestors, their offspring counts n_i
+// and log G.  Thread t owns the contiguous elements [t*P, (t+1)*P) (P =
+// ceil(N/BD) <= RS_MAX_P, and 1 below 1024 threads) for every quantity: its log-weights, weights and
+// (vector models) xbar stay in registers, the CDF and the uniforms each take
+// one sequential scan per thread plus one block scan.  Grid model (D = 0):
+// the counts go to HBM for the state-wide estimator.  Vector models (D = 1,
+// 3): the workgroup also forms the post-resampling estimate
+// sum_i n_i xbar_i / N and the weighted estimate sum_i w_i xbar_i / W.
+constexpr int RS_MAX_P = 8;
+
+template <int BD, int D>
 __global__ void __launch_bounds__(BD)
 k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, int t,
-              int32_t *const *__restrict__ counts) {
+              int32_t *const *__restrict__ counts, int xb_parity) {
   extern __shared__ double lds[];
   constexpr int NW = BD / 64;
-  double *shd = lds;
-  float *shf = (float *)(lds + NW);
-  double *C = lds + 2 * NW;
+  constexpr int DD = D > 0 ? D : 1;
+  // elements per thread the registers hold: workgroups below 1024 threads
+  // serve filters with N <= BD
+  constexpr int PM = BD >= 1024 ? RS_MAX_P : 1;
+  double *shd = lds;                 // 8 * NW doubles: multi-value reductions
+  float *shf = (float *)(lds + 8 * NW);
+  double *C = lds + 9 * NW;          // [N] CDF
   const WgJob job = jobs[blockIdx.x];
   const FusedEns &E = ens[job.ens];
   const int m = job.filter, N = E.N, tid = threadIdx.x;
-  int *cnt = (int *)(C + N);  // [N] offspring counts
+  int *cnt = (int *)(C + N);         // [N] offspring counts
+  const int P = (N + BD - 1) / BD;
+  const int k0 = min(N, tid * P), k1 = min(N, k0 + P);
   const float *lwg = E.lw + (size_t)m * N;
+  const float *Xb = (xb_parity ? E.X1 : E.X0) + (size_t)m * DD * N;
+  // 1. this thread's log-weights (and xbar), the filter maximum
+  float lw[PM];
+  float xb[PM][DD];
   float lmax = -INFINITY;
-  for (int i = tid; i < N; i += BD) {
-    float lw = lwg[i];
-    lw = (lw == lw) ? lw : -INFINITY;
-    lmax = fmaxf(lmax, lw);
-    cnt[i] = 0;
+#pragma unroll
+  for (int e = 0; e < PM; ++e) {
+    const int i = k0 + e;
+    lw[e] = -INFINITY;
+    if constexpr (D > 0) {
+      // unused slots take part in sums with weight 0: keep them finite
+#pragma unroll
+      for (int c = 0; c < D; ++c) xb[e][c] = 0.f;
+    }
+    if (i < k1) {
+      const float v = lwg[i];
+      lw[e] = (v == v) ? v : -INFINITY;
+      cnt[i] = 0;
+      if constexpr (D > 0) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) xb[e][c] = Xb[(size_t)c * N + i];
+      }
+    }
+    lmax = fmaxf(lmax, lw[e]);
   }
   const float mxf = block_max(lmax, shf);
   const bool deg = !(mxf > -INFINITY);
   const double mx = (double)mxf;
-  double carry = 0.0, s2 = 0.0;
-  for (int base = 0; base < N; base += BD) {
-    const int i = base + tid;
-    double w = 0.0;
-    if (i < N) {
-      const float lw = lwg[i];
-      w = deg ? 1.0 : exp((double)((lw == lw) ? lw : -INFINITY) - mx);
-      s2 += w * w;
+  // 2. weights, their thread-local inclusive scan, the block scan -> CDF
+  double w[PM], run = 0.0, s2 = 0.0, wx[DD];
+#pragma unroll
+  for (int c = 0; c < DD; ++c) wx[c] = 0.0;
+#pragma unroll
+  for (int e = 0; e < PM; ++e) {
+    w[e] = 0.0;
+    if (k0 + e < k1) w[e] = deg ? 1.0 : exp((double)lw[e] - mx);
+    run += w[e];
+    s2 += w[e] * w[e];
+    if constexpr (D > 0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) wx[c] += w[e] * (double)xb[e][c];
     }
-    double tot;
-    const double ex = block_exscan(w, shd, &tot);
-    if (i < N) C[i] = carry + (ex + w);
-    carry += tot;
   }
-  __syncthreads();
-  const double W = C[N - 1];
-  const double w2 = block_sum(s2, shd);
-  const int KPT = (N + BD - 1) / BD;
-  const int k0 = tid * KPT, k1 = min(N, k0 + KPT);
+  double tot;
+  const double off = block_exscan(run, shd, &tot);
+  {
+    double c = off;
+#pragma unroll
+    for (int e = 0; e < PM; ++e) {
+      c += w[e];
+      if (k0 + e < k1) C[k0 + e] = c;
+    }
+  }
+  // 3. exponential spacings over the same elements -> sorted uniforms
   ExpoWG ex{E.key, (uint32_t)m, (uint32_t)t};
-  double es = 0.0;
-  for (int j = k0; j < k1; ++j) es += ex(j);
+  double eg[PM], es = 0.0;
+#pragma unroll
+  for (int e = 0; e < PM; ++e) {
+    eg[e] = (k0 + e < k1) ? ex(k0 + e) : 0.0;
+    es += eg[e];
+  }
   double SN;
-  const double eoff = block_exscan(es, shd, &SN);
+  const double eoff = block_exscan(es, shd, &SN);  // its barriers publish C
   if (tid == 0) {
     ExpoWG tail{E.key, (uint32_t)m, (uint32_t)t};
-    lds[2 * NW - 1] = tail(N);
+    shd[8 * NW - 1] = tail(N);
   }
   __syncthreads();
-  SN += lds[2 * NW - 1];
-  double run = eoff;
+  SN += shd[8 * NW - 1];
+  const double W = C[N - 1];
+  // 4. ancestors in the LDS CDF and the offspring counts
+  double sacc = eoff;
   int i = 0;
-  for (int k = k0; k < k1; ++k) {
-    run += ex(k);
-    const double v = (run / SN) * W;
-    i = lds_search(C, N, (k == k0) ? 0 : i, v);
-    E.A[(size_t)m * N + k] = i;
-    atomicAdd(cnt + i, 1);
+#pragma unroll
+  for (int e = 0; e < PM; ++e) {
+    const int k = k0 + e;
+    if (k < k1) {
+      sacc += eg[e];
+      const double v = (sacc / SN) * W;
+      i = lds_search(C, N, e == 0 ? 0 : i, v);
+      E.A[(size_t)m * N + k] = i;
+      atomicAdd(cnt + i, 1);
+    }
   }
   __syncthreads();
-  int32_t *cg = counts[job.ens] + (size_t)m * N;
-  for (int j = tid; j < N; j += BD) cg[j] = cnt[j];
+  // 5. post-resampling sums, one fused block reduction, outputs
+  double red[1 + 2 * DD];
+  red[0] = s2;
+  if constexpr (D > 0) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double px = 0.0;
+#pragma unroll
+      for (int e = 0; e < PM; ++e)
+        if (k0 + e < k1) px += (double)cnt[k0 + e] * (double)xb[e][c];
+      red[1 + c] = px;
+      red[1 + D + c] = wx[c];
+    }
+  } else {
+    int32_t *cg = counts[job.ens] + (size_t)m * N;
+    for (int j = tid; j < N; j += BD) cg[j] = cnt[j];
+    red[1] = red[2] = 0.0;
+  }
+  constexpr int NR = 1 + 2 * DD;
+  block_sum_multi<NR>(red, shd);
   if (tid == 0) {
+    if constexpr (D > 0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        E.fmean[(size_t)m * D + c] = red[1 + c] / (double)N;
+        E.fmeanw[(size_t)m * D + c] = red[1 + D + c] / W;
+      }
+    }
     double *f = E.fstat + (size_t)m * FREC;
+    const double w2 = red[0];
     f[0] = mx;
     f[1] = W;
     f[2] = w2;
@@ -335,17 +409,27 @@ k_offspring_counts(int N, const int32_t *__restrict__ A, int32_t *__restrict__ c
 
 }  // namespace
 
-hipError_t launch_resample_wg(int BD, const WgJob *d_jobs, int n_jobs, int max_n,
+hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                               const FusedEns *d_ens, int t, int32_t *const *d_counts,
-                              hipStream_t s) {
-  const size_t lds = sizeof(double) * (2 * (size_t)(BD / 64) + 2) +
+                              int xb_parity, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) * (9 * (size_t)(BD / 64) + 2) +
                      sizeof(double) * (size_t)max_n + sizeof(int) * (size_t)max_n;
-  if (BD == 256)
-    k_resample_wg<256><<<n_jobs, 256, lds, s>>>(d_jobs, d_ens, t, d_counts);
-  else if (BD == 512)
-    k_resample_wg<512><<<n_jobs, 512, lds, s>>>(d_jobs, d_ens, t, d_counts);
-  else
-    k_resample_wg<1024><<<n_jobs, 1024, lds, s>>>(d_jobs, d_ens, t, d_counts);
+#define PF_RS_LAUNCH(B, DD) \
+  k_resample_wg<B, DD><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, t, d_counts, xb_parity)
+#define PF_RS_BD(DD)                 \
+  if (BD == 256) PF_RS_LAUNCH(256, DD); \
+  else if (BD == 512) PF_RS_LAUNCH(512, DD); \
+  else PF_RS_LAUNCH(1024, DD)
+  if (D == 0) {
+    PF_RS_BD(0);
+  } else if (D == 1) {
+    PF_RS_BD(1);
+  } else {
+    PF_RS_BD(3);
+  }
+#undef PF_RS_BD
+#undef PF_RS_LAUNCH
   return hipGetLastError();
 }
 
@@ -396,12 +480,15 @@ hipError_t set_filter_wg_lds_limit() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_filter_wg<1, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_resample_wg<256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_resample_wg<512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_resample_wg<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
+  const void *rs[] = {(const void *)k_resample_wg<256, 0>, (const void *)k_resample_wg<512, 0>,
+                      (const void *)k_resample_wg<1024, 0>, (const void *)k_resample_wg<256, 1>,
+                      (const void *)k_resample_wg<512, 1>, (const void *)k_resample_wg<1024, 1>,
+                      (const void *)k_resample_wg<256, 3>, (const void *)k_resample_wg<512, 3>,
+                      (const void *)k_resample_wg<1024, 3>};
+  for (const void *f : rs) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
   return hipFuncSetAttribute((const void *)k_filter_wg<1, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

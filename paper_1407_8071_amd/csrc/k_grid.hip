@@ -26,6 +26,17 @@ constexpr int GB = 256;  // workgroup size of the element-wise grid kernels
 // The stepping kernels run 64 * ceil(slots / (64 * SPT)) threads with SPT
 // float4 slots each (slots = J*J/4); J <= 64 needs at most 1024 slots.
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+// streaming access: the state of a step is touched once and exceeds every cache
+__device__ __forceinline__ float4 ld_stream(const float4 *p) {
+  const f4v v = __builtin_nontemporal_load((const f4v *)p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_stream(float4 *p, const float4 &a) {
+  f4v v = {a.x, a.y, a.z, a.w};
+  __builtin_nontemporal_store(v, (f4v *)p);
+}
+
 struct Slot4 {
   float4 v, w, cv, cw;  // state of 4 nodes and the compensation terms
 };
@@ -37,12 +48,32 @@ __device__ __forceinline__ void set(float4 &a, int e, float x) {
   if (e == 0) a.x = x; else if (e == 1) a.y = x; else if (e == 2) a.z = x; else a.w = x;
 }
 
+// LDS indices of the up / down / left / right neighbours of the 4 nodes of
+// slot s; a neighbour outside the grid points at the node itself, so its
+// term v_nbr - v is exactly +0 and the sum equals the truncated one.
+struct Nbr4 {
+  int u[4], d[4], l[4], r[4];
+};
+
+__device__ __forceinline__ Nbr4 neighbours(int J, int s) {
+  Nbr4 n;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = 4 * s + e;
+    const int i = k / J, j = k - i * J;
+    n.u[e] = i > 0 ? k - J : k;
+    n.d[e] = i < J - 1 ? k + J : k;
+    n.l[e] = j > 0 ? k - 1 : k;
+    n.r[e] = j < J - 1 ? k + 1 : k;
+  }
+  return n;
+}
+
 // One Euler-Maruyama step of the 4 nodes of slot s (nodes 4s .. 4s+3), reading
 // neighbour v values from the LDS plane vs.  Returns the new state in S.
 __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t purpose,
                                            uint32_t c0, uint32_t c1, uint32_t n, int s,
-                                           const float *vs, Slot4 &S) {
-  const int J = md.J;
+                                           const Nbr4 &nb, const float *vs, Slot4 &S) {
   const uint4 ra = philox(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s), key);
   const uint4 rb = philox(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s + 1), key);
   float za[4], zb[4];
@@ -51,16 +82,18 @@ __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t
   // node 4s+e: pair 2s + e/2; lanes (0,1) for the even node, (2,3) the odd
   const float zv[4] = {za[0], za[2], zb[0], zb[2]};
   const float zw[4] = {za[1], za[3], zb[1], zb[3]};
+  float vu[4], vd[4], vl[4], vr[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int k = 4 * s + e;
-    const int i = k / J, j = k - i * J;
+    vu[e] = vs[nb.u[e]];
+    vd[e] = vs[nb.d[e]];
+    vl[e] = vs[nb.l[e]];
+    vr[e] = vs[nb.r[e]];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
     const float c = get(S.v, e), w = get(S.w, e);
-    float lap = 0.f;
-    if (i > 0) lap += vs[k - J] - c;
-    if (i < J - 1) lap += vs[k + J] - c;
-    if (j > 0) lap += vs[k - 1] - c;
-    if (j < J - 1) lap += vs[k + 1] - c;
+    const float lap = (((vu[e] - c) + (vd[e] - c)) + (vl[e] - c)) + (vr[e] - c);
     const float fv = c * (c - md.p0) * (1.f - c) - w + md.p1 * lap;
     const float fw = md.p2 * (c - md.p3 * w);
     const float iv = fmaf(md.h, fv, md.sq0 * zv[e]) - get(S.cv, e);
@@ -100,9 +133,12 @@ __global__ void __launch_bounds__(1024)
 k_grid_steps(ModelDev md, Key key, int M, int N, int t, const float *__restrict__ Xin,
              const int32_t *__restrict__ anc, float *__restrict__ Xout, float *__restrict__ lw,
              const float *__restrict__ y) {
-  extern __shared__ float vs[];  // [J*J] v plane, then 8 floats of scratch
+  extern __shared__ float vs[];  // [J*J] v plane, then 16 floats of scratch
   const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
   float *shf = vs + nn;
+  Nbr4 nb[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) nb[q] = neighbours(J, min((int)(threadIdx.x + q * blockDim.x), slots - 1));
   for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
     const int m = p / N, i = p - m * N;
     const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
@@ -124,7 +160,8 @@ k_grid_steps(ModelDev md, Key key, int M, int N, int t, const float *__restrict_
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int s = threadIdx.x + q * blockDim.x;
-        if (s < slots) grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), s, vs, S[q]);
+        if (s < slots)
+          grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), s, nb[q], vs, S[q]);
       }
       __syncthreads();
 #pragma unroll
@@ -158,34 +195,52 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
                    const int32_t *__restrict__ anc, float *Xout,
                    float *__restrict__ lw, const float *__restrict__ y) {
   // Xin may equal Xout (in-place step): each workgroup reads its whole
-  // particle before the barrier and writes it after.
+  // particle before the barrier and writes it after.  The next particle of
+  // the workgroup is loaded into registers while the current one computes.
   extern __shared__ float vs[];
   const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
   float *shf = vs + nn;
-  for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
+  Nbr4 nb[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) nb[q] = neighbours(J, min((int)(threadIdx.x + q * blockDim.x), slots - 1));
+  float4 nv[SPT], nw[SPT];
+  auto load = [&](int p) {
     const int m = p / N, i = p - m * N;
     const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
     const float4 *in = (const float4 *)(Xin + ((size_t)m * N + src) * dx);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = threadIdx.x + q * blockDim.x;
+      if (s < slots) {
+        nv[q] = ld_stream(in + s);
+        nw[q] = ld_stream(in + slots + s);
+      }
+    }
+  };
+  if (blockIdx.x < M * N) load(blockIdx.x);
+  for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
+    const int m = p / N, i = p - m * N;
     Slot4 S[SPT];
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int s = threadIdx.x + q * blockDim.x;
       if (s < slots) {
-        S[q].v = in[s];
-        S[q].w = in[slots + s];
+        S[q].v = nv[q];
+        S[q].w = nw[q];
         S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
         *(float4 *)(vs + 4 * s) = S[q].v;
       }
     }
     __syncthreads();
+    if (p + (int)gridDim.x < M * N) load(p + gridDim.x);
     float4 *out = (float4 *)(Xout + ((size_t)m * N + i) * dx);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int s = threadIdx.x + q * blockDim.x;
       if (s < slots) {
-        grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)n, s, vs, S[q]);
-        out[s] = S[q].v;
-        out[slots + s] = S[q].w;
+        grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)n, s, nb[q], vs, S[q]);
+        st_stream(out + s, S[q].v);
+        st_stream(out + slots + s, S[q].w);
       }
     }
     if (lw) {
@@ -248,7 +303,7 @@ k_grid_gather(int N, int dx4, const int32_t *__restrict__ A, const float4 *__res
 // Partial sums over a chunk of particles of one filter, per state element:
 // post-resampling sum_i n_i xbar_i (n_i offspring counts) and weighted
 // sum_i w_i xbar_i, both in FP64.  Grid: (state groups, chunks, M).
-constexpr int EST_CHUNK = 32;
+constexpr int EST_CHUNK = 64;
 __global__ void __launch_bounds__(GB)
 k_grid_estimate_part(int N, int dx4, const float4 *__restrict__ Xb,
                      const int32_t *__restrict__ cnt, const float *__restrict__ lw,
@@ -276,32 +331,36 @@ k_grid_estimate_part(int N, int dx4, const float4 *__restrict__ Xb,
   }
 }
 
-// Filter means from the chunk partials, then the ensemble means (one thread
-// per state element, fixed summation order).
+// Filter means from the chunk partials: one thread per (state element, filter).
 __global__ void __launch_bounds__(GB)
-k_grid_estimate_fold(int M, int N, int dx, int nch, const double *__restrict__ part,
-                     const double *__restrict__ fstat, double *__restrict__ fmean,
-                     double *__restrict__ fmeanw, double *__restrict__ emean) {
+k_grid_filter_fold(int N, int dx, int nch, const double *__restrict__ part,
+                   const double *__restrict__ fstat, double *__restrict__ fmean,
+                   double *__restrict__ fmeanw) {
+  const int c = blockIdx.x * GB + threadIdx.x, m = blockIdx.y;
+  if (c >= dx) return;
+  double a = 0.0, b = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const double *o = part + (((size_t)m * nch + ch) * 2) * (size_t)dx;
+    a += o[c];
+    b += o[(size_t)dx + c];
+  }
+  fmean[(size_t)m * dx + c] = a / (double)N;
+  fmeanw[(size_t)m * dx + c] = b / fstat[(size_t)m * FREC + 1];
+}
+
+// Ensemble means: one thread per state element, filters in a fixed order.
+__global__ void __launch_bounds__(GB)
+k_grid_ensemble_fold(int M, int dx, const double *__restrict__ fmean,
+                     const double *__restrict__ fmeanw, double *__restrict__ emean) {
   const int c = blockIdx.x * GB + threadIdx.x;
   if (c >= dx) return;
-  double ea = 0.0, eb = 0.0;
+  double a = 0.0, b = 0.0;
   for (int m = 0; m < M; ++m) {
-    double a = 0.0, b = 0.0;
-    for (int ch = 0; ch < nch; ++ch) {
-      const double *o = part + (((size_t)m * nch + ch) * 2) * (size_t)dx;
-      a += o[c];
-      b += o[(size_t)dx + c];
-    }
-    const double W = fstat[(size_t)m * FREC + 1];
-    a /= (double)N;
-    b /= W;
-    fmean[(size_t)m * dx + c] = a;
-    fmeanw[(size_t)m * dx + c] = b;
-    ea += a;
-    eb += b;
+    a += fmean[(size_t)m * dx + c];
+    b += fmeanw[(size_t)m * dx + c];
   }
-  emean[c] = ea / (double)M;
-  emean[dx + c] = eb / (double)M;
+  emean[c] = a / (double)M;
+  emean[dx + c] = b / (double)M;
 }
 
 // Truth path on the truth stream: one workgroup, T intervals of S steps.
@@ -310,6 +369,9 @@ __global__ void __launch_bounds__(1024)
 k_grid_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *__restrict__ y) {
   extern __shared__ float vs[];
   const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
+  Nbr4 nb[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) nb[q] = neighbours(J, min((int)(threadIdx.x + q * blockDim.x), slots - 1));
   Slot4 S[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
@@ -337,7 +399,7 @@ k_grid_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int s = threadIdx.x + q * blockDim.x;
-        if (s < slots) grid_euler(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, n, s, vs, S[q]);
+        if (s < slots) grid_euler(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, n, s, nb[q], vs, S[q]);
       }
       __syncthreads();
 #pragma unroll
@@ -449,8 +511,10 @@ hipError_t launch_grid_estimate(const EnsDev &e, const float *Xb, const int32_t 
   const int dx4 = e.md.dx / 4, nch = grid_est_chunks(e.N);
   dim3 g((unsigned)((dx4 + GB - 1) / GB), (unsigned)nch, (unsigned)e.M);
   k_grid_estimate_part<<<g, GB, 0, s>>>(e.N, dx4, (const float4 *)Xb, cnt, e.lw, e.fstat, part);
-  k_grid_estimate_fold<<<(e.md.dx + GB - 1) / GB, GB, 0, s>>>(e.M, e.N, e.md.dx, nch, part,
-                                                               e.fstat, e.fmean, e.fmeanw, e.emean);
+  const dim3 gf((unsigned)((e.md.dx + GB - 1) / GB), (unsigned)e.M);
+  k_grid_filter_fold<<<gf, GB, 0, s>>>(e.N, e.md.dx, nch, part, e.fstat, e.fmean, e.fmeanw);
+  k_grid_ensemble_fold<<<(e.md.dx + GB - 1) / GB, GB, 0, s>>>(e.M, e.md.dx, e.fmean, e.fmeanw,
+                                                               e.emean);
   return hipGetLastError();
 }
 

@@ -122,35 +122,51 @@ k_uniform_tiles(Key key, int N, int T, int t, double *__restrict__ tile, double 
   }
 }
 
-// Per filter: tile offsets of the CDF and of the exponential sums (sequential
-// in tile order), the normaliser, ESS and the log G_t^N update of (eqGtN):
-// log G += mx + log(W / N) - (d_y/2) log(2 pi sigma^2).
-__global__ void k_filter_reduce(int N, int T, double lognorm, const double *__restrict__ tile,
-                                double *__restrict__ coff, double *__restrict__ soff,
-                                double *__restrict__ fstat) {
+// Per filter (one workgroup): tile offsets of the CDF and of the exponential
+// sums by a chunked block scan in tile order, the normaliser, ESS and the
+// log G_t^N update of (eqGtN): log G += mx + log(W / N) - (d_y/2) log(2 pi s^2).
+__global__ void __launch_bounds__(256)
+k_filter_reduce(int N, int T, double lognorm, const double *__restrict__ tile,
+                double *__restrict__ coff, double *__restrict__ soff,
+                double *__restrict__ fstat) {
+  __shared__ double shd[8];
+  __shared__ float shf[8];
   const int m = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double mx = -INFINITY, c = 0.0, s = 0.0, s2 = 0.0;
-  coff[(size_t)m * (T + 1)] = 0.0;
-  soff[(size_t)m * (T + 1)] = 0.0;
-  for (int q = 0; q < T; ++q) {
-    const double *r = tile + ((size_t)m * T + q) * TREC;
-    mx = fmax(mx, r[0]);
-    c += r[1];
-    s += r[3];
-    s2 += r[2];
-    coff[(size_t)m * (T + 1) + q + 1] = c;
-    soff[(size_t)m * (T + 1) + q + 1] = s;
+  const double *rec = tile + (size_t)m * T * TREC;
+  double *co = coff + (size_t)m * (T + 1), *so = soff + (size_t)m * (T + 1);
+  float lm = -INFINITY;
+  for (int q = threadIdx.x; q < T; q += blockDim.x) lm = fmaxf(lm, (float)rec[(size_t)q * TREC]);
+  const double mx = (double)block_max(lm, shf);
+  double cc = 0.0, sc = 0.0, s2 = 0.0;
+  for (int base = 0; base < T; base += blockDim.x) {
+    const int q = base + threadIdx.x;
+    const double c = q < T ? rec[(size_t)q * TREC + 1] : 0.0;
+    const double e = q < T ? rec[(size_t)q * TREC + 3] : 0.0;
+    if (q < T) s2 += rec[(size_t)q * TREC + 2];
+    double ct, et;
+    const double cx = block_exscan(c, shd, &ct);
+    const double ex = block_exscan(e, shd, &et);
+    if (q < T) {
+      co[q] = cc + cx;
+      so[q] = sc + ex;
+    }
+    cc += ct;
+    sc += et;
   }
-  double *f = fstat + (size_t)m * FREC;
-  const bool deg = !(mx > -INFINITY);
-  f[0] = mx;
-  f[1] = c;
-  f[2] = s2;
-  f[3] = deg ? 1.0 : 0.0;
-  f[4] = s;
-  f[5] = deg ? -INFINITY : f[5] + mx + log(c / (double)N) + lognorm;
-  f[6] = c * c / s2;
+  s2 = block_sum(s2, shd);
+  if (threadIdx.x == 0) {
+    co[T] = cc;
+    so[T] = sc;
+    double *f = fstat + (size_t)m * FREC;
+    const bool deg = !(mx > -INFINITY);
+    f[0] = mx;
+    f[1] = cc;
+    f[2] = s2;
+    f[3] = deg ? 1.0 : 0.0;
+    f[4] = sc;
+    f[5] = deg ? -INFINITY : f[5] + mx + log(cc / (double)N) + lognorm;
+    f[6] = cc * cc / s2;
+  }
 }
 
 struct Cdf2 {
@@ -224,21 +240,28 @@ k_ancestors(int N, int T, const double *__restrict__ Cl, const double *__restric
   }
 }
 
-// Per-filter means from the tile partial sums, then the equal-weight
-// ensemble average of Definition 3 (fixed summation order).
-__global__ void k_filter_means(int N, int T, int dx, const double *__restrict__ mpart,
-                               const double *__restrict__ wpart, const double *__restrict__ fstat,
-                               double *__restrict__ fmean, double *__restrict__ fmeanw) {
+// Per-filter means from the tile partial sums (one workgroup per filter,
+// fixed summation order), then the equal-weight ensemble average of
+// Definition 3 in the next kernel.
+__global__ void __launch_bounds__(256)
+k_filter_means(int N, int T, int dx, const double *__restrict__ mpart,
+               const double *__restrict__ wpart, const double *__restrict__ fstat,
+               double *__restrict__ fmean, double *__restrict__ fmeanw) {
+  __shared__ double sh[8];
   const int m = blockIdx.x;
   const double W = fstat[(size_t)m * FREC + 1];
-  for (int c = threadIdx.x; c < dx; c += blockDim.x) {
+  for (int c = 0; c < dx; ++c) {
     double a = 0.0, b = 0.0;
-    for (int q = 0; q < T; ++q) {
+    for (int q = threadIdx.x; q < T; q += blockDim.x) {
       a += mpart[((size_t)m * T + q) * dx + c];
       b += wpart[((size_t)m * T + q) * dx + c];
     }
-    fmean[(size_t)m * dx + c] = a / (double)N;
-    fmeanw[(size_t)m * dx + c] = b / W;
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+      fmean[(size_t)m * dx + c] = a / (double)N;
+      fmeanw[(size_t)m * dx + c] = b / W;
+    }
   }
 }
 
@@ -308,7 +331,7 @@ hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s) {
   k_tile_max<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile);
   k_cdf_tiles<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile, e.Cl);
   k_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, e.tile, e.Sl);
-  k_filter_reduce<<<e.M, 64, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
+  k_filter_reduce<<<e.M, 256, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
   k_ancestors<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
   return hipGetLastError();
 }

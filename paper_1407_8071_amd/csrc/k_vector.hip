@@ -111,6 +111,29 @@ k_vec_propagate(ModelDev md, Key key, int N, int t, const float *__restrict__ Xi
   if (lw) lw[(size_t)m * N + i] = loglik<D>(md, x, y);
 }
 
+// Batched propagation and weighting for the fused path: tile g of the table
+// is (ensemble, filter, first particle) and holds up to 256 particles; every
+// particle is read through the previous ancestors when `pending`.
+template <int D>
+__global__ void __launch_bounds__(VEC_BLOCK)
+k_vec_prop_batched(const int4 *__restrict__ tiles, const FusedEns *__restrict__ ens, int t,
+                   int parity, int pending, const float *__restrict__ y) {
+  const int4 tl = tiles[blockIdx.x];
+  const FusedEns &E = ens[tl.x];
+  const int m = tl.y, i = tl.z + threadIdx.x, N = E.N;
+  if (i >= N) return;
+  const float *Xin = parity ? E.X1 : E.X0;
+  float *Xout = parity ? E.X0 : E.X1;
+  const int src = pending ? min(max(E.A[(size_t)m * N + i], 0), N - 1) : i;
+  float x[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) x[c] = Xin[((size_t)m * D + c) * N + src];
+  em_steps<D>(E.md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * E.md.S, E.md.S, x);
+#pragma unroll
+  for (int c = 0; c < D; ++c) Xout[((size_t)m * D + c) * N + i] = x[c];
+  E.lw[(size_t)m * N + i] = loglik<D>(E.md, x, y + E.yoff);
+}
+
 template <int D>
 __global__ void __launch_bounds__(VEC_BLOCK)
 k_vec_loglik(ModelDev md, int N, const float *__restrict__ X, const float *__restrict__ y,
@@ -233,6 +256,16 @@ hipError_t launch_vec_propagate(const EnsDev &e, int t, const float *Xin, const 
                                                                       Xout, lw, y)),
                 (k_vec_propagate<1><<<vec_grid(e), VEC_BLOCK, 0, s>>>(e.md, e.key, e.N, t, Xin, anc,
                                                                       Xout, lw, y)));
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, const FusedEns *d_ens,
+                                  int t, int parity, int pending, const float *y, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (D == 3)
+    k_vec_prop_batched<3><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, t, parity, pending, y);
+  else
+    k_vec_prop_batched<1><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, t, parity, pending, y);
   return hipGetLastError();
 }
 

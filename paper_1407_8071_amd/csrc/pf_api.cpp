@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -48,7 +49,8 @@ struct Ens {
   pf_ensemble_desc d;
   int dx, dy, T;
   bool grid;
-  bool wg;  // fused path: the filter-per-workgroup kernel handles it
+  bool wg;     // fused path: one filter-per-workgroup kernel does the whole interval
+  bool tiled;  // fused path (vector, N > WG_MAX_N): multi-workgroup resampling kernels
   std::vector<int32_t> obs_idx;
   std::vector<float> prior_mean, prior_sd;
   pfk::EnsDev dev;
@@ -60,13 +62,17 @@ struct Ens {
 
 // One launch of the filter-per-workgroup kernel: every filter of the
 // ensembles of one (state dimension, workgroup size) class.
+// kinds of workgroup-per-filter launches
+enum { CLASS_FILTER_WG = 0, CLASS_RESAMPLE_VEC = 1, CLASS_RESAMPLE_GRID = 2 };
 struct WgClass {
+  int kind;
   int D, BD, max_n;  // D = 0: grid-model resampling class
   std::vector<pfk::WgJob> jobs;
   pfk::WgJob *d_jobs = nullptr;
 };
 
 // Workgroup size of the filter-per-workgroup kernel for N particles.
+// (the per-filter kernels hold one element per thread below 1024 threads)
 int wg_block(int N) { return N <= 256 ? 256 : (N <= 512 ? 512 : 1024); }
 
 // Offsets of every array of one ensemble inside the workspace.
@@ -112,10 +118,22 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid) {
 // Context-wide arrays after the ensembles: the fused ensemble table and the
 // workgroup job lists (at most one job per filter).
 size_t ctx_bytes(const pf_ensemble_desc *ens, int n_ens) {
-  size_t jobs = 0;
-  for (int e = 0; e < n_ens; ++e) jobs += (size_t)ens[e].M;
+  size_t jobs = 0, tiles = 0;
+  for (int e = 0; e < n_ens; ++e) {
+    jobs += (size_t)ens[e].M;
+    tiles += (size_t)ens[e].M * (((size_t)ens[e].N + 255) / 256);
+  }
   return align_up(sizeof(pfk::FusedEns) * (size_t)n_ens) +
-         align_up(sizeof(int32_t *) * (size_t)n_ens) + 9 * align_up(sizeof(pfk::WgJob) * jobs);
+         align_up(sizeof(int32_t *) * (size_t)n_ens) + 15 * align_up(sizeof(pfk::WgJob) * jobs) +
+         2 * align_up(sizeof(int4) * tiles);
+}
+
+// Fused-path strategy of vector ensembles with N <= WG_MAX_N: "split"
+// (batched propagation, then per-filter resampling and estimates) unless
+// PF_VEC_STRATEGY=filter_wg asks for the single filter-per-workgroup kernel.
+bool vec_single_kernel() {
+  const char *v = std::getenv("PF_VEC_STRATEGY");
+  return v && std::strcmp(v, "filter_wg") == 0;
 }
 
 pf_status check_model(const pf_model_desc &m, int idx) {
@@ -197,8 +215,10 @@ struct pf_ctx {
   // fused path
   pfk::FusedEns *d_fens = nullptr;
   std::vector<pfk::FusedEns> fz_host;
-  std::vector<WgClass> classes;       // filter-per-workgroup launches (vector models)
-  std::vector<WgClass> grid_classes;  // per-filter resampling launches (grid model)
+  std::vector<WgClass> classes;       // workgroup-per-filter launches of every kind
+  int4 *d_tiles[2] = {nullptr, nullptr};  // batched propagation tiles, D = 1 and D = 3
+  int n_tiles[2] = {0, 0};
+  std::vector<int4> tiles_host[2];
   int32_t **d_counts = nullptr;       // [n_ens] device pointers to offspring counts
   std::vector<int32_t *> counts_host;
   // event pairs around the dominant kernel while profiling is enabled
@@ -315,48 +335,55 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
 pf_status fused_run(pf_ctx *ctx, const float *d_y, hipStream_t s, bool resample_only) {
   const int parity = resample_only ? 1 - ctx->xbar : ctx->cur;
   const int pending = (!resample_only && ctx->pending) ? 1 : 0;
-  const long ev = resample_only ? -1 : prof_begin(ctx, s);
+  const int out = 1 - parity;  // buffer that holds xbar of this interval
+  // 1. propagation + weighting: the batched vector tiles (profiled: the
+  //    kernel that carries the interval), the single-kernel classes, and the
+  //    grid model's stepping kernel (profiled)
+  if (!resample_only) {
+    const long ev = (ctx->n_tiles[0] + ctx->n_tiles[1]) ? prof_begin(ctx, s) : -1;
+    for (int w = 1; w >= 0; --w)
+      PF_HIP(pfk::launch_vec_prop_batched(w ? 3 : 1, ctx->d_tiles[w], ctx->n_tiles[w], ctx->d_fens,
+                                          ctx->t, parity, pending, d_y, s));
+    prof_end(ctx, ev, s);
+  }
   for (const WgClass &c : ctx->classes)
-    PF_HIP(pfk::launch_filter_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                 ctx->t, parity, pending, d_y, resample_only ? 1 : 0, s));
-  // grid model: the interval's steps with the plane in LDS, then per-filter
-  // resampling from the log-weights, then the one-pass estimator
-  bool any_grid = false;
+    if (c.kind == CLASS_FILTER_WG) {
+      const long ev = resample_only ? -1 : prof_begin(ctx, s);
+      PF_HIP(pfk::launch_filter_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
+                                   ctx->t, parity, pending, d_y, resample_only ? 1 : 0, s));
+      prof_end(ctx, ev, s);
+    }
   size_t yo = 0;
   for (Ens &E : ctx->ens) {
     const float *y = d_y ? d_y + yo : nullptr;
     yo += (size_t)E.dy;
-    if (!E.grid) continue;
-    any_grid = true;
-    if (!resample_only) {
-      pfk::EnsDev &D = E.dev;
-      PF_HIP(pfk::launch_grid_steps(D, ctx->t, D.X[parity], pending ? D.A : nullptr,
-                                    D.X[1 - parity], D.lw, y, E.blocks, s));
-    }
-  }
-  if (any_grid) {
-    for (const WgClass &c : ctx->grid_classes)
-      PF_HIP(pfk::launch_resample_wg(c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                     ctx->t, ctx->d_counts, s));
-    for (Ens &E : ctx->ens)
-      if (E.grid) PF_HIP(pfk::launch_grid_estimate(E.dev, E.dev.X[1 - parity], E.cnt, E.gpart, s));
-  }
-  size_t yoff = 0;
-  for (Ens &E : ctx->ens) {
-    const float *y = d_y ? d_y + yoff : nullptr;
-    yoff += (size_t)E.dy;
-    if (E.wg || E.grid) continue;
+    if (!E.grid || resample_only) continue;
     pfk::EnsDev &D = E.dev;
-    const int out = 1 - parity;
-    if (!resample_only) {
-      const int32_t *anc = pending ? D.A : nullptr;
-      PF_HIP(pfk::launch_vec_propagate(D, ctx->t, D.X[parity], anc, D.X[out], D.lw, y, s));
-    }
-    PF_HIP(pfk::launch_resample(D, ctx->t, s));
-    PF_HIP(pfk::launch_vec_estimate(D, D.X[out], D.X[out], D.A, false, s));
+    const long eg = prof_begin(ctx, s);
+    PF_HIP(pfk::launch_grid_steps(D, ctx->t, D.X[parity], pending ? D.A : nullptr, D.X[out], D.lw,
+                                  y, E.blocks, s));
+    prof_end(ctx, eg, s);
   }
+  // 2. resampling and the filters' estimates
+  for (const WgClass &c : ctx->classes) {
+    if (c.kind == CLASS_RESAMPLE_VEC)
+      PF_HIP(pfk::launch_resample_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
+                                     ctx->t, ctx->d_counts, out, s));
+    else if (c.kind == CLASS_RESAMPLE_GRID)
+      PF_HIP(pfk::launch_resample_wg(0, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
+                                     ctx->t, ctx->d_counts, out, s));
+  }
+  for (Ens &E : ctx->ens) {
+    pfk::EnsDev &D = E.dev;
+    if (E.grid) {
+      PF_HIP(pfk::launch_grid_estimate(D, D.X[out], E.cnt, E.gpart, s));
+    } else if (E.tiled) {
+      PF_HIP(pfk::launch_resample(D, ctx->t, s));
+      PF_HIP(pfk::launch_vec_estimate(D, D.X[out], D.X[out], D.A, false, s));
+    }
+  }
+  // 3. the cross-filter averages
   PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), s));
-  prof_end(ctx, ev, s);
   if (resample_only) {
     ctx->cur = ctx->xbar;
   } else {
@@ -494,7 +521,8 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     F.fmean = D.fmean;
     F.fmeanw = D.fmeanw;
     F.emean = D.emean;
-    E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N;
+    E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N && vec_single_kernel();
+    E.tiled = !E.grid && E.d.N > pfk::WG_MAX_N;
     if (E.grid) {
       E.cnt = (int32_t *)(ws + L.cnt);
       E.gpart = (double *)(ws + L.gpart);
@@ -541,55 +569,63 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     for (int e = 0; e < n_ens; ++e) ctx->fz_host[(size_t)e] = ctx->ens[(size_t)e].fz;
     INIT_TRY(hipMemcpyAsync(ctx->d_fens, ctx->fz_host.data(), sizeof(pfk::FusedEns) * (size_t)n_ens,
                             hipMemcpyHostToDevice, s));
-    // classes by (state dimension, workgroup size); filters of larger N first
-    const int Ds[2] = {3, 1}, BDs[3] = {1024, 512, 256};
-    for (int D : Ds) {
-      for (int BD : BDs) {
-        WgClass c;
-        c.D = D;
-        c.BD = BD;
-        c.max_n = 0;
-        std::vector<std::pair<int, int>> order;  // (N, ensemble)
-        for (int e = 0; e < n_ens; ++e) {
-          const Ens &E = ctx->ens[(size_t)e];
-          if (E.wg && E.dx == D && wg_block(E.d.N) == BD) order.push_back({E.d.N, e});
-        }
-        if (order.empty()) continue;
-        std::stable_sort(order.begin(), order.end(),
-                         [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
-                           return a.first > b.first;
-                         });
-        for (auto &pr : order) {
-          c.max_n = std::max(c.max_n, pr.first);
-          for (int mm = 0; mm < ctx->ens[(size_t)pr.second].d.M; ++mm)
-            c.jobs.push_back(pfk::WgJob{pr.second, mm});
-        }
-        c.d_jobs = (pfk::WgJob *)(ws + o);
-        o += align_up(sizeof(pfk::WgJob) * total_jobs);
-        ctx->classes.push_back(std::move(c));
-      }
-    }
-    // grid-model resampling classes by workgroup size
-    for (int BD : BDs) {
+    // workgroup-per-filter classes by (kind, state dimension, workgroup
+    // size); filters of larger N first
+    const int BDs[3] = {1024, 512, 256};
+    auto add_class = [&](int kind, int D, int BD, auto member) {
       WgClass c;
-      c.D = 0;
+      c.kind = kind;
+      c.D = D;
       c.BD = BD;
       c.max_n = 0;
+      std::vector<std::pair<int, int>> order;  // (N, ensemble)
       for (int e = 0; e < n_ens; ++e) {
         const Ens &E = ctx->ens[(size_t)e];
-        if (!E.grid || wg_block(E.d.N) != BD || E.d.N > pfk::WG_MAX_N) continue;
-        c.max_n = std::max(c.max_n, E.d.N);
-        for (int mm = 0; mm < E.d.M; ++mm) c.jobs.push_back(pfk::WgJob{e, mm});
+        if (member(E) && wg_block(E.d.N) == BD) order.push_back({E.d.N, e});
       }
-      if (c.jobs.empty()) continue;
+      if (order.empty()) return;
+      std::stable_sort(order.begin(), order.end(),
+                       [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+                         return a.first > b.first;
+                       });
+      for (auto &pr : order) {
+        c.max_n = std::max(c.max_n, pr.first);
+        for (int mm = 0; mm < ctx->ens[(size_t)pr.second].d.M; ++mm)
+          c.jobs.push_back(pfk::WgJob{pr.second, mm});
+      }
       c.d_jobs = (pfk::WgJob *)(ws + o);
       o += align_up(sizeof(pfk::WgJob) * total_jobs);
-      ctx->grid_classes.push_back(std::move(c));
+      ctx->classes.push_back(std::move(c));
+    };
+    for (int D : {3, 1}) {
+      for (int BD : BDs) {
+        add_class(CLASS_FILTER_WG, D, BD, [D](const Ens &E) { return E.wg && E.dx == D; });
+        add_class(CLASS_RESAMPLE_VEC, D, BD, [D](const Ens &E) {
+          return !E.grid && !E.wg && !E.tiled && E.dx == D;
+        });
+      }
+    }
+    for (int BD : BDs)
+      add_class(CLASS_RESAMPLE_GRID, 0, BD,
+                [](const Ens &E) { return E.grid && E.d.N <= pfk::WG_MAX_N; });
+    // batched propagation tiles of the vector ensembles not run by the
+    // single filter-per-workgroup kernel
+    for (int e = 0; e < n_ens; ++e) {
+      const Ens &E = ctx->ens[(size_t)e];
+      if (E.grid || E.wg) continue;
+      const int which = E.dx == 3 ? 1 : 0;
+      for (int mm = 0; mm < E.d.M; ++mm)
+        for (int i0 = 0; i0 < E.d.N; i0 += 256) ctx->tiles_host[which].push_back(int4{e, mm, i0, 0});
+    }
+    for (int w = 0; w < 2; ++w) {
+      ctx->n_tiles[w] = (int)ctx->tiles_host[w].size();
+      ctx->d_tiles[w] = (int4 *)(ws + o);
+      o += align_up(sizeof(int4) * ctx->tiles_host[w].size());
+      if (ctx->n_tiles[w] > 0)
+        INIT_TRY(hipMemcpyAsync(ctx->d_tiles[w], ctx->tiles_host[w].data(),
+                                sizeof(int4) * ctx->tiles_host[w].size(), hipMemcpyHostToDevice, s));
     }
     for (WgClass &c : ctx->classes)
-      INIT_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
-                              hipMemcpyHostToDevice, s));
-    for (WgClass &c : ctx->grid_classes)
       INIT_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
                               hipMemcpyHostToDevice, s));
     INIT_TRY(pfk::set_filter_wg_lds_limit());

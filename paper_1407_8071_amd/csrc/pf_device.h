@@ -133,6 +133,27 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   for (int i = 0; i < nw; ++i) r += sh[i];
   return r;
 }
+// Workgroup sums of R values at once (fixed order); every thread gets them.
+// sh holds R * (blockDim.x / 64) doubles.
+template <int R>
+__device__ __forceinline__ void block_sum_multi(double v[R], double *sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = wave_sum(v[r]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) sh[r * nw + wid] = v[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double a = 0.0;
+    for (int i = 0; i < nw; ++i) a += sh[r * nw + i];
+    v[r] = a;
+  }
+}
+
 // Workgroup exclusive scan; returns the exclusive prefix of this thread and
 // the total in *tot.
 __device__ __forceinline__ double block_exscan(double v, double *sh, double *tot) {

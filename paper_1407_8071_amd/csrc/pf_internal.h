@@ -84,9 +84,12 @@ hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int 
                             int resample_only, hipStream_t s);
 // resampling of each job's filter from its log-weights; offspring counts to
 // d_counts[ensemble] (an array of per-ensemble device pointers)
-hipError_t launch_resample_wg(int BD, const WgJob *d_jobs, int n_jobs, int max_n,
+hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                               const FusedEns *d_ens, int t, int32_t *const *d_counts,
-                              hipStream_t s);
+                              int xb_parity, hipStream_t s);
+// batched propagation + weighting of vector-model tiles {ens, filter, i0, -}
+hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, const FusedEns *d_ens,
+                                  int t, int parity, int pending, const float *y, hipStream_t s);
 hipError_t launch_offspring_counts(const EnsDev &e, int32_t *cnt, hipStream_t s);
 
 // ---- grid model (FH-N): particles [M][N][2][J][J] ---------------------------
