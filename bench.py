@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="l63_sweep_M256", choices=sorted(pf_inputs.WORKLOADS))
-    ap.add_argument("--path", default="fused", choices=["plain", "fused"])
+    ap.add_argument("--path", default="fused", choices=["plain", "fused", "graph"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables it)")
     return ap.parse_args()
@@ -121,13 +121,17 @@ def main():
     spec = factory()
     grid = spec["kind"] == "fhn"
     torch.cuda.set_device(0)
-    f = pf.ParticleFilter([spec], [(0, M, N, 1)], fused=(a.path == "fused"))
+    f = pf.ParticleFilter([spec], [(0, M, N, 1)], fused=(a.path == "fused"),
+                          graph=(a.path == "graph"))
     T = a.warmup + a.steps
     _, y = f.simulate(0, 1, T)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    graph = a.path == "graph"
+    if graph:
+        f.set_observations(y)
     for t in range(a.warmup):
-        f.step(y[t])
+        f.step(None if graph else y[t])
     torch.cuda.synchronize()
     f.read_profile()
     f.set_profiling(True)
@@ -137,7 +141,7 @@ def main():
     t0 = time.perf_counter()
     e0.record(stream)
     for t in range(a.warmup, T):
-        f.step(y[t])
+        f.step(None if graph else y[t])
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -167,7 +171,8 @@ def main():
         slots = per * M * N * S
         achieved = slots * FLOP_PER_SLOT / k_avg_s / 1e12
         peak = VALU_SLOTS_PER_S * FLOP_PER_SLOT / 1e12
-        kname = ("k_grid_steps" if grid else "k_filter_wg") if a.path == "fused" else "k_vec_propagate"
+        kname = {"fused": "k_grid_steps" if grid else "k_vec_prop_batched",
+                 "graph": "interval graph", "plain": "k_vec_propagate"}[a.path]
         roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak, "traffic": None, "kernel": kname,
                     "algorithmic_slots_per_launch": slots}

@@ -89,7 +89,12 @@ typedef struct pf_ensemble_desc {
 
 /* Context options (pf_init `options`). */
 #define PF_OPT_PLAIN 0u /* one kernel per method step (reference path)     */
-#define PF_OPT_FUSED 1u /* one persistent fused kernel per interval        */
+#define PF_OPT_FUSED 1u /* fused interval: batched propagation with the gather
+                           and weighting fused in, per-filter resampling and
+                           estimators, no materialised post-resampling state   */
+#define PF_OPT_GRAPH 2u /* with PF_OPT_FUSED: once observations are staged
+                           (pf_set_observations), each interval after the first
+                           is one launch of a captured hipGraph               */
 
 /* Stages for pf_run_stages (bit mask). */
 #define PF_STAGE_PROPAGATE 1u /* Algorithm 1 step 2(a): draw from tau_t        */
@@ -121,8 +126,16 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models,
    S Euler-Maruyama steps per particle, Gaussian log-likelihood weighting,
    normalisation with the update of log G_t^N (eqGtN), multinomial resampling
    and the estimators.  d_y: float32, the observations y_t of every ensemble
-   concatenated in ensemble order (obs_dim of its model each).  Advances t. */
+   concatenated in ensemble order (obs_dim of its model each), or NULL to use
+   the record staged by pf_set_observations.  Advances t. */
 pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream);
+
+/* Stage the observation record on the device: d_y_all float32 [T][sum_e
+   obs_dim(e)] (interval t uses row t-1), caller-owned and kept alive while the
+   context uses it.  pf_step(ctx, NULL, stream) then reads y_t from it; with
+   PF_OPT_GRAPH the interval index is kept on the device too, so the captured
+   interval replays unchanged.  Stepping past T is an error. */
+pf_status pf_set_observations(pf_ctx *ctx, const float *d_y_all, int32_t T);
 
 /* Run selected stages (PF_STAGE_*) of the current interval without advancing
    t: the per-step hooks of the parity tests.  They run on the plain kernels,

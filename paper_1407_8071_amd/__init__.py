@@ -20,7 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpf.so")
 
 KIND = {"ou1d": 0, "lorenz63": 1, "fhn": 2}
-OPT_PLAIN, OPT_FUSED = 0, 1
+OPT_PLAIN, OPT_FUSED, OPT_GRAPH = 0, 1, 2
 STAGE_PROPAGATE, STAGE_WEIGHT, STAGE_RESAMPLE, STAGE_GATHER, STAGE_ESTIMATE = 1, 2, 4, 8, 16
 STAGE_ALL = 31
 
@@ -76,6 +76,7 @@ def lib():
         "pf_get_ancestors": [_VP, i32, _VP, _VP],
         "pf_get_filter_stats": [_VP, i32, _VP, _VP],
         "pf_set_interval": [_VP, i32],
+        "pf_set_observations": [_VP, _VP, i32],
         "pf_get_interval": [_VP, C.POINTER(i32)],
         "pf_simulate": [_VP, i32, u64, i32, _VP, _VP, _VP],
         "pf_philox_stream": [u64, u32, u32, u32, i64, _VP, _VP, _VP],
@@ -140,7 +141,7 @@ class ParticleFilter:
     the persistent fused interval kernel instead of one kernel per step.
     """
 
-    def __init__(self, models, ensembles, fused: bool = False, stream=None):
+    def __init__(self, models, ensembles, fused: bool = False, graph: bool = False, stream=None):
         import torch
         self.models = [m if isinstance(m, PFModel) else PFModel(m) for m in models]
         self.ens = [tuple(e) for e in ensembles]
@@ -148,7 +149,7 @@ class ParticleFilter:
         self._md = (_ModelDesc * nm)(*[m.desc for m in self.models])
         self._ed = (_EnsDesc * ne)(*[_EnsDesc(int(mi), int(M), int(N), 0, int(seed))
                                      for (mi, M, N, seed) in self.ens])
-        self.options = OPT_FUSED if fused else OPT_PLAIN
+        self.options = (OPT_FUSED if fused or graph else OPT_PLAIN) | (OPT_GRAPH if graph else 0)
         nbytes = C.c_size_t()
         _check(lib().pf_workspace_bytes(self._md, nm, self._ed, ne, self.options,
                                         C.byref(nbytes)))
@@ -182,8 +183,16 @@ class ParticleFilter:
         return (M, m.dx, N)
 
     # ---- the filter --------------------------------------------------------
-    def step(self, y, stream=None):
+    def step(self, y=None, stream=None):
+        """One interval; y=None reads the record staged by set_observations."""
         _check(lib().pf_step(self._ctx, _ptr(y), _stream(stream)))
+
+    def set_observations(self, y_all):
+        """Stage y_all [T, sum obs_dim] (float32, on the device; kept referenced)."""
+        import torch
+        assert y_all.dtype == torch.float32 and y_all.is_cuda and y_all.is_contiguous()
+        self._y_all = y_all
+        _check(lib().pf_set_observations(self._ctx, _ptr(y_all), int(y_all.shape[0])))
 
     def run_stages(self, stages: int, y=None, stream=None):
         _check(lib().pf_run_stages(self._ctx, stages, _ptr(y), _stream(stream)))

@@ -127,8 +127,10 @@ __device__ __forceinline__ int lds_search(const double *C, int N, int lo, double
 
 template <int D, int BD>
 __global__ void __launch_bounds__(BD)
-k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, int t, int parity,
-            int pending, const float *__restrict__ y, int resample_only) {
+k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, IvArg iv,
+            int parity, int pending, int resample_only) {
+  const int t = iv_t(iv);
+  const float *y = iv_y(iv, t);
   extern __shared__ double lds[];
   constexpr int NW = BD / 64;
   double *shd = lds;                       // NW doubles of reduction scratch
@@ -255,8 +257,9 @@ constexpr int RS_MAX_P = 8;
 
 template <int BD, int D>
 __global__ void __launch_bounds__(BD)
-k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, int t,
+k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, IvArg iv,
               int32_t *const *__restrict__ counts, int xb_parity) {
+  const int t = iv_t(iv);
   extern __shared__ double lds[];
   constexpr int NW = BD / 64;
   constexpr int DD = D > 0 ? D : 1;
@@ -410,13 +413,13 @@ k_offspring_counts(int N, const int32_t *__restrict__ A, int32_t *__restrict__ c
 }  // namespace
 
 hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
-                              const FusedEns *d_ens, int t, int32_t *const *d_counts,
+                              const FusedEns *d_ens, IvArg iv, int32_t *const *d_counts,
                               int xb_parity, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
   const size_t lds = sizeof(double) * (9 * (size_t)(BD / 64) + 2) +
                      sizeof(double) * (size_t)max_n + sizeof(int) * (size_t)max_n;
 #define PF_RS_LAUNCH(B, DD) \
-  k_resample_wg<B, DD><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, t, d_counts, xb_parity)
+  k_resample_wg<B, DD><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, d_counts, xb_parity)
 #define PF_RS_BD(DD)                 \
   if (BD == 256) PF_RS_LAUNCH(256, DD); \
   else if (BD == 512) PF_RS_LAUNCH(512, DD); \
@@ -448,11 +451,11 @@ size_t filter_wg_lds(int N, int BD) {
 }
 
 hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
-                            const FusedEns *d_ens, int t, int parity, int pending, const float *y,
+                            const FusedEns *d_ens, IvArg iv, int parity, int pending,
                             int resample_only, hipStream_t s) {
   const size_t lds = filter_wg_lds(max_n, BD);
 #define PF_WG_LAUNCH(DD, B)                                                                  \
-  k_filter_wg<DD, B><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, t, parity, pending, y, resample_only)
+  k_filter_wg<DD, B><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, parity, pending, resample_only)
   if (D == 3) {
     if (BD == 256) PF_WG_LAUNCH(3, 256);
     else if (BD == 512) PF_WG_LAUNCH(3, 512);

@@ -130,9 +130,11 @@ __device__ __forceinline__ float grid_loglik(const ModelDev &md, const float *vs
 // Interval of S steps per particle with the v plane resident in LDS.
 template <int SPT>
 __global__ void __launch_bounds__(1024)
-k_grid_steps(ModelDev md, Key key, int M, int N, int t, const float *__restrict__ Xin,
-             const int32_t *__restrict__ anc, float *__restrict__ Xout, float *__restrict__ lw,
-             const float *__restrict__ y) {
+k_grid_steps(ModelDev md, Key key, int M, int N, IvArg iv, int yoff, const float *__restrict__ Xin,
+             const int32_t *__restrict__ anc, float *__restrict__ Xout, float *__restrict__ lw) {
+  const int t = iv_t(iv);
+  const float *yb = iv_y(iv, t);
+  const float *y = yb ? yb + yoff : nullptr;
   extern __shared__ float vs[];  // [J*J] v plane, then 16 floats of scratch
   const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
   float *shf = vs + nn;
@@ -461,18 +463,18 @@ hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_grid_steps(const EnsDev &e, int t, const float *Xin, const int32_t *anc,
-                             float *Xout, float *lw, const float *y, int blocks, hipStream_t s) {
+hipError_t launch_grid_steps(const EnsDev &e, IvArg iv, int yoff, const float *Xin,
+                             const int32_t *anc, float *Xout, float *lw, int blocks, hipStream_t s) {
   int spt, threads;
   grid_shape(e.md, &spt, &threads);
   const int g = std::min(blocks, e.M * e.N);
   const size_t lds = grid_lds(e.md);
   if (spt == 1)
-    k_grid_steps<1><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, t, Xin, anc, Xout, lw, y);
+    k_grid_steps<1><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, iv, yoff, Xin, anc, Xout, lw);
   else if (spt == 2)
-    k_grid_steps<2><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, t, Xin, anc, Xout, lw, y);
+    k_grid_steps<2><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, iv, yoff, Xin, anc, Xout, lw);
   else
-    k_grid_steps<4><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, t, Xin, anc, Xout, lw, y);
+    k_grid_steps<4><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, iv, yoff, Xin, anc, Xout, lw);
   return hipGetLastError();
 }
 

@@ -82,7 +82,9 @@ k_cdf_tiles(int N, int T, const float *__restrict__ lw, double *__restrict__ til
 // Tile-local inclusive sums of the exponential variates E_j; the last tile
 // also adds E_N to its total.
 __global__ void __launch_bounds__(TILE_THREADS)
-k_uniform_tiles(Key key, int N, int T, int t, double *__restrict__ tile, double *__restrict__ Sl) {
+k_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, double *__restrict__ tile,
+                double *__restrict__ Sl) {
+  const int t = tp ? *tp : t_arg;
   __shared__ double shd[TILE_THREADS / 64];
   const int m = blockIdx.y, q = blockIdx.x;
   const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
@@ -299,8 +301,10 @@ k_ensemble_mean(int M, int dx, const double *__restrict__ fmean, const double *_
 
 // One workgroup per ensemble: equal-weight average of its filters' means.
 __global__ void __launch_bounds__(256)
-k_ensemble_means_batched(const FusedEns *__restrict__ ens) {
+k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
   __shared__ double sh[4];
+  // every earlier kernel of the interval has read the counter
+  if (t_inc && blockIdx.x == 0 && threadIdx.x == 0) *t_inc += 1;
   const FusedEns &E = ens[blockIdx.x];
   if (E.md.kind == 2) return;  // grid model: folded by its own estimator
   const int dx = E.md.dx;
@@ -321,16 +325,26 @@ k_ensemble_means_batched(const FusedEns *__restrict__ ens) {
 
 }  // namespace
 
-hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, hipStream_t s) {
-  if (n_ens > 0) k_ensemble_means_batched<<<n_ens, 256, 0, s>>>(d_ens);
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int *t_inc, hipStream_t s) {
+  if (n_ens > 0) k_ensemble_means_batched<<<n_ens, 256, 0, s>>>(d_ens, t_inc);
   return hipGetLastError();
 }
 
-hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s) {
+namespace {
+__global__ void k_set_i32(int *p, int v) { *p = v; }
+}  // namespace
+
+// a one-thread kernel instead of a memset, so that it is safe in graphs
+hipError_t launch_set_i32(int *p, int v, hipStream_t s) {
+  k_set_i32<<<1, 1, 0, s>>>(p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s, const int *tp) {
   const dim3 g((unsigned)e.T, (unsigned)e.M);
   k_tile_max<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile);
   k_cdf_tiles<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile, e.Cl);
-  k_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, e.tile, e.Sl);
+  k_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.tile, e.Sl);
   k_filter_reduce<<<e.M, 256, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
   k_ancestors<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
   return hipGetLastError();

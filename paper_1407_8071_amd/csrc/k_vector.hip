@@ -116,8 +116,10 @@ k_vec_propagate(ModelDev md, Key key, int N, int t, const float *__restrict__ Xi
 // particle is read through the previous ancestors when `pending`.
 template <int D>
 __global__ void __launch_bounds__(VEC_BLOCK)
-k_vec_prop_batched(const int4 *__restrict__ tiles, const FusedEns *__restrict__ ens, int t,
-                   int parity, int pending, const float *__restrict__ y) {
+k_vec_prop_batched(const int4 *__restrict__ tiles, const FusedEns *__restrict__ ens, IvArg iv,
+                   int parity, int pending) {
+  const int t = iv_t(iv);
+  const float *y = iv_y(iv, t);
   const int4 tl = tiles[blockIdx.x];
   const FusedEns &E = ens[tl.x];
   const int m = tl.y, i = tl.z + threadIdx.x, N = E.N;
@@ -260,12 +262,12 @@ hipError_t launch_vec_propagate(const EnsDev &e, int t, const float *Xin, const 
 }
 
 hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, const FusedEns *d_ens,
-                                  int t, int parity, int pending, const float *y, hipStream_t s) {
+                                  IvArg iv, int parity, int pending, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   if (D == 3)
-    k_vec_prop_batched<3><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, t, parity, pending, y);
+    k_vec_prop_batched<3><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
   else
-    k_vec_prop_batched<1><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, t, parity, pending, y);
+    k_vec_prop_batched<1><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
   return hipGetLastError();
 }
 

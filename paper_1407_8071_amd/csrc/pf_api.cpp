@@ -125,7 +125,7 @@ size_t ctx_bytes(const pf_ensemble_desc *ens, int n_ens) {
   }
   return align_up(sizeof(pfk::FusedEns) * (size_t)n_ens) +
          align_up(sizeof(int32_t *) * (size_t)n_ens) + 15 * align_up(sizeof(pfk::WgJob) * jobs) +
-         2 * align_up(sizeof(int4) * tiles);
+         2 * align_up(sizeof(int4) * tiles) + align_up(sizeof(int));
 }
 
 // Fused-path strategy of vector ensembles with N <= WG_MAX_N: "split"
@@ -216,6 +216,15 @@ struct pf_ctx {
   pfk::FusedEns *d_fens = nullptr;
   std::vector<pfk::FusedEns> fz_host;
   std::vector<WgClass> classes;       // workgroup-per-filter launches of every kind
+  // staged observations and graph replay
+  const float *y_all = nullptr;
+  int y_T = 0, dy_total = 0;
+  int *d_t = nullptr;  // device interval counter (graph replays)
+  bool d_t_valid = false;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int4 *d_tiles[2] = {nullptr, nullptr};  // batched propagation tiles, D = 1 and D = 3
   int n_tiles[2] = {0, 0};
   std::vector<int4> tiles_host[2];
@@ -228,6 +237,11 @@ struct pf_ctx {
   ~pf_ctx() {
     for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
+    for (int p = 0; p < 2; ++p) {
+      if (gexec[p]) (void)hipGraphExecDestroy(gexec[p]);
+      if (graph[p]) (void)hipGraphDestroy(graph[p]);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -332,64 +346,109 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
 // kernels for ensembles whose filters exceed one workgroup, and the
 // cross-filter averages.  The particles stay where propagation wrote them
 // and the next interval gathers them through the ancestors.
-pf_status fused_run(pf_ctx *ctx, const float *d_y, hipStream_t s, bool resample_only) {
-  const int parity = resample_only ? 1 - ctx->xbar : ctx->cur;
-  const int pending = (!resample_only && ctx->pending) ? 1 : 0;
+pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool resample_only,
+                       hipStream_t s) {
   const int out = 1 - parity;  // buffer that holds xbar of this interval
+  const bool prof = !ctx->capturing && !resample_only;
   // 1. propagation + weighting: the batched vector tiles (profiled: the
   //    kernel that carries the interval), the single-kernel classes, and the
   //    grid model's stepping kernel (profiled)
   if (!resample_only) {
-    const long ev = (ctx->n_tiles[0] + ctx->n_tiles[1]) ? prof_begin(ctx, s) : -1;
+    const long ev = (prof && ctx->n_tiles[0] + ctx->n_tiles[1]) ? prof_begin(ctx, s) : -1;
     for (int w = 1; w >= 0; --w)
       PF_HIP(pfk::launch_vec_prop_batched(w ? 3 : 1, ctx->d_tiles[w], ctx->n_tiles[w], ctx->d_fens,
-                                          ctx->t, parity, pending, d_y, s));
+                                          iv, parity, pending, s));
     prof_end(ctx, ev, s);
   }
   for (const WgClass &c : ctx->classes)
     if (c.kind == CLASS_FILTER_WG) {
-      const long ev = resample_only ? -1 : prof_begin(ctx, s);
+      const long ev = prof ? prof_begin(ctx, s) : -1;
       PF_HIP(pfk::launch_filter_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                   ctx->t, parity, pending, d_y, resample_only ? 1 : 0, s));
+                                   iv, parity, pending, resample_only ? 1 : 0, s));
       prof_end(ctx, ev, s);
     }
-  size_t yo = 0;
+  int yo = 0;
   for (Ens &E : ctx->ens) {
-    const float *y = d_y ? d_y + yo : nullptr;
-    yo += (size_t)E.dy;
+    const int yoff = yo;
+    yo += E.dy;
     if (!E.grid || resample_only) continue;
     pfk::EnsDev &D = E.dev;
-    const long eg = prof_begin(ctx, s);
-    PF_HIP(pfk::launch_grid_steps(D, ctx->t, D.X[parity], pending ? D.A : nullptr, D.X[out], D.lw,
-                                  y, E.blocks, s));
+    const long eg = prof ? prof_begin(ctx, s) : -1;
+    PF_HIP(pfk::launch_grid_steps(D, iv, yoff, D.X[parity], pending ? D.A : nullptr, D.X[out],
+                                  D.lw, E.blocks, s));
     prof_end(ctx, eg, s);
   }
   // 2. resampling and the filters' estimates
   for (const WgClass &c : ctx->classes) {
     if (c.kind == CLASS_RESAMPLE_VEC)
       PF_HIP(pfk::launch_resample_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                     ctx->t, ctx->d_counts, out, s));
+                                     iv, ctx->d_counts, out, s));
     else if (c.kind == CLASS_RESAMPLE_GRID)
       PF_HIP(pfk::launch_resample_wg(0, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                     ctx->t, ctx->d_counts, out, s));
+                                     iv, ctx->d_counts, out, s));
   }
   for (Ens &E : ctx->ens) {
     pfk::EnsDev &D = E.dev;
     if (E.grid) {
       PF_HIP(pfk::launch_grid_estimate(D, D.X[out], E.cnt, E.gpart, s));
     } else if (E.tiled) {
-      PF_HIP(pfk::launch_resample(D, ctx->t, s));
+      PF_HIP(pfk::launch_resample(D, iv.t, s, iv.tp));
       PF_HIP(pfk::launch_vec_estimate(D, D.X[out], D.X[out], D.A, false, s));
     }
   }
-  // 3. the cross-filter averages
-  PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), s));
+  // 3. the cross-filter averages (and, in a graph, the interval counter)
+  PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(),
+                                    iv.tp ? const_cast<int *>(iv.tp) : nullptr, s));
+  return PF_OK;
+}
+
+// The fused interval launched directly.
+pf_status fused_run(pf_ctx *ctx, const float *d_y, hipStream_t s, bool resample_only) {
+  const int parity = resample_only ? 1 - ctx->xbar : ctx->cur;
+  const int pending = (!resample_only && ctx->pending) ? 1 : 0;
+  const pfk::IvArg iv{ctx->t, nullptr, d_y, 0};
+  PF_TRY(fused_launch(ctx, iv, parity, pending, resample_only, s));
   if (resample_only) {
     ctx->cur = ctx->xbar;
   } else {
     ctx->cur = 1 - ctx->cur;
     ctx->xbar = ctx->cur;
   }
+  ctx->pending = true;
+  ctx->last_stream = s;
+  return PF_OK;
+}
+
+// The fused interval replayed from a captured graph (one graph per buffer
+// parity; interval index and observations come from device memory).
+pf_status graph_step(pf_ctx *ctx, hipStream_t s) {
+  const int parity = ctx->cur;
+  if (!ctx->gexec[parity]) {
+    if (!ctx->cap_stream) PF_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const pfk::IvArg iv{0, ctx->d_t, ctx->y_all, ctx->dy_total};
+    PF_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    const pf_status st = fused_launch(ctx, iv, parity, 1, false, ctx->cap_stream);
+    ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (st != PF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    PF_HIP(ce);
+    ctx->graph[parity] = g;
+    PF_HIP(hipGraphInstantiate(&ctx->gexec[parity], g, nullptr, nullptr, 0));
+  }
+  if (!ctx->d_t_valid) {
+    PF_HIP(pfk::launch_set_i32(ctx->d_t, ctx->t, s));
+    ctx->d_t_valid = true;
+  }
+  const long ev = prof_begin(ctx, s);
+  PF_HIP(hipGraphLaunch(ctx->gexec[parity], s));
+  prof_end(ctx, ev, s);
+  ctx->cur = 1 - ctx->cur;
+  ctx->xbar = ctx->cur;
   ctx->pending = true;
   ctx->last_stream = s;
   return PF_OK;
@@ -418,7 +477,7 @@ pf_status pf_workspace_bytes(const pf_model_desc *h_models, int32_t n_models,
                              const pf_ensemble_desc *h_ens, int32_t n_ens, uint32_t options,
                              size_t *out_bytes) {
   if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
-  if (options > PF_OPT_FUSED) return fail(PF_ERR_INVALID_ARG, "unknown options");
+  if (options > (PF_OPT_FUSED | PF_OPT_GRAPH)) return fail(PF_ERR_INVALID_ARG, "unknown options");
   PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
   if (options & PF_OPT_FUSED) PF_TRY(check_fused(h_models, h_ens, n_ens));
   *out_bytes = total_bytes(h_models, h_ens, n_ens);
@@ -430,7 +489,9 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
                   void *stream, pf_ctx **out_ctx) {
   if (!out_ctx) return fail(PF_ERR_INVALID_ARG, "out_ctx is NULL");
   *out_ctx = nullptr;
-  if (options > PF_OPT_FUSED) return fail(PF_ERR_INVALID_ARG, "unknown options");
+  if (options > (PF_OPT_FUSED | PF_OPT_GRAPH)) return fail(PF_ERR_INVALID_ARG, "unknown options");
+  if ((options & PF_OPT_GRAPH) && !(options & PF_OPT_FUSED))
+    return fail(PF_ERR_INVALID_ARG, "PF_OPT_GRAPH needs PF_OPT_FUSED");
   PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
   if (options & PF_OPT_FUSED) PF_TRY(check_fused(h_models, h_ens, n_ens));
   const size_t need = total_bytes(h_models, h_ens, n_ens);
@@ -617,6 +678,8 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
       for (int mm = 0; mm < E.d.M; ++mm)
         for (int i0 = 0; i0 < E.d.N; i0 += 256) ctx->tiles_host[which].push_back(int4{e, mm, i0, 0});
     }
+    ctx->d_t = (int *)(ws + o);
+    o += align_up(sizeof(int));
     for (int w = 0; w < 2; ++w) {
       ctx->n_tiles[w] = (int)ctx->tiles_host[w].size();
       ctx->d_tiles[w] = (int4 *)(ws + o);
@@ -649,12 +712,25 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
 
 pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream) {
   if (!ctx) return fail(PF_ERR_STATE, "pf_step before pf_init");
-  if (!d_y) return fail(PF_ERR_INVALID_ARG, "d_y is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (!d_y) {
+    if (!ctx->y_all) return fail(PF_ERR_INVALID_ARG, "d_y is NULL and no observations are staged");
+    if (ctx->t > ctx->y_T)
+      return fail(PF_ERR_INVALID_ARG, "interval %d beyond the %d staged observations", ctx->t,
+                  ctx->y_T);
+    if ((ctx->options & PF_OPT_GRAPH) && ctx->pending) {
+      PF_TRY(graph_step(ctx, s));
+      ctx->t += 1;
+      return PF_OK;
+    }
+    d_y = ctx->y_all + (size_t)(ctx->t - 1) * ctx->dy_total;
+  }
   if (ctx->options & PF_OPT_FUSED)
-    PF_TRY(fused_run(ctx, d_y, (hipStream_t)stream, false));
+    PF_TRY(fused_run(ctx, d_y, s, false));
   else
-    PF_TRY(stage_run(ctx, PF_STAGE_ALL, d_y, (hipStream_t)stream));
+    PF_TRY(stage_run(ctx, PF_STAGE_ALL, d_y, s));
   ctx->t += 1;
+  ctx->d_t_valid = false;
   return PF_OK;
 }
 
@@ -779,6 +855,27 @@ pf_status pf_set_interval(pf_ctx *ctx, int32_t t) {
   if (!ctx) return fail(PF_ERR_STATE, "no context");
   if (t < 1) return fail(PF_ERR_INVALID_ARG, "interval index starts at 1");
   ctx->t = t;
+  ctx->d_t_valid = false;
+  return PF_OK;
+}
+
+pf_status pf_set_observations(pf_ctx *ctx, const float *d_y_all, int32_t T) {
+  if (!ctx) return fail(PF_ERR_STATE, "no context");
+  if (!d_y_all || T < 1) return fail(PF_ERR_INVALID_ARG, "bad observation record");
+  int dy = 0;
+  for (const Ens &E : ctx->ens) dy += E.dy;
+  if (ctx->y_all != d_y_all || ctx->dy_total != dy) {
+    // captured graphs hold the old pointer
+    for (int p = 0; p < 2; ++p) {
+      if (ctx->gexec[p]) (void)hipGraphExecDestroy(ctx->gexec[p]);
+      if (ctx->graph[p]) (void)hipGraphDestroy(ctx->graph[p]);
+      ctx->gexec[p] = nullptr;
+      ctx->graph[p] = nullptr;
+    }
+  }
+  ctx->y_all = d_y_all;
+  ctx->y_T = T;
+  ctx->dy_total = dy;
   return PF_OK;
 }
 

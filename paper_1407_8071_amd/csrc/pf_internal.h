@@ -43,6 +43,20 @@ struct EnsDev {
   double *emean;    // [2][dx]: ensemble post-resampling and weighted means
 };
 
+// Interval index and observations of a fused launch: by value for a direct
+// launch, or read from device memory (tp, and y + (t-1) * ystride) so that a
+// captured graph replays every interval unchanged.
+struct IvArg {
+  int t;
+  const int *tp;
+  const float *y;
+  int ystride;
+};
+__device__ __forceinline__ int iv_t(const IvArg &a) { return a.tp ? *a.tp : a.t; }
+__device__ __forceinline__ const float *iv_y(const IvArg &a, int t) {
+  return a.y ? a.y + (a.ystride ? (size_t)(t - 1) * a.ystride : 0) : nullptr;
+}
+
 // Device-side record of one ensemble for the fused interval kernels.
 struct FusedEns {
   ModelDev md;
@@ -69,7 +83,7 @@ hipError_t launch_vec_simulate(const EnsDev &e, uint64_t seed, int T, float *xtr
                                hipStream_t s);
 
 // ---- resampling (any model): lw [M][N] -> A [M][N] ------------------------
-hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s);
+hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s, const int *tp = nullptr);
 hipError_t launch_combine_means(const EnsDev &e, bool ensemble_mean, hipStream_t s);
 
 // ---- filter-per-workgroup interval kernel (vector models, N <= WG_MAX_N) ---
@@ -80,23 +94,23 @@ struct WgJob {
 size_t filter_wg_lds(int N, int BD);
 hipError_t set_filter_wg_lds_limit();
 hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
-                            const FusedEns *d_ens, int t, int parity, int pending, const float *y,
+                            const FusedEns *d_ens, IvArg iv, int parity, int pending,
                             int resample_only, hipStream_t s);
 // resampling of each job's filter from its log-weights; offspring counts to
 // d_counts[ensemble] (an array of per-ensemble device pointers)
 hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
-                              const FusedEns *d_ens, int t, int32_t *const *d_counts,
+                              const FusedEns *d_ens, IvArg iv, int32_t *const *d_counts,
                               int xb_parity, hipStream_t s);
 // batched propagation + weighting of vector-model tiles {ens, filter, i0, -}
 hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, const FusedEns *d_ens,
-                                  int t, int parity, int pending, const float *y, hipStream_t s);
+                                  IvArg iv, int parity, int pending, hipStream_t s);
 hipError_t launch_offspring_counts(const EnsDev &e, int32_t *cnt, hipStream_t s);
 
 // ---- grid model (FH-N): particles [M][N][2][J][J] ---------------------------
 int grid_resident_blocks(const ModelDev &md);
 hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s);
-hipError_t launch_grid_steps(const EnsDev &e, int t, const float *Xin, const int32_t *anc,
-                             float *Xout, float *lw, const float *y, int blocks, hipStream_t s);
+hipError_t launch_grid_steps(const EnsDev &e, IvArg iv, int yoff, const float *Xin,
+                             const int32_t *anc, float *Xout, float *lw, int blocks, hipStream_t s);
 hipError_t launch_grid_stream_step(const EnsDev &e, int n, const float *Xin, const int32_t *anc,
                                    float *Xout, float *lw, const float *y, int blocks,
                                    hipStream_t s);
@@ -109,7 +123,9 @@ hipError_t launch_grid_simulate(const EnsDev &e, uint64_t seed, int T, float *xt
                                 hipStream_t s);
 
 // cross-filter averages of many ensembles at once (one workgroup each)
-hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, hipStream_t s);
+// t_inc (optional): device interval counter advanced once the means are done
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int *t_inc, hipStream_t s);
+hipError_t launch_set_i32(int *p, int v, hipStream_t s);
 
 // ---- random-number hook ----------------------------------------------------
 hipError_t launch_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
