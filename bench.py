@@ -55,6 +55,15 @@ FHN_SLOTS_PER_NODE_STEP = 0.5 * PHILOX_SLOTS + BOXMULLER_SLOTS + 7 + 8 + 4
 # FH-N streaming Euler step: every node's v and w read and written once.
 FHN_BYTES_PER_NODE_STEP = 16.0
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB; fetch scaled x2, write x1 by the same counters on a 1 GiB
+# copy), recorded in profiles/hbm_counters_fhn_stream_step_and_lorenz_propagation.md
+# for the kernels as they are now.
+MEASURED_TRAFFIC_BYTES = {
+    ("lorenz63", "fused", 256, 4096): (15616 + 16384) * 1024,
+    ("fhn", "plain", 64, 512): (409671 + 409607) * 1024,
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -176,6 +185,7 @@ def main():
         roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak, "traffic": None, "kernel": kname,
                     "algorithmic_slots_per_launch": slots}
+    roofline["traffic"] = MEASURED_TRAFFIC_BYTES.get((spec["kind"], a.path, M, N))
     roofline.update({"kernel_avg_us": k_avg_s * 1e6, "launches": k_n})
     cpu = None
     if a.cpu_seconds > 0:
