@@ -90,6 +90,22 @@ def lib():
             "or_run_ensemble": (None, [M, C.c_uint64, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D, _D]),
             "or_simulate": (None, [M, C.c_uint64, C.c_int, _D, _D]),
             "or_kalman_ou": (C.c_double, [M, C.c_int, _D, _D, _D]),
+            "or_mlp_nparams": (C.c_int, [C.c_int, C.c_int]),
+            "or_bf16": (C.c_double, [C.c_double]),
+            "or_mlp_forward": (None, [C.c_int, C.c_int, _D, _D, _D, _D, _D, C.c_int]),
+            "or_mlp_backward": (None, [C.c_int, C.c_int, _D, _D, _D, _D]),
+            "or_mlp_loss_grad": (C.c_double, [C.c_int, C.c_int, _D, C.c_int, _D, _D, _D]),
+            "or_nearest_obs": (None, [M, _I32]),
+            "or_fhn_features": (None, [M, _D, _D, _I32, C.c_int, C.c_int, _D]),
+            "or_ou_features": (None, [M, _D, _D, C.c_int, _D]),
+            "or_propagate_learned": (None, [M, _D, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D,
+                                            _D, _D, C.c_int]),
+            "or_filter_interval_learned": (C.c_int, [M, _D, C.c_uint64, C.c_uint32, C.c_int,
+                                                     C.c_int, _D, _D, _D, _D, _I32, _D, _D, _D,
+                                                     C.c_int]),
+            "or_run_ensemble_learned": (None, [M, _D, C.c_uint64, C.c_int, C.c_int, C.c_int, _D,
+                                               _D, _D, _D, _D, C.c_int]),
+            "or_ou_optimal_u": (C.c_double, [M, C.c_double, C.c_double, C.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -340,3 +356,137 @@ def kalman_ou(m: Model, y):
     var_ = np.zeros(y.size)
     ll = lib().or_kalman_ou(m.ref, y.size, _d(y), _d(mean_), _d(var_))
     return mean_, var_, ll
+
+
+# ---------------------------------------------------------------------------
+# Learned proposal (drift correction u_theta with exact increment-ratio
+# weights; see pf_oracle.h).  Parameter vectors are float64 in the order
+# W1[64][in], b1[64], W2[64][64], b2[64], W3[out][64], b3[out].
+
+HIDDEN = 64
+
+
+def mlp_nparams(in_dim, out_dim) -> int:
+    return int(lib().or_mlp_nparams(in_dim, out_dim))
+
+
+def mlp_unpack(p, in_dim, out_dim):
+    """Views (W1, b1, W2, b2, W3, b3) of a flat parameter vector."""
+    H = HIDDEN
+    sizes = [H * in_dim, H, H * H, H, out_dim * H, out_dim]
+    shapes = [(H, in_dim), (H,), (H, H), (H,), (out_dim, H), (out_dim,)]
+    out, o = [], 0
+    for n, sh in zip(sizes, shapes):
+        out.append(p[o:o + n].reshape(sh))
+        o += n
+    return out
+
+
+def bf16(x) -> np.ndarray:
+    f = lib().or_bf16
+    return np.vectorize(lambda v: f(float(v)), otypes=[np.float64])(np.asarray(x, np.float64))
+
+
+def mlp_forward(p, x, out_dim, bf16_mode=False):
+    """u_theta at the rows of x[B, in_dim]: returns (out[B, out_dim], h1, h2)."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    B, in_dim = x.shape
+    out = np.zeros((B, out_dim))
+    h1 = np.zeros((B, HIDDEN))
+    h2 = np.zeros((B, HIDDEN))
+    for r in range(B):
+        lib().or_mlp_forward(in_dim, out_dim, _d(p), _d(x[r]), _d(h1[r]), _d(h2[r]), _d(out[r]),
+                             int(bf16_mode))
+    return out, h1, h2
+
+
+def mlp_backward(p, x, dout) -> np.ndarray:
+    """d(dout . u_theta(x)) / dp for one row."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    dout = np.ascontiguousarray(dout, dtype=np.float64)
+    g = np.zeros_like(p)
+    lib().or_mlp_backward(x.size, dout.size, _d(p), _d(x), _d(dout), _d(g))
+    return g
+
+
+def mlp_loss_grad(p, X, T):
+    """Mean squared regression loss over the rows of X onto T and its gradient."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    g = np.zeros_like(p)
+    loss = lib().or_mlp_loss_grad(X.shape[1], T.shape[1], _d(p), X.shape[0], _d(X), _d(T), _d(g))
+    return loss, g
+
+
+def nearest_obs(m: Model) -> np.ndarray:
+    out = np.zeros(m.J * m.J, np.int32)
+    lib().or_nearest_obs(m.ref, _i32(out))
+    return out
+
+
+def fhn_features(m: Model, x, y, k, nodes=None) -> np.ndarray:
+    """features[len(nodes), 20] of one FH-N state at step k of the interval."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    near = nearest_obs(m)
+    nodes = range(m.J * m.J) if nodes is None else nodes
+    out = np.zeros((len(nodes), 20))
+    for r, n in enumerate(nodes):
+        lib().or_fhn_features(m.ref, _d(x), _d(y), _i32(near), k, int(n), _d(out[r]))
+    return out
+
+
+def ou_features(m: Model, x, y, k) -> np.ndarray:
+    f = np.zeros(3)
+    lib().or_ou_features(m.ref, _d(np.array([x], np.float64)), _d(np.array([y], np.float64)), k,
+                         _d(f))
+    return f
+
+
+def propagate_learned(m: Model, p, seed, filt, t, X, y, bf16_mode=True):
+    """Interval t under the learned proposal: returns (X', dlw[N])."""
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    dlw = np.zeros(X.shape[0])
+    lib().or_propagate_learned(m.ref, _d(p), C.c_uint64(seed), filt, X.shape[0], t, _d(X),
+                               _d(y), _d(dlw), int(bf16_mode))
+    return X, dlw
+
+
+def filter_interval_learned(m: Model, p, seed, filt, t, X, y, logZ=0.0, bf16_mode=True):
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    N = X.shape[0]
+    lz = C.c_double(logZ)
+    lw = np.zeros(N)
+    A = np.zeros(N, np.int32)
+    mp = np.zeros(m.dx)
+    mw = np.zeros(m.dx)
+    ess = C.c_double()
+    deg = lib().or_filter_interval_learned(m.ref, _d(p), C.c_uint64(seed), filt, N, t, _d(X),
+                                           _d(y), C.byref(lz), _d(lw), _i32(A), _d(mp), _d(mw),
+                                           C.byref(ess), int(bf16_mode))
+    return dict(X=X, lw=lw, A=A, mean_post=mp, mean_w=mw, logZ=lz.value, ess=ess.value,
+                degenerate=bool(deg))
+
+
+def run_ensemble_learned(m: Model, p, seed, M, N, y, bf16_mode=True):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    T = y.shape[0]
+    est = np.zeros((T, m.dx))
+    est_w = np.zeros((T, m.dx))
+    logZ = np.zeros(M)
+    ess = np.zeros(T)
+    lib().or_run_ensemble_learned(m.ref, _d(p), C.c_uint64(seed), M, N, T, _d(y), _d(est),
+                                  _d(est_w), _d(logZ), _d(ess), int(bf16_mode))
+    return est, est_w, logZ, ess
+
+
+def ou_optimal_u(m: Model, x, y, k) -> float:
+    return float(lib().or_ou_optimal_u(m.ref, float(x), float(y), int(k)))

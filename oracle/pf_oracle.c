@@ -500,3 +500,285 @@ double or_kalman_ou(const or_model *m, int T, const double *y, double *mean,
   }
   return ll;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Learned proposal.  The paper's convergence results hold for any importance
+   function whose weights are the exact density ratio (its closing remarks on
+   tailored importance functions, Sec. 6); the proposal here is a drift
+   correction u added to each Euler-Maruyama increment, and the weight of a
+   particle gains, per step and component, the log ratio of the model density
+   N(x + h f, sd^2 h) to the proposal density N(x + h f + h u, sd^2 h) at the
+   sampled increment.  With x' - x - h f = h u + sd sqrt(h) z the squares
+   expand to -(sqrt(h)/sd) u z - (h/(2 sd^2)) u^2. */
+
+int or_mlp_nparams(int in_dim, int out_dim) {
+  const int H = OR_MLP_HIDDEN;
+  return H * in_dim + H + H * H + H + out_dim * H + out_dim;
+}
+
+/* Round to the nearest bfloat16 (8 significant bits), ties to even. */
+double or_bf16(double x) {
+  if (x == 0.0 || isnan(x) || isinf(x)) return x;
+  int e;
+  double m = frexp(x, &e);           /* x = m 2^e, 0.5 <= |m| < 1 */
+  double r = nearbyint(ldexp(m, 8)); /* 8 significant bits, ties to even */
+  return ldexp(r, e - 8);
+}
+
+static double relu(double a) { return a > 0.0 ? a : 0.0; }
+
+void or_mlp_forward(int in_dim, int out_dim, const double *p, const double *x,
+                    double *h1_out, double *h2_out, double *out, int bf16) {
+  const int H = OR_MLP_HIDDEN;
+  const double *W1 = p, *b1 = W1 + H * in_dim, *W2 = b1 + H, *b2 = W2 + H * H;
+  const double *W3 = b2 + H, *b3 = W3 + out_dim * H;
+  double h1[OR_MLP_HIDDEN], h2[OR_MLP_HIDDEN];
+#define Q(v) (bf16 ? or_bf16(v) : (v))
+  for (int j = 0; j < H; ++j) {
+    double a = Q(b1[j]);
+    for (int i = 0; i < in_dim; ++i) a += Q(W1[j * in_dim + i]) * Q(x[i]);
+    h1[j] = Q(relu(a));
+  }
+  for (int j = 0; j < H; ++j) {
+    double a = Q(b2[j]);
+    for (int i = 0; i < H; ++i) a += Q(W2[j * H + i]) * h1[i];
+    h2[j] = Q(relu(a));
+  }
+  for (int c = 0; c < out_dim; ++c) {
+    double a = Q(b3[c]);
+    for (int i = 0; i < H; ++i) a += Q(W3[c * H + i]) * h2[i];
+    out[c] = a;
+  }
+#undef Q
+  if (h1_out) memcpy(h1_out, h1, sizeof h1);
+  if (h2_out) memcpy(h2_out, h2, sizeof h2);
+}
+
+/* Reverse-mode derivative of dout . out, layer by layer (chain rule; the
+   ReLU derivative is taken as 0 at 0). */
+void or_mlp_backward(int in_dim, int out_dim, const double *p, const double *x,
+                     const double *dout, double *grad) {
+  const int H = OR_MLP_HIDDEN;
+  const double *W2 = p + H * in_dim + H, *W3 = W2 + H * H + H;
+  double *gW1 = grad, *gb1 = gW1 + H * in_dim, *gW2 = gb1 + H, *gb2 = gW2 + H * H;
+  double *gW3 = gb2 + H, *gb3 = gW3 + out_dim * H;
+  double h1[OR_MLP_HIDDEN], h2[OR_MLP_HIDDEN], o[16];
+  double d2[OR_MLP_HIDDEN], d1[OR_MLP_HIDDEN];
+  or_mlp_forward(in_dim, out_dim, p, x, h1, h2, o, 0);
+  for (int c = 0; c < out_dim; ++c) {
+    gb3[c] += dout[c];
+    for (int i = 0; i < H; ++i) gW3[c * H + i] += dout[c] * h2[i];
+  }
+  for (int i = 0; i < H; ++i) {
+    double a = 0.0;
+    for (int c = 0; c < out_dim; ++c) a += W3[c * H + i] * dout[c];
+    d2[i] = h2[i] > 0.0 ? a : 0.0;
+  }
+  for (int j = 0; j < H; ++j) {
+    gb2[j] += d2[j];
+    for (int i = 0; i < H; ++i) gW2[j * H + i] += d2[j] * h1[i];
+  }
+  for (int i = 0; i < H; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < H; ++j) a += W2[j * H + i] * d2[j];
+    d1[i] = h1[i] > 0.0 ? a : 0.0;
+  }
+  for (int j = 0; j < H; ++j) {
+    gb1[j] += d1[j];
+    for (int i = 0; i < in_dim; ++i) gW1[j * in_dim + i] += d1[j] * x[i];
+  }
+}
+
+double or_mlp_loss_grad(int in_dim, int out_dim, const double *p, int B,
+                        const double *X, const double *T, double *grad) {
+  double o[16], d[16], loss = 0.0;
+  if (grad) memset(grad, 0, sizeof(double) * (size_t)or_mlp_nparams(in_dim, out_dim));
+  for (int r = 0; r < B; ++r) {
+    const double *x = X + (size_t)r * in_dim, *t = T + (size_t)r * out_dim;
+    or_mlp_forward(in_dim, out_dim, p, x, NULL, NULL, o, 0);
+    for (int c = 0; c < out_dim; ++c) {
+      double e = o[c] - t[c];
+      loss += e * e;
+      d[c] = 2.0 * e / (double)B;
+    }
+    if (grad) or_mlp_backward(in_dim, out_dim, p, x, d, grad);
+  }
+  return loss / (double)B;
+}
+
+void or_nearest_obs(const or_model *m, int *map) {
+  int J = m->J;
+  for (int n = 0; n < J * J; ++n) {
+    int i = n / J, j = n % J, best = 0;
+    long bd = -1;
+    for (int o = 0; o < m->dy; ++o) {
+      int r = m->obs_idx[o] / J, c = m->obs_idx[o] % J;
+      long d = (long)(i - r) * (i - r) + (long)(j - c) * (j - c);
+      if (bd < 0 || d < bd) { bd = d; best = o; }
+    }
+    map[n] = best;
+  }
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* 20 features of node `node` at step k of the interval: v patch (9), w patch
+   (9), residual of the nearest observation, tau = (S - k)/S. */
+void or_fhn_features(const or_model *m, const double *x, const double *y,
+                     const int *nearest, int k, int node, double *feat) {
+  int J = m->J, nn = J * J, i = node / J, j = node % J;
+  for (int di = -1; di <= 1; ++di)
+    for (int dj = -1; dj <= 1; ++dj) {
+      int q = clampi(i + di, 0, J - 1) * J + clampi(j + dj, 0, J - 1);
+      feat[(di + 1) * 3 + (dj + 1)] = x[q];
+      feat[9 + (di + 1) * 3 + (dj + 1)] = x[nn + q];
+    }
+  int o = nearest[node];
+  feat[18] = y[o] - x[m->obs_idx[o]];
+  feat[19] = (double)(m->S - k) / (double)m->S;
+}
+
+void or_ou_features(const or_model *m, const double *x, const double *y, int k,
+                    double *feat) {
+  feat[0] = x[0];
+  feat[1] = y[0] - x[0];
+  feat[2] = (double)(m->S - k) / (double)m->S;
+}
+
+/* u_theta for every state component at step k (FHN: out 0 drives v, out 1
+   drives w of the node; OU: the single output). */
+static void learned_drift(const or_model *m, const double *p, const double *x,
+                          const double *y, const int *nearest, int k, double *u,
+                          int bf16) {
+  double feat[20], o[2];
+  if (m->kind == OR_FHN) {
+    int nn = m->J * m->J;
+    for (int n = 0; n < nn; ++n) {
+      or_fhn_features(m, x, y, nearest, k, n, feat);
+      or_mlp_forward(20, 2, p, feat, NULL, NULL, o, bf16);
+      u[n] = o[0];
+      u[nn + n] = o[1];
+    }
+  } else {
+    or_ou_features(m, x, y, k, feat);
+    or_mlp_forward(3, 1, p, feat, NULL, NULL, o, bf16);
+    u[0] = o[0];
+  }
+}
+
+void or_propagate_learned(const or_model *m, const double *p, uint64_t seed,
+                          uint32_t filter, int N, int t, double *X,
+                          const double *y, double *dlw, int bf16) {
+  uint32_t key[2];
+  or_key(seed, key);
+  int d = m->dx;
+  int half = (m->kind == OR_FHN) ? m->J * m->J : d;
+  double *z = (double *)malloc(sizeof(double) * (size_t)d);
+  double *f = (double *)malloc(sizeof(double) * (size_t)d);
+  double *u = (double *)malloc(sizeof(double) * (size_t)d);
+  int *nearest = NULL;
+  if (m->kind == OR_FHN) {
+    nearest = (int *)malloc(sizeof(int) * (size_t)half);
+    or_nearest_obs(m, nearest);
+  }
+  const double sh = sqrt(m->h);
+  for (int i = 0; i < N; ++i) {
+    double *x = X + (size_t)i * d, acc = 0.0;
+    for (int s = 0; s < m->S; ++s) {
+      uint32_t n = (uint32_t)((t - 1) * m->S + s);
+      or_step_noise(m, key, OR_P_PROP, (uint32_t)i, filter, n, z);
+      or_drift(m, x, f);
+      learned_drift(m, p, x, y, nearest, s, u, bf16);
+      for (int c = 0; c < d; ++c) {
+        double sd = (c < half) ? m->sd[0] : m->sd[1];
+        x[c] = (x[c] + m->h * (f[c] + u[c])) + sd * sh * z[c];
+        acc += -(sh / sd) * u[c] * z[c] - (m->h / (2.0 * sd * sd)) * u[c] * u[c];
+      }
+    }
+    dlw[i] = acc;
+  }
+  free(z); free(f); free(u); free(nearest);
+}
+
+int or_filter_interval_learned(const or_model *m, const double *p, uint64_t seed,
+                               uint32_t filter, int N, int t, double *X,
+                               const double *y, double *logZ, double *lw_out,
+                               int32_t *A_out, double *mean_post, double *mean_w,
+                               double *ess, int bf16) {
+  int d = m->dx;
+  double *lw = (double *)malloc(sizeof(double) * (size_t)N);
+  double *dlw = (double *)malloc(sizeof(double) * (size_t)N);
+  double *C = (double *)malloc(sizeof(double) * (size_t)N);
+  double *U = (double *)malloc(sizeof(double) * (size_t)N);
+  int32_t *A = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  double *Xo = (double *)malloc(sizeof(double) * (size_t)N * d);
+  double mx, W, s2;
+
+  or_propagate_learned(m, p, seed, filter, N, t, X, y, dlw, bf16);
+  or_weights(m, N, X, y, lw);
+  for (int i = 0; i < N; ++i) {
+    lw[i] += dlw[i];
+    if (isnan(lw[i])) lw[i] = -INFINITY;
+  }
+  int deg = or_normalise(N, lw, &mx, &W, &s2);
+  if (logZ) {
+    const double two_pi = 6.283185307179586476925286766559;
+    if (deg)
+      *logZ = -INFINITY;
+    else
+      *logZ += mx + log(W / (double)N) - 0.5 * m->dy * log(two_pi * m->obs_var);
+  }
+  if (ess) *ess = W * W / s2;
+  if (mean_w) or_weighted_mean(N, d, X, lw, mx, mean_w);
+  or_cdf(N, lw, mx, deg, C);
+  or_sorted_uniforms(seed, filter, t, N, U);
+  or_ancestors(N, C, U, A);
+  or_gather(N, d, X, A, Xo);
+  memcpy(X, Xo, sizeof(double) * (size_t)N * d);
+  if (mean_post) or_mean(N, d, X, mean_post);
+  if (lw_out) memcpy(lw_out, lw, sizeof(double) * (size_t)N);
+  if (A_out) memcpy(A_out, A, sizeof(int32_t) * (size_t)N);
+  free(lw); free(dlw); free(C); free(U); free(A); free(Xo);
+  return deg;
+}
+
+void or_run_ensemble_learned(const or_model *m, const double *p, uint64_t seed,
+                             int M, int N, int T, const double *y, double *est,
+                             double *est_w, double *logZ, double *ess, int bf16) {
+  int d = m->dx;
+  double *X = (double *)malloc(sizeof(double) * (size_t)N * d);
+  double *mp = (double *)malloc(sizeof(double) * (size_t)d);
+  double *mw = (double *)malloc(sizeof(double) * (size_t)d);
+  if (est) memset(est, 0, sizeof(double) * (size_t)T * d);
+  if (est_w) memset(est_w, 0, sizeof(double) * (size_t)T * d);
+  if (ess) memset(ess, 0, sizeof(double) * (size_t)T);
+  for (int f = 0; f < M; ++f) {
+    double lz = 0.0;
+    or_init(m, seed, (uint32_t)f, N, X);
+    for (int t = 1; t <= T; ++t) {
+      double e;
+      or_filter_interval_learned(m, p, seed, (uint32_t)f, N, t, X,
+                                 y + (size_t)(t - 1) * m->dy, &lz, NULL, NULL, mp,
+                                 mw, &e, bf16);
+      for (int c = 0; c < d; ++c) {
+        if (est) est[(size_t)(t - 1) * d + c] += mp[c] / (double)M;
+        if (est_w) est_w[(size_t)(t - 1) * d + c] += mw[c] / (double)M;
+      }
+      if (ess) ess[t - 1] += e / (double)M;
+    }
+    if (logZ) logZ[f] = lz;
+  }
+  free(X); free(mp); free(mw);
+}
+
+/* Discrete OU x_{k+1} = phi x_k + sd sqrt(h) z_k, phi = 1 - theta h, observed
+   as y = x_S + N(0, obs_var).  Given x_k = x, y - phi^{S-k} x is Gaussian with
+   variance q_{S-k} + obs_var and covariance phi^{S-k-1} sd sqrt(h) with z_k,
+   so (sd/sqrt(h)) E[z_k | x, y] is the expression below. */
+double or_ou_optimal_u(const or_model *m, double x, double y, int k) {
+  double phi = 1.0 - m->p[0] * m->h, sd = m->sd[0];
+  int r = m->S - k;
+  double a_r = pow(phi, r), a_r1 = pow(phi, r - 1), q = 0.0;
+  for (int i = 0; i < r; ++i) q += sd * sd * m->h * pow(phi, 2 * i);
+  return sd * sd * a_r1 * (y - a_r * x) / (q + m->obs_var);
+}

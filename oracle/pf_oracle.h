@@ -138,6 +138,59 @@ void or_simulate(const or_model *m, uint64_t seed, int T, double *x_true,
 double or_kalman_ou(const or_model *m, int T, const double *y, double *mean,
                     double *var);
 
+/* ---- learned proposal --------------------------------------------------
+   A drift correction u_theta(features) added to every Euler increment:
+   x' = x + h (f(x) + u) + sd sqrt(h) z, and the importance weight of the
+   particle is multiplied by the ratio of the model and proposal Gaussian
+   increment densities, log p/q = -(sqrt(h)/sd) u z - (h/(2 sd^2)) u^2 per
+   component and step.  u_theta is an MLP in_dim -> 64 (ReLU) -> 64 (ReLU)
+   -> out_dim (linear) with parameters, in this order, W1[64][in_dim],
+   b1[64], W2[64][64], b2[64], W3[out_dim][64], b3[out_dim].
+   FH-N features of node (i, j) at step k of the interval (20): the 3x3 v
+   patch and the 3x3 w patch around the node (row-major offsets -1..1, edge
+   replicated), the residual y_o - v_o of the nearest observed node o, and
+   tau = (S - k) / S; outputs (u_v, u_w).
+   OU features (3): x, y - x, tau; output u. */
+#define OR_MLP_HIDDEN 64
+int or_mlp_nparams(int in_dim, int out_dim);
+/* h1, h2 may be NULL.  bf16 != 0 rounds inputs, weights and hidden
+   activations to bfloat16 (nearest even) before each layer. */
+void or_mlp_forward(int in_dim, int out_dim, const double *p, const double *x,
+                    double *h1, double *h2, double *out, int bf16);
+/* grad += d(dout . out)/dp at input x (FP64, no rounding) */
+void or_mlp_backward(int in_dim, int out_dim, const double *p, const double *x,
+                     const double *dout, double *grad);
+/* mean over B rows of sum_c (out_c - target_c)^2, and its gradient */
+double or_mlp_loss_grad(int in_dim, int out_dim, const double *p, int B,
+                        const double *X, const double *T, double *grad);
+double or_bf16(double x);
+/* nearest observed node of every node (ties to the lowest observation
+   index), as an index into obs_idx */
+void or_nearest_obs(const or_model *m, int *map);
+void or_fhn_features(const or_model *m, const double *x, const double *y,
+                     const int *nearest, int k, int node, double *feat);
+void or_ou_features(const or_model *m, const double *x, const double *y, int k,
+                    double *feat);
+/* Interval t of N particles under the learned proposal (Philox counters of
+   the bootstrap propagation, so p = 0 reproduces it); dlw[N] receives the
+   log increment-density ratios. */
+void or_propagate_learned(const or_model *m, const double *p, uint64_t seed,
+                          uint32_t filter, int N, int t, double *X,
+                          const double *y, double *dlw, int bf16);
+/* One full interval of one filter under the learned proposal (as
+   or_filter_interval). */
+int or_filter_interval_learned(const or_model *m, const double *p, uint64_t seed,
+                               uint32_t filter, int N, int t, double *X,
+                               const double *y, double *logZ, double *lw,
+                               int32_t *A, double *mean_post, double *mean_w,
+                               double *ess, int bf16);
+void or_run_ensemble_learned(const or_model *m, const double *p, uint64_t seed,
+                             int M, int N, int T, const double *y, double *est,
+                             double *est_w, double *logZ, double *ess, int bf16);
+/* OU: the minimiser of E|u - (sd/sqrt(h)) z_k|^2 given x_k = x and y,
+   sd^2 a_{S-k-1} (y - a_{S-k} x) / (q_{S-k} + obs_var), k 0-based. */
+double or_ou_optimal_u(const or_model *m, double x, double y, int k);
+
 #ifdef __cplusplus
 }
 #endif
