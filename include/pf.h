@@ -69,7 +69,8 @@ typedef struct pf_model_desc {
                             the per-step noise is noise_sd * sqrt(h) * z    */
   int32_t obs_dim;       /* d_y                                             */
   const int32_t *h_obs_index; /* [obs_dim] observed state indices (H is a
-                            selection); FH-N v of node (i,j) is i*J + j     */
+                            selection); FH-N v of node (i,j) is i*J + j, and
+                            FH-N models may observe v nodes only (< J*J)    */
   double obs_var;        /* Gaussian observation noise variance (eqObservLorenz,
                             eqObservFHN)                                    */
   const double *h_prior_mean; /* [state_dim] tau_0 = N(mean, diag(sd^2))    */
@@ -83,9 +84,19 @@ typedef struct pf_ensemble_desc {
   int32_t model;
   int32_t M;
   int32_t N;
-  uint32_t flags; /* reserved, must be 0 */
+  uint32_t flags; /* 0 (bootstrap proposal) or PF_ENS_LEARNED */
   uint64_t seed;
 } pf_ensemble_desc;
+
+/* Ensemble flag: draw the particles from the learned proposal instead of
+   the model's transition (FH-N models with J <= 48 only).  Every Euler-
+   Maruyama increment gets a drift correction u_theta(features of the node,
+   y_t, step) and each particle's log-weight gains the log ratio of the model
+   and proposal increment densities, so the filter stays consistent (the
+   importance-function form of Algorithm 1 that the closing remarks of
+   Sec. 6 extend the results to).  Until pf_proposal_set is called the
+   network is zero and the filter is the bootstrap filter. */
+#define PF_ENS_LEARNED 1u
 
 /* Context options (pf_init `options`). */
 #define PF_OPT_PLAIN 0u /* one kernel per method step (reference path)     */
@@ -141,7 +152,10 @@ pf_status pf_set_observations(pf_ctx *ctx, const float *d_y_all, int32_t T);
    t: the per-step hooks of the parity tests.  They run on the plain kernels,
    except that on a PF_OPT_FUSED context a request with PF_STAGE_RESAMPLE and
    without PROPAGATE / WEIGHT runs the fused kernel's resampling and estimation
-   phases on the log-weights and pre-resampling particles in place. */
+   phases on the log-weights and pre-resampling particles in place.  For an
+   ensemble with PF_ENS_LEARNED, PF_STAGE_PROPAGATE needs d_y (the proposal
+   looks at y_t) and writes the complete log-weights (observation term plus
+   the density ratio); PF_STAGE_WEIGHT leaves them as they are. */
 pf_status pf_run_stages(pf_ctx *ctx, uint32_t stages, const float *d_y, void *stream);
 
 /* Estimates after the last completed interval.  Any pointer may be NULL.
@@ -188,6 +202,33 @@ pf_status pf_simulate(pf_ctx *ctx, int32_t ens, uint64_t seed, int32_t T,
    [n] and d_z float32 [n] (Box-Muller normals); either may be NULL. */
 pf_status pf_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
                            int64_t n, uint32_t *d_bits, float *d_z, void *stream);
+
+/* ---- learned proposal ----------------------------------------------------
+   u_theta is an MLP in_dim -> 64 (ReLU) -> 64 (ReLU) -> out_dim with FP32
+   parameters, flat, in the order W1[64][in_dim], b1[64], W2[64][64], b2[64],
+   W3[out_dim][64], b3[out_dim] (row-major, y = W x + b).  Kernels round them
+   to bfloat16 (nearest even) when they load them, round inputs and hidden
+   activations to bfloat16 too, and accumulate in FP32 (MFMA).
+   FH-N features of node (i, j) at Euler step k of the interval (20 inputs):
+   the 3x3 patch of v around the node, row-major, edge replicated; the same
+   patch of w; y_o - v_o for the node's nearest observed node o (least grid
+   distance, ties to the lower observation index); (S - k) / S.
+   Outputs: the corrections of the v and w drifts of the node. */
+
+/* Number of parameters of an MLP, or -1 unless 1 <= in_dim <= 31 and
+   1 <= out_dim <= 4. */
+int32_t pf_mlp_nparams(int32_t in_dim, int32_t out_dim);
+
+/* Copy the network of ensemble `ens` (created with PF_ENS_LEARNED) from
+   d_params (float32, pf_mlp_nparams(20, 2) values) into the workspace;
+   enqueued on `stream`, used from the next interval on. */
+pf_status pf_proposal_set(pf_ctx *ctx, int32_t ens, const float *d_params, int64_t n_params,
+                          void *stream);
+
+/* d_out [rows][out_dim] = u_theta(d_x [rows][in_dim]), float32, with the
+   kernels' bfloat16 arithmetic.  rows = 0 is a no-op. */
+pf_status pf_mlp_forward(const float *d_params, int32_t in_dim, int32_t out_dim, const float *d_x,
+                         int64_t rows, float *d_out, void *stream);
 
 /* Timing of the dominant kernel (the propagation kernel on the plain path,
    the fused interval kernel on the fused path).  While enabled, every

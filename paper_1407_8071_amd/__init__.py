@@ -23,6 +23,7 @@ KIND = {"ou1d": 0, "lorenz63": 1, "fhn": 2}
 OPT_PLAIN, OPT_FUSED, OPT_GRAPH = 0, 1, 2
 STAGE_PROPAGATE, STAGE_WEIGHT, STAGE_RESAMPLE, STAGE_GATHER, STAGE_ESTIMATE = 1, 2, 4, 8, 16
 STAGE_ALL = 31
+ENS_LEARNED = 1
 
 
 class PFError(RuntimeError):
@@ -83,11 +84,15 @@ def lib():
         "pf_sync": [_VP],
         "pf_set_profiling": [_VP, i32],
         "pf_read_profile": [_VP, C.POINTER(C.c_double), C.POINTER(i64)],
+        "pf_proposal_set": [_VP, i32, _VP, i64, _VP],
+        "pf_mlp_forward": [_VP, i32, i32, _VP, i64, _VP, _VP],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    L.pf_mlp_nparams.argtypes = [i32, i32]
+    L.pf_mlp_nparams.restype = i32
     L.pf_destroy.argtypes = [_VP]
     L.pf_destroy.restype = None
     L.pf_status_str.argtypes = [C.c_int]
@@ -137,8 +142,10 @@ class PFModel:
 class ParticleFilter:
     """A context of one or more ensembles of independent bootstrap filters.
 
-    ``ensembles`` is a list of (model_index, M, N, seed).  ``fused`` selects
-    the persistent fused interval kernel instead of one kernel per step.
+    ``ensembles`` is a list of (model_index, M, N, seed) or
+    (model_index, M, N, seed, flags) with flags 0 or ENS_LEARNED.  ``fused``
+    selects the persistent fused interval kernel instead of one kernel per
+    step.
     """
 
     def __init__(self, models, ensembles, fused: bool = False, graph: bool = False, stream=None):
@@ -147,8 +154,11 @@ class ParticleFilter:
         self.ens = [tuple(e) for e in ensembles]
         nm, ne = len(self.models), len(self.ens)
         self._md = (_ModelDesc * nm)(*[m.desc for m in self.models])
-        self._ed = (_EnsDesc * ne)(*[_EnsDesc(int(mi), int(M), int(N), 0, int(seed))
-                                     for (mi, M, N, seed) in self.ens])
+        def desc(e):
+            mi, M, N, seed = e[:4]
+            flags = e[4] if len(e) > 4 else 0
+            return _EnsDesc(int(mi), int(M), int(N), int(flags), int(seed))
+        self._ed = (_EnsDesc * ne)(*[desc(e) for e in self.ens])
         self.options = (OPT_FUSED if fused or graph else OPT_PLAIN) | (OPT_GRAPH if graph else 0)
         nbytes = C.c_size_t()
         _check(lib().pf_workspace_bytes(self._md, nm, self._ed, ne, self.options,
@@ -173,7 +183,7 @@ class ParticleFilter:
 
     # ---- shapes ------------------------------------------------------------
     def dims(self, e: int):
-        mi, M, N, _ = self.ens[e]
+        mi, M, N = self.ens[e][:3]
         return self.models[mi], M, N
 
     def particle_shape(self, e: int):
@@ -199,9 +209,9 @@ class ParticleFilter:
 
     def estimate(self, stream=None):
         import torch
-        dx = sum(self.models[mi].dx for (mi, _, _, _) in self.ens)
-        nM = sum(M for (_, M, _, _) in self.ens)
-        nF = sum(M * self.models[mi].dx for (mi, M, _, _) in self.ens)
+        dx = sum(self.models[mi].dx for (mi, *_) in self.ens)
+        nM = sum(M for (_, M, *_) in self.ens)
+        nF = sum(M * self.models[mi].dx for (mi, M, *_) in self.ens)
         mean = torch.empty(dx, dtype=torch.float64, device="cuda")
         mean_w = torch.empty(dx, dtype=torch.float64, device="cuda")
         logZ = torch.empty(nM, dtype=torch.float64, device="cuda")
@@ -274,6 +284,10 @@ class ParticleFilter:
         _check(lib().pf_simulate(self._ctx, e, seed, T, _ptr(xt), _ptr(y), _stream(stream)))
         return xt, y
 
+    def set_proposal(self, e: int, params, stream=None):
+        """Network of learned ensemble e (float32 device tensor, flat)."""
+        _check(lib().pf_proposal_set(self._ctx, e, _ptr(params), params.numel(), _stream(stream)))
+
     def sync(self):
         _check(lib().pf_sync(self._ctx))
 
@@ -285,6 +299,23 @@ class ParticleFilter:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().pf_read_profile(self._ctx, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+def mlp_nparams(in_dim: int, out_dim: int) -> int:
+    n = int(lib().pf_mlp_nparams(in_dim, out_dim))
+    if n < 0:
+        raise PFError(1, "in_dim must be in [1, 31] and out_dim in [1, 4]")
+    return n
+
+
+def mlp_forward(params, x, out_dim: int, stream=None):
+    """u_theta over the rows of x [rows, in_dim] (float32 device tensors)."""
+    import torch
+    rows, in_dim = x.shape
+    out = torch.empty((rows, out_dim), dtype=torch.float32, device="cuda")
+    _check(lib().pf_mlp_forward(_ptr(params), in_dim, out_dim, _ptr(x), rows, _ptr(out),
+                                _stream(stream)))
+    return out
 
 
 def philox_stream(seed: int, c1: int, c2: int, c3: int, n: int, stream=None):

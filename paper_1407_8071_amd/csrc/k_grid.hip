@@ -94,15 +94,11 @@ __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t
   for (int e = 0; e < 4; ++e) {
     const float c = get(S.v, e), w = get(S.w, e);
     const float lap = (((vu[e] - c) + (vd[e] - c)) + (vl[e] - c)) + (vr[e] - c);
-    const float fv = c * (c - md.p0) * (1.f - c) - w + md.p1 * lap;
-    const float fw = md.p2 * (c - md.p3 * w);
-    const float iv = fmaf(md.h, fv, md.sq0 * zv[e]) - get(S.cv, e);
-    const float nv = c + iv;
-    set(S.cv, e, (nv - c) - iv);
+    float nv, nw, cv = get(S.cv, e), cw = get(S.cw, e);
+    fhn_node_step<false>(md, c, w, lap, zv[e], zw[e], 0.f, 0.f, nv, nw, cv, cw);
+    set(S.cv, e, cv);
     set(S.v, e, nv);
-    const float iw = fmaf(md.h, fw, md.sq1 * zw[e]) - get(S.cw, e);
-    const float nw = w + iw;
-    set(S.cw, e, (nw - w) - iw);
+    set(S.cw, e, cw);
     set(S.w, e, nw);
   }
 }

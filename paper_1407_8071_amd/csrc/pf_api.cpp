@@ -58,6 +58,12 @@ struct Ens {
   int blocks = 1024;       // grid model: resident workgroups of the stepping kernels
   int32_t *cnt = nullptr;  // grid model: offspring counts [M][N]
   double *gpart = nullptr; // grid model: estimator partial sums
+  // learned proposal (FH-N): FP32 parameters and each node's nearest observation
+  bool learned = false;
+  float *params = nullptr;
+  int32_t *nearest = nullptr;
+  double sd0 = 0.0, sd1 = 0.0;
+  int lblocks = 256;
 };
 
 // One launch of the filter-per-workgroup kernel: every filter of the
@@ -78,10 +84,13 @@ int wg_block(int N) { return N <= 256 ? 256 : (N <= 512 ? 512 : 1024); }
 // Offsets of every array of one ensemble inside the workspace.
 struct Layout {
   size_t obs, pmean, psd, X0, X1, lw, A, Cl, Sl, tile, coff, soff, fstat, mpart, wpart, fmean,
-      fmeanw, emean, cnt, gpart, end;
+      fmeanw, emean, cnt, gpart, params, nearest, end;
 };
 
-Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid) {
+constexpr int LEARNED_IN = 20, LEARNED_OUT = 2;  // FH-N node features, (u_v, u_w)
+constexpr int LEARNED_MAX_J = 48;
+
+Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bool learned) {
   Layout L{};
   size_t o = base;
   auto take = [&](size_t bytes) {
@@ -111,6 +120,8 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid) {
   // grid model: offspring counts and the chunk partial sums of its estimator
   L.cnt = take(grid ? sizeof(int32_t) * MN : 0);
   L.gpart = take(grid ? sizeof(double) * (size_t)M * pfk::grid_est_chunks(N) * 2 * dx : 0);
+  L.params = take(learned ? sizeof(float) * (size_t)pfk::mlp_nparams(LEARNED_IN, LEARNED_OUT) : 0);
+  L.nearest = take(learned ? sizeof(int32_t) * (size_t)(dx / 2) : 0);
   L.end = o;
   return L;
 }
@@ -156,6 +167,11 @@ pf_status check_model(const pf_model_desc &m, int idx) {
   for (int k = 0; k < m.obs_dim; ++k)
     if (m.h_obs_index[k] < 0 || m.h_obs_index[k] >= m.state_dim)
       return fail(PF_ERR_INVALID_ARG, "model %d: obs_index[%d] out of range", idx, k);
+  // FH-N: the observation operator reads v (the kernels stage only v for it)
+  if (m.kind == PF_MODEL_FHN)
+    for (int k = 0; k < m.obs_dim; ++k)
+      if (m.h_obs_index[k] >= m.grid_j * m.grid_j)
+        return fail(PF_ERR_INVALID_ARG, "model %d: FH-N obs_index[%d] is not a v node", idx, k);
   if (!(m.obs_var > 0.0) || !std::isfinite(m.obs_var))
     return fail(PF_ERR_INVALID_ARG, "model %d: obs_var must be > 0", idx);
   if (!m.h_prior_mean || !m.h_prior_sd)
@@ -177,7 +193,12 @@ pf_status check_all(const pf_model_desc *models, int n_models, const pf_ensemble
     if (d.M < 1 || d.N < 1 || d.N > (1 << 26) || (int64_t)d.M * d.N > (int64_t)1 << 30)
       return fail(PF_ERR_INVALID_ARG, "ensemble %d: bad M=%d N=%d", e, d.M, d.N);
     if (d.M > 65535) return fail(PF_ERR_INVALID_ARG, "ensemble %d: M > 65535", e);
-    if (d.flags != 0) return fail(PF_ERR_INVALID_ARG, "ensemble %d: flags must be 0", e);
+    if (d.flags & ~PF_ENS_LEARNED)
+      return fail(PF_ERR_INVALID_ARG, "ensemble %d: unknown flags 0x%x", e, d.flags);
+    if ((d.flags & PF_ENS_LEARNED) &&
+        (models[d.model].kind != PF_MODEL_FHN || models[d.model].grid_j > LEARNED_MAX_J))
+      return fail(PF_ERR_UNSUPPORTED, "ensemble %d: the learned proposal needs an FH-N model with J <= %d",
+                  e, LEARNED_MAX_J);
   }
   return PF_OK;
 }
@@ -194,7 +215,9 @@ size_t total_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int
   for (int e = 0; e < n_ens; ++e) {
     const pf_model_desc &m = models[ens[e].model];
     const int T = (ens[e].N + pfk::TILE - 1) / pfk::TILE;
-    o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T, m.kind == PF_MODEL_FHN).end;
+    o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T, m.kind == PF_MODEL_FHN,
+                  (ens[e].flags & PF_ENS_LEARNED) != 0)
+            .end;
   }
   return o + ctx_bytes(ens, n_ens);
 }
@@ -278,6 +301,16 @@ hipError_t gather(const Ens &E, int from, int to, hipStream_t s) {
                 : pfk::launch_vec_gather(D, D.X[from], D.X[to], s);
 }
 
+// offset of ensemble E's observations in the concatenated observation vector
+int learned_yoff(const pf_ctx *ctx, const Ens &E) {
+  int o = 0;
+  for (const Ens &F : ctx->ens) {
+    if (&F == &E) break;
+    o += F.dy;
+  }
+  return o;
+}
+
 pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t s) {
   const int t = ctx->t;
   if ((stages & PF_STAGE_WEIGHT) && !d_y)
@@ -287,7 +320,14 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
     for (Ens &E : ctx->ens) {
       pfk::EnsDev &D = E.dev;
       const int32_t *anc = ctx->pending ? D.A : nullptr;
-      if (!E.grid) {
+      if (E.learned) {
+        if (!d_y) return fail(PF_ERR_INVALID_ARG, "the learned proposal needs the observations");
+        const long ev = prof_begin(ctx, s);
+        PF_HIP(pfk::launch_grid_steps_learned(D, pfk::IvArg{t, nullptr, d_y, 0}, learned_yoff(ctx, E),
+                                              D.X[ctx->cur], anc, D.X[out], D.lw, E.params,
+                                              E.nearest, E.sd0, E.sd1, E.lblocks, s));
+        prof_end(ctx, ev, s);
+      } else if (!E.grid) {
         const long ev = prof_begin(ctx, s);
         PF_HIP(pfk::launch_vec_propagate(D, t, D.X[ctx->cur], anc, D.X[out], nullptr, nullptr, s));
         prof_end(ctx, ev, s);
@@ -312,7 +352,7 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
     pfk::EnsDev &D = E.dev;
     const float *y = d_y ? d_y + yoff : nullptr;
     yoff += (size_t)E.dy;
-    if (stages & PF_STAGE_WEIGHT) {
+    if ((stages & PF_STAGE_WEIGHT) && !E.learned) {
       if (E.grid)
         PF_HIP(pfk::launch_grid_loglik(D, D.X[ctx->xbar], y, s));
       else
@@ -374,8 +414,13 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     if (!E.grid || resample_only) continue;
     pfk::EnsDev &D = E.dev;
     const long eg = prof ? prof_begin(ctx, s) : -1;
-    PF_HIP(pfk::launch_grid_steps(D, iv, yoff, D.X[parity], pending ? D.A : nullptr, D.X[out],
-                                  D.lw, E.blocks, s));
+    if (E.learned)
+      PF_HIP(pfk::launch_grid_steps_learned(D, iv, yoff, D.X[parity], pending ? D.A : nullptr,
+                                            D.X[out], D.lw, E.params, E.nearest, E.sd0, E.sd1,
+                                            E.lblocks, s));
+    else
+      PF_HIP(pfk::launch_grid_steps(D, iv, yoff, D.X[parity], pending ? D.A : nullptr, D.X[out],
+                                    D.lw, E.blocks, s));
     prof_end(ctx, eg, s);
   }
   // 2. resampling and the filters' estimates
@@ -524,7 +569,8 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
       E.prior_mean[(size_t)k] = (float)m.h_prior_mean[k];
       E.prior_sd[(size_t)k] = (float)m.h_prior_sd[k];
     }
-    const Layout L = layout_of(base, E.d.M, E.d.N, E.dx, E.dy, E.T, E.grid);
+    E.learned = (E.d.flags & PF_ENS_LEARNED) != 0;
+    const Layout L = layout_of(base, E.d.M, E.d.N, E.dx, E.dy, E.T, E.grid, E.learned);
     base = L.end;
     pfk::EnsDev &D = E.dev;
     pfk::ModelDev &md = D.md;
@@ -589,6 +635,30 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
       E.gpart = (double *)(ws + L.gpart);
       E.blocks = pfk::grid_resident_blocks(md);
     }
+    std::vector<int32_t> near_host;
+    if (E.learned) {
+      E.params = (float *)(ws + L.params);
+      E.nearest = (int32_t *)(ws + L.nearest);
+      E.sd0 = m.noise_sd[0];
+      E.sd1 = m.noise_sd[1];
+      E.lblocks = pfk::learned_resident_blocks(md.J);
+      // nearest observed node of every node: least squared distance on the
+      // grid, ties to the lower observation index
+      const int J = md.J;
+      near_host.resize((size_t)J * J);
+      for (int n = 0; n < J * J; ++n) {
+        const int i = n / J, j = n % J;
+        long best = -1;
+        for (int o = 0; o < E.dy; ++o) {
+          const int r = E.obs_idx[(size_t)o] / J, c = E.obs_idx[(size_t)o] % J;
+          const long d2 = (long)(i - r) * (i - r) + (long)(j - c) * (j - c);
+          if (best < 0 || d2 < best) {
+            best = d2;
+            near_host[(size_t)n] = o;
+          }
+        }
+      }
+    }
     pf_status st = PF_OK;
 #define INIT_TRY(expr)                                  \
   do {                                                  \
@@ -612,6 +682,16 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
       INIT_TRY(pfk::launch_grid_init(D, D.X[0], s));
     else
       INIT_TRY(pfk::launch_vec_init(D, D.X[0], s));
+    if (E.learned) {
+      // u = 0 until pf_proposal_set: the bootstrap proposal
+      INIT_TRY(hipMemsetAsync(E.params, 0,
+                              sizeof(float) * pfk::mlp_nparams(LEARNED_IN, LEARNED_OUT), s));
+      INIT_TRY(hipMemcpyAsync(E.nearest, near_host.data(), sizeof(int32_t) * near_host.size(),
+                              hipMemcpyHostToDevice, s));
+      INIT_TRY(pfk::set_learned_lds_limit());
+      // the host vector must outlive the copy
+      INIT_TRY(hipStreamSynchronize(s));
+    }
   }
   // context arrays: the fused ensemble table and the workgroup job lists
   {
@@ -900,6 +980,34 @@ pf_status pf_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
                            uint32_t *d_bits, float *d_z, void *stream) {
   if (n < 0 || n > ((int64_t)1 << 32)) return fail(PF_ERR_INVALID_ARG, "n out of range");
   PF_HIP(pfk::launch_philox_stream(seed, c1, c2, c3, n, d_bits, d_z, (hipStream_t)stream));
+  return PF_OK;
+}
+
+int32_t pf_mlp_nparams(int32_t in_dim, int32_t out_dim) {
+  if (in_dim < 1 || in_dim > 31 || out_dim < 1 || out_dim > 4) return -1;
+  return pfk::mlp_nparams(in_dim, out_dim);
+}
+
+pf_status pf_proposal_set(pf_ctx *ctx, int32_t ens, const float *d_params, int64_t n_params,
+                          void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E) return fail(PF_ERR_INVALID_ARG, "bad ensemble index");
+  if (!E->learned) return fail(PF_ERR_STATE, "ensemble %d was not created with PF_ENS_LEARNED", ens);
+  if (!d_params || n_params != pfk::mlp_nparams(LEARNED_IN, LEARNED_OUT))
+    return fail(PF_ERR_INVALID_ARG, "expected %d parameters",
+                pfk::mlp_nparams(LEARNED_IN, LEARNED_OUT));
+  PF_HIP(hipMemcpyAsync(E->params, d_params, sizeof(float) * (size_t)n_params,
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_mlp_forward(const float *d_params, int32_t in_dim, int32_t out_dim, const float *d_x,
+                         int64_t rows, float *d_out, void *stream) {
+  if (pf_mlp_nparams(in_dim, out_dim) < 0)
+    return fail(PF_ERR_INVALID_ARG, "in_dim must be in [1, 31] and out_dim in [1, 4]");
+  if (rows < 0) return fail(PF_ERR_INVALID_ARG, "rows < 0");
+  if (rows > 0 && (!d_params || !d_x || !d_out)) return fail(PF_ERR_INVALID_ARG, "NULL buffer");
+  PF_HIP(pfk::launch_mlp_forward(d_params, in_dim, out_dim, d_x, rows, d_out, (hipStream_t)stream));
   return PF_OK;
 }
 

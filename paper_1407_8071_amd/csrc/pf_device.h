@@ -88,6 +88,31 @@ struct ModelDev {
   const float *prior_mean, *prior_sd; // [dx]
 };
 
+// One Euler-Maruyama step of one FH-N node from its v (c), w, the 5-point
+// Laplacian of v and the two normals: drift v(v-a)(1-v) - w + D lap,
+// eps (v - gam w), plus (DRIFT) the proposal's drift corrections uv, uw; the
+// increments are added with compensated (Kahan) sums whose running
+// corrections cv, cw live with the caller.
+template <bool DRIFT>
+__device__ __forceinline__ void fhn_node_step(const ModelDev &md, float c, float w, float lap,
+                                              float zv, float zw, float uv, float uw, float &v_new,
+                                              float &w_new, float &cv, float &cw) {
+  float fv = c * (c - md.p0) * (1.f - c) - w + md.p1 * lap;
+  float fw = md.p2 * (c - md.p3 * w);
+  if (DRIFT) {
+    fv += uv;
+    fw += uw;
+  }
+  const float iv = fmaf(md.h, fv, md.sq0 * zv) - cv;
+  const float nv = c + iv;
+  cv = (nv - c) - iv;
+  v_new = nv;
+  const float iw = fmaf(md.h, fw, md.sq1 * zw) - cw;
+  const float nw = w + iw;
+  cw = (nw - w) - iw;
+  w_new = nw;
+}
+
 // ---------------------------------------------------------------------------
 // Wave64 and workgroup reductions / scans.
 __device__ __forceinline__ float wave_max(float v) {

@@ -127,6 +127,24 @@ hipError_t launch_grid_simulate(const EnsDev &e, uint64_t seed, int T, float *xt
 hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int *t_inc, hipStream_t s);
 hipError_t launch_set_i32(int *p, int v, hipStream_t s);
 
+// ---- learned proposal (MLP in -> 64 -> 64 -> out, FP32 master parameters) ---
+constexpr int MLP_HIDDEN = 64;
+inline int mlp_nparams(int in_dim, int out_dim) {
+  return MLP_HIDDEN * in_dim + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN +
+         out_dim * MLP_HIDDEN + out_dim;
+}
+size_t learned_lds_bytes(int J);
+int learned_resident_blocks(int J);
+hipError_t set_learned_lds_limit();
+hipError_t launch_mlp_forward(const float *params, int in_dim, int out_dim, const float *X,
+                              int64_t rows, float *out, hipStream_t s);
+// interval of an FH-N ensemble under the learned proposal (needs iv.y);
+// nearest[J*J] = index of each node's nearest observation
+hipError_t launch_grid_steps_learned(const EnsDev &e, IvArg iv, int yoff, const float *Xin,
+                                     const int32_t *anc, float *Xout, float *lw,
+                                     const float *params, const int32_t *nearest, double sd0,
+                                     double sd1, int blocks, hipStream_t s);
+
 // ---- random-number hook ----------------------------------------------------
 hipError_t launch_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
                                 uint32_t *bits, float *z, hipStream_t s);

@@ -59,6 +59,25 @@ def test_workspace_bytes_and_validation(pf):
     assert "obs_index" in pf.lib().pf_last_error().decode() or True
 
 
+def test_learned_flag_validation(pf):
+    l63, f20 = pf_inputs.lorenz63(), pf_inputs.fhn(20)
+    assert _bytes(pf, [l63], [(0, 1, 8, 1, 1)])[0] == 2        # learned needs FH-N
+    st0, n0 = _bytes(pf, [f20], [(0, 2, 16, 0, 1)])
+    st1, n1 = _bytes(pf, [f20], [(0, 2, 16, 1, 1)])
+    assert st0 == 0 and st1 == 0
+    assert n1 >= n0 + 4 * 5634 + 4 * 400                       # parameters + nearest map
+    assert _bytes(pf, [pf_inputs.fhn(50)], [(0, 1, 4, 1, 1)])[0] == 2  # J > 48
+    assert pf.lib().pf_mlp_nparams(20, 2) == 5634
+    assert pf.lib().pf_mlp_nparams(3, 1) == 64 * 3 + 64 + 64 * 64 + 64 + 64 + 1
+    assert pf.lib().pf_mlp_nparams(32, 2) == -1
+    assert pf.lib().pf_mlp_nparams(20, 5) == -1
+    # argument checks happen before any device work
+    assert pf.lib().pf_mlp_forward(None, 40, 2, None, 1, None, None) == 1
+    assert pf.lib().pf_mlp_forward(None, 20, 2, None, -1, None, None) == 1
+    assert pf.lib().pf_mlp_forward(None, 20, 2, None, 0, None, None) == 0
+    assert pf.lib().pf_proposal_set(None, 0, None, 5634, None) == 1
+
+
 def test_init_rejects_missing_workspace_and_bad_order(pf):
     l63 = pf.PFModel(pf_inputs.lorenz63())
     md = (pf._ModelDesc * 1)(l63.desc)
