@@ -209,10 +209,11 @@ pf_status pf_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
    W3[out_dim][64], b3[out_dim] (row-major, y = W x + b).  Kernels round them
    to bfloat16 (nearest even) when they load them, round inputs and hidden
    activations to bfloat16 too, and accumulate in FP32 (MFMA).
-   FH-N features of node (i, j) at Euler step k of the interval (20 inputs):
+   FH-N features of node (i, j) at Euler step k of the interval (22 inputs):
    the 3x3 patch of v around the node, row-major, edge replicated; the same
-   patch of w; y_o - v_o for the node's nearest observed node o (least grid
-   distance, ties to the lower observation index); (S - k) / S.
+   patch of w; y_o - v_o for the node's nearest observed node o = (i_o, j_o)
+   (least grid distance, ties to the lower observation index); (S - k) / S;
+   (i_o - i) / 2 and (j_o - j) / 2.
    Outputs: the corrections of the v and w drifts of the node. */
 
 /* Number of parameters of an MLP, or -1 unless 1 <= in_dim <= 31 and
@@ -220,7 +221,7 @@ pf_status pf_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
 int32_t pf_mlp_nparams(int32_t in_dim, int32_t out_dim);
 
 /* Copy the network of ensemble `ens` (created with PF_ENS_LEARNED) from
-   d_params (float32, pf_mlp_nparams(20, 2) values) into the workspace;
+   d_params (float32, pf_mlp_nparams(22, 2) values) into the workspace;
    enqueued on `stream`, used from the next interval on. */
 pf_status pf_proposal_set(pf_ctx *ctx, int32_t ens, const float *d_params, int64_t n_params,
                           void *stream);
@@ -229,6 +230,87 @@ pf_status pf_proposal_set(pf_ctx *ctx, int32_t ens, const float *d_params, int64
    kernels' bfloat16 arithmetic.  rows = 0 is a no-op. */
 pf_status pf_mlp_forward(const float *d_params, int32_t in_dim, int32_t out_dim, const float *d_x,
                          int64_t rows, float *d_out, void *stream);
+
+/* ---- training of u_theta ---------------------------------------------------
+   Regression of u_theta onto the scaled Euler noise of model paths: the loss
+   is the mean over rows of |u_theta(x) - target|^2.  Its minimiser is the
+   conditional mean of the increment noise given the features, which for a
+   linear-Gaussian model is the drift of the optimal (Doob) proposal.  All of
+   it runs in HIP kernels: forward on MFMA, a hand-written backward (layer 3
+   on the VALU, layer 2 and every weight gradient on MFMA), a fixed-order
+   reduction of per-wave partial gradients and Adam on FP32 master weights. */
+
+/* Bytes of the work buffer of pf_mlp_loss_grad for `rows` rows. */
+pf_status pf_mlp_grad_work_bytes(int32_t in_dim, int32_t out_dim, int64_t rows, size_t *out_bytes);
+
+/* d_grad [pf_mlp_nparams] = gradient of (1/rows) sum_r |u(x_r) - t_r|^2 at
+   d_params, with d_x [rows][in_dim], d_target [rows][out_dim] (float32);
+   the loss to *d_loss (device float) when d_loss is not NULL.  Deterministic
+   (no atomics).  d_work: pf_mlp_grad_work_bytes bytes, caller-owned. */
+pf_status pf_mlp_loss_grad(const float *d_params, int32_t in_dim, int32_t out_dim, const float *d_x,
+                           const float *d_target, int64_t rows, float *d_grad, float *d_loss,
+                           void *d_work, size_t work_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba, Algorithm 1) at step t >= 1, in place on
+   d_params, d_m, d_v (float32, n values). */
+pf_status pf_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t n,
+                       double lr, double beta1, double beta2, double eps, int32_t t, void *stream);
+
+/* Training of an FH-N proposal (J a multiple of 4, J <= 48) on paths the
+   model simulates itself.  All draws use Philox with key(seed) and purpose
+   TRAIN (7):
+     long run q (q < n_runs): x_0 ~ tau_0 from counters (q, 0xFFFFFFFE,
+       0xFFFFFFFF, s/4) lane s%4; Euler step n from (q, 0xFFFFFFFE, n, pair);
+       start state j (j < run_len) of the run is its state at the end of
+       interval j + 1;
+     trajectory r = q * run_len + j: one interval from that start, step k
+       from (r, 0xFFFFFFFD, k, pair), and y_r = H x_S + sqrt(obs_var) eta with
+       eta_o from (r, 0xFFFFFFFD, 0xFFFFFFFF, o/4) lane o%4;
+     regression rows (r, k, node): the node's features at x_k of trajectory
+       r with y_r (as in the filter), target (noise_sd / sqrt(h)) z_k (v, w);
+     minibatch of Adam step s: batch_tiles tiles of 16 consecutive nodes,
+       tile b from the words (w0, w1, w2) of counter (b, 0xFFFFFFFC, s, 0):
+       r = floor(w0 n_traj / 2^32), k = w1 mod S, first node
+       16 floor(w2 (J*J/16) / 2^32). */
+typedef struct pf_train_desc {
+  int32_t n_runs;      /* long model runs from tau_0                      */
+  int32_t run_len;     /* intervals per run; n_runs * run_len trajectories */
+  int32_t batch_tiles; /* 16-row tiles per Adam step                      */
+  int32_t reserved;    /* 0                                               */
+  double lr, beta1, beta2, eps;
+  uint64_t seed;
+} pf_train_desc;
+
+/* Workspace bytes for training: the start states, the trajectories
+   (n_runs * run_len * S * state_dim floats), their observations, the
+   partial gradients and the Adam moments. */
+pf_status pf_train_workspace_bytes(const pf_model_desc *h_model, const pf_train_desc *d,
+                                   size_t *out_bytes);
+
+/* Simulate the long runs and the trajectories into d_work (256-byte
+   aligned, pf_train_workspace_bytes).  Waits for the host staging copies. */
+pf_status pf_train_data(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                        size_t work_bytes, void *stream);
+
+/* Device pointers into d_work: start states float32 [n_traj][state_dim],
+   trajectories [n_traj][S][state_dim] (state before each step), and
+   observations [n_traj][obs_dim].  Any output may be NULL. */
+pf_status pf_train_buffers(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                           float **d_starts, float **d_traj, float **d_y);
+
+/* Adam steps first_step .. first_step + n_steps - 1 on d_params (float32,
+   pf_mlp_nparams(22, 2), updated in place); the moments live in d_work and
+   are cleared when first_step == 1.  d_loss [n_steps] (device, may be NULL)
+   receives each minibatch's loss before its update. */
+pf_status pf_train_steps(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                         size_t work_bytes, float *d_params, int32_t first_step, int32_t n_steps,
+                         float *d_loss, void *stream);
+
+/* Gradient and loss of the minibatch of Adam step `step` at d_params, without
+   an update (the training test hook). */
+pf_status pf_train_grad(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                        size_t work_bytes, const float *d_params, int32_t step, float *d_grad,
+                        float *d_loss, void *stream);
 
 /* Timing of the dominant kernel (the propagation kernel on the plain path,
    the fused interval kernel on the fused path).  While enabled, every

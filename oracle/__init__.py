@@ -57,8 +57,9 @@ _U32 = C.POINTER(C.c_uint32)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+                os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "pf_oracle.h"))):
+            build(force=True)
         L = C.CDLL(_LIB)
         M = C.POINTER(_Model)
         sig = {
@@ -106,6 +107,12 @@ def lib():
             "or_run_ensemble_learned": (None, [M, _D, C.c_uint64, C.c_int, C.c_int, C.c_int, _D,
                                                _D, _D, _D, _D, C.c_int]),
             "or_ou_optimal_u": (C.c_double, [M, C.c_double, C.c_double, C.c_int]),
+            "or_train_run": (None, [M, C.c_uint64, C.c_uint32, C.c_int, _D]),
+            "or_train_trajectory": (None, [M, C.c_uint64, C.c_uint32, _D, _D, _D, _D]),
+            "or_train_tile": (None, [M, C.c_uint64, C.c_int, C.c_int, C.c_uint32,
+                                     C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+            "or_adam_step": (None, [C.c_int, _D, _D, _D, _D, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -427,13 +434,16 @@ def nearest_obs(m: Model) -> np.ndarray:
     return out
 
 
+FHN_FEATURES = 22
+
+
 def fhn_features(m: Model, x, y, k, nodes=None) -> np.ndarray:
-    """features[len(nodes), 20] of one FH-N state at step k of the interval."""
+    """features[len(nodes), 22] of one FH-N state at step k of the interval."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     near = nearest_obs(m)
     nodes = range(m.J * m.J) if nodes is None else nodes
-    out = np.zeros((len(nodes), 20))
+    out = np.zeros((len(nodes), FHN_FEATURES))
     for r, n in enumerate(nodes):
         lib().or_fhn_features(m.ref, _d(x), _d(y), _i32(near), k, int(n), _d(out[r]))
     return out
@@ -490,3 +500,37 @@ def run_ensemble_learned(m: Model, p, seed, M, N, y, bf16_mode=True):
 
 def ou_optimal_u(m: Model, x, y, k) -> float:
     return float(lib().or_ou_optimal_u(m.ref, float(x), float(y), int(k)))
+
+
+# ---------------------------------------------------------------------------
+# Training data of the learned proposal and Adam (definitions in pf_oracle.h)
+TRAIN_RUN, TRAIN_TRAJ, TRAIN_BATCH = 0xFFFFFFFE, 0xFFFFFFFD, 0xFFFFFFFC
+
+
+def train_run(m: Model, seed, q, run_len) -> np.ndarray:
+    out = np.zeros((run_len, m.dx))
+    lib().or_train_run(m.ref, C.c_uint64(seed), q, run_len, _d(out))
+    return out
+
+
+def train_trajectory(m: Model, seed, r, x0):
+    """(states before each step [S, dx], y [dy], noise [S, dx])."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    traj = np.zeros((m.S, m.dx))
+    y = np.zeros(m.dy)
+    z = np.zeros((m.S, m.dx))
+    lib().or_train_trajectory(m.ref, C.c_uint64(seed), r, _d(x0), _d(traj), _d(y), _d(z))
+    return traj, y, z
+
+
+def train_tile(m: Model, seed, n_traj, step, b):
+    r, k, n0 = C.c_int(), C.c_int(), C.c_int()
+    lib().or_train_tile(m.ref, C.c_uint64(seed), n_traj, step, b, C.byref(r), C.byref(k),
+                        C.byref(n0))
+    return r.value, k.value, n0.value
+
+
+def adam_step(p, g, mo, ve, lr, beta1, beta2, eps, t):
+    """In place on float64 arrays p, mo, ve."""
+    lib().or_adam_step(p.size, _d(p), _d(np.ascontiguousarray(g, dtype=np.float64)), _d(mo),
+                       _d(ve), lr, beta1, beta2, eps, t)

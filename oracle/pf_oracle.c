@@ -622,8 +622,9 @@ void or_nearest_obs(const or_model *m, int *map) {
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-/* 20 features of node `node` at step k of the interval: v patch (9), w patch
-   (9), residual of the nearest observation, tau = (S - k)/S. */
+/* 22 features of node `node` at step k of the interval: v patch (9), w patch
+   (9), residual of the nearest observation, tau = (S - k)/S, and the row and
+   column offsets of that observation, halved. */
 void or_fhn_features(const or_model *m, const double *x, const double *y,
                      const int *nearest, int k, int node, double *feat) {
   int J = m->J, nn = J * J, i = node / J, j = node % J;
@@ -636,6 +637,8 @@ void or_fhn_features(const or_model *m, const double *x, const double *y,
   int o = nearest[node];
   feat[18] = y[o] - x[m->obs_idx[o]];
   feat[19] = (double)(m->S - k) / (double)m->S;
+  feat[20] = 0.5 * (double)(m->obs_idx[o] / J - i);
+  feat[21] = 0.5 * (double)(m->obs_idx[o] % J - j);
 }
 
 void or_ou_features(const or_model *m, const double *x, const double *y, int k,
@@ -650,12 +653,12 @@ void or_ou_features(const or_model *m, const double *x, const double *y, int k,
 static void learned_drift(const or_model *m, const double *p, const double *x,
                           const double *y, const int *nearest, int k, double *u,
                           int bf16) {
-  double feat[20], o[2];
+  double feat[22], o[2];
   if (m->kind == OR_FHN) {
     int nn = m->J * m->J;
     for (int n = 0; n < nn; ++n) {
       or_fhn_features(m, x, y, nearest, k, n, feat);
-      or_mlp_forward(20, 2, p, feat, NULL, NULL, o, bf16);
+      or_mlp_forward(22, 2, p, feat, NULL, NULL, o, bf16);
       u[n] = o[0];
       u[nn + n] = o[1];
     }
@@ -781,4 +784,89 @@ double or_ou_optimal_u(const or_model *m, double x, double y, int k) {
   double a_r = pow(phi, r), a_r1 = pow(phi, r - 1), q = 0.0;
   for (int i = 0; i < r; ++i) q += sd * sd * m->h * pow(phi, 2 * i);
   return sd * sd * a_r1 * (y - a_r * x) / (q + m->obs_var);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Training data of the learned proposal (definitions in pf_oracle.h): model
+   paths from the step noise and Euler-Maruyama steps above, with their own
+   counters. */
+
+static void train_prior(const or_model *m, const uint32_t key[2], uint32_t q, double *x) {
+  uint32_t ctr[4];
+  double z[4];
+  for (int s = 0; s < m->dx; s += 4) {
+    make_ctr(ctr, q, OR_TRAIN_RUN, 0xFFFFFFFFu, OR_P_TRAIN, (uint32_t)(s / 4));
+    or_normals4(ctr, key, z);
+    for (int l = 0; l < 4 && s + l < m->dx; ++l)
+      x[s + l] = m->prior_mean[s + l] + m->prior_sd[s + l] * z[l];
+  }
+}
+
+void or_train_run(const or_model *m, uint64_t seed, uint32_t q, int run_len, double *starts) {
+  uint32_t key[2];
+  or_key(seed, key);
+  int d = m->dx;
+  double *x = (double *)malloc(sizeof(double) * (size_t)d);
+  double *z = (double *)malloc(sizeof(double) * (size_t)d);
+  double *xn = (double *)malloc(sizeof(double) * (size_t)d);
+  train_prior(m, key, q, x);
+  for (int j = 0; j < run_len; ++j) {
+    for (int s = 0; s < m->S; ++s) {
+      uint32_t n = (uint32_t)(j * m->S + s);
+      or_step_noise(m, key, OR_P_TRAIN, q, OR_TRAIN_RUN, n, z);
+      or_em_step(m, x, z, xn);
+      memcpy(x, xn, sizeof(double) * (size_t)d);
+    }
+    memcpy(starts + (size_t)j * d, x, sizeof(double) * (size_t)d);
+  }
+  free(x); free(z); free(xn);
+}
+
+void or_train_trajectory(const or_model *m, uint64_t seed, uint32_t r, const double *x0,
+                         double *traj, double *y, double *zs) {
+  uint32_t key[2], ctr[4];
+  double q4[4];
+  or_key(seed, key);
+  int d = m->dx;
+  double *x = (double *)malloc(sizeof(double) * (size_t)d);
+  double *z = (double *)malloc(sizeof(double) * (size_t)d);
+  double *xn = (double *)malloc(sizeof(double) * (size_t)d);
+  memcpy(x, x0, sizeof(double) * (size_t)d);
+  for (int k = 0; k < m->S; ++k) {
+    memcpy(traj + (size_t)k * d, x, sizeof(double) * (size_t)d);
+    or_step_noise(m, key, OR_P_TRAIN, r, OR_TRAIN_TRAJ, (uint32_t)k, z);
+    if (zs) memcpy(zs + (size_t)k * d, z, sizeof(double) * (size_t)d);
+    or_em_step(m, x, z, xn);
+    memcpy(x, xn, sizeof(double) * (size_t)d);
+  }
+  double sy = sqrt(m->obs_var);
+  for (int o = 0; o < m->dy; o += 4) {
+    make_ctr(ctr, r, OR_TRAIN_TRAJ, 0xFFFFFFFFu, OR_P_TRAIN, (uint32_t)(o / 4));
+    or_normals4(ctr, key, q4);
+    for (int l = 0; l < 4 && o + l < m->dy; ++l) y[o + l] = x[m->obs_idx[o + l]] + sy * q4[l];
+  }
+  free(x); free(z); free(xn);
+}
+
+void or_train_tile(const or_model *m, uint64_t seed, int n_traj, int step, uint32_t b,
+                   int *r, int *k, int *node0) {
+  uint32_t key[2], ctr[4], w[4];
+  or_key(seed, key);
+  make_ctr(ctr, b, OR_TRAIN_BATCH, (uint32_t)step, OR_P_TRAIN, 0u);
+  or_philox4x32_10(ctr, key, w);
+  int tiles = m->J * m->J / 16;
+  *r = (int)(((uint64_t)w[0] * (uint64_t)n_traj) >> 32);
+  *k = (int)(w[1] % (uint32_t)m->S);
+  *node0 = 16 * (int)(((uint64_t)w[2] * (uint64_t)tiles) >> 32);
+}
+
+void or_adam_step(int n, double *p, const double *g, double *mo, double *ve, double lr,
+                  double beta1, double beta2, double eps, int t) {
+  double c1 = 1.0 - pow(beta1, t), c2 = 1.0 - pow(beta2, t);
+  for (int i = 0; i < n; ++i) {
+    mo[i] = beta1 * mo[i] + (1.0 - beta1) * g[i];
+    ve[i] = beta2 * ve[i] + (1.0 - beta2) * g[i] * g[i];
+    double mh = mo[i] / c1, vh = ve[i] / c2;
+    p[i] -= lr * mh / (sqrt(vh) + eps);
+  }
 }

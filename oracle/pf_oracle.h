@@ -146,10 +146,11 @@ double or_kalman_ou(const or_model *m, int T, const double *y, double *mean,
    component and step.  u_theta is an MLP in_dim -> 64 (ReLU) -> 64 (ReLU)
    -> out_dim (linear) with parameters, in this order, W1[64][in_dim],
    b1[64], W2[64][64], b2[64], W3[out_dim][64], b3[out_dim].
-   FH-N features of node (i, j) at step k of the interval (20): the 3x3 v
+   FH-N features of node (i, j) at step k of the interval (22): the 3x3 v
    patch and the 3x3 w patch around the node (row-major offsets -1..1, edge
-   replicated), the residual y_o - v_o of the nearest observed node o, and
-   tau = (S - k) / S; outputs (u_v, u_w).
+   replicated), the residual y_o - v_o of the nearest observed node o
+   = (i_o, j_o), tau = (S - k) / S, and the offsets (i_o - i)/2, (j_o - j)/2;
+   outputs (u_v, u_w).
    OU features (3): x, y - x, tau; output u. */
 #define OR_MLP_HIDDEN 64
 int or_mlp_nparams(int in_dim, int out_dim);
@@ -190,6 +191,34 @@ void or_run_ensemble_learned(const or_model *m, const double *p, uint64_t seed,
 /* OU: the minimiser of E|u - (sd/sqrt(h)) z_k|^2 given x_k = x and y,
    sd^2 a_{S-k-1} (y - a_{S-k} x) / (q_{S-k} + obs_var), k 0-based. */
 double or_ou_optimal_u(const or_model *m, double x, double y, int k);
+
+/* ---- training data of the learned proposal -----------------------------
+   All draws use key(seed) and purpose TRAIN.
+   Long run q: x_0 ~ tau_0 from counters (q, RUN, 0xFFFFFFFF, s/4) lane s%4;
+     Euler step n = 0 .. run_len*S - 1 from counters (q, RUN, n, sub-block of
+     the model's layout); start state j of run q is x_{(j+1)S}.
+   Trajectory r (start x_0 = start state r): step k = 0 .. S-1 from counters
+     (r, TRAJ, k, ...); y_r = H x_S + obs_sd eta, eta_o from counters
+     (r, TRAJ, 0xFFFFFFFF, o/4) lane o%4.
+   Regression row (r, k, node): features of x_k of trajectory r with y_r at
+     step k; target (sd/sqrt(h)) z_k of the node's v and w.
+   Minibatch of Adam step s: tile b (16 consecutive nodes) from the words
+     (w0, w1, w2) of counter (b, BATCH, s, TRAIN << 24): r = floor(w0 n_traj
+     / 2^32), k = w1 mod S, first node 16 floor(w2 (J*J/16) / 2^32). */
+#define OR_TRAIN_RUN 0xFFFFFFFEu
+#define OR_TRAIN_TRAJ 0xFFFFFFFDu
+#define OR_TRAIN_BATCH 0xFFFFFFFCu
+void or_train_run(const or_model *m, uint64_t seed, uint32_t q, int run_len,
+                  double *starts /* [run_len][dx] */);
+void or_train_trajectory(const or_model *m, uint64_t seed, uint32_t r,
+                         const double *x0, double *traj /* [S][dx] */,
+                         double *y /* [dy] */, double *z /* [S][dx] or NULL */);
+void or_train_tile(const or_model *m, uint64_t seed, int n_traj, int step, uint32_t b,
+                   int *r, int *k, int *node0);
+/* Adam (Kingma and Ba, Alg. 1) on n parameters at step t >= 1 (bias
+   corrections 1 - beta^t). */
+void or_adam_step(int n, double *p, const double *g, double *mo, double *ve,
+                  double lr, double beta1, double beta2, double eps, int t);
 
 #ifdef __cplusplus
 }

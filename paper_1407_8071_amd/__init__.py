@@ -42,6 +42,12 @@ class _ModelDesc(C.Structure):
     ]
 
 
+class _TrainDesc(C.Structure):
+    _fields_ = [("n_runs", C.c_int32), ("run_len", C.c_int32), ("batch_tiles", C.c_int32),
+                ("reserved", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
 class _EnsDesc(C.Structure):
     _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32),
                 ("flags", C.c_uint32), ("seed", C.c_uint64)]
@@ -86,6 +92,16 @@ def lib():
         "pf_read_profile": [_VP, C.POINTER(C.c_double), C.POINTER(i64)],
         "pf_proposal_set": [_VP, i32, _VP, i64, _VP],
         "pf_mlp_forward": [_VP, i32, i32, _VP, i64, _VP, _VP],
+        "pf_mlp_grad_work_bytes": [i32, i32, i64, C.POINTER(C.c_size_t)],
+        "pf_mlp_loss_grad": [_VP, i32, i32, _VP, _VP, i64, _VP, _VP, _VP, C.c_size_t, _VP],
+        "pf_adam_step": [_VP, _VP, _VP, _VP, i64, C.c_double, C.c_double, C.c_double,
+                         C.c_double, i32, _VP],
+        "pf_train_workspace_bytes": [MD, C.POINTER(_TrainDesc), C.POINTER(C.c_size_t)],
+        "pf_train_data": [MD, C.POINTER(_TrainDesc), _VP, C.c_size_t, _VP],
+        "pf_train_buffers": [MD, C.POINTER(_TrainDesc), _VP, C.POINTER(_VP), C.POINTER(_VP),
+                             C.POINTER(_VP)],
+        "pf_train_steps": [MD, C.POINTER(_TrainDesc), _VP, C.c_size_t, _VP, i32, i32, _VP, _VP],
+        "pf_train_grad": [MD, C.POINTER(_TrainDesc), _VP, C.c_size_t, _VP, i32, _VP, _VP, _VP],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -316,6 +332,83 @@ def mlp_forward(params, x, out_dim: int, stream=None):
     _check(lib().pf_mlp_forward(_ptr(params), in_dim, out_dim, _ptr(x), rows, _ptr(out),
                                 _stream(stream)))
     return out
+
+
+def mlp_loss_grad(params, x, target, stream=None):
+    """(loss, grad) of the mean squared regression loss over the rows."""
+    import torch
+    rows, in_dim = x.shape
+    out_dim = target.shape[1]
+    n = C.c_size_t()
+    _check(lib().pf_mlp_grad_work_bytes(in_dim, out_dim, rows, C.byref(n)))
+    work = torch.empty(n.value // 4 + 1, dtype=torch.float32, device="cuda")
+    grad = torch.empty(params.numel(), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().pf_mlp_loss_grad(_ptr(params), in_dim, out_dim, _ptr(x), _ptr(target), rows,
+                                  _ptr(grad), _ptr(loss), _ptr(work), n.value, _stream(stream)))
+    return loss, grad
+
+
+def adam_step(params, grad, m, v, lr, beta1, beta2, eps, t, stream=None):
+    _check(lib().pf_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), lr,
+                              beta1, beta2, eps, t, _stream(stream)))
+
+
+class Trainer:
+    """Training of an FH-N learned proposal on model-simulated paths."""
+
+    def __init__(self, spec: dict, n_runs: int, run_len: int, batch_tiles: int, lr: float = 1e-3,
+                 beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, seed: int = 1):
+        import torch
+        self.model = spec if isinstance(spec, PFModel) else PFModel(spec)
+        self.desc = _TrainDesc(n_runs, run_len, batch_tiles, 0, lr, beta1, beta2, eps, seed)
+        n = C.c_size_t()
+        _check(lib().pf_train_workspace_bytes(C.byref(self.model.desc), C.byref(self.desc),
+                                              C.byref(n)))
+        self.nbytes = n.value
+        self.work = torch.empty(n.value + 256, dtype=torch.uint8, device="cuda")
+        self._ws = C.c_void_p((self.work.data_ptr() + 255) // 256 * 256)
+        self.n_traj = n_runs * run_len
+        self.step_count = 0
+
+    def data(self, stream=None):
+        _check(lib().pf_train_data(C.byref(self.model.desc), C.byref(self.desc), self._ws,
+                                   self.nbytes, _stream(stream)))
+
+    def buffers(self):
+        """(start states, trajectories, observations) as device tensors (views)."""
+        import torch
+        ptrs = [C.c_void_p() for _ in range(3)]
+        _check(lib().pf_train_buffers(C.byref(self.model.desc), C.byref(self.desc), self._ws,
+                                      *[C.byref(p) for p in ptrs]))
+        m, S = self.model, int(self.model.spec["S"])
+        base = self.work.data_ptr()
+        def view(p, shape):
+            off = p.value - base
+            n = int(np.prod(shape))
+            return self.work[off:off + 4 * n].view(torch.float32).view(*shape)
+        return (view(ptrs[0], (self.n_traj, m.dx)), view(ptrs[1], (self.n_traj, S, m.dx)),
+                view(ptrs[2], (self.n_traj, m.dy)))
+
+    def grad(self, params, step: int, stream=None):
+        """(loss, gradient) of the minibatch of Adam step `step`, no update."""
+        import torch
+        g = torch.empty(params.numel(), dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().pf_train_grad(C.byref(self.model.desc), C.byref(self.desc), self._ws,
+                                   self.nbytes, _ptr(params), step, _ptr(g), _ptr(loss),
+                                   _stream(stream)))
+        return loss, g
+
+    def steps(self, params, n_steps: int, stream=None):
+        """Run n_steps Adam steps on params (float32 device tensor); returns the losses."""
+        import torch
+        loss = torch.empty(max(1, n_steps), dtype=torch.float32, device="cuda")
+        _check(lib().pf_train_steps(C.byref(self.model.desc), C.byref(self.desc), self._ws,
+                                    self.nbytes, _ptr(params), self.step_count + 1, n_steps,
+                                    _ptr(loss), _stream(stream)))
+        self.step_count += n_steps
+        return loss[:n_steps]
 
 
 def philox_stream(seed: int, c1: int, c2: int, c3: int, n: int, stream=None):

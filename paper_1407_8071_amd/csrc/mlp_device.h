@@ -1,0 +1,107 @@
+// mlp_device.h -- the bfloat16 MFMA multilayer perceptron u_theta shared by
+// the learned-proposal kernels: in -> 64 (ReLU) -> 64 (ReLU) -> out with FP32
+// master parameters W1[64][in], b1[64], W2[64][64], b2[64], W3[out][64],
+// b3[out], rounded to bfloat16 (nearest even) when loaded.
+//
+// MFMA mapping (v_mfma_f32_16x16x32_bf16).  A tile is 16 rows (grid nodes or
+// training rows).  Every layer is computed transposed, H^T = W . X^T: the
+// weights are the A operand (row = output unit; lane 16 g + row holds the 8
+// K slots 8 g .. 8 g + 7), the activations the B operand (column = row of the
+// tile).  The FP32 result of a layer -- lane 16 g + c holds units 4 g + r
+// (r < 4) of every 16-unit block for tile row c -- is the B operand of the
+// next layer as it stands once the next layer's weights use the matching K
+// order: slot j of K-block kb in lane group g is hidden unit
+// 16 (2 kb + j / 4) + 4 g + j % 4.  Layer 1 takes the inputs in slots
+// 0 .. in-1, a constant 1 in slot `in` (whose weight column is b1) and zeros
+// up to 32; layer 3 pads the outputs to 16 rows.  14 MFMAs per tile.
+#pragma once
+
+#include "pf_internal.h"
+
+namespace pfk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int HID = MLP_HIDDEN;
+// inputs of the FH-N proposal: v patch (9), w patch (9), residual of the
+// nearest observation, tau, the offsets of that observation (2)
+constexpr int LEARNED_FEATURES = 22;
+
+struct MlpRegs {
+  bf16x8 a1[4];     // layer 1, one per block of 16 hidden units
+  bf16x8 a2[4][2];  // layer 2 [output block][K block]
+  bf16x8 a3[2];     // layer 3 [K block]
+  f32x4 b2[4];      // bias of layer 2 in the accumulator layout
+  f32x4 b3;         // bias of layer 3 in the accumulator layout
+};
+
+__device__ __forceinline__ int hid_slot(int kb, int g, int j) {
+  return 16 * (2 * kb + (j >> 2)) + 4 * g + (j & 3);
+}
+__device__ __forceinline__ float bf16r(float x) { return (float)(__bf16)x; }
+
+__device__ inline void mlp_load(const float *__restrict__ p, int in_dim, int out_dim, MlpRegs &w) {
+  const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
+  const float *W1 = p, *b1 = W1 + HID * in_dim, *W2 = b1 + HID, *b2 = W2 + HID * HID;
+  const float *W3 = b2 + HID, *b3 = W3 + out_dim * HID;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int u = 16 * b + c;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * g + j;
+      const float v = k < in_dim ? W1[u * in_dim + k] : (k == in_dim ? b1[u] : 0.f);
+      w.a1[b][j] = (__bf16)v;
+    }
+  }
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w.a2[ob][kb][j] = (__bf16)W2[(16 * ob + c) * HID + hid_slot(kb, g, j)];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      w.a3[kb][j] = (__bf16)(c < out_dim ? W3[c * HID + hid_slot(kb, g, j)] : 0.f);
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w.b2[ob][r] = bf16r(b2[16 * ob + 4 * g + r]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) w.b3[r] = (4 * g + r) < out_dim ? bf16r(b3[4 * g + r]) : 0.f;
+}
+
+// ReLU, rounded to bfloat16, in the B-operand order of the next layer
+__device__ __forceinline__ bf16x8 relu_pack(const f32x4 &lo, const f32x4 &hi) {
+  bf16x8 o;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    o[r] = (__bf16)fmaxf(lo[r], 0.f);
+    o[4 + r] = (__bf16)fmaxf(hi[r], 0.f);
+  }
+  return o;
+}
+
+// u_theta of the 16 tile rows whose features this lane holds in F (slots
+// 8 g .. 8 g + 7 of row c).  Lane c of group 0 receives outputs 0..3 of row c.
+__device__ __forceinline__ f32x4 mlp_tile(const MlpRegs &w, const bf16x8 &F) {
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  f32x4 a1[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) a1[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.a1[b], F, z, 0, 0, 0);
+  const bf16x8 h1[2] = {relu_pack(a1[0], a1[1]), relu_pack(a1[2], a1[3])};
+  f32x4 a2[4];
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    a2[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.a2[ob][0], h1[0], w.b2[ob], 0, 0, 0);
+    a2[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.a2[ob][1], h1[1], a2[ob], 0, 0, 0);
+  }
+  const bf16x8 h2[2] = {relu_pack(a2[0], a2[1]), relu_pack(a2[2], a2[3])};
+  f32x4 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.a3[0], h2[0], w.b3, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.a3[1], h2[1], o, 0, 0, 0);
+}
+
+}  // namespace pfk

@@ -87,7 +87,7 @@ struct Layout {
       fmeanw, emean, cnt, gpart, params, nearest, end;
 };
 
-constexpr int LEARNED_IN = 20, LEARNED_OUT = 2;  // FH-N node features, (u_v, u_w)
+constexpr int LEARNED_IN = 22, LEARNED_OUT = 2;  // FH-N node features, (u_v, u_w)
 constexpr int LEARNED_MAX_J = 48;
 
 Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bool learned) {
@@ -1008,6 +1008,234 @@ pf_status pf_mlp_forward(const float *d_params, int32_t in_dim, int32_t out_dim,
   if (rows < 0) return fail(PF_ERR_INVALID_ARG, "rows < 0");
   if (rows > 0 && (!d_params || !d_x || !d_out)) return fail(PF_ERR_INVALID_ARG, "NULL buffer");
   PF_HIP(pfk::launch_mlp_forward(d_params, in_dim, out_dim, d_x, rows, d_out, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_mlp_grad_work_bytes(int32_t in_dim, int32_t out_dim, int64_t rows, size_t *out_bytes) {
+  if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
+  const int np = pf_mlp_nparams(in_dim, out_dim);
+  if (np < 0) return fail(PF_ERR_INVALID_ARG, "in_dim must be in [1, 31] and out_dim in [1, 4]");
+  if (rows < 1) return fail(PF_ERR_INVALID_ARG, "rows < 1");
+  *out_bytes = sizeof(float) * pfk::mlp_grad_work_floats((rows + 15) / 16, np);
+  return PF_OK;
+}
+
+pf_status pf_mlp_loss_grad(const float *d_params, int32_t in_dim, int32_t out_dim, const float *d_x,
+                           const float *d_target, int64_t rows, float *d_grad, float *d_loss,
+                           void *d_work, size_t work_bytes, void *stream) {
+  size_t need = 0;
+  PF_TRY(pf_mlp_grad_work_bytes(in_dim, out_dim, rows, &need));
+  if (!d_params || !d_x || !d_target || !d_grad) return fail(PF_ERR_INVALID_ARG, "NULL buffer");
+  if (!d_work || work_bytes < need)
+    return fail(PF_ERR_WORKSPACE, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+  PF_HIP(pfk::launch_mlp_grad_rows(d_params, in_dim, out_dim, d_x, d_target, rows, (float *)d_work,
+                                   d_grad, d_loss, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t n,
+                       double lr, double beta1, double beta2, double eps, int32_t t, void *stream) {
+  if (n < 1 || n > (1 << 30)) return fail(PF_ERR_INVALID_ARG, "n out of range");
+  if (!d_params || !d_grad || !d_m || !d_v) return fail(PF_ERR_INVALID_ARG, "NULL buffer");
+  if (t < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0))
+    return fail(PF_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  PF_HIP(pfk::launch_adam(d_params, d_grad, d_m, d_v, (int)n, lr, beta1, beta2, eps, t,
+                          (hipStream_t)stream));
+  return PF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Layout of the training workspace of an FH-N model.
+struct TrainLayout {
+  size_t obs, pmean, psd, nearest, starts, traj, ys, partial, mo, ve, end;
+  int nn, n_traj, np;
+};
+
+pf_status train_check(const pf_model_desc *m, const pf_train_desc *d) {
+  if (!m || !d) return fail(PF_ERR_INVALID_ARG, "NULL descriptor");
+  PF_TRY(check_model(*m, 0));
+  if (m->kind != PF_MODEL_FHN || m->grid_j > LEARNED_MAX_J || (m->grid_j % 4) != 0)
+    return fail(PF_ERR_UNSUPPORTED, "training needs an FH-N model with J a multiple of 4, <= %d",
+                LEARNED_MAX_J);
+  if (d->n_runs < 1 || d->run_len < 1 || (int64_t)d->n_runs * d->run_len > (1 << 24))
+    return fail(PF_ERR_INVALID_ARG, "bad n_runs / run_len");
+  if (d->batch_tiles < 1 || d->batch_tiles > (1 << 20))
+    return fail(PF_ERR_INVALID_ARG, "batch_tiles out of range");
+  if (!(d->lr > 0.0) || !(d->beta1 >= 0.0 && d->beta1 < 1.0) ||
+      !(d->beta2 >= 0.0 && d->beta2 < 1.0) || !(d->eps > 0.0))
+    return fail(PF_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  return PF_OK;
+}
+
+TrainLayout train_layout(const pf_model_desc &m, const pf_train_desc &d) {
+  TrainLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.nn = m.grid_j * m.grid_j;
+  L.n_traj = d.n_runs * d.run_len;
+  L.np = pfk::mlp_nparams(LEARNED_IN, LEARNED_OUT);
+  const size_t dx = (size_t)m.state_dim;
+  L.obs = take(sizeof(int32_t) * (size_t)m.obs_dim);
+  L.pmean = take(sizeof(float) * dx);
+  L.psd = take(sizeof(float) * dx);
+  L.nearest = take(sizeof(int32_t) * (size_t)L.nn);
+  L.starts = take(sizeof(float) * (size_t)L.n_traj * dx);
+  L.traj = take(sizeof(float) * (size_t)L.n_traj * m.steps_per_obs * dx);
+  L.ys = take(sizeof(float) * (size_t)L.n_traj * m.obs_dim);
+  L.partial = take(sizeof(float) * pfk::mlp_grad_work_floats(d.batch_tiles, L.np));
+  L.mo = take(sizeof(float) * (size_t)L.np);
+  L.ve = take(sizeof(float) * (size_t)L.np);
+  L.end = o;
+  return L;
+}
+
+pfk::ModelDev train_model_dev(const pf_model_desc &m, const TrainLayout &L, char *ws) {
+  pfk::ModelDev md{};
+  md.kind = m.kind;
+  md.dx = m.state_dim;
+  md.J = m.grid_j;
+  md.S = m.steps_per_obs;
+  md.dy = m.obs_dim;
+  md.h = (float)m.h;
+  md.p0 = (float)m.params[0];
+  md.p1 = (float)m.params[1];
+  md.p2 = (float)m.params[2];
+  md.p3 = (float)m.params[3];
+  md.sq0 = (float)(m.noise_sd[0] * std::sqrt(m.h));
+  md.sq1 = (float)(m.noise_sd[1] * std::sqrt(m.h));
+  md.inv2var = (float)(1.0 / (2.0 * m.obs_var));
+  md.obs_sd = (float)std::sqrt(m.obs_var);
+  md.obs_idx = (const int32_t *)(ws + L.obs);
+  md.prior_mean = (const float *)(ws + L.pmean);
+  md.prior_sd = (const float *)(ws + L.psd);
+  return md;
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_train_workspace_bytes(const pf_model_desc *h_model, const pf_train_desc *d,
+                                   size_t *out_bytes) {
+  if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
+  PF_TRY(train_check(h_model, d));
+  *out_bytes = train_layout(*h_model, *d).end;
+  return PF_OK;
+}
+
+pf_status pf_train_buffers(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                           float **d_starts, float **d_traj, float **d_y) {
+  PF_TRY(train_check(h_model, d));
+  if (!d_work) return fail(PF_ERR_INVALID_ARG, "NULL workspace");
+  const TrainLayout L = train_layout(*h_model, *d);
+  char *ws = (char *)d_work;
+  if (d_starts) *d_starts = (float *)(ws + L.starts);
+  if (d_traj) *d_traj = (float *)(ws + L.traj);
+  if (d_y) *d_y = (float *)(ws + L.ys);
+  return PF_OK;
+}
+
+pf_status pf_train_data(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                        size_t work_bytes, void *stream) {
+  PF_TRY(train_check(h_model, d));
+  const TrainLayout L = train_layout(*h_model, *d);
+  if (!d_work || ((uintptr_t)d_work % ALIGN) != 0 || work_bytes < L.end)
+    return fail(PF_ERR_WORKSPACE, "training workspace must be 256-byte aligned and %zu bytes", L.end);
+  const pf_model_desc &m = *h_model;
+  char *ws = (char *)d_work;
+  hipStream_t s = (hipStream_t)stream;
+  const pfk::ModelDev md = train_model_dev(m, L, ws);
+  std::vector<float> pm((size_t)m.state_dim), psd((size_t)m.state_dim);
+  for (int k = 0; k < m.state_dim; ++k) {
+    pm[(size_t)k] = (float)m.h_prior_mean[k];
+    psd[(size_t)k] = (float)m.h_prior_sd[k];
+  }
+  const int J = m.grid_j;
+  std::vector<int32_t> near((size_t)L.nn);
+  for (int n = 0; n < L.nn; ++n) {
+    const int i = n / J, j = n % J;
+    long best = -1;
+    for (int o = 0; o < m.obs_dim; ++o) {
+      const int r = m.h_obs_index[o] / J, c = m.h_obs_index[o] % J;
+      const long d2 = (long)(i - r) * (i - r) + (long)(j - c) * (j - c);
+      if (best < 0 || d2 < best) {
+        best = d2;
+        near[(size_t)n] = o;
+      }
+    }
+  }
+  PF_HIP(hipMemcpyAsync(ws + L.obs, m.h_obs_index, sizeof(int32_t) * m.obs_dim,
+                        hipMemcpyHostToDevice, s));
+  PF_HIP(hipMemcpyAsync(ws + L.pmean, pm.data(), sizeof(float) * pm.size(), hipMemcpyHostToDevice, s));
+  PF_HIP(hipMemcpyAsync(ws + L.psd, psd.data(), sizeof(float) * psd.size(), hipMemcpyHostToDevice, s));
+  PF_HIP(hipMemcpyAsync(ws + L.nearest, near.data(), sizeof(int32_t) * near.size(),
+                        hipMemcpyHostToDevice, s));
+  const pfk::Key key = pfk::make_key(d->seed);
+  PF_HIP(pfk::launch_train_sim(md, key, 0, d->n_runs, d->run_len, nullptr,
+                               (float *)(ws + L.starts), nullptr, s));
+  PF_HIP(pfk::launch_train_sim(md, key, 1, L.n_traj, 1, (const float *)(ws + L.starts),
+                               (float *)(ws + L.traj), (float *)(ws + L.ys), s));
+  // the host staging vectors must outlive the copies
+  PF_HIP(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+pf_status pf_train_steps(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                         size_t work_bytes, float *d_params, int32_t first_step, int32_t n_steps,
+                         float *d_loss, void *stream) {
+  PF_TRY(train_check(h_model, d));
+  const TrainLayout L = train_layout(*h_model, *d);
+  if (!d_work || ((uintptr_t)d_work % ALIGN) != 0 || work_bytes < L.end)
+    return fail(PF_ERR_WORKSPACE, "training workspace must be 256-byte aligned and %zu bytes", L.end);
+  if (!d_params) return fail(PF_ERR_INVALID_ARG, "NULL parameters");
+  if (first_step < 1 || n_steps < 0) return fail(PF_ERR_INVALID_ARG, "bad step range");
+  const pf_model_desc &m = *h_model;
+  char *ws = (char *)d_work;
+  hipStream_t s = (hipStream_t)stream;
+  const pfk::ModelDev md = train_model_dev(m, L, ws);
+  const pfk::Key key = pfk::make_key(d->seed);
+  float *mo = (float *)(ws + L.mo), *ve = (float *)(ws + L.ve);
+  if (first_step == 1) {
+    PF_HIP(hipMemsetAsync(mo, 0, sizeof(float) * (size_t)L.np, s));
+    PF_HIP(hipMemsetAsync(ve, 0, sizeof(float) * (size_t)L.np, s));
+  }
+  const float tsv = (float)(m.noise_sd[0] / std::sqrt(m.h));
+  const float tsw = (float)(m.noise_sd[1] / std::sqrt(m.h));
+  for (int k = 0; k < n_steps; ++k)
+    PF_HIP(pfk::launch_train_fhn_step(
+        md, key, (const float *)(ws + L.traj), (const float *)(ws + L.ys),
+        (const int32_t *)(ws + L.nearest), L.n_traj, first_step + k, d->batch_tiles, tsv, tsw,
+        d_params, (float *)(ws + L.partial), mo, ve, d->lr, d->beta1, d->beta2, d->eps,
+        d_loss ? d_loss + k : nullptr, nullptr, 1, s));
+  return PF_OK;
+}
+
+pf_status pf_train_grad(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
+                        size_t work_bytes, const float *d_params, int32_t step, float *d_grad,
+                        float *d_loss, void *stream) {
+  PF_TRY(train_check(h_model, d));
+  const TrainLayout L = train_layout(*h_model, *d);
+  if (!d_work || ((uintptr_t)d_work % ALIGN) != 0 || work_bytes < L.end)
+    return fail(PF_ERR_WORKSPACE, "training workspace must be 256-byte aligned and %zu bytes", L.end);
+  if (!d_params || !d_grad) return fail(PF_ERR_INVALID_ARG, "NULL buffer");
+  if (step < 1) return fail(PF_ERR_INVALID_ARG, "step < 1");
+  const pf_model_desc &m = *h_model;
+  char *ws = (char *)d_work;
+  const pfk::ModelDev md = train_model_dev(m, L, ws);
+  PF_HIP(pfk::launch_train_fhn_step(
+      md, pfk::make_key(d->seed), (const float *)(ws + L.traj), (const float *)(ws + L.ys),
+      (const int32_t *)(ws + L.nearest), L.n_traj, step, d->batch_tiles,
+      (float)(m.noise_sd[0] / std::sqrt(m.h)), (float)(m.noise_sd[1] / std::sqrt(m.h)),
+      const_cast<float *>(d_params), (float *)(ws + L.partial), nullptr, nullptr, 0.0, 0.0, 0.0,
+      0.0, d_loss, d_grad, 0, (hipStream_t)stream));
   return PF_OK;
 }
 

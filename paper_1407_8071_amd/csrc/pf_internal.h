@@ -145,6 +145,23 @@ hipError_t launch_grid_steps_learned(const EnsDev &e, IvArg iv, int yoff, const 
                                      const float *params, const int32_t *nearest, double sd0,
                                      double sd1, int blocks, hipStream_t s);
 
+// training of u_theta: partial-gradient buffer size (floats) for ntiles
+// tiles of 16 rows, the gradient over explicit rows, Adam, one FH-N training
+// step (minibatch from stored trajectories + Adam), the training paths
+size_t mlp_grad_work_floats(int64_t ntiles, int np);
+hipError_t launch_mlp_grad_rows(const float *params, int in_dim, int out_dim, const float *X,
+                                const float *T, int64_t rows, float *partial, float *grad,
+                                float *loss, hipStream_t s);
+hipError_t launch_adam(float *params, const float *grad, float *mo, float *ve, int n, double lr,
+                       double beta1, double beta2, double eps, int t, hipStream_t s);
+hipError_t launch_train_fhn_step(const ModelDev &md, Key key, const float *traj, const float *ys,
+                                 const int32_t *nearest, int n_traj, int step, int batch_tiles,
+                                 float tsv, float tsw, float *params, float *partial, float *mo,
+                                 float *ve, double lr, double beta1, double beta2, double eps,
+                                 float *loss, float *grad, int adam, hipStream_t s);
+hipError_t launch_train_sim(const ModelDev &md, Key key, int mode, int count, int run_len,
+                            const float *in, float *out, float *ys, hipStream_t s);
+
 // ---- random-number hook ----------------------------------------------------
 hipError_t launch_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
                                 uint32_t *bits, float *z, hipStream_t s);

@@ -65,9 +65,10 @@ def test_learned_flag_validation(pf):
     st0, n0 = _bytes(pf, [f20], [(0, 2, 16, 0, 1)])
     st1, n1 = _bytes(pf, [f20], [(0, 2, 16, 1, 1)])
     assert st0 == 0 and st1 == 0
-    assert n1 >= n0 + 4 * 5634 + 4 * 400                       # parameters + nearest map
+    assert n1 >= n0 + 4 * 5762 + 4 * 400                       # parameters + nearest map
     assert _bytes(pf, [pf_inputs.fhn(50)], [(0, 1, 4, 1, 1)])[0] == 2  # J > 48
     assert pf.lib().pf_mlp_nparams(20, 2) == 5634
+    assert pf.lib().pf_mlp_nparams(22, 2) == 5762
     assert pf.lib().pf_mlp_nparams(3, 1) == 64 * 3 + 64 + 64 * 64 + 64 + 64 + 1
     assert pf.lib().pf_mlp_nparams(32, 2) == -1
     assert pf.lib().pf_mlp_nparams(20, 5) == -1

@@ -148,7 +148,7 @@ def test_zero_network_is_the_bootstrap_interval(pf, orc, torch_mod, fused):
 @pytest.mark.parametrize("spec,M,N,fused", [(F20, 2, 5, False), (F20, 2, 4, True), (F40, 1, 2, True)])
 def test_constant_correction_matches_oracle(pf, orc, torch_mod, spec, M, N, fused):
     seed, t = 31 + N, 3
-    p = np.zeros(orc.mlp_nparams(20, 2))
+    p = np.zeros(orc.mlp_nparams(22, 2))
     p[-2:] = [0.0625, -0.03125]  # b3: u_v, u_w (exact in bfloat16)
     X0 = _cloud(orc, spec, M, N, seed)
     m = orc.Model(spec)
@@ -182,7 +182,7 @@ def test_random_network_interval_matches_oracle(pf, orc, torch_mod):
     requires the states of nearly every node to agree to 1e-5."""
     spec, M, N, seed, t = F20, 1, 4, 41, 2
     rng = np.random.default_rng(3)
-    p = rng.standard_normal(orc.mlp_nparams(20, 2)) * 0.05
+    p = rng.standard_normal(orc.mlp_nparams(22, 2)) * 0.05
     p = p.astype(np.float32).astype(np.float64)
     X0 = _cloud(orc, spec, M, N, seed)
     m = orc.Model(spec)
@@ -197,7 +197,7 @@ def test_random_network_interval_matches_oracle(pf, orc, torch_mod):
     lw = f.get_logweights(0).cpu().numpy()[0].astype(np.float64)
     Xr, dlw = orc.propagate_learned(m, p, seed, 0, t, X0[0].astype(np.float64), y32)
     rlw = orc.weights(m, Xr, y32) + dlw
-    W1, b1, W2, b2, W3, b3 = orc.mlp_unpack(orc.bf16(p), 20, 2)
+    W1, b1, W2, b2, W3, b3 = orc.mlp_unpack(orc.bf16(p), 22, 2)
     lip = np.abs(W3).sum(1).max() * np.abs(W2).sum(1).max() * np.abs(W1).sum(1).max()
     du = lip * 2.0 ** -8 * 1.5       # one feature flip of a state of size <= 1.5
     dx_max = spec["h"] * spec["S"] * du * 4

@@ -9,15 +9,19 @@ proposals is the importance-function extension the paper's closing remarks
 * the MLP forward pass and its gradient against torch's own Linear/ReLU
   modules and autograd in float64, and against central finite differences;
 * bfloat16 rounding against torch's float32 -> bfloat16 cast;
-* the 20 FH-N features against hand-derived values (edge replication,
-  nearest observation with ties to the lower index, tau);
+* the 22 FH-N features against hand-derived values (edge replication,
+  nearest observation with ties to the lower index, tau, offsets);
 * u = 0 reproduces the bootstrap filter bit for bit;
 * the increment-density ratio has mean one under the proposal;
 * with an arbitrary fixed u the filter still tracks the exact Kalman mean and
   its evidence estimate stays unbiased (Lemma 2), which pins the ratio's sign
   and both of its terms;
 * the closed-form minimiser of the regression objective on the OU model
-  against a Monte Carlo regression run with numpy's own generator.
+  against a Monte Carlo regression run with numpy's own generator;
+* Adam against torch.optim.Adam;
+* the training paths: every increment of a trajectory is its Euler step with
+  the documented noise, which is N(0, 1) and independent across the run,
+  trajectory and minibatch streams.
 """
 import numpy as np
 import pytest
@@ -161,13 +165,17 @@ def test_nearest_observation_and_features(orc):
                               c + J + 1]
     g = orc.fhn_features(m, x, y, k=19, nodes=[0])
     assert g[0, 19] == 1.0 / 20
+    # offsets of the nearest observation, halved: (0,0) -> (2,2); (5,19) -> (6,18)
+    assert list(f[0, 20:]) == [1.0, 1.0]
+    assert list(f[1, 20:]) == [0.5, -0.5]
+    assert list(f[2, 20:]) == [-0.5, -0.5]  # (7,3) -> (6,2)
 
 
 @pytest.mark.parametrize("which", ["fhn", "ou"])
 def test_zero_network_is_the_bootstrap_filter(orc, which):
     if which == "fhn":
         spec = pf_inputs.fhn(20)
-        in_dim, out_dim, N = 20, 2, 3
+        in_dim, out_dim, N = 22, 2, 3
     else:
         spec = pf_inputs.ou1d(theta=1.0, sd=1.0, h=0.01, S=10, obs_var=0.3)
         in_dim, out_dim, N = 3, 1, 64
@@ -266,7 +274,7 @@ def test_learned_fhn_interval_is_finite_and_resamples(orc):
     spec = pf_inputs.fhn(20)
     m = orc.Model(spec)
     rng = np.random.default_rng(2)
-    p = _rand_params(orc, rng, 20, 2, scale=0.05)
+    p = _rand_params(orc, rng, 22, 2, scale=0.05)
     _, y = orc.simulate(m, 3, 1)
     X = orc.init(m, 4, 0, 3)
     r = orc.filter_interval_learned(m, p, 4, 0, 1, X, y[0])
@@ -275,3 +283,44 @@ def test_learned_fhn_interval_is_finite_and_resamples(orc):
     Xp, dlw = orc.propagate_learned(m, p, 4, 0, 1, X, y[0])
     assert np.all(dlw != 0.0)
     assert np.array_equal(r["lw"], orc.weights(m, Xp, y[0]) + dlw)
+
+
+def test_adam_matches_torch(orc):
+    rng = np.random.default_rng(4)
+    p0 = rng.standard_normal(50)
+    grads = rng.standard_normal((7, 50))
+    p, mo, ve = p0.copy(), np.zeros(50), np.zeros(50)
+    w = torch.nn.Parameter(torch.from_numpy(p0.copy()))
+    opt = torch.optim.Adam([w], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    for t in range(1, 8):
+        orc.adam_step(p, grads[t - 1], mo, ve, 1e-2, 0.9, 0.999, 1e-8, t)
+        w.grad = torch.from_numpy(grads[t - 1].copy())
+        opt.step()
+    assert np.allclose(p, w.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_training_paths_are_model_paths(orc):
+    spec = pf_inputs.fhn(20)
+    m = orc.Model(spec)
+    starts = orc.train_run(m, 3, 2, 3)
+    assert starts.shape == (3, 800) and np.all(np.isfinite(starts))
+    assert not np.allclose(starts[0], starts[1])
+    traj, y, z = orc.train_trajectory(m, 3, 5, starts[1])
+    assert np.array_equal(traj[0], starts[1])
+    for k in range(spec["S"] - 1):
+        assert np.allclose(orc.em_step(m, traj[k], z[k]), traj[k + 1], rtol=0, atol=0)
+    # the noise of the trajectory, the run and the step-0 bootstrap draw are
+    # distinct streams of standard normals
+    zz = z.ravel()
+    assert abs(zz.mean()) < 4 / np.sqrt(zz.size) and abs(zz.var() - 1) < 0.05
+    zb = orc.step_noise(m, 3, orc.P_PROP, 5, 0, 0)
+    assert abs(np.corrcoef(z[0], zb)[0, 1]) < 0.1
+    # y is the observation of the state after the last step
+    xS = orc.em_step(m, traj[-1], z[-1])
+    r = (y - xS[m.obs_idx]) / np.sqrt(spec["obs_var"])
+    assert np.all(np.abs(r) < 6)
+    tiles = [orc.train_tile(m, 3, 100, 7, b) for b in range(2000)]
+    rs, ks, ns = map(np.array, zip(*tiles))
+    assert rs.min() >= 0 and rs.max() < 100 and ks.min() >= 0 and ks.max() < 20
+    assert np.all(ns % 16 == 0) and ns.max() <= 400 - 16
+    assert len(set(ks)) == 20 and len(set(ns)) == 25
