@@ -55,6 +55,11 @@ FHN_SLOTS_PER_NODE_STEP = 0.5 * PHILOX_SLOTS + BOXMULLER_SLOTS + 7 + 8 + 4
 # FH-N streaming Euler step: every node's v and w read and written once.
 FHN_BYTES_PER_NODE_STEP = 16.0
 
+# Learned proposal: the MLP 22 -> 64 -> 64 -> 2 per node and Euler step,
+# 2 (22*64 + 64*64 + 64*2) FLOP, against the dense bfloat16 MFMA peak.
+MLP_FLOP_PER_NODE_STEP = 2.0 * (22 * 64 + 64 * 64 + 64 * 2)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB; fetch scaled x2, write x1 by the same counters on a 1 GiB
 # copy), recorded in profiles/hbm_counters_fhn_stream_step_and_lorenz_propagation.md
@@ -117,12 +122,125 @@ def cpu_baseline(spec, M, N, y_host, target_s):
                       f"({steps:.3g} particle-steps, FP64, one filter per core)"}
 
 
+def _run_filter(pf, torch, spec, M, N, flags, params, y, warmup, steps, est_out):
+    """Warm-up, then `steps` timed intervals with the ensemble estimate of
+    each kept on the device; returns (ms, kernel ms, kernel launches)."""
+    import ctypes as C
+    f = pf.ParticleFilter([spec], [(0, M, N, 1, flags)], fused=True)
+    if params is not None:
+        f.set_proposal(0, params)
+    stream = torch.cuda.current_stream()
+    for t in range(warmup):
+        f.step(y[t])
+    torch.cuda.synchronize()
+    f.read_profile()
+    f.set_profiling(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    dx = spec["dx"]
+    lz = torch.empty(M, dtype=torch.float64, device="cuda")
+    e0.record(stream)
+    for k, t in enumerate(range(warmup, warmup + steps)):
+        f.step(y[t])
+        pf._check(pf.lib().pf_estimate(f._ctx, C.c_void_p(est_out[k].data_ptr()), None,
+                                       C.c_void_p(lz.data_ptr()), None, pf._stream(None)))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    f.set_profiling(False)
+    k_ms, k_n = f.read_profile()
+    del dx
+    return e0.elapsed_time(e1), k_ms, k_n
+
+
+def learned_main(a):
+    """FH-N 40 x 40 with the learned proposal (M = 64 x N = 128) against the
+    bootstrap filter at N = 512 on the same GPU-simulated observations: wall
+    time per assimilated observation and MSE of v against the truth; the
+    training is timed on its own."""
+    import torch
+    import paper_1407_8071_amd as pf
+    factory, M, N, _ = pf_inputs.WORKLOADS[a.workload]
+    spec = factory()
+    tc = pf_inputs.LEARNED_TRAINING
+    torch.cuda.set_device(0)
+    # training on model-simulated trajectories
+    t0 = time.perf_counter()
+    tr = pf.Trainer(spec, tc["n_runs"], tc["run_len"], tc["batch_tiles"], seed=tc["seed"])
+    tr.data()
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    rng = np.random.default_rng(1)
+    n_in = 22
+    params = np.zeros(pf.mlp_nparams(n_in, 2), np.float32)
+    params[:64 * n_in] = rng.standard_normal(64 * n_in) * np.sqrt(2 / n_in)
+    o = 64 * n_in + 64
+    params[o:o + 4096] = rng.standard_normal(4096) * np.sqrt(2 / 64)
+    p = torch.from_numpy(params).cuda()
+    t1 = time.perf_counter()
+    n_steps = 0
+    for n, lr in tc["schedule"]:
+        tr.desc.lr = lr
+        tr.steps(p, n)
+        n_steps += n
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del tr
+    torch.cuda.empty_cache()
+    # observations from the library's truth simulator
+    T = a.warmup + a.steps
+    sim = pf.ParticleFilter([spec], [(0, 1, 1, 1)], fused=True)
+    xt, y = sim.simulate(0, 1, T)
+    torch.cuda.synchronize()
+    nn = spec["J"] ** 2
+    truth = xt[1 + a.warmup:1 + T, :nn].double()
+    res = {}
+    runs = (("learned", N, pf.ENS_LEARNED, p), ("bootstrap_N%d" % N, N, 0, None),
+            ("bootstrap_N%d" % (4 * N), 4 * N, 0, None),
+            ("bootstrap_N%d" % (16 * N), 16 * N, 0, None))
+    for name, n_p, flags, prm in runs:
+        est = torch.empty((a.steps, spec["dx"]), dtype=torch.float64, device="cuda")
+        ms, k_ms, k_n = _run_filter(pf, torch, spec, M, n_p, flags, prm, y, a.warmup, a.steps, est)
+        mse = torch.mean((est[:, :nn] - truth) ** 2).item()
+        psteps = M * n_p * spec["S"] * a.steps
+        res[name] = {"M": M, "N": n_p, "ms_per_interval": ms / a.steps, "mse_v": mse,
+                     "particle_steps_per_s": psteps / (ms / 1e3),
+                     "kernel_avg_us": k_ms / max(k_n, 1) * 1e3, "kernel_launches": k_n}
+        torch.cuda.empty_cache()
+    L = res["learned"]
+    k_avg_s = L["kernel_avg_us"] / 1e6
+    flop = MLP_FLOP_PER_NODE_STEP * nn * spec["S"] * M * N
+    achieved = flop / k_avg_s / 1e12
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_grid_steps_learned", "algorithmic_flop_per_launch": flop,
+                "kernel_avg_us": L["kernel_avg_us"], "launches": L["kernel_launches"]}
+    line = {
+        "metric": "particle-steps/s", "value": L["particle_steps_per_s"],
+        "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": L["ms_per_interval"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 MFMA network, f32 filter",
+        "data": "synthetic (GPU-simulated truth and observations; model-simulated training paths)",
+        "config": {"workload": a.workload, "model": "fhn", "J": spec["J"], "M": M, "N": N,
+                   "S": spec["S"], "path": "fused"},
+        "learned": L, "bootstrap": [v for k, v in res.items() if k != "learned"],
+        "learned_speedup_vs_bootstrap_N%d" % (4 * N):
+            res["bootstrap_N%d" % (4 * N)]["ms_per_interval"] / L["ms_per_interval"],
+        "training": {"trajectories": tc["n_runs"] * tc["run_len"], "adam_steps": n_steps,
+                     "rows_per_step": 16 * tc["batch_tiles"], "data_s": t_data, "train_s": t_train},
+        "roofline": roofline, "cpu_baseline": None,
+    }
+    print(json.dumps(line))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               "(the ensemble shards by whole filters, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "fhn40_learned_64x128":
+        learned_main(a)
+        return
     import torch
     import paper_1407_8071_amd as pf
 

@@ -20,24 +20,26 @@ constexpr int FWD_THREADS = 256;
 __global__ void __launch_bounds__(FWD_THREADS)
 k_mlp_forward(const float *__restrict__ p, int in_dim, int out_dim, const float *__restrict__ X,
               int64_t rows, float *__restrict__ out) {
-  MlpRegs w;
-  mlp_load(p, in_dim, out_dim, w);
-  const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
-  const int64_t ntiles = (rows + 15) / 16;
+  Mlp32Regs w;
+  mlp32_load(p, in_dim, out_dim, w);
+  const int l = threadIdx.x & 63, c = l & 31, h = l >> 5;
+  const int64_t ntiles = (rows + 31) / 32;
   const int64_t wave = (int64_t)blockIdx.x * (FWD_THREADS / 64) + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * (FWD_THREADS / 64);
   for (int64_t t = wave; t < ntiles; t += nwaves) {
-    const int64_t row = 16 * t + c;
+    const int64_t row = 32 * t + c;
     const bool ok = row < rows;
-    bf16x8 F;
+    bf16x8 F[2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = 8 * g + j;
-      const float v = (ok && k < in_dim) ? X[row * in_dim + k] : (k == in_dim ? 1.f : 0.f);
-      F[j] = (__bf16)v;
-    }
-    const f32x4 o = mlp_tile(w, F);
-    if (g == 0 && ok) {
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 16 * kb + 8 * h + j;
+        const float v = (ok && k < in_dim) ? X[row * in_dim + k] : (k == in_dim ? 1.f : 0.f);
+        F[kb][j] = (__bf16)v;
+      }
+    const f32x16 o = mlp32_tile(w, F);
+    if (h == 0 && ok) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (r < out_dim) out[row * out_dim + r] = o[r];
@@ -61,18 +63,24 @@ k_mlp_forward(const float *__restrict__ p, int in_dim, int out_dim, const float 
 // gather); the last step ends with the log-weight: observation term plus the
 // accumulated ratio.
 //
-// LDS (floats): planes [2 buffers][v, w][(J+2)^2], u [2][J*J], y of the
-// nearest observation [J*J], halo index of that observation [J*J] (int),
-// 32 of reduction scratch.
-constexpr int LS_THREADS = 320;  // 5 waves
+// LDS (floats): planes [2 buffers][v, w][(J+2)^2], the compensation terms of
+// the Euler sums [v, w][J*J], u [2][J*J], y of the nearest observation [J*J],
+// that observation's halo index and offsets [J*J] (int), 32 of reduction
+// scratch.
+constexpr int LS_THREADS = 256;  // 4 waves: two workgroups per CU
 
 struct LearnedConst {
   float c1v, c2v, c1w, c2w;  // sqrt(h)/sd and h/(2 sd^2) per variable class
 };
 
-__device__ __forceinline__ void put_node(float *pl, int H2, int J, int node, float v, float w) {
-  const int i = node / J, j = node - i * J, W = J + 2;
-  const int hi = (i + 1) * W + (j + 1);
+// row of node n = i J + j for n < 4096, J <= 64: (n + 1/2) / J lies at least
+// 1/(2J) inside (i, i + 1), far above the rounding of the float product
+__device__ __forceinline__ int node_row(int n, float invJ) {
+  return (int)(((float)n + 0.5f) * invJ);
+}
+
+__device__ __forceinline__ void put_node(float *pl, int H2, int J, int i, int j, float v, float w) {
+  const int W = J + 2, hi = (i + 1) * W + (j + 1);
   float *pv = pl, *pw = pl + H2;
   pv[hi] = v;
   pw[hi] = w;
@@ -92,7 +100,6 @@ __device__ __forceinline__ int halo_index(int J, int node) {
   return (i + 1) * (J + 2) + (j + 1);
 }
 
-template <int PPT>
 __global__ void __launch_bounds__(LS_THREADS)
 k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
                      const float *__restrict__ Xin, const int32_t *__restrict__ anc,
@@ -103,33 +110,30 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
   const int t = iv_t(iv);
   const float *y = iv_y(iv, t) + yoff;
   const int J = md.J, nn = J * J, np = nn / 2, W = J + 2, H2 = W * W;
+  const float invJ = 1.f / (float)J;
   float *planes = lds;                    // [2][2][H2]
-  float *U = lds + 4 * H2;                // [2][nn]
+  float *CMP = lds + 4 * H2;              // [2][nn]
+  float *U = CMP + 2 * nn;                // [2][nn]
   float *YN = U + 2 * nn;                 // [nn]
   int *ON = (int *)(YN + nn);             // [nn]
   float *red = (float *)(ON + nn);        // [32]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, c = lane & 15, g = lane >> 4;
-  const int nwaves = LS_THREADS / 64, ntiles = (nn + 15) / 16;
+  const int nwaves = LS_THREADS / 64, ntiles = (nn + 31) / 32;
+  const int c32 = lane & 31, h = lane >> 5;
+  (void)c; (void)g;
 
-  MlpRegs w;
-  mlp_load(params, LEARNED_FEATURES, 2, w);
-  // feature slots 8 g + j of this lane: patch offsets into the current buffer
-  // (v plane, then w plane), or a constant (tau, 1, 0) for the others; the
-  // residual and the observation offsets (slots 18, 20, 21) are filled in
-  // per node below
+  Mlp32Regs w;
+  mlp32_load(params, LEARNED_FEATURES, 2, w);
+  // inputs of lane half h: slots 8 h .. 8 h + 7 (patch values: offsets from
+  // the node's halo index, v plane then w plane) and, on half 0, slots
+  // 16 .. 23 (the last two w values, residual, tau, observation offsets,
+  // the constant 1, 0); half 1 holds zeros in slots 24 .. 31
   int fo[8];
-  bool frel[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int k = 8 * g + j;
-    if (k < 18) {
-      const int q = k < 9 ? k : k - 9;
-      fo[j] = (k < 9 ? 0 : H2) + (q / 3 - 1) * W + (q % 3 - 1);
-      frel[j] = true;
-    } else {
-      fo[j] = 0;
-      frel[j] = k == 18;  // the residual: replaced below
-    }
+    const int k = 8 * h + j;
+    const int q = k < 9 ? k : k - 9;
+    fo[j] = (k < 9 ? 0 : H2) + (q / 3 - 1) * W + (q % 3 - 1);
   }
   // per node: y of the nearest observation, and its halo index (bits 0-15)
   // with its row and column offsets + 128 (bits 16-23, 24-31)
@@ -144,18 +148,14 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
     const int m = p / N, i = p - m * N;
     const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
     const float *in = Xin + ((size_t)m * N + src) * (2 * nn);
-    float sv[PPT][2], sw[PPT][2], cv[PPT][2], cw[PPT][2];
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      const int pr = tid + q * LS_THREADS;
-      if (pr < np) {
-        const float2 a = *(const float2 *)(in + 2 * pr);
-        const float2 b = *(const float2 *)(in + nn + 2 * pr);
-        sv[q][0] = a.x; sv[q][1] = a.y; sw[q][0] = b.x; sw[q][1] = b.y;
-        cv[q][0] = cv[q][1] = cw[q][0] = cw[q][1] = 0.f;
-        put_node(planes, H2, J, 2 * pr, a.x, b.x);
-        put_node(planes, H2, J, 2 * pr + 1, a.y, b.y);
-      }
+    for (int pr = tid; pr < np; pr += LS_THREADS) {
+      const float2 a = *(const float2 *)(in + 2 * pr);
+      const float2 b = *(const float2 *)(in + nn + 2 * pr);
+      const int ni = node_row(2 * pr, invJ), nj = 2 * pr - ni * J;
+      put_node(planes, H2, J, ni, nj, a.x, b.x);
+      put_node(planes, H2, J, ni, nj + 1, a.y, b.y);
+      *(float2 *)(CMP + 2 * pr) = make_float2(0.f, 0.f);
+      *(float2 *)(CMP + nn + 2 * pr) = make_float2(0.f, 0.f);
     }
     __syncthreads();
     float dl = 0.f;
@@ -164,73 +164,73 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
     for (int st = 0; st < md.S; ++st) {
       const float tau = (float)(md.S - st) / (float)md.S;
       const float *pc = planes + cur * 2 * H2;
-      // (A) drift corrections of every node
-      for (int tt = wid; tt < ntiles; tt += nwaves) {
-        const int node = min(16 * tt + c, nn - 1);
-        const int ctr = halo_index(J, node);
-        bf16x8 F;
+      // (A) drift corrections of every node: 32-node MLP tiles per wave; the
+      // inputs of the next tile are read while this tile's MFMAs run
+      auto inputs = [&](int tt, bf16x8 F[2]) {
+        const int node = min(32 * tt + c32, nn - 1);
+        const int ni = node_row(node, invJ), nj = node - ni * J;
+        const int ctr = (ni + 1) * W + (nj + 1);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = 8 * g + j;
-          const float cst = k == 19 ? tau : (k == LEARNED_FEATURES ? 1.f : 0.f);
-          F[j] = (__bf16)(frel[j] ? pc[ctr + fo[j]] : cst);
+        for (int j = 0; j < 8; ++j) F[0][j] = (__bf16)pc[ctr + fo[j]];
+        const float w7 = pc[ctr + H2 + W], w8 = pc[ctr + H2 + W + 1];
+        const unsigned on = (unsigned)ON[node];
+        const float res = YN[node] - pc[on & 0xFFFFu];
+        const float f1[8] = {w7, w8, res, tau, 0.5f * (float)((int)((on >> 16) & 0xFFu) - 128),
+                             0.5f * (float)((int)(on >> 24) - 128), 1.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) F[1][j] = (__bf16)(h == 0 ? f1[j] : 0.f);
+      };
+      bf16x8 Fc[2], Fn[2];
+      if (wid < ntiles) inputs(wid, Fc);
+      for (int tt = wid; tt < ntiles; tt += nwaves) {
+        if (tt + nwaves < ntiles) inputs(tt + nwaves, Fn);
+        const f32x16 o = mlp32_tile(w, Fc);
+        if (h == 0 && 32 * tt + c32 < nn) {
+          U[32 * tt + c32] = o[0];
+          U[nn + 32 * tt + c32] = o[1];
         }
-        if (g == 2) {
-          const unsigned on = (unsigned)ON[node];
-          F[2] = (__bf16)(YN[node] - pc[on & 0xFFFFu]);
-          F[4] = (__bf16)(0.5f * (float)((int)((on >> 16) & 0xFFu) - 128));
-          F[5] = (__bf16)(0.5f * (float)((int)(on >> 24) - 128));
-        }
-        const f32x4 o = mlp_tile(w, F);
-        if (g == 0 && 16 * tt + c < nn) {
-          U[16 * tt + c] = o[0];
-          U[nn + 16 * tt + c] = o[1];
-        }
+        Fc[0] = Fn[0];
+        Fc[1] = Fn[1];
       }
       __syncthreads();
-      // (B) Euler-Maruyama with the corrected drift
+      // (B) Euler-Maruyama with the corrected drift; the compensation terms
+      // of the sums stay in LDS
       float *pn = planes + (cur ^ 1) * 2 * H2;
+      for (int pr = tid; pr < np; pr += LS_THREADS) {
+        float z[4];
+        normals4(philox((uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st),
+                        (P_PROP << 24) | (uint32_t)pr, key), z);
+        const int ni = node_row(2 * pr, invJ), nj0 = 2 * pr - ni * J;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        const int pr = tid + q * LS_THREADS;
-        if (pr < np) {
-          float z[4];
-          normals4(philox((uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st),
-                          (P_PROP << 24) | (uint32_t)pr, key), z);
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const int node = 2 * pr + e;
-            const int hi = halo_index(J, node);
-            const float cc = sv[q][e];
-            const float lap = (((pc[hi - W] - cc) + (pc[hi + W] - cc)) + (pc[hi - 1] - cc)) +
-                              (pc[hi + 1] - cc);
-            const float uv = U[node], uw = U[nn + node];
-            const float zv = z[2 * e], zw = z[2 * e + 1];
-            float nv, nw;
-            fhn_node_step<true>(md, cc, sw[q][e], lap, zv, zw, uv, uw, nv, nw, cv[q][e], cw[q][e]);
-            sv[q][e] = nv;
-            sw[q][e] = nw;
-            dl += (-(lc.c1v * uv * zv) - lc.c2v * uv * uv) + (-(lc.c1w * uw * zw) - lc.c2w * uw * uw);
-          }
-          put_node(pn, H2, J, 2 * pr, sv[q][0], sw[q][0]);
-          put_node(pn, H2, J, 2 * pr + 1, sv[q][1], sw[q][1]);
+        for (int e = 0; e < 2; ++e) {
+          const int node = 2 * pr + e;
+          const int hi = (ni + 1) * W + (nj0 + e + 1);
+          const float cc = pc[hi], ww = pc[H2 + hi];
+          const float lap = (((pc[hi - W] - cc) + (pc[hi + W] - cc)) + (pc[hi - 1] - cc)) +
+                            (pc[hi + 1] - cc);
+          const float uv = U[node], uw = U[nn + node];
+          const float zv = z[2 * e], zw = z[2 * e + 1];
+          float nv, nw, cv = CMP[node], cw = CMP[nn + node];
+          fhn_node_step<true>(md, cc, ww, lap, zv, zw, uv, uw, nv, nw, cv, cw);
+          CMP[node] = cv;
+          CMP[nn + node] = cw;
+          dl += (-(lc.c1v * uv * zv) - lc.c2v * uv * uv) + (-(lc.c1w * uw * zw) - lc.c2w * uw * uw);
+          put_node(pn, H2, J, ni, nj0 + e, nv, nw);
         }
       }
       __syncthreads();
       cur ^= 1;
     }
     // state out, then the log-weight: observation term + density ratio
+    const float *pc = planes + cur * 2 * H2;
     float *out = Xout + ((size_t)m * N + i) * (2 * nn);
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      const int pr = tid + q * LS_THREADS;
-      if (pr < np) {
-        *(float2 *)(out + 2 * pr) = make_float2(sv[q][0], sv[q][1]);
-        *(float2 *)(out + nn + 2 * pr) = make_float2(sw[q][0], sw[q][1]);
-      }
+    for (int pr = tid; pr < np; pr += LS_THREADS) {
+      const int ni = node_row(2 * pr, invJ), nj = 2 * pr - ni * J;
+      const int hi = (ni + 1) * W + (nj + 1);
+      *(float2 *)(out + 2 * pr) = make_float2(pc[hi], pc[hi + 1]);
+      *(float2 *)(out + nn + 2 * pr) = make_float2(pc[H2 + hi], pc[H2 + hi + 1]);
     }
     if (lw) {
-      const float *pc = planes + cur * 2 * H2;
       float acc = 0.f;
       for (int k = tid; k < md.dy; k += LS_THREADS) {
         const float r = y[k] - pc[halo_index(J, md.obs_idx[k])];
@@ -264,29 +264,20 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
 
 size_t learned_lds_bytes(int J) {
   const size_t H2 = (size_t)(J + 2) * (J + 2), nn = (size_t)J * J;
-  return sizeof(float) * (4 * H2 + 4 * nn + 32);
+  return sizeof(float) * (4 * H2 + 6 * nn + 32);
 }
 
 hipError_t set_learned_lds_limit() {
-  const int bytes = (int)learned_lds_bytes(48);
-  const void *fs[4] = {(const void *)k_grid_steps_learned<1>, (const void *)k_grid_steps_learned<2>,
-                       (const void *)k_grid_steps_learned<3>, (const void *)k_grid_steps_learned<4>};
-  for (const void *f : fs) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return hipFuncSetAttribute((const void *)k_grid_steps_learned,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)learned_lds_bytes(48));
 }
 
 int learned_resident_blocks(int J) {
-  const int np = J * J / 2, ppt = (np + LS_THREADS - 1) / LS_THREADS;
-  const size_t lds = learned_lds_bytes(J);
   int per_cu = 0, dev = 0, cus = 256;
-  const void *f = ppt <= 1 ? (const void *)k_grid_steps_learned<1>
-                  : ppt <= 2 ? (const void *)k_grid_steps_learned<2>
-                  : ppt <= 3 ? (const void *)k_grid_steps_learned<3>
-                             : (const void *)k_grid_steps_learned<4>;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, LS_THREADS, lds) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_grid_steps_learned,
+                                                   LS_THREADS, learned_lds_bytes(J)) !=
+          hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (hipGetDevice(&dev) == hipSuccess)
@@ -297,7 +288,7 @@ int learned_resident_blocks(int J) {
 hipError_t launch_mlp_forward(const float *params, int in_dim, int out_dim, const float *X,
                               int64_t rows, float *out, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  const int64_t tiles = (rows + 15) / 16;
+  const int64_t tiles = (rows + 31) / 32;
   const int64_t waves = (int64_t)FWD_THREADS / 64;
   const int blocks = (int)std::min<int64_t>((tiles + waves - 1) / waves, 4096);
   hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(FWD_THREADS), 0, s, params, in_dim, out_dim,
@@ -310,29 +301,14 @@ hipError_t launch_grid_steps_learned(const EnsDev &e, IvArg iv, int yoff, const 
                                      const float *params, const int32_t *nearest, double sd0,
                                      double sd1, int blocks, hipStream_t s) {
   const ModelDev &md = e.md;
-  if (!iv.y || md.kind != 2) return hipErrorInvalidValue;
-  const int np = md.J * md.J / 2;
-  const int ppt = (np + LS_THREADS - 1) / LS_THREADS;
+  if (!iv.y || md.kind != 2 || md.J > 48) return hipErrorInvalidValue;
   const double h = md.h;
   const LearnedConst lc{(float)(std::sqrt(h) / sd0), (float)(h / (2.0 * sd0 * sd0)),
                         (float)(std::sqrt(h) / sd1), (float)(h / (2.0 * sd1 * sd1))};
-  const size_t lds = learned_lds_bytes(md.J);
   const int MN = e.M * e.N;
-  const dim3 grid((unsigned)std::min(MN, blocks));
-#define LAUNCH_LS(P)                                                                        \
-  hipLaunchKernelGGL(k_grid_steps_learned<P>, grid, dim3(LS_THREADS), lds, s, md, e.key, e.M, \
-                     e.N, iv, yoff, Xin, anc, Xout, lw, params, nearest, lc)
-  if (ppt <= 1)
-    LAUNCH_LS(1);
-  else if (ppt <= 2)
-    LAUNCH_LS(2);
-  else if (ppt <= 3)
-    LAUNCH_LS(3);
-  else if (ppt <= 4)
-    LAUNCH_LS(4);
-  else
-    return hipErrorInvalidValue;
-#undef LAUNCH_LS
+  hipLaunchKernelGGL(k_grid_steps_learned, dim3((unsigned)std::min(MN, blocks)),
+                     dim3(LS_THREADS), learned_lds_bytes(md.J), s, md, e.key, e.M, e.N, iv, yoff,
+                     Xin, anc, Xout, lw, params, nearest, lc);
   return hipGetLastError();
 }
 

@@ -246,8 +246,8 @@ k_mlp_grad(const float *__restrict__ p, int in_dim, int out_dim, Src src, int64_
       f32x4 hv, h2v;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        hv[r] = fmaxf(a1[b][r], 0.f);
-        h2v[r] = fmaxf(a2[b][r], 0.f);
+        hv[r] = relu(a1[b][r]);
+        h2v[r] = relu(a2[b][r]);
       }
       put4(h1t, LROW, c, 16 * b + 4 * g, hv);
       put4(h2t, LROW, c, 16 * b + 4 * g, h2v);

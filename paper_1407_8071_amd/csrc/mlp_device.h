@@ -74,13 +74,19 @@ __device__ inline void mlp_load(const float *__restrict__ p, int in_dim, int out
   for (int r = 0; r < 4; ++r) w.b3[r] = (4 * g + r) < out_dim ? bf16r(b3[4 * g + r]) : 0.f;
 }
 
+// ReLU as one integer max on the bit pattern: a float with the sign bit set
+// (negative, or -0) is a negative int32 and becomes +0; others pass.
+__device__ __forceinline__ float relu(float x) {
+  return __int_as_float(max(__float_as_int(x), 0));
+}
+
 // ReLU, rounded to bfloat16, in the B-operand order of the next layer
 __device__ __forceinline__ bf16x8 relu_pack(const f32x4 &lo, const f32x4 &hi) {
   bf16x8 o;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    o[r] = (__bf16)fmaxf(lo[r], 0.f);
-    o[4 + r] = (__bf16)fmaxf(hi[r], 0.f);
+    o[r] = (__bf16)relu(lo[r]);
+    o[4 + r] = (__bf16)relu(hi[r]);
   }
   return o;
 }
@@ -102,6 +108,106 @@ __device__ __forceinline__ f32x4 mlp_tile(const MlpRegs &w, const bf16x8 &F) {
   const bf16x8 h2[2] = {relu_pack(a2[0], a2[1]), relu_pack(a2[2], a2[3])};
   f32x4 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.a3[0], h2[0], w.b3, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.a3[1], h2[1], o, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// The same network on v_mfma_f32_32x32x16_bf16 (tiles of 32 rows), which
+// issues at about twice the rate of the 16x16x32 form on gfx950.  Operands:
+// A lane 32 h + i holds A[i][8 h .. 8 h + 7] of a 16-wide K block, B lane
+// 32 h + c holds B[8 h .. 8 h + 7][c], and element r of the 16 accumulators
+// of lane 32 h + c is C[8 (r / 4) + 4 h + r % 4][c].  With the next layer's K
+// slot j of K-block kb in lane half h taken as hidden unit
+// 32 (kb / 2) + 8 (2 (kb % 2) + j / 4) + 4 h + j % 4, the B operand of K-block
+// kb is accumulator elements 8 (kb % 2) .. 8 (kb % 2) + 7 of 32-unit block
+// kb / 2, i.e. a contiguous slice.  Inputs: slots 16 kb + 8 h + j of the
+// lane, the constant 1 in slot `in` (bias of layer 1); 4 + 8 + 4 MFMAs per
+// 32 rows.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct Mlp32Regs {
+  bf16x8 a1[2][2];  // layer 1 [32-unit block][K block]
+  bf16x8 a2[2][4];  // layer 2 [32-unit block][K block]
+  bf16x8 a3[4];     // layer 3 [K block] (outputs padded to 32 rows)
+  f32x16 b2[2];     // bias of layer 2 in the accumulator layout
+  float b3[4];      // bias of layer 3 (added on lanes of half 0)
+};
+
+__device__ __forceinline__ int hid_slot32(int kb, int h, int j) {
+  return 32 * (kb >> 1) + 8 * (2 * (kb & 1) + (j >> 2)) + 4 * h + (j & 3);
+}
+
+__device__ inline void mlp32_load(const float *__restrict__ p, int in_dim, int out_dim,
+                                  Mlp32Regs &w) {
+  const int l = threadIdx.x & 63, c = l & 31, h = l >> 5;
+  const float *W1 = p, *b1 = W1 + HID * in_dim, *W2 = b1 + HID, *b2 = W2 + HID * HID;
+  const float *W3 = b2 + HID, *b3 = W3 + out_dim * HID;
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) {
+    const int u = 32 * ob + c;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 16 * kb + 8 * h + j;
+        const float v = k < in_dim ? W1[u * in_dim + k] : (k == in_dim ? b1[u] : 0.f);
+        w.a1[ob][kb][j] = (__bf16)v;
+      }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w.a2[ob][kb][j] = (__bf16)W2[u * HID + hid_slot32(kb, h, j)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) w.b2[ob][r] = bf16r(b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)]);
+  }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      w.a3[kb][j] = (__bf16)(c < out_dim ? W3[c * HID + hid_slot32(kb, h, j)] : 0.f);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) w.b3[r] = r < out_dim ? bf16r(b3[r]) : 0.f;
+}
+
+__device__ __forceinline__ bf16x8 relu_pack8(const f32x16 &a, int off) {
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = (__bf16)relu(a[off + j]);
+  return o;
+}
+
+// u_theta of the 32 tile rows whose inputs this lane holds (F[kb] = slots
+// 16 kb + 8 h .. + 7 of row c).  Lanes of half 0 receive outputs 0..3 of
+// row c in elements 0..3 (bias included).
+__device__ __forceinline__ f32x16 mlp32_tile(const Mlp32Regs &w, const bf16x8 F[2]) {
+  f32x16 z;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) z[r] = 0.f;
+  f32x16 a1[2];
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) {
+    a1[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a1[ob][0], F[0], z, 0, 0, 0);
+    a1[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a1[ob][1], F[1], a1[ob], 0, 0, 0);
+  }
+  const bf16x8 h1[4] = {relu_pack8(a1[0], 0), relu_pack8(a1[0], 8), relu_pack8(a1[1], 0),
+                        relu_pack8(a1[1], 8)};
+  f32x16 a2[2];
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) {
+    a2[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a2[ob][0], h1[0], w.b2[ob], 0, 0, 0);
+#pragma unroll
+    for (int kb = 1; kb < 4; ++kb)
+      a2[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a2[ob][kb], h1[kb], a2[ob], 0, 0, 0);
+  }
+  const bf16x8 h2[4] = {relu_pack8(a2[0], 0), relu_pack8(a2[0], 8), relu_pack8(a2[1], 0),
+                        relu_pack8(a2[1], 8)};
+  // layer 3 as two independent chains of two (halves the dependent latency)
+  f32x16 o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[0], h2[0], z, 0, 0, 0);
+  f32x16 q = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[2], h2[2], z, 0, 0, 0);
+  o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[1], h2[1], o, 0, 0, 0);
+  q = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[3], h2[3], q, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) o[r] = (o[r] + q[r]) + w.b3[r];
+  return o;
 }
 
 }  // namespace pfk

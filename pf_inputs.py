@@ -74,7 +74,15 @@ WORKLOADS = {
     "l63_sweep_M4096": (lorenz63, 4096, 1 << 8, 1000),
     "fhn40_64x512": (fhn, 64, 512, 200),
     "fhn20_4x64": (lambda: fhn(20), 4, 64, 20),
+    # learned proposal, compared with the bootstrap filter at N = 512
+    "fhn40_learned_64x128": (fhn, 64, 128, 200),
 }
+
+# training of the learned proposal for the fhn40 learned workload: 1e4
+# one-interval trajectories (100 model runs x 100 intervals), Adam steps of
+# 4096 tiles of 16 nodes with the learning rate stepped down
+LEARNED_TRAINING = dict(n_runs=100, run_len=100, batch_tiles=4096,
+                        schedule=((2000, 3e-4), (2000, 1e-4), (2000, 3e-5)), seed=21)
 
 
 def mixed_batch(seed: int = 1, n_l63: int = 1024, n_fhn: int = 32):
