@@ -118,6 +118,24 @@ typedef struct pf_ensemble_desc {
 
 typedef struct pf_ctx pf_ctx; /* opaque; the library owns only this host struct */
 
+/* Launch shapes of the fused path.  Every choice computes the same filter;
+   they differ in speed only (the per-filter resampling reductions run in a
+   different order with a different workgroup size, so the last bits of the
+   normalising sums and, at a CDF boundary, an ancestor index can change). */
+typedef struct pf_tuning {
+  int32_t vec_single_kernel;  /* 1: one workgroup runs a whole vector-model
+                                 filter interval (N <= 8192); 0: batched
+                                 propagation tiles, then per-filter resampling */
+  int32_t prop_tile;          /* particles per batched-propagation workgroup:
+                                 64, 128 or 256                                */
+  int32_t resample_bd_min;    /* smallest per-filter resampling workgroup: 64,
+                                 128, 256, 512 or 1024 (a filter of N particles
+                                 takes the smallest allowed size >= N, else
+                                 1024)                                          */
+  int32_t grid_blocks_per_cu; /* resident workgroups per CU of the batched FH-N
+                                 stepping kernel; 0 = as many as fit           */
+} pf_tuning;
+
 /* Bytes of device workspace pf_init needs for these descriptors. */
 pf_status pf_workspace_bytes(const pf_model_desc *h_models, int32_t n_models,
                              const pf_ensemble_desc *h_ens, int32_t n_ens,
@@ -311,6 +329,20 @@ pf_status pf_train_steps(const pf_model_desc *h_model, const pf_train_desc *d, v
 pf_status pf_train_grad(const pf_model_desc *h_model, const pf_train_desc *d, void *d_work,
                         size_t work_bytes, const float *d_params, int32_t step, float *d_grad,
                         float *d_loss, void *stream);
+
+/* ---- launch-shape tuning of the fused path ---------------------------------
+   pf_init starts from {0, 256, 256, 0}. */
+pf_status pf_get_tuning(const pf_ctx *ctx, pf_tuning *out);
+/* Rebuild the launch plan for `u` (waits for the context's queued work; the
+   next interval uses it; captured graphs are re-captured). */
+pf_status pf_set_tuning(pf_ctx *ctx, const pf_tuning *u, void *stream);
+/* Autotuner: times `reps` fused intervals (after one warm-up) on the device
+   for each candidate, searching one knob at a time (single-kernel vector
+   path, propagation tile, resampling workgroup floor, grid residency), keeps
+   the fastest, writes it to *out (may be NULL) and resets every filter to
+   its prior draw at interval 1 (the timed intervals move them).  Needs a
+   PF_OPT_FUSED context and one interval's observations d_y. */
+pf_status pf_autotune(pf_ctx *ctx, const float *d_y, int32_t reps, void *stream, pf_tuning *out);
 
 /* Timing of the dominant kernel (the propagation kernel on the plain path,
    the fused interval kernel on the fused path).  While enabled, every

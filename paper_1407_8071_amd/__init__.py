@@ -42,6 +42,14 @@ class _ModelDesc(C.Structure):
     ]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("vec_single_kernel", C.c_int32), ("prop_tile", C.c_int32),
+                ("resample_bd_min", C.c_int32), ("grid_blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class _TrainDesc(C.Structure):
     _fields_ = [("n_runs", C.c_int32), ("run_len", C.c_int32), ("batch_tiles", C.c_int32),
                 ("reserved", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
@@ -91,6 +99,9 @@ def lib():
         "pf_set_profiling": [_VP, i32],
         "pf_read_profile": [_VP, C.POINTER(C.c_double), C.POINTER(i64)],
         "pf_proposal_set": [_VP, i32, _VP, i64, _VP],
+        "pf_get_tuning": [_VP, C.POINTER(_Tuning)],
+        "pf_set_tuning": [_VP, C.POINTER(_Tuning), _VP],
+        "pf_autotune": [_VP, _VP, i32, _VP, C.POINTER(_Tuning)],
         "pf_mlp_forward": [_VP, i32, i32, _VP, i64, _VP, _VP],
         "pf_mlp_grad_work_bytes": [i32, i32, i64, C.POINTER(C.c_size_t)],
         "pf_mlp_loss_grad": [_VP, i32, i32, _VP, _VP, i64, _VP, _VP, _VP, C.c_size_t, _VP],
@@ -299,6 +310,54 @@ class ParticleFilter:
         y = torch.empty((T, m.dy), dtype=torch.float32, device="cuda")
         _check(lib().pf_simulate(self._ctx, e, seed, T, _ptr(xt), _ptr(y), _stream(stream)))
         return xt, y
+
+    # ---- launch-shape tuning -------------------------------------------------
+    def tuning(self) -> dict:
+        u = _Tuning()
+        _check(lib().pf_get_tuning(self._ctx, C.byref(u)))
+        return u.as_dict()
+
+    def set_tuning(self, tuning: dict, stream=None):
+        u = _Tuning(**{k: int(v) for k, v in tuning.items()})
+        _check(lib().pf_set_tuning(self._ctx, C.byref(u), _stream(stream)))
+
+    def autotune(self, y, reps: int = 5, stream=None) -> dict:
+        """Time candidate launch plans on the device with observations y (one
+        interval), keep the fastest; the filters restart from their prior."""
+        u = _Tuning()
+        _check(lib().pf_autotune(self._ctx, _ptr(y), reps, _stream(stream), C.byref(u)))
+        return u.as_dict()
+
+    def signature(self) -> str:
+        """Batch shape that a tuning depends on: models and (M, N, flags)."""
+        import hashlib
+        parts = []
+        for m in self.models:
+            sp = m.spec
+            parts.append(f"{sp['kind']}:{m.dx}:{sp.get('J', 0)}:{sp['S']}")
+        parts += [f"{e[0]}:{e[1]}:{e[2]}:{e[4] if len(e) > 4 else 0}" for e in self.ens]
+        return hashlib.sha1("|".join(parts).encode()).hexdigest()
+
+    def autotune_cached(self, y, cache_path: str, reps: int = 5, stream=None) -> dict:
+        """The tuning stored for this batch shape and device in the JSON file
+        `cache_path`, else the autotuner's choice (then stored)."""
+        import json
+        import torch
+        key = f"{torch.cuda.get_device_name()}|{self.signature()}"
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        if key in cache:
+            self.set_tuning(cache[key], stream)
+            return cache[key]
+        t = self.autotune(y, reps, stream)
+        cache[key] = t
+        tmp = cache_path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+        return t
 
     def set_proposal(self, e: int, params, stream=None):
         """Network of learned ensemble e (float32 device tensor, flat)."""

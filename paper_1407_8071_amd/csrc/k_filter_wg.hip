@@ -421,7 +421,9 @@ hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, in
 #define PF_RS_LAUNCH(B, DD) \
   k_resample_wg<B, DD><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, d_counts, xb_parity)
 #define PF_RS_BD(DD)                 \
-  if (BD == 256) PF_RS_LAUNCH(256, DD); \
+  if (BD == 64) PF_RS_LAUNCH(64, DD); \
+  else if (BD == 128) PF_RS_LAUNCH(128, DD); \
+  else if (BD == 256) PF_RS_LAUNCH(256, DD); \
   else if (BD == 512) PF_RS_LAUNCH(512, DD); \
   else PF_RS_LAUNCH(1024, DD)
   if (D == 0) {

@@ -123,33 +123,40 @@ __device__ __forceinline__ float grid_loglik(const ModelDev &md, const float *vs
   return (lw == lw) ? lw : -INFINITY;
 }
 
-// Interval of S steps per particle with the v plane resident in LDS.
+// Interval of S steps per particle with the v plane resident in LDS, over a
+// table of {ensemble, filter, particle} entries of grid ensembles that share
+// J (one launch serves a whole batch of them).
 template <int SPT>
 __global__ void __launch_bounds__(1024)
-k_grid_steps(ModelDev md, Key key, int M, int N, IvArg iv, int yoff, const float *__restrict__ Xin,
-             const int32_t *__restrict__ anc, float *__restrict__ Xout, float *__restrict__ lw) {
+k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict__ ens, IvArg iv,
+             int parity, int pending, int J) {
   const int t = iv_t(iv);
   const float *yb = iv_y(iv, t);
-  const float *y = yb ? yb + yoff : nullptr;
   extern __shared__ float vs[];  // [J*J] v plane, then 16 floats of scratch
-  const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
+  const int nn = J * J, slots = nn / 4, dx = 2 * nn;
   float *shf = vs + nn;
   Nbr4 nb[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) nb[q] = neighbours(J, min((int)(threadIdx.x + q * blockDim.x), slots - 1));
-  for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
-    const int m = p / N, i = p - m * N;
-    const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
+  for (int p = blockIdx.x; p < n_p; p += gridDim.x) {
+    const int4 pt = ptab[p];
+    const FusedEns &E = ens[pt.x];
+    const ModelDev md = E.md;
+    const Key key = E.key;
+    const int m = pt.y, i = pt.z, N = E.N;
+    const float *Xin = parity ? E.X1 : E.X0;
+    float *Xout = parity ? E.X0 : E.X1;
+    const int src = pending ? min(max(E.A[(size_t)m * N + i], 0), N - 1) : i;
     const float4 *in = (const float4 *)(Xin + ((size_t)m * N + src) * dx);
     Slot4 S[SPT];
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
-      const int s = threadIdx.x + q * blockDim.x;
-      if (s < slots) {
-        S[q].v = in[s];
-        S[q].w = in[slots + s];
+      const int sl = threadIdx.x + q * blockDim.x;
+      if (sl < slots) {
+        S[q].v = in[sl];
+        S[q].w = in[slots + sl];
         S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
-        *(float4 *)(vs + 4 * s) = S[q].v;
+        *(float4 *)(vs + 4 * sl) = S[q].v;
       }
     }
     __syncthreads();
@@ -157,30 +164,30 @@ k_grid_steps(ModelDev md, Key key, int M, int N, IvArg iv, int yoff, const float
     for (int st = 0; st < md.S; ++st) {
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
-        const int s = threadIdx.x + q * blockDim.x;
-        if (s < slots)
-          grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), s, nb[q], vs, S[q]);
+        const int sl = threadIdx.x + q * blockDim.x;
+        if (sl < slots)
+          grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), sl, nb[q], vs, S[q]);
       }
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
-        const int s = threadIdx.x + q * blockDim.x;
-        if (s < slots) *(float4 *)(vs + 4 * s) = S[q].v;
+        const int sl = threadIdx.x + q * blockDim.x;
+        if (sl < slots) *(float4 *)(vs + 4 * sl) = S[q].v;
       }
       __syncthreads();
     }
     float4 *out = (float4 *)(Xout + ((size_t)m * N + i) * dx);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
-      const int s = threadIdx.x + q * blockDim.x;
-      if (s < slots) {
-        out[s] = S[q].v;
-        out[slots + s] = S[q].w;
+      const int sl = threadIdx.x + q * blockDim.x;
+      if (sl < slots) {
+        out[sl] = S[q].v;
+        out[slots + sl] = S[q].w;
       }
     }
-    if (lw) {
-      const float l = grid_loglik(md, vs, y, shf);
-      if (threadIdx.x == 0) lw[(size_t)m * N + i] = l;
+    if (yb) {
+      const float l = grid_loglik(md, vs, yb + E.yoff, shf);
+      if (threadIdx.x == 0) E.lw[(size_t)m * N + i] = l;
     }
     __syncthreads();
   }
@@ -361,6 +368,67 @@ k_grid_ensemble_fold(int M, int dx, const double *__restrict__ fmean,
   emean[dx + c] = b / (double)M;
 }
 
+// The estimator kernels above over tables of ensembles (fused path): the
+// partials of job {ensemble, filter, chunk} from the buffer `out`, the fold
+// of job {ensemble, filter}, the ensemble fold of the listed ensembles.
+__global__ void __launch_bounds__(GB)
+k_grid_estimate_part_b(const int4 *__restrict__ jobs, const FusedEns *__restrict__ ens, int out,
+                       int dx4) {
+  const int4 jb = jobs[blockIdx.x];
+  const FusedEns &E = ens[jb.x];
+  const int g = blockIdx.y * GB + threadIdx.x;
+  if (g >= dx4) return;
+  const int m = jb.y, ch = jb.z, N = E.N, nch = E.nch;
+  const float4 *Xb = (const float4 *)(out ? E.X1 : E.X0);
+  const double mx = E.fstat[(size_t)m * FREC + 0];
+  const bool deg = E.fstat[(size_t)m * FREC + 3] != 0.0;
+  double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
+  const int i0 = ch * EST_CHUNK, i1 = min(N, i0 + EST_CHUNK);
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
+    const float4 x = Xb[((size_t)m * N + i) * dx4 + g];
+    const double n = (double)E.cnt[(size_t)m * N + i];
+    const double w = deg ? 1.0 : exp((double)E.lw[(size_t)m * N + i] - mx);
+    pv[0] += n * x.x; pv[1] += n * x.y; pv[2] += n * x.z; pv[3] += n * x.w;
+    wv[0] += w * x.x; wv[1] += w * x.y; wv[2] += w * x.z; wv[3] += w * x.w;
+  }
+  double *o = E.gpart + (((size_t)m * nch + ch) * 2) * (size_t)dx4 * 4;
+  for (int l = 0; l < 4; ++l) {
+    o[(size_t)g * 4 + l] = pv[l];
+    o[(size_t)dx4 * 4 + (size_t)g * 4 + l] = wv[l];
+  }
+}
+
+__global__ void __launch_bounds__(GB)
+k_grid_filter_fold_b(const int4 *__restrict__ jobs, const FusedEns *__restrict__ ens, int dx) {
+  const int4 jb = jobs[blockIdx.x];
+  const FusedEns &E = ens[jb.x];
+  const int c = blockIdx.y * GB + threadIdx.x, m = jb.y, nch = E.nch;
+  if (c >= dx) return;
+  double a = 0.0, b = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const double *o = E.gpart + (((size_t)m * nch + ch) * 2) * (size_t)dx;
+    a += o[c];
+    b += o[(size_t)dx + c];
+  }
+  E.fmean[(size_t)m * dx + c] = a / (double)E.N;
+  E.fmeanw[(size_t)m * dx + c] = b / E.fstat[(size_t)m * FREC + 1];
+}
+
+__global__ void __launch_bounds__(GB)
+k_grid_ensemble_fold_b(const int *__restrict__ gens, const FusedEns *__restrict__ ens, int dx) {
+  const FusedEns &E = ens[gens[blockIdx.x]];
+  const int c = blockIdx.y * GB + threadIdx.x;
+  if (c >= dx) return;
+  double a = 0.0, b = 0.0;
+  for (int m = 0; m < E.M; ++m) {
+    a += E.fmean[(size_t)m * dx + c];
+    b += E.fmeanw[(size_t)m * dx + c];
+  }
+  E.emean[c] = a / (double)E.M;
+  E.emean[dx + c] = b / (double)E.M;
+}
+
 // Truth path on the truth stream: one workgroup, T intervals of S steps.
 template <int SPT>
 __global__ void __launch_bounds__(1024)
@@ -441,7 +509,9 @@ void grid_shape(const ModelDev &md, int *spt, int *threads) {
 }
 }  // namespace
 
-int grid_resident_blocks(const ModelDev &md) {
+int grid_resident_blocks_j(int J) {
+  ModelDev md{};
+  md.J = J;
   int dev = 0, per_cu = 0, spt, threads;
   grid_shape(md, &spt, &threads);
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
@@ -454,23 +524,43 @@ int grid_resident_blocks(const ModelDev &md) {
   return std::max(1, per_cu) * prop.multiProcessorCount;
 }
 
+int grid_resident_blocks(const ModelDev &md) { return grid_resident_blocks_j(md.J); }
+
 hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s) {
   k_grid_init<<<e.M * e.N, GB, 0, s>>>(e.md, e.key, e.N, X);
   return hipGetLastError();
 }
 
-hipError_t launch_grid_steps(const EnsDev &e, IvArg iv, int yoff, const float *Xin,
-                             const int32_t *anc, float *Xout, float *lw, int blocks, hipStream_t s) {
+hipError_t launch_grid_steps_batched(int J, const int4 *d_ptab, int n_p, const FusedEns *d_ens,
+                                     IvArg iv, int parity, int pending, int blocks, hipStream_t s) {
+  if (n_p <= 0) return hipSuccess;
+  ModelDev md{};
+  md.J = J;
   int spt, threads;
-  grid_shape(e.md, &spt, &threads);
-  const int g = std::min(blocks, e.M * e.N);
-  const size_t lds = grid_lds(e.md);
+  grid_shape(md, &spt, &threads);
+  const int g = std::max(1, std::min(blocks, n_p));
+  const size_t lds = grid_lds(md);
   if (spt == 1)
-    k_grid_steps<1><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, iv, yoff, Xin, anc, Xout, lw);
+    k_grid_steps<1><<<g, threads, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
   else if (spt == 2)
-    k_grid_steps<2><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, iv, yoff, Xin, anc, Xout, lw);
+    k_grid_steps<2><<<g, threads, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
   else
-    k_grid_steps<4><<<g, threads, lds, s>>>(e.md, e.key, e.M, e.N, iv, yoff, Xin, anc, Xout, lw);
+    k_grid_steps<4><<<g, threads, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_estimate_batched(int J, const int4 *d_part_jobs, int n_part,
+                                        const int4 *d_fold_jobs, int n_fold, const int *d_gens,
+                                        int n_gens, const FusedEns *d_ens, int out, hipStream_t s) {
+  if (n_gens <= 0) return hipSuccess;
+  const int dx = 2 * J * J, dx4 = dx / 4;
+  k_grid_estimate_part_b<<<dim3(n_part, (dx4 + GB - 1) / GB), GB, 0, s>>>(d_part_jobs, d_ens, out,
+                                                                          dx4);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_grid_filter_fold_b<<<dim3(n_fold, (dx + GB - 1) / GB), GB, 0, s>>>(d_fold_jobs, d_ens, dx);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_grid_ensemble_fold_b<<<dim3(n_gens, (dx + GB - 1) / GB), GB, 0, s>>>(d_gens, d_ens, dx);
   return hipGetLastError();
 }
 

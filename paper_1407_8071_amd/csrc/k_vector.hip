@@ -261,13 +261,15 @@ hipError_t launch_vec_propagate(const EnsDev &e, int t, const float *Xin, const 
   return hipGetLastError();
 }
 
-hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, const FusedEns *d_ens,
-                                  IvArg iv, int parity, int pending, hipStream_t s) {
+hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, int tile_width,
+                                  const FusedEns *d_ens, IvArg iv, int parity, int pending,
+                                  hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
+  if (tile_width < 64 || tile_width > VEC_BLOCK || tile_width % 64) return hipErrorInvalidValue;
   if (D == 3)
-    k_vec_prop_batched<3><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
+    k_vec_prop_batched<3><<<n_tiles, tile_width, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
   else
-    k_vec_prop_batched<1><<<n_tiles, VEC_BLOCK, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
+    k_vec_prop_batched<1><<<n_tiles, tile_width, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
   return hipGetLastError();
 }
 

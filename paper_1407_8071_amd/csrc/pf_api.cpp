@@ -79,7 +79,11 @@ struct WgClass {
 
 // Workgroup size of the filter-per-workgroup kernel for N particles.
 // (the per-filter kernels hold one element per thread below 1024 threads)
-int wg_block(int N) { return N <= 256 ? 256 : (N <= 512 ? 512 : 1024); }
+int wg_block(int N, int bd_min = 256) {
+  for (int bd = 64; bd <= 512; bd <<= 1)
+    if (bd >= bd_min && N <= bd) return bd;
+  return 1024;
+}
 
 // Offsets of every array of one ensemble inside the workspace.
 struct Layout {
@@ -126,25 +130,52 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bo
   return L;
 }
 
-// Context-wide arrays after the ensembles: the fused ensemble table and the
-// workgroup job lists (at most one job per filter).
-size_t ctx_bytes(const pf_ensemble_desc *ens, int n_ens) {
-  size_t jobs = 0, tiles = 0;
+// Context-wide arrays after the ensembles: the fused ensemble table, the
+// launch plan's tables sized for any tuning (workgroup job lists, at most one
+// job per filter per class; batched propagation tiles of the narrowest
+// width; the batched grid tables) and the device interval counter.
+constexpr int MAX_CLASSES = 32;
+constexpr int MIN_PROP_TILE = 64;
+
+struct CtxSizes {
+  size_t jobs = 0, tiles = 0, gparticles = 0, gpart_jobs = 0, gfold_jobs = 0;
+};
+
+CtxSizes ctx_sizes(const pf_model_desc *models, const pf_ensemble_desc *ens, int n_ens) {
+  CtxSizes z;
   for (int e = 0; e < n_ens; ++e) {
-    jobs += (size_t)ens[e].M;
-    tiles += (size_t)ens[e].M * (((size_t)ens[e].N + 255) / 256);
+    z.jobs += (size_t)ens[e].M;
+    z.tiles += (size_t)ens[e].M * (((size_t)ens[e].N + MIN_PROP_TILE - 1) / MIN_PROP_TILE);
+    if (models[ens[e].model].kind == PF_MODEL_FHN) {
+      z.gparticles += (size_t)ens[e].M * ens[e].N;
+      z.gpart_jobs += (size_t)ens[e].M * pfk::grid_est_chunks(ens[e].N);
+      z.gfold_jobs += (size_t)ens[e].M;
+    }
   }
-  return align_up(sizeof(pfk::FusedEns) * (size_t)n_ens) +
-         align_up(sizeof(int32_t *) * (size_t)n_ens) + 15 * align_up(sizeof(pfk::WgJob) * jobs) +
-         2 * align_up(sizeof(int4) * tiles) + align_up(sizeof(int));
+  return z;
 }
 
-// Fused-path strategy of vector ensembles with N <= WG_MAX_N: "split"
-// (batched propagation, then per-filter resampling and estimates) unless
-// PF_VEC_STRATEGY=filter_wg asks for the single filter-per-workgroup kernel.
-bool vec_single_kernel() {
-  const char *v = std::getenv("PF_VEC_STRATEGY");
-  return v && std::strcmp(v, "filter_wg") == 0;
+size_t ctx_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int n_ens) {
+  const CtxSizes z = ctx_sizes(models, ens, n_ens);
+  return align_up(sizeof(pfk::FusedEns) * (size_t)n_ens) +
+         align_up(sizeof(int32_t *) * (size_t)n_ens) +
+         MAX_CLASSES * align_up(sizeof(pfk::WgJob) * z.jobs) + 2 * align_up(sizeof(int4) * z.tiles) +
+         align_up(sizeof(int4) * z.gparticles) + align_up(sizeof(int4) * z.gpart_jobs) +
+         align_up(sizeof(int4) * z.gfold_jobs) + align_up(sizeof(int) * (size_t)n_ens) +
+         align_up(sizeof(int));
+}
+
+pf_status check_tuning(const pf_tuning &u) {
+  if (u.vec_single_kernel != 0 && u.vec_single_kernel != 1)
+    return fail(PF_ERR_INVALID_ARG, "vec_single_kernel must be 0 or 1");
+  if (u.prop_tile != 64 && u.prop_tile != 128 && u.prop_tile != 256)
+    return fail(PF_ERR_INVALID_ARG, "prop_tile must be 64, 128 or 256");
+  if (u.resample_bd_min != 64 && u.resample_bd_min != 128 && u.resample_bd_min != 256 &&
+      u.resample_bd_min != 512 && u.resample_bd_min != 1024)
+    return fail(PF_ERR_INVALID_ARG, "resample_bd_min must be 64, 128, 256, 512 or 1024");
+  if (u.grid_blocks_per_cu < 0 || u.grid_blocks_per_cu > 64)
+    return fail(PF_ERR_INVALID_ARG, "grid_blocks_per_cu must be in [0, 64]");
+  return PF_OK;
 }
 
 pf_status check_model(const pf_model_desc &m, int idx) {
@@ -219,7 +250,7 @@ size_t total_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int
                   (ens[e].flags & PF_ENS_LEARNED) != 0)
             .end;
   }
-  return o + ctx_bytes(ens, n_ens);
+  return o + ctx_bytes(models, ens, n_ens);
 }
 
 }  // namespace
@@ -253,6 +284,21 @@ struct pf_ctx {
   std::vector<int4> tiles_host[2];
   int32_t **d_counts = nullptr;       // [n_ens] device pointers to offspring counts
   std::vector<int32_t *> counts_host;
+  // launch plan of the fused path (pf_tuning) and its tables
+  pf_tuning tuning{0, 256, 256, 0};
+  int prop_tile = 256;
+  pfk::WgJob *d_job_base = nullptr;  // MAX_CLASSES arrays of `max_jobs`
+  size_t max_jobs = 0;
+  struct GridGroup {
+    int J = 0, blocks = 1024;
+    std::vector<int4> ptab, part_jobs, fold_jobs;
+    std::vector<int> gens;
+    int4 *d_ptab = nullptr, *d_part = nullptr, *d_fold = nullptr;
+    int *d_gens = nullptr;
+  };
+  std::vector<GridGroup> ggroups;
+  int4 *d_gptab = nullptr, *d_gpart = nullptr, *d_gfold = nullptr;
+  int *d_ggens = nullptr;
   // event pairs around the dominant kernel while profiling is enabled
   bool profiling = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -396,8 +442,8 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
   if (!resample_only) {
     const long ev = (prof && ctx->n_tiles[0] + ctx->n_tiles[1]) ? prof_begin(ctx, s) : -1;
     for (int w = 1; w >= 0; --w)
-      PF_HIP(pfk::launch_vec_prop_batched(w ? 3 : 1, ctx->d_tiles[w], ctx->n_tiles[w], ctx->d_fens,
-                                          iv, parity, pending, s));
+      PF_HIP(pfk::launch_vec_prop_batched(w ? 3 : 1, ctx->d_tiles[w], ctx->n_tiles[w],
+                                          ctx->prop_tile, ctx->d_fens, iv, parity, pending, s));
     prof_end(ctx, ev, s);
   }
   for (const WgClass &c : ctx->classes)
@@ -407,21 +453,26 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
                                    iv, parity, pending, resample_only ? 1 : 0, s));
       prof_end(ctx, ev, s);
     }
-  int yo = 0;
-  for (Ens &E : ctx->ens) {
-    const int yoff = yo;
-    yo += E.dy;
-    if (!E.grid || resample_only) continue;
-    pfk::EnsDev &D = E.dev;
-    const long eg = prof ? prof_begin(ctx, s) : -1;
-    if (E.learned)
+  if (!resample_only) {
+    // every bootstrap grid ensemble of one grid size in one launch (profiled)
+    for (const auto &g : ctx->ggroups) {
+      const long eg = prof ? prof_begin(ctx, s) : -1;
+      PF_HIP(pfk::launch_grid_steps_batched(g.J, g.d_ptab, (int)g.ptab.size(), ctx->d_fens, iv,
+                                            parity, pending, g.blocks, s));
+      prof_end(ctx, eg, s);
+    }
+    int yo = 0;
+    for (Ens &E : ctx->ens) {
+      const int yoff = yo;
+      yo += E.dy;
+      if (!E.learned) continue;
+      pfk::EnsDev &D = E.dev;
+      const long eg = prof ? prof_begin(ctx, s) : -1;
       PF_HIP(pfk::launch_grid_steps_learned(D, iv, yoff, D.X[parity], pending ? D.A : nullptr,
                                             D.X[out], D.lw, E.params, E.nearest, E.sd0, E.sd1,
                                             E.lblocks, s));
-    else
-      PF_HIP(pfk::launch_grid_steps(D, iv, yoff, D.X[parity], pending ? D.A : nullptr, D.X[out],
-                                    D.lw, E.blocks, s));
-    prof_end(ctx, eg, s);
+      prof_end(ctx, eg, s);
+    }
   }
   // 2. resampling and the filters' estimates
   for (const WgClass &c : ctx->classes) {
@@ -432,9 +483,13 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
       PF_HIP(pfk::launch_resample_wg(0, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
                                      iv, ctx->d_counts, out, s));
   }
+  for (const auto &g : ctx->ggroups)
+    PF_HIP(pfk::launch_grid_estimate_batched(g.J, g.d_part, (int)g.part_jobs.size(), g.d_fold,
+                                             (int)g.fold_jobs.size(), g.d_gens, (int)g.gens.size(),
+                                             ctx->d_fens, out, s));
   for (Ens &E : ctx->ens) {
     pfk::EnsDev &D = E.dev;
-    if (E.grid) {
+    if (E.learned) {
       PF_HIP(pfk::launch_grid_estimate(D, D.X[out], E.cnt, E.gpart, s));
     } else if (E.tiled) {
       PF_HIP(pfk::launch_resample(D, iv.t, s, iv.tp));
@@ -499,6 +554,15 @@ pf_status graph_step(pf_ctx *ctx, hipStream_t s) {
   return PF_OK;
 }
 
+void drop_graphs(pf_ctx *ctx) {
+  for (int p = 0; p < 2; ++p) {
+    if (ctx->gexec[p]) (void)hipGraphExecDestroy(ctx->gexec[p]);
+    if (ctx->graph[p]) (void)hipGraphDestroy(ctx->graph[p]);
+    ctx->gexec[p] = nullptr;
+    ctx->graph[p] = nullptr;
+  }
+}
+
 // Resolve pending ancestors: gather every ensemble into the other buffer.
 pf_status materialise(pf_ctx *ctx, hipStream_t s) {
   if (!ctx->pending) return PF_OK;
@@ -506,6 +570,155 @@ pf_status materialise(pf_ctx *ctx, hipStream_t s) {
   ctx->xbar = ctx->cur;
   ctx->cur = 1 - ctx->cur;
   ctx->pending = false;
+  return PF_OK;
+}
+
+// The launch plan of the fused path for a tuning: which vector ensembles run
+// in the single filter-per-workgroup kernel, the workgroup-per-filter classes
+// (by kind, state dimension and workgroup size, filters of larger N first),
+// the batched propagation tiles, and the batched grid tables (per grid size
+// J; ensembles with the learned proposal keep their own launch).  The tables
+// live at fixed offsets sized for any tuning; the caller has made sure no
+// work still reads them.
+pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
+  PF_TRY(check_tuning(u));
+  const int n_ens = (int)ctx->ens.size();
+  for (Ens &E : ctx->ens) E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N && u.vec_single_kernel;
+  ctx->classes.clear();
+  int next_class = 0;
+  const int BDs[5] = {1024, 512, 256, 128, 64};
+  auto add_class = [&](int kind, int D, int BD, int bd_min, auto member) {
+    WgClass c;
+    c.kind = kind;
+    c.D = D;
+    c.BD = BD;
+    c.max_n = 0;
+    std::vector<std::pair<int, int>> order;  // (N, ensemble)
+    for (int e = 0; e < n_ens; ++e) {
+      const Ens &E = ctx->ens[(size_t)e];
+      if (member(E) && wg_block(E.d.N, bd_min) == BD) order.push_back({E.d.N, e});
+    }
+    if (order.empty()) return;
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+                       return a.first > b.first;
+                     });
+    for (auto &pr : order) {
+      c.max_n = std::max(c.max_n, pr.first);
+      for (int mm = 0; mm < ctx->ens[(size_t)pr.second].d.M; ++mm)
+        c.jobs.push_back(pfk::WgJob{pr.second, mm});
+    }
+    c.d_jobs = ctx->d_job_base + (size_t)next_class++ * (align_up(sizeof(pfk::WgJob) * ctx->max_jobs) /
+                                                        sizeof(pfk::WgJob));
+    ctx->classes.push_back(std::move(c));
+  };
+  // the single-kernel path holds one element per thread below 1024 threads
+  const int wg_min = std::max(256, u.resample_bd_min);
+  for (int D : {3, 1}) {
+    for (int BD : BDs) {
+      if (BD >= 256) add_class(CLASS_FILTER_WG, D, BD, wg_min, [D](const Ens &E) { return E.wg && E.dx == D; });
+      add_class(CLASS_RESAMPLE_VEC, D, BD, u.resample_bd_min, [D](const Ens &E) {
+        return !E.grid && !E.wg && !E.tiled && E.dx == D;
+      });
+    }
+  }
+  for (int BD : BDs)
+    add_class(CLASS_RESAMPLE_GRID, 0, BD, u.resample_bd_min,
+              [](const Ens &E) { return E.grid && E.d.N <= pfk::WG_MAX_N; });
+  if (next_class > MAX_CLASSES) return fail(PF_ERR_STATE, "too many launch classes");
+  // batched propagation tiles of the vector ensembles not run by the single
+  // filter-per-workgroup kernel
+  ctx->prop_tile = u.prop_tile;
+  for (int w = 0; w < 2; ++w) ctx->tiles_host[w].clear();
+  for (int e = 0; e < n_ens; ++e) {
+    const Ens &E = ctx->ens[(size_t)e];
+    if (E.grid || E.wg) continue;
+    const int which = E.dx == 3 ? 1 : 0;
+    for (int mm = 0; mm < E.d.M; ++mm)
+      for (int i0 = 0; i0 < E.d.N; i0 += u.prop_tile) ctx->tiles_host[which].push_back(int4{e, mm, i0, 0});
+  }
+  for (int w = 0; w < 2; ++w) ctx->n_tiles[w] = (int)ctx->tiles_host[w].size();
+  // batched grid tables, one group per grid size
+  ctx->ggroups.clear();
+  size_t op = 0, oj = 0, of = 0, og = 0;
+  for (int e = 0; e < n_ens; ++e) {
+    const Ens &E = ctx->ens[(size_t)e];
+    if (!E.grid || E.learned) continue;
+    const int J = E.dev.md.J;
+    pf_ctx::GridGroup *g = nullptr;
+    for (auto &gg : ctx->ggroups)
+      if (gg.J == J) g = &gg;
+    if (!g) {
+      ctx->ggroups.emplace_back();
+      g = &ctx->ggroups.back();
+      g->J = J;
+    }
+    const int nch = pfk::grid_est_chunks(E.d.N);
+    for (int mm = 0; mm < E.d.M; ++mm) {
+      for (int i = 0; i < E.d.N; ++i) g->ptab.push_back(int4{e, mm, i, 0});
+      for (int ch = 0; ch < nch; ++ch) g->part_jobs.push_back(int4{e, mm, ch, 0});
+      g->fold_jobs.push_back(int4{e, mm, 0, 0});
+    }
+    g->gens.push_back(e);
+  }
+  for (auto &g : ctx->ggroups) {
+    const int occ = pfk::grid_resident_blocks_j(g.J);
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    g.blocks = u.grid_blocks_per_cu > 0 ? std::min(occ, u.grid_blocks_per_cu * cus) : occ;
+    g.d_ptab = ctx->d_gptab + op;
+    g.d_part = ctx->d_gpart + oj;
+    g.d_fold = ctx->d_gfold + of;
+    g.d_gens = ctx->d_ggens + og;
+    op += g.ptab.size();
+    oj += g.part_jobs.size();
+    of += g.fold_jobs.size();
+    og += g.gens.size();
+  }
+  // upload
+  for (WgClass &c : ctx->classes)
+    PF_HIP(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
+                          hipMemcpyHostToDevice, s));
+  for (int w = 0; w < 2; ++w)
+    if (ctx->n_tiles[w] > 0)
+      PF_HIP(hipMemcpyAsync(ctx->d_tiles[w], ctx->tiles_host[w].data(),
+                            sizeof(int4) * ctx->tiles_host[w].size(), hipMemcpyHostToDevice, s));
+  for (auto &g : ctx->ggroups) {
+    PF_HIP(hipMemcpyAsync(g.d_ptab, g.ptab.data(), sizeof(int4) * g.ptab.size(),
+                          hipMemcpyHostToDevice, s));
+    PF_HIP(hipMemcpyAsync(g.d_part, g.part_jobs.data(), sizeof(int4) * g.part_jobs.size(),
+                          hipMemcpyHostToDevice, s));
+    PF_HIP(hipMemcpyAsync(g.d_fold, g.fold_jobs.data(), sizeof(int4) * g.fold_jobs.size(),
+                          hipMemcpyHostToDevice, s));
+    PF_HIP(hipMemcpyAsync(g.d_gens, g.gens.data(), sizeof(int) * g.gens.size(),
+                          hipMemcpyHostToDevice, s));
+  }
+  // the host tables are kept in the context, so the copies may stay queued;
+  // captured graphs refer to the old plan
+  drop_graphs(ctx);
+  ctx->tuning = u;
+  return PF_OK;
+}
+
+// Every filter back to its prior draw and interval 1 (log-evidence and
+// statistics cleared), as after pf_init.
+pf_status reset_filters(pf_ctx *ctx, hipStream_t s) {
+  for (Ens &E : ctx->ens) {
+    pfk::EnsDev &D = E.dev;
+    PF_HIP(hipMemsetAsync(D.fstat, 0, sizeof(double) * (size_t)E.d.M * pfk::FREC, s));
+    PF_HIP(hipMemsetAsync(D.emean, 0, sizeof(double) * 2 * (size_t)E.dx, s));
+    PF_HIP(hipMemsetAsync(D.A, 0, sizeof(int32_t) * (size_t)E.d.M * E.d.N, s));
+    if (E.grid)
+      PF_HIP(pfk::launch_grid_init(D, D.X[0], s));
+    else
+      PF_HIP(pfk::launch_vec_init(D, D.X[0], s));
+  }
+  ctx->cur = 0;
+  ctx->xbar = 1;
+  ctx->pending = false;
+  ctx->t = 1;
+  ctx->d_t_valid = false;
   return PF_OK;
 }
 
@@ -628,12 +841,18 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     F.fmean = D.fmean;
     F.fmeanw = D.fmeanw;
     F.emean = D.emean;
-    E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N && vec_single_kernel();
+    E.wg = false;  // set by the launch plan
     E.tiled = !E.grid && E.d.N > pfk::WG_MAX_N;
+    F.cnt = nullptr;
+    F.gpart = nullptr;
+    F.nch = 0;
     if (E.grid) {
       E.cnt = (int32_t *)(ws + L.cnt);
       E.gpart = (double *)(ws + L.gpart);
       E.blocks = pfk::grid_resident_blocks(md);
+      F.cnt = E.cnt;
+      F.gpart = E.gpart;
+      F.nch = pfk::grid_est_chunks(E.d.N);
     }
     std::vector<int32_t> near_host;
     if (E.learned) {
@@ -693,9 +912,10 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
       INIT_TRY(hipStreamSynchronize(s));
     }
   }
-  // context arrays: the fused ensemble table and the workgroup job lists
+  // context arrays: the fused ensemble table, the plan tables, the counter
   {
     pf_status st = PF_OK;
+    const CtxSizes z = ctx_sizes(h_models, h_ens, n_ens);
     ctx->d_fens = (pfk::FusedEns *)(ws + base);
     size_t o = base + align_up(sizeof(pfk::FusedEns) * (size_t)n_ens);
     ctx->d_counts = (int32_t **)(ws + o);
@@ -704,74 +924,33 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     for (int e = 0; e < n_ens; ++e) ctx->counts_host[(size_t)e] = ctx->ens[(size_t)e].cnt;
     INIT_TRY(hipMemcpyAsync(ctx->d_counts, ctx->counts_host.data(), sizeof(int32_t *) * (size_t)n_ens,
                             hipMemcpyHostToDevice, s));
-    size_t total_jobs = 0;
-    for (int e = 0; e < n_ens; ++e) total_jobs += (size_t)h_ens[e].M;
     ctx->fz_host.resize((size_t)n_ens);
     for (int e = 0; e < n_ens; ++e) ctx->fz_host[(size_t)e] = ctx->ens[(size_t)e].fz;
     INIT_TRY(hipMemcpyAsync(ctx->d_fens, ctx->fz_host.data(), sizeof(pfk::FusedEns) * (size_t)n_ens,
                             hipMemcpyHostToDevice, s));
-    // workgroup-per-filter classes by (kind, state dimension, workgroup
-    // size); filters of larger N first
-    const int BDs[3] = {1024, 512, 256};
-    auto add_class = [&](int kind, int D, int BD, auto member) {
-      WgClass c;
-      c.kind = kind;
-      c.D = D;
-      c.BD = BD;
-      c.max_n = 0;
-      std::vector<std::pair<int, int>> order;  // (N, ensemble)
-      for (int e = 0; e < n_ens; ++e) {
-        const Ens &E = ctx->ens[(size_t)e];
-        if (member(E) && wg_block(E.d.N) == BD) order.push_back({E.d.N, e});
-      }
-      if (order.empty()) return;
-      std::stable_sort(order.begin(), order.end(),
-                       [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
-                         return a.first > b.first;
-                       });
-      for (auto &pr : order) {
-        c.max_n = std::max(c.max_n, pr.first);
-        for (int mm = 0; mm < ctx->ens[(size_t)pr.second].d.M; ++mm)
-          c.jobs.push_back(pfk::WgJob{pr.second, mm});
-      }
-      c.d_jobs = (pfk::WgJob *)(ws + o);
-      o += align_up(sizeof(pfk::WgJob) * total_jobs);
-      ctx->classes.push_back(std::move(c));
-    };
-    for (int D : {3, 1}) {
-      for (int BD : BDs) {
-        add_class(CLASS_FILTER_WG, D, BD, [D](const Ens &E) { return E.wg && E.dx == D; });
-        add_class(CLASS_RESAMPLE_VEC, D, BD, [D](const Ens &E) {
-          return !E.grid && !E.wg && !E.tiled && E.dx == D;
-        });
-      }
+    ctx->max_jobs = z.jobs;
+    ctx->d_job_base = (pfk::WgJob *)(ws + o);
+    o += MAX_CLASSES * align_up(sizeof(pfk::WgJob) * z.jobs);
+    for (int w = 0; w < 2; ++w) {
+      ctx->d_tiles[w] = (int4 *)(ws + o);
+      o += align_up(sizeof(int4) * z.tiles);
     }
-    for (int BD : BDs)
-      add_class(CLASS_RESAMPLE_GRID, 0, BD,
-                [](const Ens &E) { return E.grid && E.d.N <= pfk::WG_MAX_N; });
-    // batched propagation tiles of the vector ensembles not run by the
-    // single filter-per-workgroup kernel
-    for (int e = 0; e < n_ens; ++e) {
-      const Ens &E = ctx->ens[(size_t)e];
-      if (E.grid || E.wg) continue;
-      const int which = E.dx == 3 ? 1 : 0;
-      for (int mm = 0; mm < E.d.M; ++mm)
-        for (int i0 = 0; i0 < E.d.N; i0 += 256) ctx->tiles_host[which].push_back(int4{e, mm, i0, 0});
-    }
+    ctx->d_gptab = (int4 *)(ws + o);
+    o += align_up(sizeof(int4) * z.gparticles);
+    ctx->d_gpart = (int4 *)(ws + o);
+    o += align_up(sizeof(int4) * z.gpart_jobs);
+    ctx->d_gfold = (int4 *)(ws + o);
+    o += align_up(sizeof(int4) * z.gfold_jobs);
+    ctx->d_ggens = (int *)(ws + o);
+    o += align_up(sizeof(int) * (size_t)n_ens);
     ctx->d_t = (int *)(ws + o);
     o += align_up(sizeof(int));
-    for (int w = 0; w < 2; ++w) {
-      ctx->n_tiles[w] = (int)ctx->tiles_host[w].size();
-      ctx->d_tiles[w] = (int4 *)(ws + o);
-      o += align_up(sizeof(int4) * ctx->tiles_host[w].size());
-      if (ctx->n_tiles[w] > 0)
-        INIT_TRY(hipMemcpyAsync(ctx->d_tiles[w], ctx->tiles_host[w].data(),
-                                sizeof(int4) * ctx->tiles_host[w].size(), hipMemcpyHostToDevice, s));
-    }
-    for (WgClass &c : ctx->classes)
-      INIT_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
-                              hipMemcpyHostToDevice, s));
     INIT_TRY(pfk::set_filter_wg_lds_limit());
+    if (st == PF_OK) st = build_plan(ctx, ctx->tuning, s);
+    if (st != PF_OK) {
+      delete ctx;
+      return st;
+    }
   }
   // the host copies above must stay valid until the uploads ran
   {
@@ -944,15 +1123,7 @@ pf_status pf_set_observations(pf_ctx *ctx, const float *d_y_all, int32_t T) {
   if (!d_y_all || T < 1) return fail(PF_ERR_INVALID_ARG, "bad observation record");
   int dy = 0;
   for (const Ens &E : ctx->ens) dy += E.dy;
-  if (ctx->y_all != d_y_all || ctx->dy_total != dy) {
-    // captured graphs hold the old pointer
-    for (int p = 0; p < 2; ++p) {
-      if (ctx->gexec[p]) (void)hipGraphExecDestroy(ctx->gexec[p]);
-      if (ctx->graph[p]) (void)hipGraphDestroy(ctx->graph[p]);
-      ctx->gexec[p] = nullptr;
-      ctx->graph[p] = nullptr;
-    }
-  }
+  if (ctx->y_all != d_y_all || ctx->dy_total != dy) drop_graphs(ctx);  // they hold the old pointer
   ctx->y_all = d_y_all;
   ctx->y_T = T;
   ctx->dy_total = dy;
@@ -980,6 +1151,89 @@ pf_status pf_philox_stream(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
                            uint32_t *d_bits, float *d_z, void *stream) {
   if (n < 0 || n > ((int64_t)1 << 32)) return fail(PF_ERR_INVALID_ARG, "n out of range");
   PF_HIP(pfk::launch_philox_stream(seed, c1, c2, c3, n, d_bits, d_z, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_get_tuning(const pf_ctx *ctx, pf_tuning *out) {
+  if (!ctx || !out) return fail(PF_ERR_INVALID_ARG, "NULL argument");
+  *out = ctx->tuning;
+  return PF_OK;
+}
+
+pf_status pf_set_tuning(pf_ctx *ctx, const pf_tuning *u, void *stream) {
+  if (!ctx || !u) return fail(PF_ERR_INVALID_ARG, "NULL argument");
+  PF_TRY(check_tuning(*u));
+  hipStream_t s = (hipStream_t)stream;
+  // the tables are rewritten in place: let queued work that reads them finish
+  if (ctx->last_stream) PF_HIP(hipStreamSynchronize(ctx->last_stream));
+  PF_HIP(hipStreamSynchronize(s));
+  PF_TRY(build_plan(ctx, *u, s));
+  ctx->last_stream = s;
+  return PF_OK;
+}
+
+pf_status pf_autotune(pf_ctx *ctx, const float *d_y, int32_t reps, void *stream, pf_tuning *out) {
+  if (!ctx) return fail(PF_ERR_STATE, "no context");
+  if (!(ctx->options & PF_OPT_FUSED)) return fail(PF_ERR_STATE, "the tuning applies to the fused path");
+  if (!d_y) return fail(PF_ERR_INVALID_ARG, "the timed intervals need observations");
+  if (reps < 1 || reps > 1000) return fail(PF_ERR_INVALID_ARG, "reps out of range");
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->last_stream) PF_HIP(hipStreamSynchronize(ctx->last_stream));
+  bool any_vec = false, any_small = false, any_grid = !ctx->ggroups.empty(), any_resample = false;
+  for (const Ens &E : ctx->ens) {
+    if (!E.grid && E.d.N <= pfk::WG_MAX_N) any_vec = true;
+    if (E.d.N <= 512) any_small = true;
+    if (E.d.N <= pfk::WG_MAX_N) any_resample = true;
+  }
+  hipEvent_t e0, e1;
+  PF_HIP(hipEventCreate(&e0));
+  PF_HIP(hipEventCreate(&e1));
+  // wall time of `reps` fused intervals under tuning u (after one warm-up)
+  auto measure = [&](const pf_tuning &u, float *ms) -> pf_status {
+    PF_HIP(hipStreamSynchronize(s));
+    PF_TRY(build_plan(ctx, u, s));
+    PF_TRY(fused_run(ctx, d_y, s, false));
+    PF_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) PF_TRY(fused_run(ctx, d_y, s, false));
+    PF_HIP(hipEventRecord(e1, s));
+    PF_HIP(hipEventSynchronize(e1));
+    PF_HIP(hipEventElapsedTime(ms, e0, e1));
+    return PF_OK;
+  };
+  pf_tuning best = ctx->tuning;
+  float best_ms = 0.f;
+  pf_status st = measure(best, &best_ms);
+  // coordinate search, one knob at a time in the order of their effect
+  auto try_knob = [&](int32_t pf_tuning::*field, std::initializer_list<int> values) {
+    for (int v : values) {
+      if (st != PF_OK) return;
+      if (best.*field == v) continue;
+      pf_tuning u = best;
+      u.*field = v;
+      float ms = 0.f;
+      st = measure(u, &ms);
+      if (st == PF_OK && ms < best_ms) {
+        best_ms = ms;
+        best = u;
+      }
+    }
+  };
+  if (any_vec) try_knob(&pf_tuning::vec_single_kernel, {0, 1});
+  if (any_vec && !best.vec_single_kernel) try_knob(&pf_tuning::prop_tile, {64, 128, 256});
+  if (any_resample) {
+    if (any_small) try_knob(&pf_tuning::resample_bd_min, {64, 128, 256, 512});
+    try_knob(&pf_tuning::resample_bd_min, {1024});
+  }
+  if (any_grid) try_knob(&pf_tuning::grid_blocks_per_cu, {0, 1, 2, 4, 8});
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  PF_TRY(st);
+  PF_HIP(hipStreamSynchronize(s));
+  PF_TRY(build_plan(ctx, best, s));
+  // the timed intervals moved the filters: back to the prior draw at t = 1
+  PF_TRY(reset_filters(ctx, s));
+  if (out) *out = best;
+  ctx->last_stream = s;
   return PF_OK;
 }
 

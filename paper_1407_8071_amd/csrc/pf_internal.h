@@ -67,6 +67,10 @@ struct FusedEns {
   float *X0, *X1, *lw;
   int32_t *A;
   double *fstat, *fmean, *fmeanw, *emean;
+  // grid model: offspring counts [M][N], estimator partials [M][nch][2][dx]
+  int32_t *cnt;
+  double *gpart;
+  int32_t nch;
 };
 
 // ---- vector models (OU, Lorenz 63): particles [M][dx][N] ------------------
@@ -102,15 +106,14 @@ hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, in
                               const FusedEns *d_ens, IvArg iv, int32_t *const *d_counts,
                               int xb_parity, hipStream_t s);
 // batched propagation + weighting of vector-model tiles {ens, filter, i0, -}
-hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, const FusedEns *d_ens,
-                                  IvArg iv, int parity, int pending, hipStream_t s);
+hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, int tile_width,
+                                  const FusedEns *d_ens, IvArg iv, int parity, int pending,
+                                  hipStream_t s);
 hipError_t launch_offspring_counts(const EnsDev &e, int32_t *cnt, hipStream_t s);
 
 // ---- grid model (FH-N): particles [M][N][2][J][J] ---------------------------
 int grid_resident_blocks(const ModelDev &md);
 hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s);
-hipError_t launch_grid_steps(const EnsDev &e, IvArg iv, int yoff, const float *Xin,
-                             const int32_t *anc, float *Xout, float *lw, int blocks, hipStream_t s);
 hipError_t launch_grid_stream_step(const EnsDev &e, int n, const float *Xin, const int32_t *anc,
                                    float *Xout, float *lw, const float *y, int blocks,
                                    hipStream_t s);
@@ -121,6 +124,17 @@ hipError_t launch_grid_estimate(const EnsDev &e, const float *Xb, const int32_t 
                                 double *part, hipStream_t s);
 hipError_t launch_grid_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,
                                 hipStream_t s);
+
+// Batched grid model (fused path): every particle of the grid ensembles of
+// one grid size J in one launch, from a table of {ensemble, filter, particle}
+// entries; the estimator from tables of {ensemble, filter, chunk} and
+// {ensemble, filter} jobs and a list of ensembles.
+hipError_t launch_grid_steps_batched(int J, const int4 *d_ptab, int n_p, const FusedEns *d_ens,
+                                     IvArg iv, int parity, int pending, int blocks, hipStream_t s);
+hipError_t launch_grid_estimate_batched(int J, const int4 *d_part_jobs, int n_part,
+                                        const int4 *d_fold_jobs, int n_fold, const int *d_gens,
+                                        int n_gens, const FusedEns *d_ens, int out, hipStream_t s);
+int grid_resident_blocks_j(int J);
 
 // cross-filter averages of many ensembles at once (one workgroup each)
 // t_inc (optional): device interval counter advanced once the means are done

@@ -1,0 +1,149 @@
+"""GPU tests of the uneven serving-style batch (MI355X only).
+
+Many tenants -- Lorenz filters of very different N (tiny, one tile, many
+tiles, above one workgroup), FH-N grids of several N batched into one
+stepping launch, OU -- run as one fused interval per observation, directly or
+replayed from a captured graph.  Each tenant is independent of the others,
+so its log-weights, ancestors, statistics and estimates must be exactly those
+of the same tenant run alone under the same launch plan.  Different launch
+plans (pf_tuning) compute the same filter: identical propagation and
+log-weights, normalising sums equal to rounding, and ancestors that differ
+only where a uniform falls at a CDF boundary.  The autotuner returns a valid
+plan and restarts the filters from their prior draw.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import pf_inputs
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [pf_inputs.lorenz63(), pf_inputs.fhn(20),
+         pf_inputs.ou1d(theta=1.0, sd=1.0, h=0.01, S=10, obs_var=0.3), pf_inputs.fhn(8)]
+# (model, M, N, seed): L63 tenants of every size class, FH-N 20 x 20 and 8 x 8
+# tenants (two batched groups), an OU ensemble
+ENSEMBLES = [(0, 1, 64, 101), (0, 1, 70, 102), (0, 1, 257, 103), (0, 1, 1000, 104),
+             (0, 1, 3000, 105), (0, 1, 8192, 106), (0, 1, 9000, 107), (0, 3, 500, 108),
+             (1, 1, 128, 201), (1, 1, 256, 202), (1, 1, 512, 203), (1, 2, 64, 204),
+             (2, 2, 100, 301), (3, 2, 40, 401)]
+T = 3
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pf(torch_mod):
+    import paper_1407_8071_amd as pf
+    pf.lib()
+    return pf
+
+
+@pytest.fixture(scope="module")
+def observations(orc, torch_mod):
+    ys = []
+    for e, (mi, M, N, seed) in enumerate(ENSEMBLES):
+        _, y = orc.simulate(orc.Model(SPECS[mi]), 900 + e, T)
+        ys.append(y.astype(np.float32))
+    return ys
+
+
+def _snapshot(f, e):
+    return (f.get_logweights(e).cpu().numpy(), f.get_ancestors(e).cpu().numpy(),
+            f.get_filter_stats(e).cpu().numpy())
+
+
+def _run_batch(pf, torch_mod, ys, tuning=None, graph=False):
+    y_all = torch_mod.from_numpy(np.ascontiguousarray(np.concatenate(ys, axis=1))).cuda()
+    f = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True, graph=graph)
+    if tuning is not None:
+        f.set_tuning(tuning)
+    if graph:
+        f.set_observations(y_all)
+    snaps, ests = [], []
+    for t in range(T):
+        f.step(None if graph else y_all[t])
+        f.sync()
+        snaps.append([_snapshot(f, e) for e in range(len(ENSEMBLES))])
+        ests.append(f.estimate()[3].cpu().numpy())  # per-filter means
+    return snaps, ests
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_members_match_runs_alone(pf, orc, torch_mod, observations, graph):
+    tuning = {"vec_single_kernel": 0, "prop_tile": 64, "resample_bd_min": 64,
+              "grid_blocks_per_cu": 0}
+    snaps, ests = _run_batch(pf, torch_mod, observations, tuning, graph)
+    off = 0
+    for e, (mi, M, N, seed) in enumerate(ENSEMBLES):
+        dx = SPECS[mi]["dx"]
+        f = pf.ParticleFilter([SPECS[mi]], [(0, M, N, seed)], fused=True)
+        f.set_tuning(tuning)
+        yd = torch_mod.from_numpy(observations[e]).cuda()
+        for t in range(T):
+            f.step(yd[t])
+            f.sync()
+            alone = _snapshot(f, 0)
+            for a, b in zip(alone, snaps[t][e]):
+                assert np.array_equal(a, b, equal_nan=True), f"ensemble {e} interval {t + 1}"
+            fm = f.estimate()[3].cpu().numpy()
+            assert np.array_equal(fm, ests[t][off:off + M * dx]), f"ensemble {e} estimate"
+        off += M * dx
+
+
+def test_launch_plans_compute_the_same_filter(pf, torch_mod, observations):
+    plans = [None,
+             {"vec_single_kernel": 0, "prop_tile": 64, "resample_bd_min": 64, "grid_blocks_per_cu": 1},
+             {"vec_single_kernel": 0, "prop_tile": 128, "resample_bd_min": 1024, "grid_blocks_per_cu": 2},
+             {"vec_single_kernel": 1, "prop_tile": 256, "resample_bd_min": 512, "grid_blocks_per_cu": 0}]
+    runs = [_run_batch(pf, torch_mod, observations, p)[0] for p in plans]
+    base = runs[0]
+    for other in runs[1:]:
+        mism = tot = 0
+        for e in range(len(ENSEMBLES)):
+            lw0, A0, st0 = base[0][e]
+            lw1, A1, st1 = other[0][e]
+            # first interval: same particles in, same propagation and weights
+            assert np.array_equal(lw0, lw1, equal_nan=True)
+            st0 = st0.reshape(-1, 4)
+            st1 = st1.reshape(-1, 4)
+            assert np.array_equal(st0[:, 0], st1[:, 0])            # max log-weight
+            assert np.allclose(st0[:, 1:3], st1[:, 1:3], rtol=1e-12, atol=0)
+            mism += int((A0 != A1).sum())
+            tot += A0.size
+        assert mism <= max(4, 1e-4 * tot), (mism, tot)
+
+
+def test_autotune_restarts_from_the_prior(pf, torch_mod, observations, tmp_path):
+    y_all = torch_mod.from_numpy(np.ascontiguousarray(np.concatenate(observations, axis=1))).cuda()
+    f = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True)
+    best = f.autotune(y_all[0], reps=2)
+    assert best["prop_tile"] in (64, 128, 256)
+    assert best["resample_bd_min"] in (64, 128, 256, 512, 1024)
+    assert best["vec_single_kernel"] in (0, 1) and 0 <= best["grid_blocks_per_cu"] <= 8
+    assert f.interval() == 1
+    g = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True)
+    g.set_tuning(best)
+    for t in range(2):
+        f.step(y_all[t])
+        g.step(y_all[t])
+    f.sync()
+    g.sync()
+    for e in range(len(ENSEMBLES)):
+        for a, b in zip(_snapshot(f, e), _snapshot(g, e)):
+            assert np.array_equal(a, b, equal_nan=True)
+    # the JSON cache returns the stored plan for the same batch shape
+    path = str(tmp_path / "tuning.json")
+    h = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True)
+    t1 = h.autotune_cached(y_all[0], path, reps=1)
+    stored = json.load(open(path))
+    assert list(stored.values()) == [t1]
+    k = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True)
+    assert k.autotune_cached(y_all[0], path, reps=1) == t1
+    assert k.tuning() == t1
