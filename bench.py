@@ -232,6 +232,141 @@ def learned_main(a):
     print(json.dumps(line))
 
 
+def _mix_oracle_worker(args):
+    spec, seed, N, intervals, y = args
+    import oracle
+    m = oracle.Model(spec)
+    X = oracle.init(m, seed, 0, N)
+    lz = 0.0
+    t0 = time.perf_counter()
+    for t in range(1, intervals + 1):
+        r = oracle.filter_interval(m, seed, 0, t, X, y[t - 1], lz)
+        X, lz = r["X"], r["logZ"]
+    return time.perf_counter() - t0, N * spec["S"] * intervals
+
+
+def mix_main(a):
+    """The uneven serving mix: 1024 Lorenz 63 tenants with N log-uniform in
+    [64, 8192] and 32 FH-N 20 x 20 tenants with N in {128, 256, 512}, each an
+    ensemble of one filter with its own seed and observations, advanced by
+    one graph-replayed fused interval per observation under the autotuner's
+    launch plan.  Also times the plain multi-launch path on a few intervals."""
+    import concurrent.futures as cf
+    import torch
+    import paper_1407_8071_amd as pf
+    n_l, n_f = pf_inputs.mixed_batch(1)
+    specs = [pf_inputs.lorenz63(), pf_inputs.fhn(20)]
+    ens = [(0, 1, n, 1000 + i) for i, n in enumerate(n_l)] + \
+          [(1, 1, n, 5000 + i) for i, n in enumerate(n_f)]
+    torch.cuda.set_device(0)
+    T = a.warmup + a.steps
+    # truth and observations of every tenant on the GPU (the library's simulator)
+    sim = pf.ParticleFilter(specs, [(0, 1, 1, 1), (1, 1, 1, 1)], fused=True)
+    ys = []
+    for i, (mi, _, _, seed) in enumerate(ens):
+        _, y = sim.simulate(mi, seed, T)
+        ys.append(y)
+    y_all = torch.cat(ys, dim=1).contiguous()
+    del sim
+    psteps_interval = sum(n * specs[mi]["S"] for (mi, _, n, _) in ens)
+    l63_ps = sum(n * 40 for n in n_l)
+    fhn_ps = sum(n * 20 for n in n_f)
+    # autotuned launch plan, then graph replay of the staged observations
+    f = pf.ParticleFilter(specs, ens, graph=True)
+    t0 = time.perf_counter()
+    tuning = f.autotune(y_all[0], reps=3)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    f.set_observations(y_all)
+    for t in range(a.warmup):
+        f.step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t1 = time.perf_counter()
+    e0.record(stream)
+    for t in range(a.steps):
+        f.step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    ms = e0.elapsed_time(e1)
+    est = f.estimate()[0].cpu().numpy()
+    assert np.all(np.isfinite(est)), "non-finite estimate"
+    del f
+    # the propagation kernels (Lorenz tiles + batched FH-N steps) with events,
+    # on a directly launched fused context with the same plan
+    g = pf.ParticleFilter(specs, ens, fused=True)
+    g.set_tuning(tuning)
+    for t in range(3):
+        g.step(y_all[t])
+    torch.cuda.synchronize()
+    g.read_profile()
+    g.set_profiling(True)
+    nprof = min(20, T - 3)
+    for t in range(3, 3 + nprof):
+        g.step(y_all[t])
+    torch.cuda.synchronize()
+    g.set_profiling(False)
+    k_ms, k_n = g.read_profile()
+    del g
+    slots = (L63_SLOTS_PER_PARTICLE_STEP * l63_ps + FHN_SLOTS_PER_NODE_STEP * 400 * fhn_ps) * nprof
+    achieved = slots * FLOP_PER_SLOT / (k_ms / 1e3) / 1e12
+    peak = VALU_SLOTS_PER_S * FLOP_PER_SLOT / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": "k_vec_prop_batched + k_grid_steps (batched), summed",
+                "algorithmic_slots_per_interval": slots / nprof,
+                "kernel_ms_per_interval": k_ms / nprof, "launches": k_n}
+    # the plain path: one kernel per method step and ensemble
+    pl = pf.ParticleFilter(specs, ens, fused=False)
+    pl.step(y_all[0])
+    torch.cuda.synchronize()
+    n_plain = 3
+    q0 = torch.cuda.Event(enable_timing=True)
+    q1 = torch.cuda.Event(enable_timing=True)
+    q0.record(stream)
+    for t in range(1, 1 + n_plain):
+        pl.step(y_all[t])
+    q1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = q0.elapsed_time(q1) / n_plain
+    del pl
+    cpu = None
+    if a.cpu_seconds > 0:
+        import oracle
+        oracle.lib()
+        yh = [y.double().cpu().numpy() for y in ys]
+        cores = max(1, min(16, os.cpu_count() or 1))
+        # a bounded sample: the first tenants of each model, a few intervals
+        sample = list(range(12)) + list(range(len(n_l), len(n_l) + 4))
+        jobs = [(specs[ens[i][0]], ens[i][3], ens[i][2], 2, yh[i]) for i in sample]
+        tc = time.perf_counter()
+        with cf.ThreadPoolExecutor(cores) as pool:
+            res = list(pool.map(_mix_oracle_worker, jobs))
+        cw = time.perf_counter() - tc
+        steps = sum(r[1] for r in res)
+        cpu = {"value": steps / cw, "unit": "particle-steps/s", "cores": min(cores, len(jobs)),
+               "wall_s": cw, "kind": "oracle",
+               "sample": f"12 Lorenz + 4 FH-N tenants of the mix x 2 intervals "
+                         f"({steps:.3g} particle-steps, FP64, one filter per core)"}
+    line = {
+        "metric": "particle-steps/s", "value": psteps_interval * a.steps / (ms / 1e3),
+        "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (GPU-simulated truth and observations per tenant)",
+        "config": {"workload": a.workload, "tenants_l63": len(n_l), "tenants_fhn20": len(n_f),
+                   "particles_l63": int(sum(n_l)), "particles_fhn": int(sum(n_f)),
+                   "particle_steps_per_interval": psteps_interval, "path": "graph",
+                   "tuning": tuning, "tune_s": tune_s, "wall_s": wall},
+        "plain_path_ms_per_interval": plain_ms,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -240,6 +375,9 @@ def main():
         sys.exit(2)
     if a.workload == "fhn40_learned_64x128":
         learned_main(a)
+        return
+    if a.workload == "mix_l63x1024_fhn20x32":
+        mix_main(a)
         return
     import torch
     import paper_1407_8071_amd as pf
