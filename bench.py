@@ -314,9 +314,12 @@ def mix_main(a):
     slots = (L63_SLOTS_PER_PARTICLE_STEP * l63_ps + FHN_SLOTS_PER_NODE_STEP * 400 * fhn_ps) * nprof
     achieved = slots * FLOP_PER_SLOT / (k_ms / 1e3) / 1e12
     peak = VALU_SLOTS_PER_S * FLOP_PER_SLOT / 1e12
+    lorenz_kernel = ("k_filter_wg (whole Lorenz intervals, resampling included)"
+                     if tuning["vec_single_kernel"] else "k_vec_prop_batched")
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None,
-                "kernel": "k_vec_prop_batched + k_grid_steps (batched), summed",
+                "kernel": lorenz_kernel + " + k_grid_steps (batched FH-N), summed; "
+                          "algorithmic work = propagation slots only",
                 "algorithmic_slots_per_interval": slots / nprof,
                 "kernel_ms_per_interval": k_ms / nprof, "launches": k_n}
     # the plain path: one kernel per method step and ensemble
