@@ -255,40 +255,6 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
 // sum_i n_i xbar_i / N and the weighted estimate sum_i w_i xbar_i / W.
 constexpr int RS_MAX_P = 8;
 
-// Called by every workgroup of an ensemble after thread 0 has written its
-// filter's means: the workgroup that finishes last forms the ensemble means
-// (1/M) sum_m of both estimators, summing the filters in one fixed order
-// (lane l of the first wave takes m = l, l + 64, ..., then a shuffle tree),
-// and resets the counter for the next interval.  Device-scope fences order
-// the filter means before the count and the count before the reads.
-template <int D>
-__device__ void ensemble_mean_last_block(const FusedEns &E, int *flag) {
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int done = atomicAdd(E.mctr, 1);
-    *flag = done == E.M - 1;
-  }
-  __syncthreads();
-  if (!*flag) return;
-  __threadfence();
-  if (threadIdx.x < 64) {
-    for (int c = 0; c < D; ++c) {
-      double a = 0.0, b = 0.0;
-      for (int m = threadIdx.x; m < E.M; m += 64) {
-        a += E.fmean[(size_t)m * D + c];
-        b += E.fmeanw[(size_t)m * D + c];
-      }
-      a = wave_sum(a);
-      b = wave_sum(b);
-      if (threadIdx.x == 0) {
-        E.emean[c] = a / (double)E.M;
-        E.emean[D + c] = b / (double)E.M;
-      }
-    }
-    if (threadIdx.x == 0) atomicExch(E.mctr, 0);
-  }
-}
-
 template <int BD, int D>
 __global__ void __launch_bounds__(BD)
 k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, IvArg iv,
@@ -432,9 +398,6 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
     f[4] = SN;
     f[5] = deg ? -INFINITY : f[5] + mx + log(W / (double)N) + E.lognorm;
     f[6] = W * W / w2;
-  }
-  if constexpr (D > 0) {
-    if (E.own_mean) ensemble_mean_last_block<D>(E, (int *)shf);
   }
 }
 

@@ -108,7 +108,7 @@ __device__ __forceinline__ float grid_loglik(const ModelDev &md, const float *vs
                                              float *shf) {
   float acc = 0.f;
   for (int k = threadIdx.x; k < md.dy; k += blockDim.x) {
-    const float r = y[k] - vs[md.obs_idx[k]];
+    const float r = gptr(y)[k] - vs[gptr(md.obs_idx)[k]];
     acc = fmaf(r, r, acc);
   }
   // block sum in FP32 (fixed order over waves)
@@ -146,15 +146,16 @@ k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict_
     const int m = pt.y, i = pt.z, N = E.N;
     const float *Xin = parity ? E.X1 : E.X0;
     float *Xout = parity ? E.X0 : E.X1;
-    const int src = pending ? min(max(E.A[(size_t)m * N + i], 0), N - 1) : i;
-    const float4 *in = (const float4 *)(Xin + ((size_t)m * N + src) * dx);
+    const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
+    const gmem<f4v> *in = gptr((const f4v *)(Xin + ((size_t)m * N + src) * dx));
     Slot4 S[SPT];
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int sl = threadIdx.x + q * blockDim.x;
       if (sl < slots) {
-        S[q].v = in[sl];
-        S[q].w = in[slots + sl];
+        const f4v a = in[sl], b = in[slots + sl];
+        S[q].v = make_float4(a.x, a.y, a.z, a.w);
+        S[q].w = make_float4(b.x, b.y, b.z, b.w);
         S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
         *(float4 *)(vs + 4 * sl) = S[q].v;
       }
@@ -176,18 +177,18 @@ k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict_
       }
       __syncthreads();
     }
-    float4 *out = (float4 *)(Xout + ((size_t)m * N + i) * dx);
+    gmem<f4v> *out = gptr((f4v *)(Xout + ((size_t)m * N + i) * dx));
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int sl = threadIdx.x + q * blockDim.x;
       if (sl < slots) {
-        out[sl] = S[q].v;
-        out[slots + sl] = S[q].w;
+        out[sl] = f4v{S[q].v.x, S[q].v.y, S[q].v.z, S[q].v.w};
+        out[slots + sl] = f4v{S[q].w.x, S[q].w.y, S[q].w.z, S[q].w.w};
       }
     }
     if (yb) {
       const float l = grid_loglik(md, vs, yb + E.yoff, shf);
-      if (threadIdx.x == 0) E.lw[(size_t)m * N + i] = l;
+      if (threadIdx.x == 0) gptr(E.lw)[(size_t)m * N + i] = l;
     }
     __syncthreads();
   }

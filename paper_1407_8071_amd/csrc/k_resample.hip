@@ -306,8 +306,7 @@ k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
   // every earlier kernel of the interval has read the counter
   if (t_inc && blockIdx.x == 0 && threadIdx.x == 0) *t_inc += 1;
   const FusedEns &E = ens[blockIdx.x];
-  // grid model: folded by its own estimator; own_mean: by the resampler
-  if (E.md.kind == 2 || E.own_mean) return;
+  if (E.md.kind == 2) return;  // grid model: folded by its own estimator
   const int dx = E.md.dx;
   for (int c = 0; c < dx; ++c) {
     double a = 0.0, b = 0.0;

@@ -327,19 +327,32 @@ k_mlp_grad(const float *__restrict__ p, int in_dim, int out_dim, Src src, int64_
   if (lane == 0) out[np] = lsum * inv_rows;
 }
 
-// grad[i] = sum over waves w of partial[w * stride + i] (fixed order), and
-// the loss from slot np when `loss` is given; then, if `adam`, one Adam step
-// of the FP32 parameters with bias corrections c1 = 1 - beta1^t,
-// c2 = 1 - beta2^t.
-__global__ void __launch_bounds__(256)
+// grad[i] = sum over waves w of partial[w * stride + i], and the loss from
+// slot np when `loss` is given; then, if `adam`, one Adam step of the FP32
+// parameters with bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+// A workgroup takes 64 consecutive parameters; its 16 wave slices sum every
+// 16th wave's partial (coalesced rows) and the slices are combined in LDS in
+// a fixed order, so the result does not depend on scheduling.
+constexpr int RED_SLICES = 16;
+
+__global__ void __launch_bounds__(64 * RED_SLICES)
 k_grad_reduce_adam(const float *__restrict__ partial, int nwaves, int stride, int np,
                    float *__restrict__ grad, float *__restrict__ loss, float *__restrict__ p,
                    float *__restrict__ mo, float *__restrict__ ve, float lr, float beta1,
                    float beta2, float omb1, float omb2, float eps, float c1, float c2, int adam) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i > np || (i == np && !loss)) return;
+  __shared__ float sh[RED_SLICES][64];
+  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const bool valid = i < np || (i == np && loss);
   float s = 0.f;
-  for (int w = 0; w < nwaves; ++w) s += partial[(size_t)w * stride + i];
+  if (valid)
+    for (int w = sl; w < nwaves; w += RED_SLICES) s += partial[(size_t)w * stride + i];
+  sh[sl][lane] = s;
+  __syncthreads();
+  if (sl != 0 || !valid) return;
+  s = 0.f;
+#pragma unroll
+  for (int k = 0; k < RED_SLICES; ++k) s += sh[k][lane];
   if (i == np) {
     *loss = s;
     return;
@@ -488,8 +501,8 @@ hipError_t launch_mlp_grad_rows(const float *params, int in_dim, int out_dim, co
                      out_dim, src, ntiles, 1.f / (float)std::max<int64_t>(rows, 1), partial, np);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_reduce_adam, dim3((np + 1 + 255) / 256), dim3(256), 0, s, partial,
-                     blocks * TR_WAVES, np + 1, np, grad, loss, nullptr, nullptr, nullptr, 0.f,
+  hipLaunchKernelGGL(k_grad_reduce_adam, dim3((np + 1 + 63) / 64), dim3(64 * RED_SLICES), 0, s,
+                     partial, blocks * TR_WAVES, np + 1, np, grad, loss, nullptr, nullptr, nullptr, 0.f,
                      0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, 0);
   return hipGetLastError();
 }
@@ -498,7 +511,8 @@ hipError_t launch_adam(float *params, const float *grad, float *mo, float *ve, i
                        double beta1, double beta2, double eps, int t, hipStream_t s) {
   const float c1 = (float)(1.0 - std::pow(beta1, t));
   const float c2 = (float)(1.0 - std::pow(beta2, t));
-  hipLaunchKernelGGL(k_grad_reduce_adam, dim3((n + 255) / 256), dim3(256), 0, s, grad, 1, n, n,
+  hipLaunchKernelGGL(k_grad_reduce_adam, dim3((n + 63) / 64), dim3(64 * RED_SLICES), 0, s, grad, 1,
+                     n, n,
                      nullptr, nullptr, params, mo, ve, (float)lr, (float)beta1, (float)beta2,
                      (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps, c1, c2, 1);
   return hipGetLastError();
@@ -519,8 +533,8 @@ hipError_t launch_train_fhn_step(const ModelDev &md, Key key, const float *traj,
   if (e != hipSuccess) return e;
   const float c1 = (float)(1.0 - std::pow(beta1, step));
   const float c2 = (float)(1.0 - std::pow(beta2, step));
-  hipLaunchKernelGGL(k_grad_reduce_adam, dim3((np + 1 + 255) / 256), dim3(256), 0, s, partial,
-                     blocks * TR_WAVES, np + 1, np, grad, loss, params, mo, ve, (float)lr,
+  hipLaunchKernelGGL(k_grad_reduce_adam, dim3((np + 1 + 63) / 64), dim3(64 * RED_SLICES), 0, s,
+                     partial, blocks * TR_WAVES, np + 1, np, grad, loss, params, mo, ve, (float)lr,
                      (float)beta1, (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2),
                      (float)eps, c1, c2, adam);
   return hipGetLastError();

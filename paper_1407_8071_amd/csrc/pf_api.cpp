@@ -88,7 +88,7 @@ int wg_block(int N, int bd_min = 256) {
 // Offsets of every array of one ensemble inside the workspace.
 struct Layout {
   size_t obs, pmean, psd, X0, X1, lw, A, Cl, Sl, tile, coff, soff, fstat, mpart, wpart, fmean,
-      fmeanw, emean, cnt, gpart, params, nearest, mctr, end;
+      fmeanw, emean, cnt, gpart, params, nearest, end;
 };
 
 constexpr int LEARNED_IN = 22, LEARNED_OUT = 2;  // FH-N node features, (u_v, u_w)
@@ -126,7 +126,6 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bo
   L.gpart = take(grid ? sizeof(double) * (size_t)M * pfk::grid_est_chunks(N) * 2 * dx : 0);
   L.params = take(learned ? sizeof(float) * (size_t)pfk::mlp_nparams(LEARNED_IN, LEARNED_OUT) : 0);
   L.nearest = take(learned ? sizeof(int32_t) * (size_t)(dx / 2) : 0);
-  L.mctr = take(sizeof(int32_t));
   L.end = o;
   return L;
 }
@@ -288,7 +287,6 @@ struct pf_ctx {
   // launch plan of the fused path (pf_tuning) and its tables
   pf_tuning tuning{0, 256, 256, 0};
   int prop_tile = 256;
-  bool means_launch = true;  // some ensemble needs the cross-filter means kernel
   pfk::WgJob *d_job_base = nullptr;  // MAX_CLASSES arrays of `max_jobs`
   size_t max_jobs = 0;
   struct GridGroup {
@@ -498,11 +496,9 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
       PF_HIP(pfk::launch_vec_estimate(D, D.X[out], D.X[out], D.A, false, s));
     }
   }
-  // 3. the cross-filter averages not formed by the resampler (and, in a
-  //    graph, the interval counter)
-  if (ctx->means_launch || iv.tp)
-    PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(),
-                                      iv.tp ? const_cast<int *>(iv.tp) : nullptr, s));
+  // 3. the cross-filter averages (and, in a graph, the interval counter)
+  PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(),
+                                    iv.tp ? const_cast<int *>(iv.tp) : nullptr, s));
   return PF_OK;
 }
 
@@ -642,15 +638,6 @@ pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
       for (int i0 = 0; i0 < E.d.N; i0 += u.prop_tile) ctx->tiles_host[which].push_back(int4{e, mm, i0, 0});
   }
   for (int w = 0; w < 2; ++w) ctx->n_tiles[w] = (int)ctx->tiles_host[w].size();
-  // ensembles resampled by the per-filter resampler form their ensemble
-  // mean in its last workgroup
-  ctx->means_launch = false;
-  for (int e = 0; e < n_ens; ++e) {
-    Ens &E = ctx->ens[(size_t)e];
-    E.fz.own_mean = (!E.grid && !E.wg && !E.tiled) ? 1 : 0;
-    ctx->fz_host[(size_t)e].own_mean = E.fz.own_mean;
-    if (!E.grid && !E.fz.own_mean) ctx->means_launch = true;
-  }
   // batched grid tables, one group per grid size
   ctx->ggroups.clear();
   size_t op = 0, oj = 0, of = 0, og = 0;
@@ -690,8 +677,6 @@ pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
     og += g.gens.size();
   }
   // upload
-  PF_HIP(hipMemcpyAsync(ctx->d_fens, ctx->fz_host.data(), sizeof(pfk::FusedEns) * (size_t)n_ens,
-                        hipMemcpyHostToDevice, s));
   for (WgClass &c : ctx->classes)
     PF_HIP(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(pfk::WgJob) * c.jobs.size(),
                           hipMemcpyHostToDevice, s));
@@ -861,8 +846,6 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     F.cnt = nullptr;
     F.gpart = nullptr;
     F.nch = 0;
-    F.own_mean = 0;
-    F.mctr = (int32_t *)(ws + L.mctr);
     if (E.grid) {
       E.cnt = (int32_t *)(ws + L.cnt);
       E.gpart = (double *)(ws + L.gpart);
@@ -912,7 +895,6 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
                             hipMemcpyHostToDevice, s));
     INIT_TRY(hipMemsetAsync(D.fstat, 0, sizeof(double) * (size_t)E.d.M * pfk::FREC, s));
     INIT_TRY(hipMemsetAsync(D.emean, 0, sizeof(double) * 2 * (size_t)E.dx, s));
-    INIT_TRY(hipMemsetAsync(E.fz.mctr, 0, sizeof(int32_t), s));
     // every ancestor index is valid from the start
     INIT_TRY(hipMemsetAsync(D.A, 0, sizeof(int32_t) * (size_t)E.d.M * E.d.N, s));
     if (E.grid)

@@ -9,6 +9,21 @@
 namespace pfk {
 
 // ---------------------------------------------------------------------------
+// Global-memory views of pointers the compiler cannot prove global (loaded
+// from device-side tables): accesses through them compile to global_* rather
+// than flat_* instructions, which would also hold the LDS wait counter.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ const gmem<T> *gptr(const T *p) {
+  return (const gmem<T> *)p;
+}
+template <class T>
+__device__ __forceinline__ gmem<T> *gptr(T *p) {
+  return (gmem<T> *)p;
+}
+
+// ---------------------------------------------------------------------------
 // Random numbers.  Philox4x32-10 (Salmon et al., SC'11): per round two 32x32
 // -> 64-bit products of counter words 0 and 2 with the published multipliers,
 // the Weyl key schedule, ten rounds.  The counter layout that every kernel

@@ -71,11 +71,6 @@ struct FusedEns {
   int32_t *cnt;
   double *gpart;
   int32_t nch;
-  // own_mean: the per-filter resampling kernel's last workgroup of the
-  // interval forms the ensemble mean (mctr counts finished filters and is
-  // reset by that workgroup)
-  int32_t own_mean;
-  int32_t *mctr;
 };
 
 // ---- vector models (OU, Lorenz 63): particles [M][dx][N] ------------------
