@@ -54,11 +54,12 @@ k_mlp_forward(const float *__restrict__ p, int in_dim, int out_dim, const float 
 // one-node halo that replicates the edge (which is both the edge replication
 // of the 3x3 feature patch and the no-flux truncation of the Laplacian: an
 // outside neighbour equals the node, so its term is exactly +0).  Per Euler
-// step: (A) every wave runs MLP tiles of 16 consecutive nodes (features from
+// step: (A) every wave runs MLP tiles of 32 consecutive nodes (features from
 // the current planes) and stores (u_v, u_w) of each node in LDS; (B) every
 // thread advances its node pairs (Philox call of pair p at step n, the same
 // counters as the bootstrap kernels) with the drift correction, accumulates
-// the log increment-density ratio, and writes the other plane buffer.  Two
+// the log increment-density ratio, and writes the interior of the other
+// plane buffer; (C) the edge nodes are copied into that buffer's halo.  Three
 // barriers per step.  The first read goes through the ancestors (fused
 // gather); the last step ends with the log-weight: observation term plus the
 // accumulated ratio.
@@ -79,20 +80,23 @@ __device__ __forceinline__ int node_row(int n, float invJ) {
   return (int)(((float)n + 0.5f) * invJ);
 }
 
-__device__ __forceinline__ void put_node(float *pl, int H2, int J, int i, int j, float v, float w) {
-  const int W = J + 2, hi = (i + 1) * W + (j + 1);
-  float *pv = pl, *pw = pl + H2;
-  pv[hi] = v;
-  pw[hi] = w;
-  const bool top = i == 0, bot = i == J - 1, lef = j == 0, rig = j == J - 1;
-  if (top) { pv[hi - W] = v; pw[hi - W] = w; }
-  if (bot) { pv[hi + W] = v; pw[hi + W] = w; }
-  if (lef) { pv[hi - 1] = v; pw[hi - 1] = w; }
-  if (rig) { pv[hi + 1] = v; pw[hi + 1] = w; }
-  if (top && lef) { pv[hi - W - 1] = v; pw[hi - W - 1] = w; }
-  if (top && rig) { pv[hi - W + 1] = v; pw[hi - W + 1] = w; }
-  if (bot && lef) { pv[hi + W - 1] = v; pw[hi + W - 1] = w; }
-  if (bot && rig) { pv[hi + W + 1] = v; pw[hi + W + 1] = w; }
+// Replicate the edge nodes of both planes into the one-node halo (corners
+// take the corner node); the interior must be complete and visible.
+__device__ __forceinline__ void fill_halo(float *pl, int H2, int J) {
+  const int W = J + 2, nh = 2 * W + 2 * J;
+  for (int k = threadIdx.x; k < nh; k += LS_THREADS) {
+    int r, c;
+    if (k < 2 * W) {
+      r = k < W ? 0 : W - 1;
+      c = k < W ? k : k - W;
+    } else {
+      r = (k < 2 * W + J ? k - 2 * W : k - 2 * W - J) + 1;
+      c = k < 2 * W + J ? 0 : W - 1;
+    }
+    const int src = min(max(r, 1), J) * W + min(max(c, 1), J), dst = r * W + c;
+    pl[dst] = pl[src];
+    pl[H2 + dst] = pl[H2 + src];
+  }
 }
 
 __device__ __forceinline__ int halo_index(int J, int node) {
@@ -100,7 +104,7 @@ __device__ __forceinline__ int halo_index(int J, int node) {
   return (i + 1) * (J + 2) + (j + 1);
 }
 
-__global__ void __launch_bounds__(LS_THREADS)
+__global__ void __launch_bounds__(LS_THREADS, 2)
 k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
                      const float *__restrict__ Xin, const int32_t *__restrict__ anc,
                      float *__restrict__ Xout, float *__restrict__ lw,
@@ -152,11 +156,16 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
       const float2 a = *(const float2 *)(in + 2 * pr);
       const float2 b = *(const float2 *)(in + nn + 2 * pr);
       const int ni = node_row(2 * pr, invJ), nj = 2 * pr - ni * J;
-      put_node(planes, H2, J, ni, nj, a.x, b.x);
-      put_node(planes, H2, J, ni, nj + 1, a.y, b.y);
+      const int hi = (ni + 1) * W + (nj + 1);
+      planes[hi] = a.x;
+      planes[hi + 1] = a.y;
+      planes[H2 + hi] = b.x;
+      planes[H2 + hi + 1] = b.y;
       *(float2 *)(CMP + 2 * pr) = make_float2(0.f, 0.f);
       *(float2 *)(CMP + nn + 2 * pr) = make_float2(0.f, 0.f);
     }
+    __syncthreads();
+    fill_halo(planes, H2, J);
     __syncthreads();
     float dl = 0.f;
     int cur = 0;
@@ -215,9 +224,12 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
           CMP[node] = cv;
           CMP[nn + node] = cw;
           dl += (-(lc.c1v * uv * zv) - lc.c2v * uv * uv) + (-(lc.c1w * uw * zw) - lc.c2w * uw * uw);
-          put_node(pn, H2, J, ni, nj0 + e, nv, nw);
+          pn[hi] = nv;
+          pn[H2 + hi] = nw;
         }
       }
+      __syncthreads();
+      fill_halo(pn, H2, J);
       __syncthreads();
       cur ^= 1;
     }

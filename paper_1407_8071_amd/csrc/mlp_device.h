@@ -168,11 +168,24 @@ __device__ inline void mlp32_load(const float *__restrict__ p, int in_dim, int o
   for (int r = 0; r < 4; ++r) w.b3[r] = r < out_dim ? bf16r(b3[r]) : 0.f;
 }
 
+// ReLU after the rounding, two values per instruction: rounding to nearest
+// even keeps the sign, so a bfloat16 with its sign bit set (negative, -0) is a
+// negative int16 and a packed integer max with 0 gives +0, which is the
+// rounding of ReLU's result; the others pass unchanged.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ bf16x8 relu_pack8(const f32x16 &a, int off) {
-  bf16x8 o;
+  u32x4 q;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) o[j] = (__bf16)relu(a[off + j]);
-  return o;
+  for (int j = 0; j < 4; ++j) {
+    const f32x2 f = {a[off + 2 * j], a[off + 2 * j + 1]};
+    const s16x2 b = __builtin_bit_cast(s16x2, __builtin_convertvector(f, bf16x2));
+    q[j] = __builtin_bit_cast(unsigned, __builtin_elementwise_max(b, (s16x2){0, 0}));
+  }
+  return __builtin_bit_cast(bf16x8, q);
 }
 
 // u_theta of the 32 tile rows whose inputs this lane holds (F[kb] = slots
