@@ -17,11 +17,11 @@ namespace {
 // u_theta over the rows of X [rows][in_dim] -> out [rows][out_dim].
 constexpr int FWD_THREADS = 256;
 
-__global__ void __launch_bounds__(FWD_THREADS)
+__global__ void __launch_bounds__(FWD_THREADS, 2)
 k_mlp_forward(const float *__restrict__ p, int in_dim, int out_dim, const float *__restrict__ X,
               int64_t rows, float *__restrict__ out) {
   Mlp32Regs w;
-  mlp32_load(p, in_dim, out_dim, w);
+  mlp32_load(p, in_dim, out_dim, w, InputsInOrder{in_dim});
   const int l = threadIdx.x & 63, c = l & 31, h = l >> 5;
   const int64_t ntiles = (rows + 31) / 32;
   const int64_t wave = (int64_t)blockIdx.x * (FWD_THREADS / 64) + (threadIdx.x >> 6);
@@ -66,8 +66,8 @@ k_mlp_forward(const float *__restrict__ p, int in_dim, int out_dim, const float 
 //
 // LDS (floats): planes [2 buffers][v, w][(J+2)^2], the compensation terms of
 // the Euler sums [v, w][J*J], u [2][J*J], y of the nearest observation [J*J],
-// that observation's halo index and offsets [J*J] (int), 32 of reduction
-// scratch.
+// the halo indices of the patch corner and of that observation [J*J] (int),
+// the observation's offsets [J*J] (bfloat16 pair), 32 of reduction scratch.
 constexpr int LS_THREADS = 256;  // 4 waves: two workgroups per CU
 
 struct LearnedConst {
@@ -99,6 +99,21 @@ __device__ __forceinline__ void fill_halo(float *pl, int H2, int J) {
   }
 }
 
+// Input slots of the FH-N proposal (features in the order of
+// fhn_features: v patch 0..8, w patch 9..17, residual, tau, row and column
+// offsets).  Lane half h reads patch positions 0..7 of plane h (slots 8 h + j,
+// one base address per half); slots 16..23 of half 0 hold v and w at patch
+// position 8, the residual, tau, the offsets, the constant 1 and a zero;
+// slots 24..31 are zero.
+struct FhnSlots {
+  __device__ int operator()(int k) const {
+    if (k < 8) return k;
+    if (k < 16) return 9 + (k - 8);
+    constexpr int tail[8] = {8, 17, 18, 19, 20, 21, SLOT_ONE, SLOT_ZERO};
+    return k < 24 ? tail[k - 16] : SLOT_ZERO;
+  }
+};
+
 __device__ __forceinline__ int halo_index(int J, int node) {
   const int i = node / J, j = node - i * J;
   return (i + 1) * (J + 2) + (j + 1);
@@ -119,33 +134,25 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
   float *CMP = lds + 4 * H2;              // [2][nn]
   float *U = CMP + 2 * nn;                // [2][nn]
   float *YN = U + 2 * nn;                 // [nn]
-  int *ON = (int *)(YN + nn);             // [nn]
-  float *red = (float *)(ON + nn);        // [32]
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, c = lane & 15, g = lane >> 4;
+  int *NO = (int *)(YN + nn);             // [nn]
+  unsigned *OFF = (unsigned *)(NO + nn);  // [nn]
+  float *red = (float *)(OFF + nn);       // [32]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int nwaves = LS_THREADS / 64, ntiles = (nn + 31) / 32;
   const int c32 = lane & 31, h = lane >> 5;
-  (void)c; (void)g;
 
   Mlp32Regs w;
-  mlp32_load(params, LEARNED_FEATURES, 2, w);
-  // inputs of lane half h: slots 8 h .. 8 h + 7 (patch values: offsets from
-  // the node's halo index, v plane then w plane) and, on half 0, slots
-  // 16 .. 23 (the last two w values, residual, tau, observation offsets,
-  // the constant 1, 0); half 1 holds zeros in slots 24 .. 31
-  int fo[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int k = 8 * h + j;
-    const int q = k < 9 ? k : k - 9;
-    fo[j] = (k < 9 ? 0 : H2) + (q / 3 - 1) * W + (q % 3 - 1);
-  }
-  // per node: y of the nearest observation, and its halo index (bits 0-15)
-  // with its row and column offsets + 128 (bits 16-23, 24-31)
+  mlp32_load(params, LEARNED_FEATURES, 2, w, FhnSlots{});
+  // per node: y of the nearest observation; the halo index of the node's
+  // patch corner (bits 0-15) and of that observation (bits 16-31); the
+  // observation's row and column offsets / 2 as a bfloat16 pair
   for (int n = tid; n < nn; n += LS_THREADS) {
     const int o = nearest[n], ob = md.obs_idx[o];
     YN[n] = y[o];
-    const int di = ob / J - n / J, dj = ob % J - n % J;
-    ON[n] = halo_index(J, ob) | ((di + 128) << 16) | ((dj + 128) << 24);
+    const int ni = n / J, nj = n - ni * J;
+    NO[n] = (ni * W + nj) | (halo_index(J, ob) << 16);
+    const f32x2 off = {0.5f * (float)(ob / J - ni), 0.5f * (float)(ob % J - nj)};
+    OFF[n] = __builtin_bit_cast(unsigned, __builtin_convertvector(off, bf16x2));
   }
 
   for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
@@ -175,24 +182,38 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
       const float *pc = planes + cur * 2 * H2;
       // (A) drift corrections of every node: 32-node MLP tiles per wave; the
       // inputs of the next tile are read while this tile's MFMAs run
-      auto inputs = [&](int tt, bf16x8 F[2]) {
-        const int node = min(32 * tt + c32, nn - 1);
-        const int ni = node_row(node, invJ), nj = node - ni * J;
-        const int ctr = (ni + 1) * W + (nj + 1);
+      // (no = NO of the tile's node, read one tile earlier still, so that no
+      // LDS read waits on another)
+      auto tile_node = [&](int tt) { return min(32 * tt + c32, nn - 1); };
+      // half 1 holds zeros in slots 24..31: an AND with a lane mask (a select
+      // would let the compiler move the reads under a branch)
+      const unsigned keep = h == 0 ? 0xFFFFFFFFu : 0u;
+      const unsigned one_lo = keep & 0x3F80u;  // bfloat16 (1, 0)
+      auto inputs = [&](int tt, int no, bf16x8 F[2]) {
+        const int node = tile_node(tt), base = no & 0xFFFF;
+        const float *r0 = pc + base + h * H2, *r1 = r0 + W, *r2 = r1 + W;
+        const float q[8] = {r0[0], r0[1], r0[2], r1[0], r1[1], r1[2], r2[0], r2[1]};
 #pragma unroll
-        for (int j = 0; j < 8; ++j) F[0][j] = (__bf16)pc[ctr + fo[j]];
-        const float w7 = pc[ctr + H2 + W], w8 = pc[ctr + H2 + W + 1];
-        const unsigned on = (unsigned)ON[node];
-        const float res = YN[node] - pc[on & 0xFFFFu];
-        const float f1[8] = {w7, w8, res, tau, 0.5f * (float)((int)((on >> 16) & 0xFFu) - 128),
-                             0.5f * (float)((int)(on >> 24) - 128), 1.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < 8; ++j) F[1][j] = (__bf16)(h == 0 ? f1[j] : 0.f);
+        for (int j = 0; j < 8; ++j) F[0][j] = (__bf16)q[j];
+        const float v8 = pc[base + 2 * W + 2], w8 = pc[base + H2 + 2 * W + 2];
+        const float res = YN[node] - pc[no >> 16];
+        const f32x2 a = {v8, w8}, b = {res, tau};
+        u32x4 f1;
+        f1[0] = keep & __builtin_bit_cast(unsigned, __builtin_convertvector(a, bf16x2));
+        f1[1] = keep & __builtin_bit_cast(unsigned, __builtin_convertvector(b, bf16x2));
+        f1[2] = keep & OFF[node];
+        f1[3] = one_lo;
+        F[1] = __builtin_bit_cast(bf16x8, f1);
       };
+      // (the read of the next tile is unconditional -- the last one repeats
+      // a valid tile -- so that it stays in the MFMA block and its LDS
+      // latency hides under the MFMAs)
       bf16x8 Fc[2], Fn[2];
-      if (wid < ntiles) inputs(wid, Fc);
+      int no_n = NO[tile_node(min(wid + nwaves, ntiles - 1))];
+      if (wid < ntiles) inputs(wid, NO[tile_node(wid)], Fc);
       for (int tt = wid; tt < ntiles; tt += nwaves) {
-        if (tt + nwaves < ntiles) inputs(tt + nwaves, Fn);
+        const int no_nn = NO[tile_node(min(tt + 2 * nwaves, ntiles - 1))];
+        inputs(min(tt + nwaves, ntiles - 1), no_n, Fn);
         const f32x16 o = mlp32_tile(w, Fc);
         if (h == 0 && 32 * tt + c32 < nn) {
           U[32 * tt + c32] = o[0];
@@ -200,33 +221,41 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
         }
         Fc[0] = Fn[0];
         Fc[1] = Fn[1];
+        no_n = no_nn;
       }
       __syncthreads();
       // (B) Euler-Maruyama with the corrected drift; the compensation terms
       // of the sums stay in LDS
       float *pn = planes + (cur ^ 1) * 2 * H2;
       for (int pr = tid; pr < np; pr += LS_THREADS) {
+        // every LDS read of the pair first (the stores below go to the other
+        // buffer, which the compiler cannot tell apart)
+        const int ni = node_row(2 * pr, invJ), nj0 = 2 * pr - ni * J;
+        const int hi = (ni + 1) * W + (nj0 + 1);
+        const float c0 = pc[hi], c1 = pc[hi + 1], l0 = pc[hi - 1], r1 = pc[hi + 2];
+        const float u0 = pc[hi - W], u1 = pc[hi - W + 1], d0 = pc[hi + W], d1 = pc[hi + W + 1];
+        const float w0 = pc[H2 + hi], w1 = pc[H2 + hi + 1];
+        const float2 uv = *(const float2 *)(U + 2 * pr), uw = *(const float2 *)(U + nn + 2 * pr);
+        float2 cv = *(const float2 *)(CMP + 2 * pr), cw = *(const float2 *)(CMP + nn + 2 * pr);
         float z[4];
         normals4(philox((uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st),
                         (P_PROP << 24) | (uint32_t)pr, key), z);
-        const int ni = node_row(2 * pr, invJ), nj0 = 2 * pr - ni * J;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int node = 2 * pr + e;
-          const int hi = (ni + 1) * W + (nj0 + e + 1);
-          const float cc = pc[hi], ww = pc[H2 + hi];
-          const float lap = (((pc[hi - W] - cc) + (pc[hi + W] - cc)) + (pc[hi - 1] - cc)) +
-                            (pc[hi + 1] - cc);
-          const float uv = U[node], uw = U[nn + node];
-          const float zv = z[2 * e], zw = z[2 * e + 1];
-          float nv, nw, cv = CMP[node], cw = CMP[nn + node];
-          fhn_node_step<true>(md, cc, ww, lap, zv, zw, uv, uw, nv, nw, cv, cw);
-          CMP[node] = cv;
-          CMP[nn + node] = cw;
-          dl += (-(lc.c1v * uv * zv) - lc.c2v * uv * uv) + (-(lc.c1w * uw * zw) - lc.c2w * uw * uw);
-          pn[hi] = nv;
-          pn[H2 + hi] = nw;
-        }
+        // node 2 pr: right neighbour c1; node 2 pr + 1: left neighbour c0
+        const float lap0 = (((u0 - c0) + (d0 - c0)) + (l0 - c0)) + (c1 - c0);
+        const float lap1 = (((u1 - c1) + (d1 - c1)) + (c0 - c1)) + (r1 - c1);
+        float nv0, nw0, nv1, nw1;
+        fhn_node_step<true>(md, c0, w0, lap0, z[0], z[1], uv.x, uw.x, nv0, nw0, cv.x, cw.x);
+        fhn_node_step<true>(md, c1, w1, lap1, z[2], z[3], uv.y, uw.y, nv1, nw1, cv.y, cw.y);
+        dl += (-(lc.c1v * uv.x * z[0]) - lc.c2v * uv.x * uv.x) +
+              (-(lc.c1w * uw.x * z[1]) - lc.c2w * uw.x * uw.x);
+        dl += (-(lc.c1v * uv.y * z[2]) - lc.c2v * uv.y * uv.y) +
+              (-(lc.c1w * uw.y * z[3]) - lc.c2w * uw.y * uw.y);
+        *(float2 *)(CMP + 2 * pr) = cv;
+        *(float2 *)(CMP + nn + 2 * pr) = cw;
+        pn[hi] = nv0;
+        pn[hi + 1] = nv1;
+        pn[H2 + hi] = nw0;
+        pn[H2 + hi + 1] = nw1;
       }
       __syncthreads();
       fill_halo(pn, H2, J);
@@ -276,7 +305,7 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
 
 size_t learned_lds_bytes(int J) {
   const size_t H2 = (size_t)(J + 2) * (J + 2), nn = (size_t)J * J;
-  return sizeof(float) * (4 * H2 + 6 * nn + 32);
+  return sizeof(float) * (4 * H2 + 7 * nn + 32);
 }
 
 hipError_t set_learned_lds_limit() {

@@ -136,8 +136,18 @@ __device__ __forceinline__ int hid_slot32(int kb, int h, int j) {
   return 32 * (kb >> 1) + 8 * (2 * (kb & 1) + (j >> 2)) + 4 * h + (j & 3);
 }
 
+// Input slot k = 16 kb + 8 h + j of layer 1 carries input slot_in(k): an
+// index below in_dim, SLOT_ONE (the constant 1, whose weight column is b1) or
+// SLOT_ZERO.  The default order is the inputs, then the 1, then zeros.
+constexpr int SLOT_ONE = -1, SLOT_ZERO = -2;
+struct InputsInOrder {
+  int in_dim;
+  __device__ int operator()(int k) const { return k < in_dim ? k : (k == in_dim ? SLOT_ONE : SLOT_ZERO); }
+};
+
+template <class SlotIn>
 __device__ inline void mlp32_load(const float *__restrict__ p, int in_dim, int out_dim,
-                                  Mlp32Regs &w) {
+                                  Mlp32Regs &w, SlotIn slot_in) {
   const int l = threadIdx.x & 63, c = l & 31, h = l >> 5;
   const float *W1 = p, *b1 = W1 + HID * in_dim, *W2 = b1 + HID, *b2 = W2 + HID * HID;
   const float *W3 = b2 + HID, *b3 = W3 + out_dim * HID;
@@ -148,8 +158,8 @@ __device__ inline void mlp32_load(const float *__restrict__ p, int in_dim, int o
     for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int k = 16 * kb + 8 * h + j;
-        const float v = k < in_dim ? W1[u * in_dim + k] : (k == in_dim ? b1[u] : 0.f);
+        const int f = slot_in(16 * kb + 8 * h + j);
+        const float v = f >= 0 ? W1[u * in_dim + f] : (f == SLOT_ONE ? b1[u] : 0.f);
         w.a1[ob][kb][j] = (__bf16)v;
       }
 #pragma unroll
