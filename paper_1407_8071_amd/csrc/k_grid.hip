@@ -2,10 +2,11 @@
 // variables per node, particle-major state [M][N][2][J][J]: the v plane then
 // the w plane of each particle, contiguous).
 //
-// A workgroup owns one particle at a time.  Thread t handles the float4
-// slots s = t, t + blockDim, ... of the particle (nodes 4s .. 4s+3 in row-major
-// order): v and w of its nodes live in registers, and the v plane is staged
-// in LDS because the 5-point Laplacian reads the neighbours' v.
+// A thread handles float4 slots s of a particle (nodes 4s .. 4s+3 in
+// row-major order): v and w of its nodes live in registers, and the v plane
+// is staged in LDS because the 5-point Laplacian reads the neighbours' v.
+// The streaming kernel gives a workgroup one particle (slots s = t,
+// t + blockDim, ...); the blocked kernel a few particles of one ensemble.
 //   - k_grid_steps: every Euler step of the interval with the plane resident
 //     in LDS (temporal blocking: the state crosses HBM once per interval);
 //     the first read goes through the ancestor index (fused gather) and the
@@ -16,6 +17,7 @@
 // Euler-Maruyama with compensated FP32 sums, the noise of nodes 2p, 2p+1 from
 // the Philox call of node pair p at step n.
 #include <algorithm>
+#include <atomic>
 
 #include "pf_internal.h"
 
@@ -23,8 +25,9 @@ namespace pfk {
 namespace {
 
 constexpr int GB = 256;  // workgroup size of the element-wise grid kernels
-// The stepping kernels run 64 * ceil(slots / (64 * SPT)) threads with SPT
-// float4 slots each (slots = J*J/4); J <= 64 needs at most 1024 slots.
+// The streaming and simulation kernels run 64 * ceil(slots / (64 * SPT))
+// threads with SPT float4 slots each (slots = J*J/4); J <= 64 needs at most
+// 1024 slots.
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 // streaming access: the state of a step is touched once and exceeds every cache
@@ -123,72 +126,90 @@ __device__ __forceinline__ float grid_loglik(const ModelDev &md, const float *vs
   return (lw == lw) ? lw : -INFINITY;
 }
 
+// -(1/(2 sigma^2)) sum_k (y_k - v[obs_k])^2 of one particle by one wavefront:
+// lane l sums the terms k = l, l + 64, ... in order, then a butterfly over
+// the 64 lanes (every lane returns the total).
+__device__ __forceinline__ float wave_loglik(const ModelDev &md, const float *vs, const float *y,
+                                             int lane) {
+  float acc = 0.f;
+  for (int k = lane; k < md.dy; k += 64) {
+    const float r = gptr(y)[k] - vs[gptr(md.obs_idx)[k]];
+    acc = fmaf(r, r, acc);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  const float lw = -acc * md.inv2var;
+  return (lw == lw) ? lw : -INFINITY;
+}
+
 // Interval of S steps per particle with the v plane resident in LDS, over a
-// table of {ensemble, filter, particle} entries of grid ensembles that share
-// J (one launch serves a whole batch of them).
-template <int SPT>
+// table of {ensemble, filter, particle, -} entries of grid ensembles that
+// share J (one launch serves a whole batch of them).  A workgroup holds ppb
+// particles of one ensemble at a time -- thread t works on slot t % slots of
+// particle t / slots -- so that ppb * slots threads fill whole wavefronts
+// (J = 40: 2 x 400 slots in 832 threads; J = 20: 5 x 100 in 512).  Every
+// ensemble's entries are padded to a multiple of ppb with ensemble -1.
+// MULTI = false is the ppb = 1 form, whose particle indices stay uniform
+// (scalar registers).
+template <bool MULTI>
 __global__ void __launch_bounds__(1024)
 k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict__ ens, IvArg iv,
-             int parity, int pending, int J) {
+             int parity, int pending, int J, int ppb_arg) {
   const int t = iv_t(iv);
   const float *yb = iv_y(iv, t);
-  extern __shared__ float vs[];  // [J*J] v plane, then 16 floats of scratch
+  extern __shared__ float planes[];  // [ppb][J*J] v planes
+  const int ppb = MULTI ? ppb_arg : 1;
   const int nn = J * J, slots = nn / 4, dx = 2 * nn;
-  float *shf = vs + nn;
-  Nbr4 nb[SPT];
-#pragma unroll
-  for (int q = 0; q < SPT; ++q) nb[q] = neighbours(J, min((int)(threadIdx.x + q * blockDim.x), slots - 1));
-  for (int p = blockIdx.x; p < n_p; p += gridDim.x) {
-    const int4 pt = ptab[p];
-    const FusedEns &E = ens[pt.x];
+  const int q = MULTI ? (int)threadIdx.x / slots : 0, sl = (int)threadIdx.x - q * slots;
+  const bool has_slot = MULTI ? q < ppb : sl < slots;
+  float *vs = planes + (has_slot ? q : 0) * nn;
+  const Nbr4 nb = neighbours(J, has_slot ? sl : 0);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int p0 = blockIdx.x * ppb; p0 < n_p; p0 += gridDim.x * ppb) {
+    // the first entry of a group is never padding
+    const FusedEns &E = ens[ptab[p0].x];
     const ModelDev md = E.md;
     const Key key = E.key;
-    const int m = pt.y, i = pt.z, N = E.N;
+    const int N = E.N;
+    int4 pt = make_int4(-1, 0, 0, 0);
+    if (!MULTI) pt = ptab[p0];
+    else if (has_slot) pt = ptab[p0 + q];
+    const bool on = MULTI ? pt.x >= 0 : has_slot;
+    const int m = pt.y, i = pt.z;
     const float *Xin = parity ? E.X1 : E.X0;
     float *Xout = parity ? E.X0 : E.X1;
-    const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
-    const gmem<f4v> *in = gptr((const f4v *)(Xin + ((size_t)m * N + src) * dx));
-    Slot4 S[SPT];
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-      const int sl = threadIdx.x + q * blockDim.x;
-      if (sl < slots) {
-        const f4v a = in[sl], b = in[slots + sl];
-        S[q].v = make_float4(a.x, a.y, a.z, a.w);
-        S[q].w = make_float4(b.x, b.y, b.z, b.w);
-        S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
-        *(float4 *)(vs + 4 * sl) = S[q].v;
-      }
+    Slot4 S;
+    if (on) {
+      const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
+      const gmem<f4v> *in = gptr((const f4v *)(Xin + ((size_t)m * N + src) * dx));
+      const f4v a = in[sl], b = in[slots + sl];
+      S.v = make_float4(a.x, a.y, a.z, a.w);
+      S.w = make_float4(b.x, b.y, b.z, b.w);
+      S.cv = S.cw = make_float4(0.f, 0.f, 0.f, 0.f);
+      *(float4 *)(vs + 4 * sl) = S.v;
     }
     __syncthreads();
     const int n0 = (t - 1) * md.S;
     for (int st = 0; st < md.S; ++st) {
-#pragma unroll
-      for (int q = 0; q < SPT; ++q) {
-        const int sl = threadIdx.x + q * blockDim.x;
-        if (sl < slots)
-          grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), sl, nb[q], vs, S[q]);
-      }
+      if (on) grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), sl, nb, vs, S);
       __syncthreads();
-#pragma unroll
-      for (int q = 0; q < SPT; ++q) {
-        const int sl = threadIdx.x + q * blockDim.x;
-        if (sl < slots) *(float4 *)(vs + 4 * sl) = S[q].v;
-      }
+      if (on) *(float4 *)(vs + 4 * sl) = S.v;
       __syncthreads();
     }
-    gmem<f4v> *out = gptr((f4v *)(Xout + ((size_t)m * N + i) * dx));
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-      const int sl = threadIdx.x + q * blockDim.x;
-      if (sl < slots) {
-        out[sl] = f4v{S[q].v.x, S[q].v.y, S[q].v.z, S[q].v.w};
-        out[slots + sl] = f4v{S[q].w.x, S[q].w.y, S[q].w.z, S[q].w.w};
-      }
+    if (on) {
+      gmem<f4v> *out = gptr((f4v *)(Xout + ((size_t)m * N + i) * dx));
+      out[sl] = f4v{S.v.x, S.v.y, S.v.z, S.v.w};
+      out[slots + sl] = f4v{S.w.x, S.w.y, S.w.z, S.w.w};
     }
     if (yb) {
-      const float l = grid_loglik(md, vs, yb + E.yoff, shf);
-      if (threadIdx.x == 0) gptr(E.lw)[(size_t)m * N + i] = l;
+      // one wavefront per particle of the group
+      for (int qq = wid; qq < ppb; qq += nwaves) {
+        const int4 pq = ptab[p0 + qq];
+        if (pq.x >= 0) {
+          const float l = wave_loglik(md, planes + qq * nn, yb + E.yoff, lane);
+          if (lane == 0) gptr(E.lw)[(size_t)pq.y * N + pq.z] = l;
+        }
+      }
     }
     __syncthreads();
   }
@@ -497,6 +518,10 @@ k_grid_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
 
 size_t grid_lds(const ModelDev &md) { return sizeof(float) * ((size_t)md.J * md.J + 16); }
 
+// k_grid_steps: threads and LDS for ppb particles per workgroup
+int steps_threads(int J, int ppb) { return 64 * ((ppb * J * J / 4 + 63) / 64); }
+size_t steps_lds(int J, int ppb) { return sizeof(float) * (size_t)ppb * J * J; }
+
 }  // namespace
 
 namespace {
@@ -510,22 +535,68 @@ void grid_shape(const ModelDev &md, int *spt, int *threads) {
 }
 }  // namespace
 
+// Particles per workgroup of k_grid_steps.  The kernel is VALU-bound, so
+// the criterion is the share of useful lanes among the wavefront lanes it
+// issues (ppb * slots / threads), among the shapes that keep at least 16
+// wavefronts resident per CU (latency hiding); the one-particle form keeps
+// its indices in scalar registers and so has the fewer VGPRs.  Cached per J
+// (the launch and the table padding must agree).
+namespace {
+int steps_blocks_per_cu(int J, int ppb) {
+  int per_cu = 0;
+  const hipError_t e =
+      ppb == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<false>, steps_threads(J, 1), steps_lds(J, 1))
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<true>, steps_threads(J, ppb), steps_lds(J, ppb));
+  return e == hipSuccess ? per_cu : 0;
+}
+}  // namespace
+
+int grid_steps_ppb(int J) {
+  static std::atomic<int> cache[65];
+  if (J < 2 || J > 64) return 1;
+  const int c = cache[J].load(std::memory_order_relaxed);
+  if (c > 0) return c;
+  const int slots = J * J / 4;
+  int best = 1, best_waves = 0;
+  double best_fill = -1.0;
+  for (int k = 1; k <= 8 && k * slots <= 1024; ++k) {
+    const int threads = steps_threads(J, k);
+    const int waves = steps_blocks_per_cu(J, k) * threads / 64;
+    const double fill = (double)(k * slots) / threads;
+    const bool ok = waves >= 16, best_ok = best_waves >= 16;
+    if ((ok && !best_ok) || (ok == best_ok && (ok ? fill > best_fill + 1e-9 : waves > best_waves))) {
+      best = k;
+      best_fill = fill;
+      best_waves = waves;
+    }
+  }
+  cache[J].store(best, std::memory_order_relaxed);
+  return best;
+}
+
 int grid_resident_blocks_j(int J) {
-  ModelDev md{};
-  md.J = J;
+  const int ppb = grid_steps_ppb(J);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
+  return std::max(1, steps_blocks_per_cu(J, ppb)) * prop.multiProcessorCount;
+}
+
+// resident workgroups of the streaming one-step kernel
+int grid_resident_blocks(const ModelDev &md) {
   int dev = 0, per_cu = 0, spt, threads;
   grid_shape(md, &spt, &threads);
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
-  hipError_t e = spt == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<1>, threads, grid_lds(md))
-               : spt == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<2>, threads, grid_lds(md))
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<4>, threads, grid_lds(md));
+  const size_t lds = grid_lds(md);
+  hipError_t e = spt == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_stream_step<1>, threads, lds)
+               : spt == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_stream_step<2>, threads, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_stream_step<4>, threads, lds);
   if (e != hipSuccess) return 1024;
   return std::max(1, per_cu) * prop.multiProcessorCount;
 }
-
-int grid_resident_blocks(const ModelDev &md) { return grid_resident_blocks_j(md.J); }
 
 hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s) {
   k_grid_init<<<e.M * e.N, GB, 0, s>>>(e.md, e.key, e.N, X);
@@ -535,18 +606,15 @@ hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s) {
 hipError_t launch_grid_steps_batched(int J, const int4 *d_ptab, int n_p, const FusedEns *d_ens,
                                      IvArg iv, int parity, int pending, int blocks, hipStream_t s) {
   if (n_p <= 0) return hipSuccess;
-  ModelDev md{};
-  md.J = J;
-  int spt, threads;
-  grid_shape(md, &spt, &threads);
-  const int g = std::max(1, std::min(blocks, n_p));
-  const size_t lds = grid_lds(md);
-  if (spt == 1)
-    k_grid_steps<1><<<g, threads, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
-  else if (spt == 2)
-    k_grid_steps<2><<<g, threads, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
+  const int ppb = grid_steps_ppb(J);
+  if (n_p % ppb != 0) return hipErrorInvalidValue;  // the table is padded per ensemble
+  const int g = std::max(1, std::min(blocks, n_p / ppb));
+  if (ppb == 1)
+    k_grid_steps<false><<<g, steps_threads(J, 1), steps_lds(J, 1), s>>>(d_ptab, n_p, d_ens, iv, parity,
+                                                                       pending, J, 1);
   else
-    k_grid_steps<4><<<g, threads, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
+    k_grid_steps<true><<<g, steps_threads(J, ppb), steps_lds(J, ppb), s>>>(d_ptab, n_p, d_ens, iv,
+                                                                          parity, pending, J, ppb);
   return hipGetLastError();
 }
 

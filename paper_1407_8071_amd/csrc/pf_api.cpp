@@ -147,7 +147,8 @@ CtxSizes ctx_sizes(const pf_model_desc *models, const pf_ensemble_desc *ens, int
     z.jobs += (size_t)ens[e].M;
     z.tiles += (size_t)ens[e].M * (((size_t)ens[e].N + MIN_PROP_TILE - 1) / MIN_PROP_TILE);
     if (models[ens[e].model].kind == PF_MODEL_FHN) {
-      z.gparticles += (size_t)ens[e].M * ens[e].N;
+      // room for the padding of the stepping kernel's groups (at most 7)
+      z.gparticles += (size_t)ens[e].M * ens[e].N + 7;
       z.gpart_jobs += (size_t)ens[e].M * pfk::grid_est_chunks(ens[e].N);
       z.gfold_jobs += (size_t)ens[e].M;
     }
@@ -659,6 +660,9 @@ pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
       for (int ch = 0; ch < nch; ++ch) g->part_jobs.push_back(int4{e, mm, ch, 0});
       g->fold_jobs.push_back(int4{e, mm, 0, 0});
     }
+    // the stepping kernel takes ppb entries of one ensemble per workgroup
+    const size_t ppb = (size_t)pfk::grid_steps_ppb(J);
+    while (g->ptab.size() % ppb) g->ptab.push_back(int4{-1, 0, 0, 0});
     g->gens.push_back(e);
   }
   for (auto &g : ctx->ggroups) {

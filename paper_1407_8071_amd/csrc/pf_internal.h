@@ -135,6 +135,10 @@ hipError_t launch_grid_estimate_batched(int J, const int4 *d_part_jobs, int n_pa
                                         const int4 *d_fold_jobs, int n_fold, const int *d_gens,
                                         int n_gens, const FusedEns *d_ens, int out, hipStream_t s);
 int grid_resident_blocks_j(int J);
+// particles per workgroup of the batched stepping kernel (1..8, fixed per J
+// and device); its particle table holds each ensemble's entries padded to a
+// multiple of this with ensemble -1
+int grid_steps_ppb(int J);
 
 // cross-filter averages of many ensembles at once (one workgroup each)
 // t_inc (optional): device interval counter advanced once the means are done
