@@ -152,9 +152,9 @@ __device__ __forceinline__ float wave_loglik(const ModelDev &md, const float *vs
 // MULTI = false is the ppb = 1 form, whose particle indices stay uniform
 // (scalar registers).
 template <bool MULTI>
-__global__ void __launch_bounds__(1024)
-k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict__ ens, IvArg iv,
-             int parity, int pending, int J, int ppb_arg) {
+__device__ __forceinline__ void grid_steps(const int4 *__restrict__ ptab, int n_p,
+                                           const FusedEns *__restrict__ ens, IvArg iv, int parity,
+                                           int pending, int J, int ppb_arg) {
   const int t = iv_t(iv);
   const float *yb = iv_y(iv, t);
   extern __shared__ float planes[];  // [ppb][J*J] v planes
@@ -213,6 +213,20 @@ k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict_
     }
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(1024)
+k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict__ ens, IvArg iv,
+             int parity, int pending, int J) {
+  grid_steps<false>(ptab, n_p, ens, iv, parity, pending, J, 1);
+}
+
+// (at most 64 VGPRs, 8 wavefronts per SIMD: the few values it spills are
+// reloaded once per particle group, outside the Euler steps)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+k_grid_steps_multi(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict__ ens,
+                   IvArg iv, int parity, int pending, int J, int ppb) {
+  grid_steps<true>(ptab, n_p, ens, iv, parity, pending, J, ppb);
 }
 
 // One Euler step n of every particle, state through HBM.
@@ -537,16 +551,17 @@ void grid_shape(const ModelDev &md, int *spt, int *threads) {
 
 // Particles per workgroup of k_grid_steps.  The kernel is VALU-bound, so
 // the criterion is the share of useful lanes among the wavefront lanes it
-// issues (ppb * slots / threads), among the shapes that keep at least 16
-// wavefronts resident per CU (latency hiding); the one-particle form keeps
-// its indices in scalar registers and so has the fewer VGPRs.  Cached per J
-// (the launch and the table padding must agree).
+// issues (ppb * slots / threads), among the shapes that keep at least 3
+// workgroups and 16 wavefronts resident per CU (the other workgroups' waves
+// cover each workgroup's two barriers per Euler step; measured: for J = 40,
+// one particle in 4 resident workgroups of 7 waves beats two in 2 of 13).
+// Cached per J (the launch and the table padding must agree).
 namespace {
 int steps_blocks_per_cu(int J, int ppb) {
   int per_cu = 0;
   const hipError_t e =
-      ppb == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<false>, steps_threads(J, 1), steps_lds(J, 1))
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps<true>, steps_threads(J, ppb), steps_lds(J, ppb));
+      ppb == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps, steps_threads(J, 1), steps_lds(J, 1))
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps_multi, steps_threads(J, ppb), steps_lds(J, ppb));
   return e == hipSuccess ? per_cu : 0;
 }
 }  // namespace
@@ -559,15 +574,17 @@ int grid_steps_ppb(int J) {
   const int slots = J * J / 4;
   int best = 1, best_waves = 0;
   double best_fill = -1.0;
+  bool best_ok = false;
   for (int k = 1; k <= 8 && k * slots <= 1024; ++k) {
-    const int threads = steps_threads(J, k);
-    const int waves = steps_blocks_per_cu(J, k) * threads / 64;
+    const int threads = steps_threads(J, k), blocks = steps_blocks_per_cu(J, k);
+    const int waves = blocks * threads / 64;
     const double fill = (double)(k * slots) / threads;
-    const bool ok = waves >= 16, best_ok = best_waves >= 16;
+    const bool ok = blocks >= 3 && waves >= 16;
     if ((ok && !best_ok) || (ok == best_ok && (ok ? fill > best_fill + 1e-9 : waves > best_waves))) {
       best = k;
       best_fill = fill;
       best_waves = waves;
+      best_ok = ok;
     }
   }
   cache[J].store(best, std::memory_order_relaxed);
@@ -610,10 +627,10 @@ hipError_t launch_grid_steps_batched(int J, const int4 *d_ptab, int n_p, const F
   if (n_p % ppb != 0) return hipErrorInvalidValue;  // the table is padded per ensemble
   const int g = std::max(1, std::min(blocks, n_p / ppb));
   if (ppb == 1)
-    k_grid_steps<false><<<g, steps_threads(J, 1), steps_lds(J, 1), s>>>(d_ptab, n_p, d_ens, iv, parity,
-                                                                       pending, J, 1);
+    k_grid_steps<<<g, steps_threads(J, 1), steps_lds(J, 1), s>>>(d_ptab, n_p, d_ens, iv, parity,
+                                                                pending, J);
   else
-    k_grid_steps<true><<<g, steps_threads(J, ppb), steps_lds(J, ppb), s>>>(d_ptab, n_p, d_ens, iv,
+    k_grid_steps_multi<<<g, steps_threads(J, ppb), steps_lds(J, ppb), s>>>(d_ptab, n_p, d_ens, iv,
                                                                           parity, pending, J, ppb);
   return hipGetLastError();
 }
