@@ -98,6 +98,30 @@ struct ExpoWG {
   }
 };
 
+// smallest i in [0, N) with C[i] > v (clamped to N - 1) without a known
+// lower bound: bisection over the last entries of 64-entry blocks, then
+// within the block (12 dependent LDS reads for N = 4096 instead of ~22 for a
+// doubling search from 0)
+__device__ __forceinline__ int lds_search_blocked(const double *C, int N, double v) {
+  int a = 0, b = (N - 1) >> 6;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (C[min(64 * mid + 63, N - 1)] > v)
+      b = mid;
+    else
+      a = mid + 1;
+  }
+  int lo = 64 * a, hi = min(64 * a + 63, N - 1);  // C[lo - 1] <= v
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] > v)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
 // smallest i in [0, N) with C[i] > v (clamped to N - 1), starting from the
 // known lower bound lo (C[lo - 1] <= v)
 __device__ __forceinline__ int lds_search(const double *C, int N, int lo, double v) {
@@ -276,6 +300,8 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
   const int P = (N + BD - 1) / BD;
   const int k0 = min(N, tid * P), k1 = min(N, k0 + P);
   const float *lwg = E.lw + (size_t)m * N;
+  // thread 0 reads the running evidence now, so that its latency is hidden
+  const double lg_prev = tid == 0 ? E.fstat[(size_t)m * FREC + 5] : 0.0;
   const float *Xb = (xb_parity ? E.X1 : E.X0) + (size_t)m * DD * N;
   // 1. this thread's log-weights (and xbar), the filter maximum
   float lw[PM];
@@ -337,14 +363,14 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
     eg[e] = (k0 + e < k1) ? ex(k0 + e) : 0.0;
     es += eg[e];
   }
+  // the last thread, whose range is last (or empty), adds E_N: it enters
+  // the total S_N but no thread's exclusive prefix
+  if (tid == BD - 1) {
+    ExpoWG tail{E.key, (uint32_t)m, (uint32_t)t};
+    es += tail(N);
+  }
   double SN;
   const double eoff = block_exscan(es, shd, &SN);  // its barriers publish C
-  if (tid == 0) {
-    ExpoWG tail{E.key, (uint32_t)m, (uint32_t)t};
-    shd[8 * NW - 1] = tail(N);
-  }
-  __syncthreads();
-  SN += shd[8 * NW - 1];
   const double W = C[N - 1];
   // 4. ancestors in the LDS CDF and the offspring counts
   double sacc = eoff;
@@ -355,7 +381,7 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
     if (k < k1) {
       sacc += eg[e];
       const double v = (sacc / SN) * W;
-      i = lds_search(C, N, e == 0 ? 0 : i, v);
+      i = e == 0 ? lds_search_blocked(C, N, v) : lds_search(C, N, i, v);
       E.A[(size_t)m * N + k] = i;
       atomicAdd(cnt + i, 1);
     }
@@ -380,7 +406,7 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
     red[1] = red[2] = 0.0;
   }
   constexpr int NR = 1 + 2 * DD;
-  block_sum_multi<NR>(red, shd);
+  block_sum_multi_t0<NR>(red, shd);
   if (tid == 0) {
     if constexpr (D > 0) {
 #pragma unroll
@@ -396,7 +422,7 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
     f[2] = w2;
     f[3] = deg ? 1.0 : 0.0;
     f[4] = SN;
-    f[5] = deg ? -INFINITY : f[5] + mx + log(W / (double)N) + E.lognorm;
+    f[5] = deg ? -INFINITY : lg_prev + mx + log(W / (double)N) + E.lognorm;
     f[6] = W * W / w2;
   }
 }

@@ -129,26 +129,52 @@ __device__ __forceinline__ void fhn_node_step(const ModelDev &md, float c, float
 }
 
 // ---------------------------------------------------------------------------
-// Wave64 and workgroup reductions / scans.
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+// Wave64 and workgroup reductions / scans.  The wave level uses DPP lane
+// moves (row shifts within 16-lane rows, then the row broadcasts of lanes 15
+// and 31): a Hillis-Steele inclusive scan in six VALU steps, without the LDS
+// crossbar that a generic shuffle goes through.  Called by every lane of the
+// wave (full EXEC).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v, int identity) {
+  // lanes whose source is outside the pattern, or whose row is masked off,
+  // receive the identity
+  return __builtin_amdgcn_update_dpp(identity, v, CTRL, ROWS, 0xf, false);
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {  // identity +0.0
+  const int lo = dpp_i32<CTRL, ROWS>(__double2loint(v), 0);
+  const int hi = dpp_i32<CTRL, ROWS>(__double2hiint(v), 0);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114,
+              DPP_ROW_SHR8 = 0x118, DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142,
+              DPP_ROW_BCAST31 = 0x143;
+
+__device__ __forceinline__ float wave_max(float v) {
+  const int id = __float_as_int(-INFINITY);
+  v = fmaxf(v, __int_as_float(dpp_i32<DPP_ROW_SHR1, 0xf>(__float_as_int(v), id)));
+  v = fmaxf(v, __int_as_float(dpp_i32<DPP_ROW_SHR2, 0xf>(__float_as_int(v), id)));
+  v = fmaxf(v, __int_as_float(dpp_i32<DPP_ROW_SHR4, 0xf>(__float_as_int(v), id)));
+  v = fmaxf(v, __int_as_float(dpp_i32<DPP_ROW_SHR8, 0xf>(__float_as_int(v), id)));
+  v = fmaxf(v, __int_as_float(dpp_i32<DPP_ROW_BCAST15, 0xa>(__float_as_int(v), id)));
+  v = fmaxf(v, __int_as_float(dpp_i32<DPP_ROW_BCAST31, 0xc>(__float_as_int(v), id)));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 // inclusive scan across the 64 lanes
 __device__ __forceinline__ double wave_scan(double v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
+  v += dpp_f64<DPP_ROW_SHR1, 0xf>(v);
+  v += dpp_f64<DPP_ROW_SHR2, 0xf>(v);
+  v += dpp_f64<DPP_ROW_SHR4, 0xf>(v);
+  v += dpp_f64<DPP_ROW_SHR8, 0xf>(v);
+  v += dpp_f64<DPP_ROW_BCAST15, 0xa>(v);
+  v += dpp_f64<DPP_ROW_BCAST31, 0xc>(v);
   return v;
+}
+// the wave total (the scan's last lane), in every lane
+__device__ __forceinline__ double wave_sum(double v) {
+  v = wave_scan(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 // Workgroup max over blockDim.x threads (multiple of 64, <= 1024).
@@ -173,10 +199,11 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   for (int i = 0; i < nw; ++i) r += sh[i];
   return r;
 }
-// Workgroup sums of R values at once (fixed order); every thread gets them.
-// sh holds R * (blockDim.x / 64) doubles.
+// Workgroup sums of R values at once (fixed order); the results are valid in
+// thread 0 only (the other threads skip the fold).  sh holds
+// R * (blockDim.x / 64) doubles.
 template <int R>
-__device__ __forceinline__ void block_sum_multi(double v[R], double *sh) {
+__device__ __forceinline__ void block_sum_multi_t0(double v[R], double *sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = wave_sum(v[r]);
@@ -186,11 +213,13 @@ __device__ __forceinline__ void block_sum_multi(double v[R], double *sh) {
     for (int r = 0; r < R; ++r) sh[r * nw + wid] = v[r];
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    double a = 0.0;
-    for (int i = 0; i < nw; ++i) a += sh[r * nw + i];
-    v[r] = a;
+    for (int r = 0; r < R; ++r) {
+      double a = 0.0;
+      for (int i = 0; i < nw; ++i) a += sh[r * nw + i];
+      v[r] = a;
+    }
   }
 }
 
@@ -199,8 +228,7 @@ __device__ __forceinline__ void block_sum_multi(double v[R], double *sh) {
 __device__ __forceinline__ double block_exscan(double v, double *sh, double *tot) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const double inc = wave_scan(v);
-  double exc = __shfl_up(inc, 1, 64);
-  if (lane == 0) exc = 0.0;
+  const double exc = dpp_f64<DPP_WAVE_SHR1, 0xf>(inc);  // lane 0 receives 0
   __syncthreads();
   if (lane == 63) sh[wid] = inc;
   __syncthreads();
