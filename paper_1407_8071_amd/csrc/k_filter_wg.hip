@@ -70,12 +70,12 @@ template <int D>
 __device__ __forceinline__ float wg_loglik(const ModelDev &md, const float x[D], const float *y) {
   float acc = 0.f;
   for (int k = 0; k < md.dy; ++k) {
-    const int o = md.obs_idx[k];
+    const int o = gptr(md.obs_idx)[k];
     float xo = x[0];
 #pragma unroll
     for (int c = 1; c < D; ++c)
       if (o == c) xo = x[c];
-    const float r = y[k] - xo;
+    const float r = gptr(y)[k] - xo;
     acc = fmaf(r, r, acc);
   }
   const float lw = -acc * md.inv2var;
@@ -164,10 +164,11 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
   const FusedEns &E = ens[job.ens];
   const int m = job.filter, N = E.N, tid = threadIdx.x;
   float *lws = (float *)(C + N);           // [N] log-weights
-  const float *Xin = parity ? E.X1 : E.X0;
-  float *Xb = parity ? E.X0 : E.X1;        // xbar of this interval
+  // (pointers from the ensemble table: global-address-space accesses)
+  const gmem<float> *Xin = gptr(parity ? E.X1 : E.X0);
+  gmem<float> *Xb = gptr(parity ? E.X0 : E.X1);  // xbar of this interval
   const size_t xo = (size_t)m * D * N;
-  float *lwg = E.lw + (size_t)m * N;
+  gmem<float> *lwg = gptr(E.lw + (size_t)m * N);
 
   // 1. propagation and weighting
   float lmax = -INFINITY;
@@ -177,7 +178,7 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
       lw = lwg[i];
       lw = (lw == lw) ? lw : -INFINITY;
     } else {
-      const int src = pending ? min(max(E.A[(size_t)m * N + i], 0), N - 1) : i;
+      const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
       float x[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) x[c] = Xin[xo + (size_t)c * N + src];
@@ -242,7 +243,7 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
     run += ex(k);
     const double v = (run / SN) * W;
     i = lds_search(C, N, (k == k0) ? 0 : i, v);
-    E.A[(size_t)m * N + k] = i;
+    gptr(E.A)[(size_t)m * N + k] = i;
 #pragma unroll
     for (int c = 0; c < D; ++c) px[c] += (double)Xb[xo + (size_t)c * N + i];
   }
@@ -252,7 +253,7 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
 
   // 5. the filter's estimates and log G_t^N
   if (tid == 0) {
-    double *f = E.fstat + (size_t)m * FREC;
+    gmem<double> *f = gptr(E.fstat + (size_t)m * FREC);
     f[0] = mx;
     f[1] = W;
     f[2] = w2;
@@ -262,8 +263,8 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
     f[6] = W * W / w2;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      E.fmean[(size_t)m * D + c] = psum[c] / (double)N;
-      E.fmeanw[(size_t)m * D + c] = wsum[c] / W;
+      gptr(E.fmean)[(size_t)m * D + c] = psum[c] / (double)N;
+      gptr(E.fmeanw)[(size_t)m * D + c] = wsum[c] / W;
     }
   }
 }
@@ -299,10 +300,11 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
   int *cnt = (int *)(C + N);         // [N] offspring counts
   const int P = (N + BD - 1) / BD;
   const int k0 = min(N, tid * P), k1 = min(N, k0 + P);
-  const float *lwg = E.lw + (size_t)m * N;
+  // (pointers from the ensemble table: global-address-space accesses)
+  const gmem<float> *lwg = gptr(E.lw + (size_t)m * N);
   // thread 0 reads the running evidence now, so that its latency is hidden
-  const double lg_prev = tid == 0 ? E.fstat[(size_t)m * FREC + 5] : 0.0;
-  const float *Xb = (xb_parity ? E.X1 : E.X0) + (size_t)m * DD * N;
+  const double lg_prev = tid == 0 ? gptr(E.fstat)[(size_t)m * FREC + 5] : 0.0;
+  const gmem<float> *Xb = gptr((xb_parity ? E.X1 : E.X0) + (size_t)m * DD * N);
   // 1. this thread's log-weights (and xbar), the filter maximum
   float lw[PM];
   float xb[PM][DD];
@@ -382,7 +384,7 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
       sacc += eg[e];
       const double v = (sacc / SN) * W;
       i = e == 0 ? lds_search_blocked(C, N, v) : lds_search(C, N, i, v);
-      E.A[(size_t)m * N + k] = i;
+      gptr(E.A)[(size_t)m * N + k] = i;
       atomicAdd(cnt + i, 1);
     }
   }
@@ -401,7 +403,7 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
       red[1 + D + c] = wx[c];
     }
   } else {
-    int32_t *cg = counts[job.ens] + (size_t)m * N;
+    gmem<int32_t> *cg = gptr(counts[job.ens] + (size_t)m * N);
     for (int j = tid; j < N; j += BD) cg[j] = cnt[j];
     red[1] = red[2] = 0.0;
   }
@@ -411,11 +413,11 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
     if constexpr (D > 0) {
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        E.fmean[(size_t)m * D + c] = red[1 + c] / (double)N;
-        E.fmeanw[(size_t)m * D + c] = red[1 + D + c] / W;
+        gptr(E.fmean)[(size_t)m * D + c] = red[1 + c] / (double)N;
+        gptr(E.fmeanw)[(size_t)m * D + c] = red[1 + D + c] / W;
       }
     }
-    double *f = E.fstat + (size_t)m * FREC;
+    gmem<double> *f = gptr(E.fstat + (size_t)m * FREC);
     const double w2 = red[0];
     f[0] = mx;
     f[1] = W;

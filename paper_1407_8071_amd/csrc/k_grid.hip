@@ -349,19 +349,25 @@ __global__ void __launch_bounds__(GB)
 k_grid_estimate_part(int N, int dx4, const float4 *__restrict__ Xb,
                      const int32_t *__restrict__ cnt, const float *__restrict__ lw,
                      const double *__restrict__ fstat, double *__restrict__ part) {
+  // the chunk's offspring counts and weights, computed once per workgroup
+  __shared__ double nsh[EST_CHUNK], wsh[EST_CHUNK];
   const int g = blockIdx.x * GB + threadIdx.x;
   const int ch = blockIdx.y, m = blockIdx.z;
   const int nch = gridDim.y;
-  if (g >= dx4) return;
   const double mx = fstat[(size_t)m * FREC + 0];
   const bool deg = fstat[(size_t)m * FREC + 3] != 0.0;
-  double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
   const int i0 = ch * EST_CHUNK, i1 = min(N, i0 + EST_CHUNK);
+  for (int k = threadIdx.x; k < i1 - i0; k += GB) {
+    nsh[k] = (double)cnt[(size_t)m * N + i0 + k];
+    wsh[k] = deg ? 1.0 : exp((double)lw[(size_t)m * N + i0 + k] - mx);
+  }
+  __syncthreads();
+  if (g >= dx4) return;
+  double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
 #pragma unroll 4
   for (int i = i0; i < i1; ++i) {
     const float4 x = Xb[((size_t)m * N + i) * dx4 + g];
-    const double n = (double)cnt[(size_t)m * N + i];
-    const double w = deg ? 1.0 : exp((double)lw[(size_t)m * N + i] - mx);
+    const double n = nsh[i - i0], w = wsh[i - i0];
     pv[0] += n * x.x; pv[1] += n * x.y; pv[2] += n * x.z; pv[3] += n * x.w;
     wv[0] += w * x.x; wv[1] += w * x.y; wv[2] += w * x.z; wv[3] += w * x.w;
   }
@@ -410,25 +416,32 @@ k_grid_ensemble_fold(int M, int dx, const double *__restrict__ fmean,
 __global__ void __launch_bounds__(GB)
 k_grid_estimate_part_b(const int4 *__restrict__ jobs, const FusedEns *__restrict__ ens, int out,
                        int dx4) {
+  // the chunk's offspring counts and weights, computed once per workgroup
+  __shared__ double nsh[EST_CHUNK], wsh[EST_CHUNK];
   const int4 jb = jobs[blockIdx.x];
   const FusedEns &E = ens[jb.x];
   const int g = blockIdx.y * GB + threadIdx.x;
-  if (g >= dx4) return;
   const int m = jb.y, ch = jb.z, N = E.N, nch = E.nch;
-  const float4 *Xb = (const float4 *)(out ? E.X1 : E.X0);
-  const double mx = E.fstat[(size_t)m * FREC + 0];
-  const bool deg = E.fstat[(size_t)m * FREC + 3] != 0.0;
-  double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
+  // (pointers from the ensemble table: global-address-space accesses)
+  const gmem<f4v> *Xb = gptr((const f4v *)(out ? E.X1 : E.X0));
+  const double mx = gptr(E.fstat)[(size_t)m * FREC + 0];
+  const bool deg = gptr(E.fstat)[(size_t)m * FREC + 3] != 0.0;
   const int i0 = ch * EST_CHUNK, i1 = min(N, i0 + EST_CHUNK);
+  for (int k = threadIdx.x; k < i1 - i0; k += GB) {
+    nsh[k] = (double)gptr(E.cnt)[(size_t)m * N + i0 + k];
+    wsh[k] = deg ? 1.0 : exp((double)gptr(E.lw)[(size_t)m * N + i0 + k] - mx);
+  }
+  __syncthreads();
+  if (g >= dx4) return;
+  double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
 #pragma unroll 4
   for (int i = i0; i < i1; ++i) {
-    const float4 x = Xb[((size_t)m * N + i) * dx4 + g];
-    const double n = (double)E.cnt[(size_t)m * N + i];
-    const double w = deg ? 1.0 : exp((double)E.lw[(size_t)m * N + i] - mx);
+    const f4v x = Xb[((size_t)m * N + i) * dx4 + g];
+    const double n = nsh[i - i0], w = wsh[i - i0];
     pv[0] += n * x.x; pv[1] += n * x.y; pv[2] += n * x.z; pv[3] += n * x.w;
     wv[0] += w * x.x; wv[1] += w * x.y; wv[2] += w * x.z; wv[3] += w * x.w;
   }
-  double *o = E.gpart + (((size_t)m * nch + ch) * 2) * (size_t)dx4 * 4;
+  gmem<double> *o = gptr(E.gpart + (((size_t)m * nch + ch) * 2) * (size_t)dx4 * 4);
   for (int l = 0; l < 4; ++l) {
     o[(size_t)g * 4 + l] = pv[l];
     o[(size_t)dx4 * 4 + (size_t)g * 4 + l] = wv[l];
@@ -443,12 +456,12 @@ k_grid_filter_fold_b(const int4 *__restrict__ jobs, const FusedEns *__restrict__
   if (c >= dx) return;
   double a = 0.0, b = 0.0;
   for (int ch = 0; ch < nch; ++ch) {
-    const double *o = E.gpart + (((size_t)m * nch + ch) * 2) * (size_t)dx;
+    const gmem<double> *o = gptr(E.gpart + (((size_t)m * nch + ch) * 2) * (size_t)dx);
     a += o[c];
     b += o[(size_t)dx + c];
   }
-  E.fmean[(size_t)m * dx + c] = a / (double)E.N;
-  E.fmeanw[(size_t)m * dx + c] = b / E.fstat[(size_t)m * FREC + 1];
+  gptr(E.fmean)[(size_t)m * dx + c] = a / (double)E.N;
+  gptr(E.fmeanw)[(size_t)m * dx + c] = b / gptr(E.fstat)[(size_t)m * FREC + 1];
 }
 
 __global__ void __launch_bounds__(GB)
@@ -458,11 +471,11 @@ k_grid_ensemble_fold_b(const int *__restrict__ gens, const FusedEns *__restrict_
   if (c >= dx) return;
   double a = 0.0, b = 0.0;
   for (int m = 0; m < E.M; ++m) {
-    a += E.fmean[(size_t)m * dx + c];
-    b += E.fmeanw[(size_t)m * dx + c];
+    a += gptr(E.fmean)[(size_t)m * dx + c];
+    b += gptr(E.fmeanw)[(size_t)m * dx + c];
   }
-  E.emean[c] = a / (double)E.M;
-  E.emean[dx + c] = b / (double)E.M;
+  gptr(E.emean)[c] = a / (double)E.M;
+  gptr(E.emean)[dx + c] = b / (double)E.M;
 }
 
 // Truth path on the truth stream: one workgroup, T intervals of S steps.

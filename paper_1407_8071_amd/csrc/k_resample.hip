@@ -311,14 +311,14 @@ k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
   for (int c = 0; c < dx; ++c) {
     double a = 0.0, b = 0.0;
     for (int m = threadIdx.x; m < E.M; m += blockDim.x) {
-      a += E.fmean[(size_t)m * dx + c];
-      b += E.fmeanw[(size_t)m * dx + c];
+      a += gptr(E.fmean)[(size_t)m * dx + c];
+      b += gptr(E.fmeanw)[(size_t)m * dx + c];
     }
     a = block_sum(a, sh);
     b = block_sum(b, sh);
     if (threadIdx.x == 0) {
-      E.emean[c] = a / (double)E.M;
-      E.emean[dx + c] = b / (double)E.M;
+      gptr(E.emean)[c] = a / (double)E.M;
+      gptr(E.emean)[dx + c] = b / (double)E.M;
     }
   }
 }

@@ -66,12 +66,12 @@ template <int D>
 __device__ __forceinline__ float loglik(const ModelDev &md, const float x[D], const float *y) {
   float acc = 0.f;
   for (int k = 0; k < md.dy; ++k) {
-    const int o = md.obs_idx[k];
+    const int o = gptr(md.obs_idx)[k];
     float xo = x[0];
 #pragma unroll
     for (int c = 1; c < D; ++c)
       if (o == c) xo = x[c];
-    const float r = y[k] - xo;
+    const float r = gptr(y)[k] - xo;
     acc = fmaf(r, r, acc);
   }
   const float lw = -acc * md.inv2var;
@@ -124,16 +124,17 @@ k_vec_prop_batched(const int4 *__restrict__ tiles, const FusedEns *__restrict__ 
   const FusedEns &E = ens[tl.x];
   const int m = tl.y, i = tl.z + threadIdx.x, N = E.N;
   if (i >= N) return;
-  const float *Xin = parity ? E.X1 : E.X0;
-  float *Xout = parity ? E.X0 : E.X1;
-  const int src = pending ? min(max(E.A[(size_t)m * N + i], 0), N - 1) : i;
+  // (pointers from the ensemble table: global-address-space accesses)
+  const gmem<float> *Xin = gptr(parity ? E.X1 : E.X0);
+  gmem<float> *Xout = gptr(parity ? E.X0 : E.X1);
+  const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
   float x[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) x[c] = Xin[((size_t)m * D + c) * N + src];
   em_steps<D>(E.md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * E.md.S, E.md.S, x);
 #pragma unroll
   for (int c = 0; c < D; ++c) Xout[((size_t)m * D + c) * N + i] = x[c];
-  E.lw[(size_t)m * N + i] = loglik<D>(E.md, x, y + E.yoff);
+  gptr(E.lw)[(size_t)m * N + i] = loglik<D>(E.md, x, y + E.yoff);
 }
 
 template <int D>
