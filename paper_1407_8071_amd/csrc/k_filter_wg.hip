@@ -280,7 +280,9 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
 // sum_i n_i xbar_i / N and the weighted estimate sum_i w_i xbar_i / W.
 constexpr int RS_MAX_P = 8;
 
-template <int BD, int D>
+// PM: elements per thread the registers hold, at least ceil(N / BD) for every
+// filter of the launch (1 below 1024 threads, which serve filters of N <= BD).
+template <int BD, int D, int PM>
 __global__ void __launch_bounds__(BD)
 k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, IvArg iv,
               int32_t *const *__restrict__ counts, int xb_parity) {
@@ -288,9 +290,6 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
   extern __shared__ double lds[];
   constexpr int NW = BD / 64;
   constexpr int DD = D > 0 ? D : 1;
-  // elements per thread the registers hold: workgroups below 1024 threads
-  // serve filters with N <= BD
-  constexpr int PM = BD >= 1024 ? RS_MAX_P : 1;
   double *shd = lds;                 // 8 * NW doubles: multi-value reductions
   float *shf = (float *)(lds + 8 * NW);
   double *C = lds + 9 * NW;          // [N] CDF
@@ -305,27 +304,23 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
   // thread 0 reads the running evidence now, so that its latency is hidden
   const double lg_prev = tid == 0 ? gptr(E.fstat)[(size_t)m * FREC + 5] : 0.0;
   const gmem<float> *Xb = gptr((xb_parity ? E.X1 : E.X0) + (size_t)m * DD * N);
-  // 1. this thread's log-weights (and xbar), the filter maximum
+  // 1. this thread's log-weights (and xbar), the filter maximum.  The loads
+  // are unconditional (index clamped to N - 1; a slot past the thread's
+  // range gets weight 0 and count 0), so that they all issue at once and
+  // xbar, first used in step 5, arrives while steps 2-4 run.
   float lw[PM];
   float xb[PM][DD];
   float lmax = -INFINITY;
 #pragma unroll
   for (int e = 0; e < PM; ++e) {
-    const int i = k0 + e;
-    lw[e] = -INFINITY;
+    const int i = k0 + e, ic = min(i, N - 1);
+    const bool ok = i < k1;
+    const float v = lwg[ic];
+    lw[e] = (ok && v == v) ? v : -INFINITY;
+    if (ok) cnt[i] = 0;
     if constexpr (D > 0) {
-      // unused slots take part in sums with weight 0: keep them finite
 #pragma unroll
-      for (int c = 0; c < D; ++c) xb[e][c] = 0.f;
-    }
-    if (i < k1) {
-      const float v = lwg[i];
-      lw[e] = (v == v) ? v : -INFINITY;
-      cnt[i] = 0;
-      if constexpr (D > 0) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) xb[e][c] = Xb[(size_t)c * N + i];
-      }
+      for (int c = 0; c < D; ++c) xb[e][c] = Xb[(size_t)c * N + ic];
     }
     lmax = fmaxf(lmax, lw[e]);
   }
@@ -333,19 +328,14 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
   const bool deg = !(mxf > -INFINITY);
   const double mx = (double)mxf;
   // 2. weights, their thread-local inclusive scan, the block scan -> CDF
-  double w[PM], run = 0.0, s2 = 0.0, wx[DD];
-#pragma unroll
-  for (int c = 0; c < DD; ++c) wx[c] = 0.0;
+  // (xbar is first used in step 5, so its loads complete under steps 2-4)
+  double w[PM], run = 0.0, s2 = 0.0;
 #pragma unroll
   for (int e = 0; e < PM; ++e) {
     w[e] = 0.0;
     if (k0 + e < k1) w[e] = deg ? 1.0 : exp((double)lw[e] - mx);
     run += w[e];
     s2 += w[e] * w[e];
-    if constexpr (D > 0) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) wx[c] += w[e] * (double)xb[e][c];
-    }
   }
   double tot;
   const double off = block_exscan(run, shd, &tot);
@@ -395,12 +385,14 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
   if constexpr (D > 0) {
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      double px = 0.0;
+      double px = 0.0, wx = 0.0;
 #pragma unroll
-      for (int e = 0; e < PM; ++e)
+      for (int e = 0; e < PM; ++e) {
         if (k0 + e < k1) px += (double)cnt[k0 + e] * (double)xb[e][c];
+        wx += w[e] * (double)xb[e][c];
+      }
       red[1 + c] = px;
-      red[1 + D + c] = wx[c];
+      red[1 + D + c] = wx;
     }
   } else {
     gmem<int32_t> *cg = gptr(counts[job.ens] + (size_t)m * N);
@@ -446,14 +438,20 @@ hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, in
   if (n_jobs <= 0) return hipSuccess;
   const size_t lds = sizeof(double) * (9 * (size_t)(BD / 64) + 2) +
                      sizeof(double) * (size_t)max_n + sizeof(int) * (size_t)max_n;
-#define PF_RS_LAUNCH(B, DD) \
-  k_resample_wg<B, DD><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, d_counts, xb_parity)
+  const int pm = BD < 1024 ? 1 : (max_n <= 1024 ? 1 : max_n <= 2048 ? 2 : max_n <= 4096 ? 4 : 8);
+  if (BD < 1024 && max_n > BD) return hipErrorInvalidValue;
+  if (max_n > RS_MAX_P * 1024) return hipErrorInvalidValue;
+#define PF_RS_LAUNCH(B, DD, P) \
+  k_resample_wg<B, DD, P><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, d_counts, xb_parity)
 #define PF_RS_BD(DD)                 \
-  if (BD == 64) PF_RS_LAUNCH(64, DD); \
-  else if (BD == 128) PF_RS_LAUNCH(128, DD); \
-  else if (BD == 256) PF_RS_LAUNCH(256, DD); \
-  else if (BD == 512) PF_RS_LAUNCH(512, DD); \
-  else PF_RS_LAUNCH(1024, DD)
+  if (BD == 64) PF_RS_LAUNCH(64, DD, 1); \
+  else if (BD == 128) PF_RS_LAUNCH(128, DD, 1); \
+  else if (BD == 256) PF_RS_LAUNCH(256, DD, 1); \
+  else if (BD == 512) PF_RS_LAUNCH(512, DD, 1); \
+  else if (pm == 1) PF_RS_LAUNCH(1024, DD, 1); \
+  else if (pm == 2) PF_RS_LAUNCH(1024, DD, 2); \
+  else if (pm == 4) PF_RS_LAUNCH(1024, DD, 4); \
+  else PF_RS_LAUNCH(1024, DD, 8)
   if (D == 0) {
     PF_RS_BD(0);
   } else if (D == 1) {
@@ -513,11 +511,15 @@ hipError_t set_filter_wg_lds_limit() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_filter_wg<1, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  const void *rs[] = {(const void *)k_resample_wg<256, 0>, (const void *)k_resample_wg<512, 0>,
-                      (const void *)k_resample_wg<1024, 0>, (const void *)k_resample_wg<256, 1>,
-                      (const void *)k_resample_wg<512, 1>, (const void *)k_resample_wg<1024, 1>,
-                      (const void *)k_resample_wg<256, 3>, (const void *)k_resample_wg<512, 3>,
-                      (const void *)k_resample_wg<1024, 3>};
+  const void *rs[] = {(const void *)k_resample_wg<256, 0, 1>,  (const void *)k_resample_wg<512, 0, 1>,
+                      (const void *)k_resample_wg<1024, 0, 1>, (const void *)k_resample_wg<1024, 0, 2>,
+                      (const void *)k_resample_wg<1024, 0, 4>, (const void *)k_resample_wg<1024, 0, 8>,
+                      (const void *)k_resample_wg<256, 1, 1>,  (const void *)k_resample_wg<512, 1, 1>,
+                      (const void *)k_resample_wg<1024, 1, 1>, (const void *)k_resample_wg<1024, 1, 2>,
+                      (const void *)k_resample_wg<1024, 1, 4>, (const void *)k_resample_wg<1024, 1, 8>,
+                      (const void *)k_resample_wg<256, 3, 1>,  (const void *)k_resample_wg<512, 3, 1>,
+                      (const void *)k_resample_wg<1024, 3, 1>, (const void *)k_resample_wg<1024, 3, 2>,
+                      (const void *)k_resample_wg<1024, 3, 4>, (const void *)k_resample_wg<1024, 3, 8>};
   for (const void *f : rs) {
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
