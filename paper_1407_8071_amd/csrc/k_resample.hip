@@ -242,6 +242,98 @@ k_ancestors(int N, int T, const double *__restrict__ Cl, const double *__restric
   }
 }
 
+// The same ancestors with the tile offsets of the CDF in LDS and 4
+// consecutive k per thread (a 256-thread workgroup covers 1024 k, so each
+// thread's chain of dependent searches is short): the first search of a
+// thread finds the tile by bisection over the offsets in LDS (the offset
+// after tile q is C at its last element), then bisects within that tile;
+// the others gallop onward.  The result is the same smallest i with
+// C_i > U_k C_{N-1} (clamped to N - 1).
+constexpr int ANC_PER_THREAD = 4, ANC_SPAN = TILE_THREADS * ANC_PER_THREAD;
+constexpr int ANC_LDS_TILES = 4096;  // tile offsets held in LDS: N <= 4096 * TILE
+
+struct Cdf2L {
+  const double *Cl;
+  const double *co;  // LDS
+  int N;
+  __device__ __forceinline__ double at(int i) const { return co[i / TILE] + Cl[i]; }
+};
+
+__device__ __forceinline__ int gallop_l(const Cdf2L &c, int lo, double v) {
+  const int hi_max = c.N - 1;
+  if (lo >= hi_max) return hi_max;
+  if (c.at(lo) > v) return lo;
+  int step = 1, known_le = lo, hi = lo;
+  while (true) {
+    hi = known_le + step;
+    if (hi >= hi_max) {
+      hi = hi_max;
+      break;
+    }
+    if (c.at(hi) > v) break;
+    known_le = hi;
+    step <<= 1;
+  }
+  int a = known_le + 1, b = hi;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (c.at(mid) > v)
+      b = mid;
+    else
+      a = mid + 1;
+  }
+  return a;
+}
+
+__global__ void __launch_bounds__(TILE_THREADS)
+k_ancestors_lds(int N, int T, const double *__restrict__ Cl, const double *__restrict__ coff,
+                const double *__restrict__ Sl, const double *__restrict__ soff,
+                const double *__restrict__ fstat, int32_t *__restrict__ A) {
+  __shared__ double co[ANC_LDS_TILES + 1];
+  const int m = blockIdx.y;
+  const double *cof = coff + (size_t)m * (T + 1);
+  for (int j = threadIdx.x; j <= T; j += TILE_THREADS) co[j] = cof[j];
+  __syncthreads();
+  const int base = blockIdx.x * ANC_SPAN + threadIdx.x * ANC_PER_THREAD;
+  if (base >= N) return;
+  const double W = fstat[(size_t)m * FREC + 1];
+  const double SN = fstat[(size_t)m * FREC + 4];
+  const double so = soff[(size_t)m * (T + 1) + base / TILE];  // the 4 k share a tile
+  const double *cl = Cl + (size_t)m * N;
+  const Cdf2L c{cl, co, N};
+  int i;
+  {
+    const double v = ((so + Sl[(size_t)m * N + base]) / SN) * W;
+    int a = 0, b = T - 1;
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if (co[mid + 1] > v)
+        b = mid;
+      else
+        a = mid + 1;
+    }
+    const double off = co[a];
+    int lo = a * TILE, hi = min(N - 1, (a + 1) * TILE - 1);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (off + cl[mid] > v)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    i = lo;
+    A[(size_t)m * N + base] = i;
+  }
+#pragma unroll
+  for (int e = 1; e < ANC_PER_THREAD; ++e) {
+    const int k = base + e;
+    if (k >= N) break;
+    const double v = ((so + Sl[(size_t)m * N + k]) / SN) * W;
+    i = gallop_l(c, i, v);
+    A[(size_t)m * N + k] = i;
+  }
+}
+
 // Per-filter means from the tile partial sums (one workgroup per filter,
 // fixed summation order), then the equal-weight ensemble average of
 // Definition 3 in the next kernel.
@@ -346,7 +438,12 @@ hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s, const int *tp)
   k_cdf_tiles<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile, e.Cl);
   k_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.tile, e.Sl);
   k_filter_reduce<<<e.M, 256, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
-  k_ancestors<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
+  if (e.T <= ANC_LDS_TILES) {
+    const dim3 ga((unsigned)((e.N + ANC_SPAN - 1) / ANC_SPAN), (unsigned)e.M);
+    k_ancestors_lds<<<ga, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
+  } else {
+    k_ancestors<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
+  }
   return hipGetLastError();
 }
 
