@@ -40,18 +40,37 @@ __device__ __forceinline__ double filter_max(const double *__restrict__ tile, in
   return (double)block_max(v, sh);
 }
 
-// Tile-local inclusive scan of w_i = exp(lw_i - mx) in FP64 (w = 1 for every
-// particle when no weight is positive).  Thread t owns the 16 consecutive
-// elements [16t, 16t+16) of the tile.
+// Tile-local inclusive scans, one launch: the CDF of w_i = exp(lw_i - mx) in
+// FP64 (w = 1 for every particle when no weight is positive), and the sums
+// of the exponential variates E_j (the last tile also adds E_N to its
+// total).  Thread t owns the 16 consecutive elements [16t, 16t+16) of the
+// tile; the exponentials come first since they need no other launch's
+// result.
 __global__ void __launch_bounds__(TILE_THREADS)
-k_cdf_tiles(int N, int T, const float *__restrict__ lw, double *__restrict__ tile,
-            double *__restrict__ Cl) {
+k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float *__restrict__ lw,
+                    double *__restrict__ tile, double *__restrict__ Cl, double *__restrict__ Sl) {
+  const int t = tp ? *tp : t_arg;
   __shared__ float shf[TILE_THREADS / 64];
   __shared__ double shd[TILE_THREADS / 64];
   const int m = blockIdx.y, q = blockIdx.x;
+  const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
+  // exponential variates first: they need no other launch's result
+  double s[TILE_PER_THREAD];
+  double srun = 0.0;
+#pragma unroll
+  for (int g = 0; g < TILE_PER_THREAD / 4; ++g) {
+    const int j0 = base + 4 * g;
+    uint4 r = make_uint4(0, 0, 0, 0);
+    if (j0 < N) r = philox((uint32_t)(j0 >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
+    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if (j0 + l < N) srun += -log(u01d(rw[l]));
+      s[4 * g + l] = srun;
+    }
+  }
   const double mx = filter_max(tile, m, T, shf);
   const bool deg = !(mx > -INFINITY);
-  const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
   double w[TILE_PER_THREAD];
   double run = 0.0, sq = 0.0;
 #pragma unroll
@@ -63,8 +82,9 @@ k_cdf_tiles(int N, int T, const float *__restrict__ lw, double *__restrict__ til
     sq += we * we;
     w[e] = run;
   }
-  double tot;
+  double tot, stot;
   const double off = block_exscan(run, shd, &tot);
+  const double soffv = block_exscan(srun, shd, &stot);
   const int last = min(N - 1, q * TILE + TILE - 1);
 #pragma unroll
   for (int e = 0; e < TILE_PER_THREAD; ++e) {
@@ -72,56 +92,22 @@ k_cdf_tiles(int N, int T, const float *__restrict__ lw, double *__restrict__ til
     if (i < N) {
       const double c = off + w[e];
       Cl[(size_t)m * N + i] = c;
-      if (i == last) tile[((size_t)m * T + q) * TREC + 1] = c;
-    }
-  }
-  const double s2 = block_sum(sq, shd);
-  if (threadIdx.x == 0) tile[((size_t)m * T + q) * TREC + 2] = s2;
-}
-
-// Tile-local inclusive sums of the exponential variates E_j; the last tile
-// also adds E_N to its total.
-__global__ void __launch_bounds__(TILE_THREADS)
-k_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, double *__restrict__ tile,
-                double *__restrict__ Sl) {
-  const int t = tp ? *tp : t_arg;
-  __shared__ double shd[TILE_THREADS / 64];
-  const int m = blockIdx.y, q = blockIdx.x;
-  const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
-  double s[TILE_PER_THREAD];
-  double run = 0.0;
-#pragma unroll
-  for (int g = 0; g < TILE_PER_THREAD / 4; ++g) {
-    const int j0 = base + 4 * g;
-    uint4 r = make_uint4(0, 0, 0, 0);
-    if (j0 < N) r = philox((uint32_t)(j0 >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
-    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      if (j0 + l < N) run += -log(u01d(rw[l]));
-      s[4 * g + l] = run;
-    }
-  }
-  double tot;
-  const double off = block_exscan(run, shd, &tot);
-  const int last = min(N - 1, q * TILE + TILE - 1);
-#pragma unroll
-  for (int e = 0; e < TILE_PER_THREAD; ++e) {
-    const int j = base + e;
-    if (j < N) {
-      const double c = off + s[e];
-      Sl[(size_t)m * N + j] = c;
-      if (j == last) {
+      const double cs = soffv + s[e];
+      Sl[(size_t)m * N + i] = cs;
+      if (i == last) {
+        tile[((size_t)m * T + q) * TREC + 1] = c;
         double tail = 0.0;
         if (q == T - 1) {
           const uint4 r = philox((uint32_t)(N >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
           const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
           tail = -log(u01d(rw[N & 3]));
         }
-        tile[((size_t)m * T + q) * TREC + 3] = c + tail;
+        tile[((size_t)m * T + q) * TREC + 3] = cs + tail;
       }
     }
   }
+  const double s2 = block_sum(sq, shd);
+  if (threadIdx.x == 0) tile[((size_t)m * T + q) * TREC + 2] = s2;
 }
 
 // Per filter (one workgroup): tile offsets of the CDF and of the exponential
@@ -435,8 +421,7 @@ hipError_t launch_set_i32(int *p, int v, hipStream_t s) {
 hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s, const int *tp) {
   const dim3 g((unsigned)e.T, (unsigned)e.M);
   k_tile_max<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile);
-  k_cdf_tiles<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile, e.Cl);
-  k_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.tile, e.Sl);
+  k_cdf_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.lw, e.tile, e.Cl, e.Sl);
   k_filter_reduce<<<e.M, 256, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
   if (e.T <= ANC_LDS_TILES) {
     const dim3 ga((unsigned)((e.N + ANC_SPAN - 1) / ANC_SPAN), (unsigned)e.M);
