@@ -283,9 +283,9 @@ constexpr int RS_MAX_P = 8;
 // PM: elements per thread the registers hold, at least ceil(N / BD) for every
 // filter of the launch (1 below 1024 threads, which serve filters of N <= BD).
 template <int BD, int D, int PM>
-__global__ void __launch_bounds__(BD)
-k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, IvArg iv,
-              int32_t *const *__restrict__ counts, int xb_parity) {
+__device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
+                                            const FusedEns *__restrict__ ens, IvArg iv,
+                                            int32_t *const *__restrict__ counts, int xb_parity) {
   const int t = iv_t(iv);
   extern __shared__ double lds[];
   constexpr int NW = BD / 64;
@@ -418,6 +418,29 @@ k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, 
     f[4] = SN;
     f[5] = deg ? -INFINITY : lg_prev + mx + log(W / (double)N) + E.lognorm;
     f[6] = W * W / w2;
+  }
+}
+
+// The kernel: PMAX is the largest ceil(N / BD) of the launch's filters; each
+// workgroup runs the body compiled for its own filter's count (a uniform
+// branch), so that small filters in a launch with large ones read no more
+// than they need.
+template <int BD, int D, int PMAX>
+__global__ void __launch_bounds__(BD)
+k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, IvArg iv,
+              int32_t *const *__restrict__ counts, int xb_parity) {
+  if constexpr (PMAX == 1) {
+    resample_wg<BD, D, 1>(jobs, ens, iv, counts, xb_parity);
+  } else {
+    const int P = (ens[jobs[blockIdx.x].ens].N + BD - 1) / BD;
+    if (P <= 1)
+      resample_wg<BD, D, 1>(jobs, ens, iv, counts, xb_parity);
+    else if (P <= 2 || PMAX == 2)
+      resample_wg<BD, D, (PMAX >= 2 ? 2 : 1)>(jobs, ens, iv, counts, xb_parity);
+    else if (P <= 4 || PMAX == 4)
+      resample_wg<BD, D, (PMAX >= 4 ? 4 : 1)>(jobs, ens, iv, counts, xb_parity);
+    else
+      resample_wg<BD, D, PMAX>(jobs, ens, iv, counts, xb_parity);
   }
 }
 
