@@ -79,6 +79,10 @@ def parse():
     ap.add_argument("--path", default="fused", choices=["plain", "fused", "graph"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables it)")
+    ap.add_argument("--accuracy", type=int, default=1,
+                    help="1: after the timed run, an untimed pass that reports the MSE of the "
+                         "ensemble estimate against the simulated truth (and, for the Lorenz "
+                         "sweep, against a 64 x 2^20-particle reference filter)")
     return ap.parse_args()
 
 
@@ -150,6 +154,44 @@ def _run_filter(pf, torch, spec, M, N, flags, params, y, warmup, steps, est_out)
     k_ms, k_n = f.read_profile()
     del dx
     return e0.elapsed_time(e1), k_ms, k_n
+
+
+def _estimates(pf, torch, spec, M, N, y, T):
+    """Untimed: a fresh fused filter over y[0:T]; the ensemble estimate of
+    every interval, [T][dx] on the device."""
+    import ctypes as C
+    f = pf.ParticleFilter([spec], [(0, M, N, 1)], fused=True)
+    est = torch.empty((T, spec["dx"]), dtype=torch.float64, device="cuda")
+    lz = torch.empty(M, dtype=torch.float64, device="cuda")
+    for t in range(T):
+        f.step(y[t])
+        pf._check(pf.lib().pf_estimate(f._ctx, C.c_void_p(est[t].data_ptr()), None,
+                                       C.c_void_p(lz.data_ptr()), None, pf._stream(None)))
+    torch.cuda.synchronize()
+    del f
+    return est
+
+
+def accuracy(pf, torch, spec, M, N, xt, y, T, reference):
+    """MSE of the ensemble estimate of x_t against the simulated truth over
+    T intervals (FH-N: the v nodes), the paper's C_ipf = 1/M + 1/N, and for
+    the Lorenz sweep the MSE against the estimate of 64 filters x 2^20
+    particles on the same observations (variance ~ 1/(64 * 2^20), bias
+    ~ 2^-40), which isolates the ensemble's own error (Thm 1, Cor. 2)."""
+    comps = spec["J"] ** 2 if spec["kind"] == "fhn" else spec["dx"]
+    est = _estimates(pf, torch, spec, M, N, y, T)
+    truth = xt[1:T + 1, :comps].double()
+    out = {"intervals": T, "components": "v nodes" if spec["kind"] == "fhn" else "x1, x2, x3",
+           "mse_vs_truth": torch.mean((est[:, :comps] - truth) ** 2).item(),
+           "c_ipf": 1.0 / M + 1.0 / N}
+    if reference:
+        ref = _estimates(pf, torch, spec, 64, 1 << 20, y, T)
+        out["mse_vs_reference_64x2^20"] = torch.mean((est[:, :comps] - ref[:, :comps]) ** 2).item()
+        out["reference_mse_vs_truth"] = torch.mean((ref[:, :comps] - truth) ** 2).item()
+        del ref
+    del est
+    torch.cuda.empty_cache()
+    return out
 
 
 def learned_main(a):
@@ -392,7 +434,7 @@ def main():
     f = pf.ParticleFilter([spec], [(0, M, N, 1)], fused=(a.path == "fused"),
                           graph=(a.path == "graph"))
     T = a.warmup + a.steps
-    _, y = f.simulate(0, 1, T)
+    xt, y = f.simulate(0, 1, T)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     graph = a.path == "graph"
@@ -449,6 +491,12 @@ def main():
     cpu = None
     if a.cpu_seconds > 0:
         cpu = cpu_baseline(spec, M, N, y.double().cpu().numpy(), a.cpu_seconds)
+    acc = None
+    if a.accuracy:
+        del f
+        torch.cuda.empty_cache()
+        acc = accuracy(pf, torch, spec, M, N, xt, y, T,
+                       reference=a.workload.startswith("l63_sweep"))
     line = {
         "metric": "particle-steps/s", "value": value, "unit": "particle-steps/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
@@ -456,7 +504,7 @@ def main():
         "data": "synthetic (GPU-simulated truth and observations)",
         "config": {"workload": a.workload, "model": spec["kind"], "M": M, "N": N, "S": S,
                    "nodes_per_particle": nodes, "path": a.path, "wall_s": wall},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "accuracy": acc,
     }
     print(json.dumps(line))
 
