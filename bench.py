@@ -194,6 +194,36 @@ def accuracy(pf, torch, spec, M, N, xt, y, T, reference):
     return out
 
 
+def cpu_baseline_learned(spec, params, y_host, target_s):
+    """The FP64 oracle of the learned filter (its bfloat16-rounding mode, the
+    GPU's arithmetic) on a bounded sample: one filter per host core, each a
+    few particles through the first interval."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.lib()
+    m = oracle.Model(spec)
+    cores = max(1, min(16, os.cpu_count() or 1))
+
+    def work(job):
+        filt, n = job
+        X = oracle.init(m, 1, filt, n)
+        t0 = time.perf_counter()
+        oracle.filter_interval_learned(m, params, 1, filt, 1, X, y_host[0], 0.0)
+        return time.perf_counter() - t0
+
+    dt1 = max(work((0, 1)), 1e-6)
+    n_per = max(1, int(target_s / dt1))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as pool:
+        list(pool.map(work, [(f, n_per) for f in range(cores)]))
+    wall = time.perf_counter() - t0
+    steps = cores * n_per * spec["S"]
+    return {"value": steps / wall, "unit": "particle-steps/s", "cores": cores, "wall_s": wall,
+            "kind": "oracle",
+            "sample": f"{cores} filters x N={n_per} x 1 interval of the learned filter "
+                      f"({steps} particle-steps of {spec['J']}x{spec['J']} nodes, FP64)"}
+
+
 def learned_main(a):
     """FH-N 40 x 40 with the learned proposal (M = 64 x N = 128) against the
     bootstrap filter at N = 512 on the same GPU-simulated observations: wall
@@ -249,6 +279,10 @@ def learned_main(a):
                      "kernel_avg_us": k_ms / max(k_n, 1) * 1e3, "kernel_launches": k_n}
         torch.cuda.empty_cache()
     L = res["learned"]
+    cpu = None
+    if a.cpu_seconds > 0:
+        cpu = cpu_baseline_learned(spec, p.double().cpu().numpy(), y.double().cpu().numpy(),
+                                   a.cpu_seconds)
     k_avg_s = L["kernel_avg_us"] / 1e6
     flop = MLP_FLOP_PER_NODE_STEP * nn * spec["S"] * M * N
     achieved = flop / k_avg_s / 1e12
@@ -269,7 +303,7 @@ def learned_main(a):
             res["bootstrap_N%d" % (4 * N)]["ms_per_interval"] / L["ms_per_interval"],
         "training": {"trajectories": tc["n_runs"] * tc["run_len"], "adam_steps": n_steps,
                      "rows_per_step": 16 * tc["batch_tiles"], "data_s": t_data, "train_s": t_train},
-        "roofline": roofline, "cpu_baseline": None,
+        "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 
