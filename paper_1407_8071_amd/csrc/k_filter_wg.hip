@@ -35,15 +35,18 @@ __device__ __forceinline__ void wg_drift(const ModelDev &md, const float x[D], f
   }
 }
 
-// S Euler-Maruyama steps with the compensated FP32 state update (the same
-// arithmetic as the plain propagation kernel).
+// S Euler-Maruyama steps with the FP32 increments summed in an offset from
+// the start state (the same arithmetic as the batched propagation kernel).
 template <int D>
 __device__ __forceinline__ void wg_em(const ModelDev &md, Key key, uint32_t c0, uint32_t c1,
                                       int n0, float x[D]) {
   const int n1 = n0 + md.S;
-  float comp[D];
+  float x0[D], off[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) comp[c] = 0.f;
+  for (int c = 0; c < D; ++c) {
+    x0[c] = x[c];
+    off[c] = 0.f;
+  }
   for (int q = n0 >> 2; (q << 2) < n1; ++q) {
     float z[4 * D];
 #pragma unroll
@@ -53,17 +56,16 @@ __device__ __forceinline__ void wg_em(const ModelDev &md, Key key, uint32_t c0, 
     for (int r = 0; r < 4; ++r) {
       const int n = 4 * q + r;
       if (n < n0 || n >= n1) continue;
-      float f[D];
-      wg_drift<D>(md, x, f);
+      float xc[D], f[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const float inc = fmaf(md.h, f[c], md.sq0 * z[r * D + c]) - comp[c];
-        const float nx = x[c] + inc;
-        comp[c] = (nx - x[c]) - inc;
-        x[c] = nx;
-      }
+      for (int c = 0; c < D; ++c) xc[c] = x0[c] + off[c];
+      wg_drift<D>(md, xc, f);
+#pragma unroll
+      for (int c = 0; c < D; ++c) off[c] += fmaf(md.h, f[c], md.sq0 * z[r * D + c]);
     }
   }
+#pragma unroll
+  for (int c = 0; c < D; ++c) x[c] = x0[c] + off[c];
 }
 
 template <int D>
