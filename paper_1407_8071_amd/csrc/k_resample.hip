@@ -164,8 +164,10 @@ struct Cdf2 {
 };
 
 // Smallest i in [lo, N-1] with C(i) > v, given C(lo - 1) <= v: exponential
-// search from lo, then bisection.  The answer is clamped to N - 1.
-__device__ __forceinline__ int gallop(const Cdf2 &c, int lo, double v) {
+// search from lo, then bisection.  The answer is clamped to N - 1.  (Cdf:
+// the two-level CDF with its tile offsets in global memory or in LDS.)
+template <class Cdf>
+__device__ __forceinline__ int gallop(const Cdf &c, int lo, double v) {
   const int hi_max = c.N - 1;
   if (lo >= hi_max) return hi_max;
   if (c.at(lo) > v) return lo;
@@ -245,32 +247,6 @@ struct Cdf2L {
   __device__ __forceinline__ double at(int i) const { return co[i / TILE] + Cl[i]; }
 };
 
-__device__ __forceinline__ int gallop_l(const Cdf2L &c, int lo, double v) {
-  const int hi_max = c.N - 1;
-  if (lo >= hi_max) return hi_max;
-  if (c.at(lo) > v) return lo;
-  int step = 1, known_le = lo, hi = lo;
-  while (true) {
-    hi = known_le + step;
-    if (hi >= hi_max) {
-      hi = hi_max;
-      break;
-    }
-    if (c.at(hi) > v) break;
-    known_le = hi;
-    step <<= 1;
-  }
-  int a = known_le + 1, b = hi;
-  while (a < b) {
-    const int mid = (a + b) >> 1;
-    if (c.at(mid) > v)
-      b = mid;
-    else
-      a = mid + 1;
-  }
-  return a;
-}
-
 __global__ void __launch_bounds__(TILE_THREADS)
 k_ancestors_lds(int N, int T, const double *__restrict__ Cl, const double *__restrict__ coff,
                 const double *__restrict__ Sl, const double *__restrict__ soff,
@@ -315,7 +291,7 @@ k_ancestors_lds(int N, int T, const double *__restrict__ Cl, const double *__res
     const int k = base + e;
     if (k >= N) break;
     const double v = ((so + Sl[(size_t)m * N + k]) / SN) * W;
-    i = gallop_l(c, i, v);
+    i = gallop(c, i, v);
     A[(size_t)m * N + k] = i;
   }
 }
