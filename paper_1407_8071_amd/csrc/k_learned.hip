@@ -38,12 +38,9 @@ k_mlp_forward(const float *__restrict__ p, int in_dim, int out_dim, const float 
         const float v = (ok && k < in_dim) ? X[row * in_dim + k] : (k == in_dim ? 1.f : 0.f);
         F[kb][j] = (__bf16)v;
       }
-    const f32x16 o = mlp32_tile(w, F);
-    if (h == 0 && ok) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r < out_dim) out[row * out_dim + r] = o[r];
-    }
+    const f32x2 u = mlp32_tile<4>(w, F);
+    if (ok && h < out_dim) out[row * out_dim + h] = u[0];
+    if (ok && 2 + h < out_dim) out[row * out_dim + 2 + h] = u[1];
   }
 }
 
@@ -214,11 +211,8 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
       for (int tt = wid; tt < ntiles; tt += nwaves) {
         const int no_nn = NO[tile_node(min(tt + 2 * nwaves, ntiles - 1))];
         inputs(min(tt + nwaves, ntiles - 1), no_n, Fn);
-        const f32x16 o = mlp32_tile(w, Fc);
-        if (h == 0 && 32 * tt + c32 < nn) {
-          U[32 * tt + c32] = o[0];
-          U[nn + 32 * tt + c32] = o[1];
-        }
+        const f32x2 u = mlp32_tile<2>(w, Fc);
+        if (32 * tt + c32 < nn) U[h * nn + 32 * tt + c32] = u[0];  // u_v, u_w by lane half
         Fc[0] = Fn[0];
         Fc[1] = Fn[1];
         no_n = no_nn;

@@ -120,16 +120,28 @@ __device__ __forceinline__ f32x4 mlp_tile(const MlpRegs &w, const bf16x8 &F) {
 // 32 (kb / 2) + 8 (2 (kb % 2) + j / 4) + 4 h + j % 4, the B operand of K-block
 // kb is accumulator elements 8 (kb % 2) .. 8 (kb % 2) + 7 of 32-unit block
 // kb / 2, i.e. a contiguous slice.  Inputs: slots 16 kb + 8 h + j of the
-// lane, the constant 1 in slot `in` (bias of layer 1); 4 + 8 + 4 MFMAs per
-// 32 rows.
+// lane, the constant 1 in slot `in` (bias of layer 1).  Layers 1 and 2 take
+// 4 + 8 MFMAs per 32 rows.
+//
+// Layer 3 (at most 4 outputs) runs on v_mfma_f32_4x4x4bf16_1k, 16
+// independent 4x4x4 blocks: block b = lane / 4 takes row i of A from lane
+// 4 b + i, column j of B from lane 4 b + j, and returns D[i][j] in element i
+// of lane 4 b + j.  With B column j = the 4 hidden values that lane 4 b + j
+// holds in one register pair (its own node, its half's units) and A row i =
+// W3[i] at those units, 8 instructions leave in lane 32 h + c the sums of
+// outputs 0..3 of row c over half h's 32 hidden units; one lane-half swap
+// and an add finish them.  (A 32x32x16 layer 3 padded to 32 output rows
+// took 4 instructions of 32 matrix-pipe cycles each; the 8 small ones take
+// about 7 each.)
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct Mlp32Regs {
   bf16x8 a1[2][2];  // layer 1 [32-unit block][K block]
   bf16x8 a2[2][4];  // layer 2 [32-unit block][K block]
-  bf16x8 a3[4];     // layer 3 [K block] (outputs padded to 32 rows)
+  bf16x4 a3[8];     // layer 3 [K block][register pair]: W3[lane % 4] at its units
   f32x16 b2[2];     // bias of layer 2 in the accumulator layout
-  float b3[4];      // bias of layer 3 (added on lanes of half 0)
+  f32x4 c3;         // layer 3 accumulator start: its bias on lanes of half 0
 };
 
 __device__ __forceinline__ int hid_slot32(int kb, int h, int j) {
@@ -169,13 +181,15 @@ __device__ inline void mlp32_load(const float *__restrict__ p, int in_dim, int o
 #pragma unroll
     for (int r = 0; r < 16; ++r) w.b2[ob][r] = bf16r(b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)]);
   }
+  const int o3 = l & 3;  // output row this lane supplies to layer 3's A
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      w.a3[kb][j] = (__bf16)(c < out_dim ? W3[c * HID + hid_slot32(kb, h, j)] : 0.f);
+      w.a3[2 * kb + j / 4][j % 4] =
+          (__bf16)(o3 < out_dim ? W3[o3 * HID + hid_slot32(kb, h, j)] : 0.f);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) w.b3[r] = r < out_dim ? bf16r(b3[r]) : 0.f;
+  for (int r = 0; r < 4; ++r) w.c3[r] = (h == 0 && r < out_dim) ? bf16r(b3[r]) : 0.f;
 }
 
 // ReLU after the rounding, two values per instruction: rounding to nearest
@@ -198,10 +212,19 @@ __device__ __forceinline__ bf16x8 relu_pack8(const f32x16 &a, int off) {
   return __builtin_bit_cast(bf16x8, q);
 }
 
+__device__ __forceinline__ float swap_halves_add(float lo_src, float hi_src) {
+  // lanes of half 0 get lo_src(l) + lo_src(l + 32), lanes of half 1
+  // hi_src(l - 32) + hi_src(l)
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo_src), __float_as_uint(hi_src),
+                                                  false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
 // u_theta of the 32 tile rows whose inputs this lane holds (F[kb] = slots
-// 16 kb + 8 h .. + 7 of row c).  Lanes of half 0 receive outputs 0..3 of
-// row c in elements 0..3 (bias included).
-__device__ __forceinline__ f32x16 mlp32_tile(const Mlp32Regs &w, const bf16x8 F[2]) {
+// 16 kb + 8 h .. + 7 of row c).  Lane 32 h + c receives output h of row c in
+// element 0 and (NOUT = 4) output 2 + h in element 1, bias included.
+template <int NOUT>
+__device__ __forceinline__ f32x2 mlp32_tile(const Mlp32Regs &w, const bf16x8 F[2]) {
   f32x16 z;
 #pragma unroll
   for (int r = 0; r < 16; ++r) z[r] = 0.f;
@@ -223,14 +246,22 @@ __device__ __forceinline__ f32x16 mlp32_tile(const Mlp32Regs &w, const bf16x8 F[
   }
   const bf16x8 h2[4] = {relu_pack8(a2[0], 0), relu_pack8(a2[0], 8), relu_pack8(a2[1], 0),
                         relu_pack8(a2[1], 8)};
-  // layer 3 as two independent chains of two (halves the dependent latency)
-  f32x16 o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[0], h2[0], z, 0, 0, 0);
-  f32x16 q = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[2], h2[2], z, 0, 0, 0);
-  o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[1], h2[1], o, 0, 0, 0);
-  q = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[3], h2[3], q, 0, 0, 0);
+  // layer 3: 8 small-block MFMAs over this half's hidden units, then the
+  // two halves' sums
+  f32x4 o = w.c3;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) o[r] = (o[r] + q[r]) + w.b3[r];
-  return o;
+  for (int kb = 0; kb < 4; ++kb) {
+    o = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(w.a3[2 * kb],
+                                               __builtin_shufflevector(h2[kb], h2[kb], 0, 1, 2, 3),
+                                               o, 0, 0, 0);
+    o = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(w.a3[2 * kb + 1],
+                                               __builtin_shufflevector(h2[kb], h2[kb], 4, 5, 6, 7),
+                                               o, 0, 0, 0);
+  }
+  f32x2 u;
+  u[0] = swap_halves_add(o[0], o[1]);
+  u[1] = NOUT > 2 ? swap_halves_add(o[2], o[3]) : 0.f;
+  return u;
 }
 
 }  // namespace pfk
