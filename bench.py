@@ -9,7 +9,8 @@ Lorenz 63 time-error sweep split M = 256 filters x N = 4096 particles
 synthetic: the library's own truth simulator on the GPU.
 
 Prints one JSON line with the throughput, the dominant kernel's roofline
-(timed live with HIP events around each of its launches) and the FP64 oracle
+(timed live with HIP events around its launches in every PROF_EVERY-th timed
+interval) and the FP64 oracle
 timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
@@ -46,6 +47,13 @@ FLOP_PER_SLOT = 2.0
 # sqrt, sin, cos x 4, 3 multiplies).
 PHILOX_SLOTS = 80.0
 BOXMULLER_SLOTS = 29.0
+# The dominant kernel's launches are bracketed by HIP events on every
+# PROF_EVERY-th interval of the timed region only: an event pair costs the
+# stream ~6 us (the Lorenz 256 x 4096 interval measured 0.104 ms without and
+# 0.110 ms with a pair around every propagation launch), which would slow
+# the very intervals whose throughput is reported.
+PROF_EVERY = 8
+
 # Lorenz 63 particle-step: 3 Philox calls per 4 steps, 1.5 Box-Muller pairs,
 # drift (7) and the Euler update (2 FMAs per component).
 L63_SLOTS_PER_PARTICLE_STEP = 0.75 * PHILOX_SLOTS + 1.5 * BOXMULLER_SLOTS + 7 + 6
@@ -138,13 +146,13 @@ def _run_filter(pf, torch, spec, M, N, flags, params, y, warmup, steps, est_out)
         f.step(y[t])
     torch.cuda.synchronize()
     f.read_profile()
-    f.set_profiling(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     dx = spec["dx"]
     lz = torch.empty(M, dtype=torch.float64, device="cuda")
     e0.record(stream)
     for k, t in enumerate(range(warmup, warmup + steps)):
+        f.set_profiling(k % PROF_EVERY == 0)
         f.step(y[t])
         pf._check(pf.lib().pf_estimate(f._ctx, C.c_void_p(est_out[k].data_ptr()), None,
                                        C.c_void_p(lz.data_ptr()), None, pf._stream(None)))
@@ -289,7 +297,8 @@ def learned_main(a):
     roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
                 "kernel": "k_grid_steps_learned", "algorithmic_flop_per_launch": flop,
-                "kernel_avg_us": L["kernel_avg_us"], "launches": L["kernel_launches"]}
+                "kernel_avg_us": L["kernel_avg_us"], "launches": L["kernel_launches"],
+                "timed_intervals": f"every {PROF_EVERY}th of the timed region"}
     line = {
         "metric": "particle-steps/s", "value": L["particle_steps_per_s"],
         "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -478,13 +487,13 @@ def main():
         f.step(None if graph else y[t])
     torch.cuda.synchronize()
     f.read_profile()
-    f.set_profiling(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for t in range(a.warmup, T):
+    for k, t in enumerate(range(a.warmup, T)):
+        f.set_profiling(k % PROF_EVERY == 0)
         f.step(None if graph else y[t])
     e1.record(stream)
     torch.cuda.synchronize()
@@ -521,7 +530,8 @@ def main():
                     "frac": achieved / peak, "traffic": None, "kernel": kname,
                     "algorithmic_slots_per_launch": slots}
     roofline["traffic"] = MEASURED_TRAFFIC_BYTES.get((spec["kind"], a.path, M, N))
-    roofline.update({"kernel_avg_us": k_avg_s * 1e6, "launches": k_n})
+    roofline.update({"kernel_avg_us": k_avg_s * 1e6, "launches": k_n,
+                     "timed_intervals": f"every {PROF_EVERY}th of the timed region"})
     cpu = None
     if a.cpu_seconds > 0:
         cpu = cpu_baseline(spec, M, N, y.double().cpu().numpy(), a.cpu_seconds)

@@ -306,50 +306,24 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
   // thread 0 reads the running evidence now, so that its latency is hidden
   const double lg_prev = tid == 0 ? gptr(E.fstat)[(size_t)m * FREC + 5] : 0.0;
   const gmem<float> *Xb = gptr((xb_parity ? E.X1 : E.X0) + (size_t)m * DD * N);
-  // 1. this thread's log-weights (and xbar), the filter maximum.  The loads
-  // are unconditional (index clamped to N - 1; a slot past the thread's
-  // range gets weight 0 and count 0), so that they all issue at once and
-  // xbar, first used in step 5, arrives while steps 2-4 run.
+  // 1. this thread's log-weights (and xbar).  The loads are unconditional
+  // (index clamped to N - 1; a slot past the thread's range gets weight 0
+  // and count 0), so that they all issue at once; the log-weights are first
+  // used after step 2 and xbar in step 5, so both arrive under ALU work.
   float lw[PM];
   float xb[PM][DD];
-  float lmax = -INFINITY;
 #pragma unroll
   for (int e = 0; e < PM; ++e) {
     const int i = k0 + e, ic = min(i, N - 1);
-    const bool ok = i < k1;
-    const float v = lwg[ic];
-    lw[e] = (ok && v == v) ? v : -INFINITY;
-    if (ok) cnt[i] = 0;
+    lw[e] = lwg[ic];
+    if (i < k1) cnt[i] = 0;
     if constexpr (D > 0) {
 #pragma unroll
       for (int c = 0; c < D; ++c) xb[e][c] = Xb[(size_t)c * N + ic];
     }
-    lmax = fmaxf(lmax, lw[e]);
   }
-  const float mxf = block_max(lmax, shf);
-  const bool deg = !(mxf > -INFINITY);
-  const double mx = (double)mxf;
-  // 2. weights, their thread-local inclusive scan, the block scan -> CDF
-  // (xbar is first used in step 5, so its loads complete under steps 2-4)
-  double w[PM], run = 0.0, s2 = 0.0;
-#pragma unroll
-  for (int e = 0; e < PM; ++e) {
-    w[e] = 0.0;
-    if (k0 + e < k1) w[e] = deg ? 1.0 : exp((double)lw[e] - mx);
-    run += w[e];
-    s2 += w[e] * w[e];
-  }
-  double tot;
-  const double off = block_exscan(run, shd, &tot);
-  {
-    double c = off;
-#pragma unroll
-    for (int e = 0; e < PM; ++e) {
-      c += w[e];
-      if (k0 + e < k1) C[k0 + e] = c;
-    }
-  }
-  // 3. exponential spacings over the same elements -> sorted uniforms
+  // 2. exponential spacings over the same elements (they do not depend on
+  // the weights: computed while the loads are in flight)
   ExpoWG ex{E.key, (uint32_t)m, (uint32_t)t};
   double eg[PM], es = 0.0;
 #pragma unroll
@@ -363,8 +337,37 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
     ExpoWG tail{E.key, (uint32_t)m, (uint32_t)t};
     es += tail(N);
   }
-  double SN;
-  const double eoff = block_exscan(es, shd, &SN);  // its barriers publish C
+  // 3. the filter maximum, the weights and their thread-local inclusive
+  // scan; one block scan of the weights and the spacings -> CDF, S_N
+  float lmax = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < PM; ++e) {
+    lw[e] = (k0 + e < k1 && lw[e] == lw[e]) ? lw[e] : -INFINITY;
+    lmax = fmaxf(lmax, lw[e]);
+  }
+  const float mxf = block_max(lmax, shf);
+  const bool deg = !(mxf > -INFINITY);
+  const double mx = (double)mxf;
+  double w[PM], run = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < PM; ++e) {
+    w[e] = 0.0;
+    if (k0 + e < k1) w[e] = deg ? 1.0 : exp((double)lw[e] - mx);
+    run += w[e];
+    s2 += w[e] * w[e];
+  }
+  double sc[2], tot[2];
+  block_exscan2(run, es, shd, sc, tot);
+  {
+    double c = sc[0];
+#pragma unroll
+    for (int e = 0; e < PM; ++e) {
+      c += w[e];
+      if (k0 + e < k1) C[k0 + e] = c;
+    }
+  }
+  const double eoff = sc[1], SN = tot[1];
+  __syncthreads();  // publishes C
   const double W = C[N - 1];
   // 4. ancestors in the LDS CDF and the offspring counts
   double sacc = eoff;

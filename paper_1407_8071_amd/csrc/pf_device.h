@@ -241,4 +241,33 @@ __device__ __forceinline__ double block_exscan(double v, double *sh, double *tot
   return off + exc;
 }
 
+// Two workgroup exclusive scans with one pair of barriers (each value's
+// arithmetic is that of block_exscan); sh holds 2 * (blockDim.x / 64)
+// doubles.
+__device__ __forceinline__ void block_exscan2(double v0, double v1, double *sh, double ex[2],
+                                              double tot[2]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const double i0 = wave_scan(v0), i1 = wave_scan(v1);
+  const double e0 = dpp_f64<DPP_WAVE_SHR1, 0xf>(i0), e1 = dpp_f64<DPP_WAVE_SHR1, 0xf>(i1);
+  __syncthreads();
+  if (lane == 63) {
+    sh[wid] = i0;
+    sh[nw + wid] = i1;
+  }
+  __syncthreads();
+  double o0 = 0.0, a0 = 0.0, o1 = 0.0, a1 = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < wid) {
+      o0 += sh[i];
+      o1 += sh[nw + i];
+    }
+    a0 += sh[i];
+    a1 += sh[nw + i];
+  }
+  ex[0] = o0 + e0;
+  ex[1] = o1 + e1;
+  tot[0] = a0;
+  tot[1] = a1;
+}
+
 }  // namespace pfk
