@@ -43,10 +43,13 @@ VALU_SLOTS_PER_S = 256 * 128 * 2.4e9
 FLOP_PER_SLOT = 2.0
 
 # Algorithmic VALU slots of one Philox4x32-10 call (10 rounds x (2 wide
-# products x 2 + 4 XORs)) and of one Box-Muller pair (2 uniforms x 5, log2,
+# products x 2 + 2 three-way XORs x 1: gfx950's v_bitop3_b32 takes a ^ b ^ c
+# in one instruction, which the register-only probe places at ~1.4 slots, so
+# 1 is the lower count) and of one Box-Muller pair (2 uniforms x 3 -- the
+# 23 random bits moved into a float's mantissa, one subtraction --, log2,
 # sqrt, sin, cos x 4, 3 multiplies).
-PHILOX_SLOTS = 80.0
-BOXMULLER_SLOTS = 29.0
+PHILOX_SLOTS = 60.0
+BOXMULLER_SLOTS = 25.0
 # The dominant kernel's launches are bracketed by HIP events on every
 # PROF_EVERY-th interval of the timed region only: an event pair costs the
 # stream ~6 us (the Lorenz 256 x 4096 interval measured 0.104 ms without and

@@ -51,7 +51,7 @@ __device__ __forceinline__ void wg_em(const ModelDev &md, Key key, uint32_t c0, 
     float z[4 * D];
 #pragma unroll
     for (int j = 0; j < D; ++j)
-      normals4(philox(c0, c1, (uint32_t)q, (P_PROP << 24) | (uint32_t)j, key), &z[4 * j]);
+      normals4(philox<2, 3>(c0, c1, (uint32_t)q, (P_PROP << 24) | (uint32_t)j, key), &z[4 * j]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int n = 4 * q + r;
@@ -92,7 +92,7 @@ struct ExpoWG {
   __device__ __forceinline__ double operator()(int j) {
     if ((j >> 2) != cached) {
       cached = j >> 2;
-      r = philox((uint32_t)cached, m, t, P_RESAMPLE << 24, key);
+      r = philox<2, 3>((uint32_t)cached, m, t, P_RESAMPLE << 24, key);
     }
     const int l = j & 3;
     const uint32_t w = l == 0 ? r.x : l == 1 ? r.y : l == 2 ? r.z : r.w;

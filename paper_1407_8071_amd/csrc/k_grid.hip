@@ -77,8 +77,8 @@ __device__ __forceinline__ Nbr4 neighbours(int J, int s) {
 __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t purpose,
                                            uint32_t c0, uint32_t c1, uint32_t n, int s,
                                            const Nbr4 &nb, const float *vs, Slot4 &S) {
-  const uint4 ra = philox(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s), key);
-  const uint4 rb = philox(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s + 1), key);
+  const uint4 ra = philox<4, 3>(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s), key);
+  const uint4 rb = philox<4, 3>(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s + 1), key);
   float za[4], zb[4];
   normals4(ra, za);
   normals4(rb, zb);

@@ -232,7 +232,7 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
         const float2 uv = *(const float2 *)(U + 2 * pr), uw = *(const float2 *)(U + nn + 2 * pr);
         float2 cv = *(const float2 *)(CMP + 2 * pr), cw = *(const float2 *)(CMP + nn + 2 * pr);
         float z[4];
-        normals4(philox((uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st),
+        normals4(philox<4, 3>((uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st),
                         (P_PROP << 24) | (uint32_t)pr, key), z);
         // node 2 pr: right neighbour c1; node 2 pr + 1: left neighbour c0
         const float lap0 = (((u0 - c0) + (d0 - c0)) + (l0 - c0)) + (c1 - c0);

@@ -61,7 +61,7 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
   for (int g = 0; g < TILE_PER_THREAD / 4; ++g) {
     const int j0 = base + 4 * g;
     uint4 r = make_uint4(0, 0, 0, 0);
-    if (j0 < N) r = philox((uint32_t)(j0 >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
+    if (j0 < N) r = philox<2, 3>((uint32_t)(j0 >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
     const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
@@ -98,7 +98,7 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
         tile[((size_t)m * T + q) * TREC + 1] = c;
         double tail = 0.0;
         if (q == T - 1) {
-          const uint4 r = philox((uint32_t)(N >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
+          const uint4 r = philox<10, 10>((uint32_t)(N >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
           const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
           tail = -log(u01d(rw[N & 3]));
         }

@@ -46,7 +46,7 @@ __device__ __forceinline__ void em_steps(const ModelDev &md, Key key, uint32_t p
     float z[4 * D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const uint4 w = philox(c0, c1, (uint32_t)q, (purpose << 24) | (uint32_t)j, key);
+      const uint4 w = philox<2, 3>(c0, c1, (uint32_t)q, (purpose << 24) | (uint32_t)j, key);
       normals4(w, &z[4 * j]);
     }
 #pragma unroll

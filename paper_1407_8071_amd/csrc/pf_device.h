@@ -43,6 +43,21 @@ __host__ __device__ inline Key make_key(uint64_t seed) {
   return Key{(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x14078071u};
 }
 
+// Three-way XOR: one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c) instead of
+// two v_xor_b32.  Worth it only when at most one operand is uniform across
+// the wavefront (otherwise the plain form computes the uniform part on the
+// scalar unit and the bitop3 would need a VGPR copy).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// Philox4x32-10.  N0_FROM / N2_FROM: the first round whose new word 0 / 2 is
+// taken with xor3, i.e. from which both counter words entering it vary
+// across lanes.  With one per-lane counter word at the start every word is
+// per-lane after four rounds (the default); a per-lane c0 (particle or
+// element index, uniform c1..c3) gets there for word 0 in round 2 and for
+// word 2 in round 3.
+template <int N0_FROM = 4, int N2_FROM = 4>
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         Key key) {
   uint32_t k0 = key.k0, k1 = key.k1;
@@ -50,8 +65,10 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
     const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = r >= N0_FROM ? xor3((uint32_t)(p1 >> 32), c1, k0)
+                                     : (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = r >= N2_FROM ? xor3((uint32_t)(p0 >> 32), c3, k1)
+                                     : (uint32_t)(p0 >> 32) ^ c3 ^ k1;
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -63,9 +80,15 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 }
 
 // u = (2 (x >> 9) + 1) 2^-24 in (0, 1): the integer has at most 24
-// significant bits, so the float is exact.
+// significant bits, so the float is exact.  Formed without an
+// integer-to-float conversion (a half-rate instruction): the bit pattern
+// 0x3F800000 | (x >> 9) -- one v_alignbit_b32, the low word of the 64-bit
+// pair (0x7F : x) shifted right by 9 -- is the float 1 + (x >> 9) 2^-23 in
+// [1, 2), and subtracting the float 1 - 2^-24 leaves exactly
+// (2 (x >> 9) + 1) 2^-24, which is representable, so the subtraction does
+// not round.
 __device__ __forceinline__ float u01f(uint32_t x) {
-  return (float)((x >> 9) * 2u + 1u) * 0x1p-24f;
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9)) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double u01d(uint32_t x) {
   return (double)((x >> 9) * 2u + 1u) * 0x1p-24;

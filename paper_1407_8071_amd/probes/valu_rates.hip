@@ -21,6 +21,8 @@ __global__ void __launch_bounds__(256) NAME(uint32_t *out, uint32_t seed) {    \
 }
 DEFK(k_fma32, float, (float)(threadIdx.x + i), asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a[i]) : "v"((float)b), "v"((float)c)))
 DEFK(k_xor, uint32_t, threadIdx.x + i, asm volatile("v_xor_b32 %0, %0, %1" : "+v"(a[i]) : "v"(b)))
+DEFK(k_xor3, uint32_t, threadIdx.x + i, asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a[i]) : "v"(b), "v"(c)))
+DEFK(k_alignbit, uint32_t, threadIdx.x + i, asm volatile("v_alignbit_b32 %0, %1, %0, 9" : "+v"(a[i]) : "v"(b)))
 DEFK(k_mulhi, uint32_t, threadIdx.x + i, asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a[i]) : "v"(b)))
 DEFK(k_mullo, uint32_t, threadIdx.x + i, asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a[i]) : "v"(b)))
 DEFK(k_mad64, uint64_t, threadIdx.x + i, {uint64_t cc; asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(a[i]), "=s"(cc) : "v"(b), "v"(c)); (void)cc;})
@@ -36,6 +38,7 @@ int main() {
   uint32_t *out;
   if (hipMalloc(&out, sizeof(uint32_t) * blocks * threads) != hipSuccess) return 1;
   struct { const char *n; K k; } ks[] = {{"v_fma_f32", k_fma32}, {"v_xor_b32", k_xor},
+    {"v_bitop3_b32", k_xor3}, {"v_alignbit_b32", k_alignbit},
     {"v_mul_hi_u32", k_mulhi}, {"v_mul_lo_u32", k_mullo}, {"v_mad_u64_u32", k_mad64}, {"v_sin_f32", k_sin},
     {"v_log_f32", k_log}, {"v_sqrt_f32", k_sqrt}, {"v_fma_f64", k_fma64}, {"v_cvt_f32_u32", k_cvt}};
   hipEvent_t e0, e1; hipEventCreate(&e0); hipEventCreate(&e1);
