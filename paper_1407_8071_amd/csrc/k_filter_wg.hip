@@ -282,6 +282,30 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
 // sum_i n_i xbar_i / N and the weighted estimate sum_i w_i xbar_i / W.
 constexpr int RS_MAX_P = 8;
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Elements k0 .. k0 + PM - 1 of a row of N floats into registers, indices
+// clamped into the row.  vec4: k0 and N are multiples of 4 and the row
+// starts on a 16-byte boundary, so 4-element chunks are either inside the
+// row or wholly past its end (then the last chunk is read instead).
+template <int PM>
+__device__ __forceinline__ void load_span(const gmem<float> *row, int k0, int N, bool vec4,
+                                          float out[PM]) {
+  if constexpr (PM % 4 == 0) {
+    if (vec4) {
+#pragma unroll
+      for (int j = 0; j < PM / 4; ++j) {
+        const f4v v = *(const gmem<f4v> *)(row + min(k0 + 4 * j, N - 4));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[4 * j + q] = v[q];
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < PM; ++e) out[e] = row[min(k0 + e, N - 1)];
+}
+
 // PM: elements per thread the registers hold, at least ceil(N / BD) for every
 // filter of the launch (1 below 1024 threads, which serve filters of N <= BD).
 template <int BD, int D, int PM>
@@ -303,25 +327,23 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
   const int k0 = min(N, tid * P), k1 = min(N, k0 + P);
   // (pointers from the ensemble table: global-address-space accesses)
   const gmem<float> *lwg = gptr(E.lw + (size_t)m * N);
-  // thread 0 reads the running evidence now, so that its latency is hidden
-  const double lg_prev = tid == 0 ? gptr(E.fstat)[(size_t)m * FREC + 5] : 0.0;
+  constexpr int NR = 1 + 2 * DD;         // sums of the final reduction
+  constexpr int T5 = BD > 64 ? 64 : NR;  // the thread that updates log G
+  // that thread reads the running evidence now, so that its latency is hidden
+  const double lg_prev = tid == T5 ? gptr(E.fstat)[(size_t)m * FREC + 5] : 0.0;
   const gmem<float> *Xb = gptr((xb_parity ? E.X1 : E.X0) + (size_t)m * DD * N);
-  // 1. this thread's log-weights (and xbar).  The loads are unconditional
-  // (index clamped to N - 1; a slot past the thread's range gets weight 0
-  // and count 0), so that they all issue at once; the log-weights are first
-  // used after step 2 and xbar in step 5, so both arrive under ALU work.
+  // 1. this thread's log-weights.  The loads are unconditional (index
+  // clamped; a slot past the thread's range gets weight 0 and count 0), so
+  // that they all issue at once; they are first used after step 2.  Where
+  // every thread's range starts on a 16-byte boundary (P and N multiples of
+  // 4) they are 16-byte loads: one instruction per 4 elements instead of 4
+  // lane-strided ones that each touch 4 times the cache lines they use.
+  const bool vec4 = PM % 4 == 0 && P % 4 == 0 && N % 4 == 0;
   float lw[PM];
-  float xb[PM][DD];
+  load_span<PM>(lwg, k0, N, vec4, lw);
 #pragma unroll
-  for (int e = 0; e < PM; ++e) {
-    const int i = k0 + e, ic = min(i, N - 1);
-    lw[e] = lwg[ic];
-    if (i < k1) cnt[i] = 0;
-    if constexpr (D > 0) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) xb[e][c] = Xb[(size_t)c * N + ic];
-    }
-  }
+  for (int e = 0; e < PM; ++e)
+    if (k0 + e < k1) cnt[k0 + e] = 0;
   // 2. exponential spacings over the same elements (they do not depend on
   // the weights: computed while the loads are in flight)
   ExpoWG ex{E.key, (uint32_t)m, (uint32_t)t};
@@ -348,6 +370,14 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
   const float mxf = block_max(lmax, shf);
   const bool deg = !(mxf > -INFINITY);
   const double mx = (double)mxf;
+  // xbar (vector models), first used in step 5: issued only now, so that
+  // the log-weights of every workgroup did not share the memory system with
+  // three times their volume, and arriving under steps 3-4
+  float xb[DD][PM];
+  if constexpr (D > 0) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) load_span<PM>(Xb + (size_t)c * N, k0, N, vec4, xb[c]);
+  }
   double w[PM], run = 0.0, s2 = 0.0;
 #pragma unroll
   for (int e = 0; e < PM; ++e) {
@@ -393,8 +423,8 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
       double px = 0.0, wx = 0.0;
 #pragma unroll
       for (int e = 0; e < PM; ++e) {
-        if (k0 + e < k1) px += (double)cnt[k0 + e] * (double)xb[e][c];
-        wx += w[e] * (double)xb[e][c];
+        if (k0 + e < k1) px += (double)cnt[k0 + e] * (double)xb[c][e];
+        wx += w[e] * (double)xb[c][e];
       }
       red[1 + c] = px;
       red[1 + D + c] = wx;
@@ -404,26 +434,33 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
     for (int j = tid; j < N; j += BD) cg[j] = cnt[j];
     red[1] = red[2] = 0.0;
   }
-  constexpr int NR = 1 + 2 * DD;
-  block_sum_multi_t0<NR>(red, shd);
-  if (tid == 0) {
-    if constexpr (D > 0) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        gptr(E.fmean)[(size_t)m * D + c] = red[1 + c] / (double)N;
-        gptr(E.fmeanw)[(size_t)m * D + c] = red[1 + D + c] / W;
-      }
+  // thread r < NR folds sum r; the quotients of the outputs are taken side
+  // by side in those lanes (one division sequence, per-lane operands), and
+  // the logarithm of log G by thread T5 (another wave, where there is one)
+  const double a = block_sum_multi_lane<NR>(red, shd);
+  gmem<double> *f = gptr(E.fstat + (size_t)m * FREC);
+  if (tid < (D > 0 ? NR : 1)) {
+    double num = a, den = W;
+    gmem<double> *dst = f + 6;
+    if (tid == 0) {
+      num = W * W;  // ESS = W^2 / sum w^2
+      den = a;
+    } else if (tid <= D) {
+      den = (double)N;
+      dst = gptr(E.fmean + (size_t)m * D + (tid - 1));
+    } else {
+      dst = gptr(E.fmeanw + (size_t)m * D + (tid - 1 - D));
     }
-    gmem<double> *f = gptr(E.fstat + (size_t)m * FREC);
-    const double w2 = red[0];
-    f[0] = mx;
-    f[1] = W;
-    f[2] = w2;
-    f[3] = deg ? 1.0 : 0.0;
-    f[4] = SN;
-    f[5] = deg ? -INFINITY : lg_prev + mx + log(W / (double)N) + E.lognorm;
-    f[6] = W * W / w2;
+    *dst = num / den;
+    if (tid == 0) {
+      f[0] = mx;
+      f[1] = W;
+      f[2] = a;  // sum w^2
+      f[3] = deg ? 1.0 : 0.0;
+      f[4] = SN;
+    }
   }
+  if (tid == T5) f[5] = deg ? -INFINITY : lg_prev + mx + log(W / (double)N) + E.lognorm;
 }
 
 // The kernel: PMAX is the largest ceil(N / BD) of the launch's filters; each

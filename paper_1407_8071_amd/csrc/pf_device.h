@@ -246,6 +246,27 @@ __device__ __forceinline__ void block_sum_multi_t0(double v[R], double *sh) {
   }
 }
 
+// Workgroup sums of R <= 64 values at once (fixed order, that of
+// block_sum_multi_t0); thread r < R returns the sum of value r, so that the
+// R final folds run side by side in the lanes of wave 0.  sh holds
+// R * (blockDim.x / 64) doubles.
+template <int R>
+__device__ __forceinline__ double block_sum_multi_lane(double v[R], double *sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = wave_sum(v[r]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) sh[r * nw + wid] = v[r];
+  }
+  __syncthreads();
+  double a = 0.0;
+  if (threadIdx.x < R)
+    for (int i = 0; i < nw; ++i) a += sh[threadIdx.x * nw + i];
+  return a;
+}
+
 // Workgroup exclusive scan; returns the exclusive prefix of this thread and
 // the total in *tot.
 __device__ __forceinline__ double block_exscan(double v, double *sh, double *tot) {
