@@ -497,12 +497,18 @@ k_offspring_counts(int N, const int32_t *__restrict__ A, int32_t *__restrict__ c
 
 }  // namespace
 
+// LDS bytes of a resampling workgroup (BD threads) for filters of up to N
+// particles: reduction scratch, the CDF, the offspring counts.
+size_t resample_wg_lds(int N, int BD) {
+  return sizeof(double) * (9 * (size_t)(BD / 64) + 2) + sizeof(double) * (size_t)N +
+         sizeof(int) * (size_t)N;
+}
+
 hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                               const FusedEns *d_ens, IvArg iv, int32_t *const *d_counts,
                               int xb_parity, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  const size_t lds = sizeof(double) * (9 * (size_t)(BD / 64) + 2) +
-                     sizeof(double) * (size_t)max_n + sizeof(int) * (size_t)max_n;
+  const size_t lds = resample_wg_lds(max_n, BD);
   const int pm = BD < 1024 ? 1 : (max_n <= 1024 ? 1 : max_n <= 2048 ? 2 : max_n <= 4096 ? 4 : 8);
   if (BD < 1024 && max_n > BD) return hipErrorInvalidValue;
   if (max_n > RS_MAX_P * 1024) return hipErrorInvalidValue;
@@ -563,8 +569,10 @@ hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int 
 }
 
 hipError_t set_filter_wg_lds_limit() {
-  // allow the largest dynamic LDS request (N = 8192 at BD = 1024)
-  const int bytes = (int)filter_wg_lds(WG_MAX_N, 1024);
+  // allow the largest dynamic LDS request of either kernel (N = 8192 at
+  // BD = 1024)
+  const size_t fw = filter_wg_lds(WG_MAX_N, 1024), rw = resample_wg_lds(WG_MAX_N, 1024);
+  const int bytes = (int)(fw > rw ? fw : rw);
   hipError_t e;
   e = hipFuncSetAttribute((const void *)k_filter_wg<3, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;

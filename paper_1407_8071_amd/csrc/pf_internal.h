@@ -96,6 +96,7 @@ struct WgJob {
   int32_t ens, filter;
 };
 size_t filter_wg_lds(int N, int BD);
+size_t resample_wg_lds(int N, int BD);
 hipError_t set_filter_wg_lds_limit();
 hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                             const FusedEns *d_ens, IvArg iv, int parity, int pending,
