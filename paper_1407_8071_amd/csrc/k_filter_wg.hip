@@ -275,8 +275,10 @@ k_filter_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, Iv
 // the LDS CDF, the sorted uniforms, the ancestors, their offspring counts n_i
 // and log G.  Thread t owns the contiguous elements [t*P, (t+1)*P) (P =
 // ceil(N/BD) <= RS_MAX_P, and 1 below 1024 threads) for every quantity: its log-weights, weights and
-// (vector models) xbar stay in registers, the CDF and the uniforms each take
-// one sequential scan per thread plus one block scan.  Grid model (D = 0):
+// (vector models) xbar stay in registers; the CDF and the uniforms each take
+// one sequential scan per thread, and their two block scans run as one.
+// The exponential spacings do not depend on the weights and are drawn while
+// the log-weights load.  Grid model (D = 0):
 // the counts go to HBM for the state-wide estimator.  Vector models (D = 1,
 // 3): the workgroup also forms the post-resampling estimate
 // sum_i n_i xbar_i / N and the weighted estimate sum_i w_i xbar_i / W.
