@@ -18,6 +18,7 @@
 // the Philox call of node pair p at step n.
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "pf_internal.h"
 
@@ -72,11 +73,50 @@ __device__ __forceinline__ Nbr4 neighbours(int J, int s) {
   return n;
 }
 
+// Neighbour addresses of slot s when J is a multiple of 4, so that the
+// slot's 4 nodes lie in one row: the 4 nodes above and the 4 below as one
+// 16-byte read each (the slot itself on the top / bottom row: no-flux), the
+// left neighbour of the first node and the right neighbour of the last (the
+// node itself at the left / right edge); the inner left and right
+// neighbours are the slot's own values.
+struct Row4 {
+  int u, d, l, r;
+};
+
+__device__ __forceinline__ Row4 row4_addrs(int J, int s) {
+  const int k = 4 * s, i = k / J, j = k - i * J;
+  return Row4{i > 0 ? k - J : k, i < J - 1 ? k + J : k, j > 0 ? k - 1 : k,
+              j + 3 < J - 1 ? k + 4 : k + 3};
+}
+
+// v of the up, down, left and right neighbours of the slot's 4 nodes
+__device__ __forceinline__ void fetch_nbrs(const Nbr4 &nb, const float *vs, const float4 &,
+                                           float vu[4], float vd[4], float vl[4], float vr[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    vu[e] = vs[nb.u[e]];
+    vd[e] = vs[nb.d[e]];
+    vl[e] = vs[nb.l[e]];
+    vr[e] = vs[nb.r[e]];
+  }
+}
+__device__ __forceinline__ void fetch_nbrs(const Row4 &nb, const float *vs, const float4 &v,
+                                           float vu[4], float vd[4], float vl[4], float vr[4]) {
+  const float4 a = *(const float4 *)(vs + nb.u), b = *(const float4 *)(vs + nb.d);
+  const float L = vs[nb.l], R = vs[nb.r];
+  vu[0] = a.x; vu[1] = a.y; vu[2] = a.z; vu[3] = a.w;
+  vd[0] = b.x; vd[1] = b.y; vd[2] = b.z; vd[3] = b.w;
+  vl[0] = L;   vl[1] = v.x; vl[2] = v.y; vl[3] = v.z;
+  vr[0] = v.y; vr[1] = v.z; vr[2] = v.w; vr[3] = R;
+}
+
 // One Euler-Maruyama step of the 4 nodes of slot s (nodes 4s .. 4s+3), reading
-// neighbour v values from the LDS plane vs.  Returns the new state in S.
+// neighbour v values from the LDS plane vs (which holds S.v for this slot).
+// Returns the new state in S.
+template <class NB>
 __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t purpose,
                                            uint32_t c0, uint32_t c1, uint32_t n, int s,
-                                           const Nbr4 &nb, const float *vs, Slot4 &S) {
+                                           const NB &nb, const float *vs, Slot4 &S) {
   const uint4 ra = philox<4, 3>(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s), key);
   const uint4 rb = philox<4, 3>(c0, c1, n, (purpose << 24) | (uint32_t)(2 * s + 1), key);
   float za[4], zb[4];
@@ -86,13 +126,7 @@ __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t
   const float zv[4] = {za[0], za[2], zb[0], zb[2]};
   const float zw[4] = {za[1], za[3], zb[1], zb[3]};
   float vu[4], vd[4], vl[4], vr[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    vu[e] = vs[nb.u[e]];
-    vd[e] = vs[nb.d[e]];
-    vl[e] = vs[nb.l[e]];
-    vr[e] = vs[nb.r[e]];
-  }
+  fetch_nbrs(nb, vs, S.v, vu, vd, vl, vr);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const float c = get(S.v, e), w = get(S.w, e);
@@ -150,8 +184,8 @@ __device__ __forceinline__ float wave_loglik(const ModelDev &md, const float *vs
 // (J = 40: 2 x 400 slots in 832 threads; J = 20: 5 x 100 in 512).  Every
 // ensemble's entries are padded to a multiple of ppb with ensemble -1.
 // MULTI = false is the ppb = 1 form, whose particle indices stay uniform
-// (scalar registers).
-template <bool MULTI>
+// (scalar registers).  ROW4: J is a multiple of 4 (neighbours by Row4).
+template <bool MULTI, bool ROW4>
 __device__ __forceinline__ void grid_steps(const int4 *__restrict__ ptab, int n_p,
                                            const FusedEns *__restrict__ ens, IvArg iv, int parity,
                                            int pending, int J, int ppb_arg) {
@@ -163,7 +197,11 @@ __device__ __forceinline__ void grid_steps(const int4 *__restrict__ ptab, int n_
   const int q = MULTI ? (int)threadIdx.x / slots : 0, sl = (int)threadIdx.x - q * slots;
   const bool has_slot = MULTI ? q < ppb : sl < slots;
   float *vs = planes + (has_slot ? q : 0) * nn;
-  const Nbr4 nb = neighbours(J, has_slot ? sl : 0);
+  std::conditional_t<ROW4, Row4, Nbr4> nb;
+  if constexpr (ROW4)
+    nb = row4_addrs(J, has_slot ? sl : 0);
+  else
+    nb = neighbours(J, has_slot ? sl : 0);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   for (int p0 = blockIdx.x * ppb; p0 < n_p; p0 += gridDim.x * ppb) {
     // the first entry of a group is never padding
@@ -215,18 +253,20 @@ __device__ __forceinline__ void grid_steps(const int4 *__restrict__ ptab, int n_
   }
 }
 
+template <bool ROW4>
 __global__ void __launch_bounds__(1024)
 k_grid_steps(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict__ ens, IvArg iv,
              int parity, int pending, int J) {
-  grid_steps<false>(ptab, n_p, ens, iv, parity, pending, J, 1);
+  grid_steps<false, ROW4>(ptab, n_p, ens, iv, parity, pending, J, 1);
 }
 
 // (at most 64 VGPRs, 8 wavefronts per SIMD: the few values it spills are
 // reloaded once per particle group, outside the Euler steps)
+template <bool ROW4>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_grid_steps_multi(const int4 *__restrict__ ptab, int n_p, const FusedEns *__restrict__ ens,
                    IvArg iv, int parity, int pending, int J, int ppb) {
-  grid_steps<true>(ptab, n_p, ens, iv, parity, pending, J, ppb);
+  grid_steps<true, ROW4>(ptab, n_p, ens, iv, parity, pending, J, ppb);
 }
 
 // One Euler step n of every particle, state through HBM.
@@ -570,11 +610,15 @@ void grid_shape(const ModelDev &md, int *spt, int *threads) {
 // one particle in 4 resident workgroups of 7 waves beats two in 2 of 13).
 // Cached per J (the launch and the table padding must agree).
 namespace {
+template <bool ROW4>
+hipError_t steps_occupancy(int *per_cu, int J, int ppb) {
+  return ppb == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_grid_steps<ROW4>, steps_threads(J, 1), steps_lds(J, 1))
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_grid_steps_multi<ROW4>, steps_threads(J, ppb), steps_lds(J, ppb));
+}
 int steps_blocks_per_cu(int J, int ppb) {
   int per_cu = 0;
-  const hipError_t e =
-      ppb == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps, steps_threads(J, 1), steps_lds(J, 1))
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_steps_multi, steps_threads(J, ppb), steps_lds(J, ppb));
+  const hipError_t e = J % 4 == 0 ? steps_occupancy<true>(&per_cu, J, ppb)
+                                  : steps_occupancy<false>(&per_cu, J, ppb);
   return e == hipSuccess ? per_cu : 0;
 }
 }  // namespace
@@ -639,12 +683,17 @@ hipError_t launch_grid_steps_batched(int J, const int4 *d_ptab, int n_p, const F
   const int ppb = grid_steps_ppb(J);
   if (n_p % ppb != 0) return hipErrorInvalidValue;  // the table is padded per ensemble
   const int g = std::max(1, std::min(blocks, n_p / ppb));
-  if (ppb == 1)
-    k_grid_steps<<<g, steps_threads(J, 1), steps_lds(J, 1), s>>>(d_ptab, n_p, d_ens, iv, parity,
-                                                                pending, J);
+  const int th = steps_threads(J, ppb);
+  const size_t lds = steps_lds(J, ppb);
+  const bool row4 = J % 4 == 0;
+  if (ppb == 1 && row4)
+    k_grid_steps<true><<<g, th, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
+  else if (ppb == 1)
+    k_grid_steps<false><<<g, th, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J);
+  else if (row4)
+    k_grid_steps_multi<true><<<g, th, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J, ppb);
   else
-    k_grid_steps_multi<<<g, steps_threads(J, ppb), steps_lds(J, ppb), s>>>(d_ptab, n_p, d_ens, iv,
-                                                                          parity, pending, J, ppb);
+    k_grid_steps_multi<false><<<g, th, lds, s>>>(d_ptab, n_p, d_ens, iv, parity, pending, J, ppb);
   return hipGetLastError();
 }
 

@@ -19,6 +19,11 @@ pytestmark = pytest.mark.gpu
 
 F20 = pf_inputs.fhn(20)
 F40 = pf_inputs.fhn(40)
+# grid sides that are not multiples of 4 (a slot of 4 nodes may straddle two
+# rows: the stepping kernel's general neighbour path) and a small one that is
+F10 = pf_inputs.fhn(10)
+F12 = pf_inputs.fhn(12)
+F42 = pf_inputs.fhn(42)
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +65,9 @@ def test_prior_draw(pf, orc, torch_mod, spec, M, N):
 
 
 @pytest.mark.parametrize("spec,M,N,t,fused", [(F20, 2, 16, 3, False), (F20, 3, 7, 1, True),
-                                              (F40, 1, 6, 2, False), (F40, 2, 4, 5, True)])
+                                              (F40, 1, 6, 2, False), (F40, 2, 4, 5, True),
+                                              (F10, 2, 5, 2, True), (F12, 2, 4, 2, True),
+                                              (F42, 1, 3, 1, True), (F10, 2, 3, 2, False)])
 def test_propagate_and_weight(pf, orc, torch_mod, spec, M, N, t, fused):
     seed = 70 + N
     X0 = _cloud(spec, M, N, seed)
