@@ -304,6 +304,10 @@ struct pf_ctx {
   bool profiling = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
   size_t ev_used = 0;
+  // second stream of the fused interval: the grid ensembles' chain, forked
+  // from and joined to the caller's stream by two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~pf_ctx() {
     for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
@@ -312,6 +316,9 @@ struct pf_ctx {
       if (graph[p]) (void)hipGraphDestroy(graph[p]);
     }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -433,10 +440,43 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
 // kernels for ensembles whose filters exceed one workgroup, and the
 // cross-filter averages.  The particles stay where propagation wrote them
 // and the next interval gathers them through the ancestors.
+// The two chains of a fused interval share no data until the cross-filter
+// means: the vector ensembles' (propagation tiles, single-kernel filters,
+// resampling with their estimates) and the grid ensembles' (stepping,
+// learned stepping, resampling, state-wide estimators).  When a batch holds
+// both, the grid chain runs on a second stream (default priority) forked
+// from the caller's stream and joined back before the means, so that one
+// chain's latency-bound launches overlap the other's compute; in a captured
+// graph the fork and join become dependencies.  While profiling, both run
+// in order on the caller's stream, so that the timed kernels do not share
+// the device.
+pf_status side_stream(pf_ctx *ctx) {
+  if (!ctx->side) PF_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  if (!ctx->ev_fork) PF_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  if (!ctx->ev_join) PF_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  return PF_OK;
+}
+
 pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool resample_only,
                        hipStream_t s) {
   const int out = 1 - parity;  // buffer that holds xbar of this interval
   const bool prof = !ctx->capturing && !resample_only;
+  bool vec_work = ctx->n_tiles[0] + ctx->n_tiles[1] > 0, grid_work = !ctx->ggroups.empty();
+  for (const WgClass &c : ctx->classes) {
+    if (c.kind == CLASS_FILTER_WG || c.kind == CLASS_RESAMPLE_VEC) vec_work = true;
+    if (c.kind == CLASS_RESAMPLE_GRID) grid_work = true;
+  }
+  for (const Ens &E : ctx->ens) {
+    if (E.learned) grid_work = true;
+    else if (E.tiled) vec_work = true;
+  }
+  hipStream_t g = s;  // the grid chain's stream
+  if (vec_work && grid_work && !resample_only && !ctx->profiling) {
+    PF_TRY(side_stream(ctx));
+    PF_HIP(hipEventRecord(ctx->ev_fork, s));
+    PF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    g = ctx->side;
+  }
   // 1. propagation + weighting: the batched vector tiles (profiled: the
   //    kernel that carries the interval), the single-kernel classes, and the
   //    grid model's stepping kernel (profiled)
@@ -456,11 +496,11 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     }
   if (!resample_only) {
     // every bootstrap grid ensemble of one grid size in one launch (profiled)
-    for (const auto &g : ctx->ggroups) {
-      const long eg = prof ? prof_begin(ctx, s) : -1;
-      PF_HIP(pfk::launch_grid_steps_batched(g.J, g.d_ptab, (int)g.ptab.size(), ctx->d_fens, iv,
-                                            parity, pending, g.blocks, s));
-      prof_end(ctx, eg, s);
+    for (const auto &gg : ctx->ggroups) {
+      const long eg = prof ? prof_begin(ctx, g) : -1;
+      PF_HIP(pfk::launch_grid_steps_batched(gg.J, gg.d_ptab, (int)gg.ptab.size(), ctx->d_fens, iv,
+                                            parity, pending, gg.blocks, g));
+      prof_end(ctx, eg, g);
     }
     int yo = 0;
     for (Ens &E : ctx->ens) {
@@ -468,11 +508,11 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
       yo += E.dy;
       if (!E.learned) continue;
       pfk::EnsDev &D = E.dev;
-      const long eg = prof ? prof_begin(ctx, s) : -1;
+      const long eg = prof ? prof_begin(ctx, g) : -1;
       PF_HIP(pfk::launch_grid_steps_learned(D, iv, yoff, D.X[parity], pending ? D.A : nullptr,
                                             D.X[out], D.lw, E.params, E.nearest, E.sd0, E.sd1,
-                                            E.lblocks, s));
-      prof_end(ctx, eg, s);
+                                            E.lblocks, g));
+      prof_end(ctx, eg, g);
     }
   }
   // 2. resampling and the filters' estimates
@@ -482,20 +522,24 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
                                      iv, ctx->d_counts, out, s));
     else if (c.kind == CLASS_RESAMPLE_GRID)
       PF_HIP(pfk::launch_resample_wg(0, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                     iv, ctx->d_counts, out, s));
+                                     iv, ctx->d_counts, out, g));
   }
-  for (const auto &g : ctx->ggroups)
-    PF_HIP(pfk::launch_grid_estimate_batched(g.J, g.d_part, (int)g.part_jobs.size(), g.d_fold,
-                                             (int)g.fold_jobs.size(), g.d_gens, (int)g.gens.size(),
-                                             ctx->d_fens, out, s));
+  for (const auto &gg : ctx->ggroups)
+    PF_HIP(pfk::launch_grid_estimate_batched(gg.J, gg.d_part, (int)gg.part_jobs.size(), gg.d_fold,
+                                             (int)gg.fold_jobs.size(), gg.d_gens, (int)gg.gens.size(),
+                                             ctx->d_fens, out, g));
   for (Ens &E : ctx->ens) {
     pfk::EnsDev &D = E.dev;
     if (E.learned) {
-      PF_HIP(pfk::launch_grid_estimate(D, D.X[out], E.cnt, E.gpart, s));
+      PF_HIP(pfk::launch_grid_estimate(D, D.X[out], E.cnt, E.gpart, g));
     } else if (E.tiled) {
       PF_HIP(pfk::launch_resample(D, iv.t, s, iv.tp));
       PF_HIP(pfk::launch_vec_estimate(D, D.X[out], D.X[out], D.A, false, s));
     }
+  }
+  if (g != s) {
+    PF_HIP(hipEventRecord(ctx->ev_join, g));
+    PF_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
   // 3. the cross-filter averages (and, in a graph, the interval counter)
   PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(),
