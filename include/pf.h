@@ -156,7 +156,12 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models,
    normalisation with the update of log G_t^N (eqGtN), multinomial resampling
    and the estimators.  d_y: float32, the observations y_t of every ensemble
    concatenated in ensemble order (obs_dim of its model each), or NULL to use
-   the record staged by pf_set_observations.  Advances t. */
+   the record staged by pf_set_observations.  Advances t.  With PF_OPT_FUSED
+   and a batch that holds both vector-model and grid-model ensembles, the
+   grid ensembles' part of the interval runs on a stream of the context,
+   forked from `stream` and joined back to it before the cross-filter means
+   (unless profiling is on): all of the interval still follows earlier work
+   on `stream` and precedes later work on it. */
 pf_status pf_step(pf_ctx *ctx, const float *d_y, void *stream);
 
 /* Stage the observation record on the device: d_y_all float32 [T][sum_e
