@@ -495,6 +495,8 @@ k_grid_filter_fold_b(const int4 *__restrict__ jobs, const FusedEns *__restrict__
   const int c = blockIdx.y * GB + threadIdx.x, m = jb.y, nch = E.nch;
   if (c >= dx) return;
   double a = 0.0, b = 0.0;
+  // (unrolled: the loads of several terms issue before their in-order sums)
+#pragma unroll 8
   for (int ch = 0; ch < nch; ++ch) {
     const gmem<double> *o = gptr(E.gpart + (((size_t)m * nch + ch) * 2) * (size_t)dx);
     a += o[c];
@@ -510,6 +512,7 @@ k_grid_ensemble_fold_b(const int *__restrict__ gens, const FusedEns *__restrict_
   const int c = blockIdx.y * GB + threadIdx.x;
   if (c >= dx) return;
   double a = 0.0, b = 0.0;
+#pragma unroll 8
   for (int m = 0; m < E.M; ++m) {
     a += gptr(E.fmean)[(size_t)m * dx + c];
     b += gptr(E.fmeanw)[(size_t)m * dx + c];
