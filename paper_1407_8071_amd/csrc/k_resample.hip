@@ -43,22 +43,26 @@ __device__ __forceinline__ double filter_max(const double *__restrict__ tile, in
 // Tile-local inclusive scans, one launch: the CDF of w_i = exp(lw_i - mx) in
 // FP64 (w = 1 for every particle when no weight is positive), and the sums
 // of the exponential variates E_j (the last tile also adds E_N to its
-// total).  Thread t owns the 16 consecutive elements [16t, 16t+16) of the
-// tile; the exponentials come first since they need no other launch's
-// result.
-__global__ void __launch_bounds__(TILE_THREADS)
+// total).  1024 threads per tile, thread t owning the 4 consecutive
+// elements [4t, 4t+4) (one Philox call): with a tile per workgroup a
+// single-filter launch has few workgroups, and 16 waves per workgroup hide
+// the latency of the FP64 exponentials and logarithms.  The exponentials
+// come first since they need no other launch's result.
+constexpr int CDF_THREADS = 1024, CDF_PER_THREAD = TILE / CDF_THREADS;
+static_assert(CDF_PER_THREAD % 4 == 0, "whole Philox calls per thread");
+__global__ void __launch_bounds__(CDF_THREADS)
 k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float *__restrict__ lw,
                     double *__restrict__ tile, double *__restrict__ Cl, double *__restrict__ Sl) {
   const int t = tp ? *tp : t_arg;
-  __shared__ float shf[TILE_THREADS / 64];
-  __shared__ double shd[TILE_THREADS / 64];
+  __shared__ float shf[CDF_THREADS / 64];
+  __shared__ double shd[CDF_THREADS / 64];
   const int m = blockIdx.y, q = blockIdx.x;
-  const int base = q * TILE + threadIdx.x * TILE_PER_THREAD;
+  const int base = q * TILE + threadIdx.x * CDF_PER_THREAD;
   // exponential variates first: they need no other launch's result
-  double s[TILE_PER_THREAD];
+  double s[CDF_PER_THREAD];
   double srun = 0.0;
 #pragma unroll
-  for (int g = 0; g < TILE_PER_THREAD / 4; ++g) {
+  for (int g = 0; g < CDF_PER_THREAD / 4; ++g) {
     const int j0 = base + 4 * g;
     uint4 r = make_uint4(0, 0, 0, 0);
     if (j0 < N) r = philox<2, 3>((uint32_t)(j0 >> 2), (uint32_t)m, (uint32_t)t, P_RESAMPLE << 24, key);
@@ -71,10 +75,10 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
   }
   const double mx = filter_max(tile, m, T, shf);
   const bool deg = !(mx > -INFINITY);
-  double w[TILE_PER_THREAD];
+  double w[CDF_PER_THREAD];
   double run = 0.0, sq = 0.0;
 #pragma unroll
-  for (int e = 0; e < TILE_PER_THREAD; ++e) {
+  for (int e = 0; e < CDF_PER_THREAD; ++e) {
     const int i = base + e;
     double we = 0.0;
     if (i < N) we = deg ? 1.0 : exp((double)sane_lw(lw[(size_t)m * N + i]) - mx);
@@ -87,7 +91,7 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
   const double soffv = block_exscan(srun, shd, &stot);
   const int last = min(N - 1, q * TILE + TILE - 1);
 #pragma unroll
-  for (int e = 0; e < TILE_PER_THREAD; ++e) {
+  for (int e = 0; e < CDF_PER_THREAD; ++e) {
     const int i = base + e;
     if (i < N) {
       const double c = off + w[e];
@@ -397,7 +401,7 @@ hipError_t launch_set_i32(int *p, int v, hipStream_t s) {
 hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s, const int *tp) {
   const dim3 g((unsigned)e.T, (unsigned)e.M);
   k_tile_max<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile);
-  k_cdf_uniform_tiles<<<g, TILE_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.lw, e.tile, e.Cl, e.Sl);
+  k_cdf_uniform_tiles<<<g, CDF_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.lw, e.tile, e.Cl, e.Sl);
   k_filter_reduce<<<e.M, 256, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
   if (e.T <= ANC_LDS_TILES) {
     const dim3 ga((unsigned)((e.N + ANC_SPAN - 1) / ANC_SPAN), (unsigned)e.M);

@@ -168,38 +168,43 @@ k_vec_gather(int N, const int32_t *__restrict__ A, const float *__restrict__ Xin
 
 // Per-tile partial sums of the post-resampling particles (for (f, pi_t^N))
 // and of the weighted pre-resampling particles (for sum_i w^(i) xbar^(i)).
+// 1024 threads per tile of 4096, 4 lane-strided elements each, whose loads
+// (and the gathers through the ancestors) issue together; one reduction of
+// all 2 D sums.
+constexpr int EST_THREADS = 1024, EST_PER_THREAD = TILE / EST_THREADS;
 template <int D>
-__global__ void __launch_bounds__(TILE_THREADS)
+__global__ void __launch_bounds__(EST_THREADS)
 k_vec_estimate_tiles(int N, int T, const float *__restrict__ Xpost, const float *__restrict__ Xpre,
                      const int32_t *__restrict__ anc, const float *__restrict__ lw,
                      const double *__restrict__ fstat, double *__restrict__ mpart,
                      double *__restrict__ wpart) {
-  __shared__ double sh[TILE_THREADS / 64];
+  __shared__ double sh[2 * D * (EST_THREADS / 64)];
   const int m = blockIdx.y, q = blockIdx.x;
   const double mx = fstat[(size_t)m * FREC + 0];
   const bool deg = fstat[(size_t)m * FREC + 3] != 0.0;
-  double sp[D], sw[D];
+  double v[2 * D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) sp[c] = sw[c] = 0.0;
-  for (int e = 0; e < TILE_PER_THREAD; ++e) {
-    const int i = q * TILE + e * TILE_THREADS + threadIdx.x;
-    if (i >= N) break;
-    const double w = deg ? 1.0 : exp((double)lw[(size_t)m * N + i] - mx);
-    // post-resampling particle k = i: stored, or xbar read through a_i
-    const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
+  for (int c = 0; c < 2 * D; ++c) v[c] = 0.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      sp[c] += (double)Xpost[((size_t)m * D + c) * N + src];
-      sw[c] += w * (double)Xpre[((size_t)m * D + c) * N + i];
+  for (int e = 0; e < EST_PER_THREAD; ++e) {
+    const int i = q * TILE + e * EST_THREADS + threadIdx.x;
+    if (i < N) {
+      const double w = deg ? 1.0 : exp((double)lw[(size_t)m * N + i] - mx);
+      // post-resampling particle k = i: stored, or xbar read through a_i
+      const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        v[c] += (double)Xpost[((size_t)m * D + c) * N + src];
+        v[D + c] += w * (double)Xpre[((size_t)m * D + c) * N + i];
+      }
     }
   }
+  block_sum_multi_t0<2 * D>(v, sh);
+  if (threadIdx.x == 0) {
 #pragma unroll
-  for (int c = 0; c < D; ++c) {
-    const double a = block_sum(sp[c], sh);
-    const double b = block_sum(sw[c], sh);
-    if (threadIdx.x == 0) {
-      mpart[((size_t)m * T + q) * D + c] = a;
-      wpart[((size_t)m * T + q) * D + c] = b;
+    for (int c = 0; c < D; ++c) {
+      mpart[((size_t)m * T + q) * D + c] = v[c];
+      wpart[((size_t)m * T + q) * D + c] = v[D + c];
     }
   }
 }
@@ -293,10 +298,10 @@ hipError_t launch_vec_estimate(const EnsDev &e, const float *Xpost, const float 
                                const int32_t *anc, bool ensemble_mean, hipStream_t s) {
   dim3 g((unsigned)e.T, (unsigned)e.M);
   PF_DISPATCH_D(e,
-                (k_vec_estimate_tiles<3><<<g, TILE_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, anc,
+                (k_vec_estimate_tiles<3><<<g, EST_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, anc,
                                                                     e.lw, e.fstat, e.mpart,
                                                                     e.wpart)),
-                (k_vec_estimate_tiles<1><<<g, TILE_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, anc,
+                (k_vec_estimate_tiles<1><<<g, EST_THREADS, 0, s>>>(e.N, e.T, Xpost, Xpre, anc,
                                                                     e.lw, e.fstat, e.mpart,
                                                                     e.wpart)));
   hipError_t err = hipGetLastError();
