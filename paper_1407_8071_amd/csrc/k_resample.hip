@@ -358,14 +358,38 @@ k_ensemble_mean(int M, int dx, const double *__restrict__ fmean, const double *_
 }
 
 // One workgroup per ensemble: equal-weight average of its filters' means.
-__global__ void __launch_bounds__(256)
+// (256 threads, or 1024 where an ensemble has more filters; for dx <= 3 every
+// thread takes all 2 dx sums over its filters in one pass, and one block
+// reduction folds them.)
+__global__ void __launch_bounds__(1024)
 k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
-  __shared__ double sh[4];
+  __shared__ double sh[16];
+  __shared__ double shm[6 * 16];
   // every earlier kernel of the interval has read the counter
   if (t_inc && blockIdx.x == 0 && threadIdx.x == 0) *t_inc += 1;
   const FusedEns &E = ens[blockIdx.x];
   if (E.md.kind == 2) return;  // grid model: folded by its own estimator
   const int dx = E.md.dx;
+  if (dx <= 3) {
+    double v[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) v[r] = 0.0;
+    for (int m = threadIdx.x; m < E.M; m += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c < dx) {
+          v[c] += gptr(E.fmean)[(size_t)m * dx + c];
+          v[3 + c] += gptr(E.fmeanw)[(size_t)m * dx + c];
+        }
+    }
+    block_sum_multi_t0<6>(v, shm);
+    if (threadIdx.x == 0)
+      for (int c = 0; c < dx; ++c) {
+        gptr(E.emean)[c] = v[c] / (double)E.M;
+        gptr(E.emean)[dx + c] = v[3 + c] / (double)E.M;
+      }
+    return;
+  }
   for (int c = 0; c < dx; ++c) {
     double a = 0.0, b = 0.0;
     for (int m = threadIdx.x; m < E.M; m += blockDim.x) {
@@ -383,8 +407,9 @@ k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
 
 }  // namespace
 
-hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int *t_inc, hipStream_t s) {
-  if (n_ens > 0) k_ensemble_means_batched<<<n_ens, 256, 0, s>>>(d_ens, t_inc);
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, int *t_inc,
+                                 hipStream_t s) {
+  if (n_ens > 0) k_ensemble_means_batched<<<n_ens, max_m > 256 ? 1024 : 256, 0, s>>>(d_ens, t_inc);
   return hipGetLastError();
 }
 

@@ -542,7 +542,9 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     PF_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
   // 3. the cross-filter averages (and, in a graph, the interval counter)
-  PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(),
+  int max_m = 1;
+  for (const Ens &E : ctx->ens) max_m = std::max(max_m, (int)E.d.M);
+  PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), max_m,
                                     iv.tp ? const_cast<int *>(iv.tp) : nullptr, s));
   return PF_OK;
 }

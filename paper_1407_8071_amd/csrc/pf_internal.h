@@ -143,7 +143,9 @@ int grid_steps_ppb(int J);
 
 // cross-filter averages of many ensembles at once (one workgroup each)
 // t_inc (optional): device interval counter advanced once the means are done
-hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int *t_inc, hipStream_t s);
+// max_m: the largest filter count of the ensembles (sets the workgroup size)
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, int *t_inc,
+                                 hipStream_t s);
 hipError_t launch_set_i32(int *p, int v, hipStream_t s);
 
 // ---- learned proposal (MLP in -> 64 -> 64 -> out, FP32 master parameters) ---
