@@ -147,3 +147,31 @@ def test_autotune_restarts_from_the_prior(pf, torch_mod, observations, tmp_path)
     k = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True)
     assert k.autotune_cached(y_all[0], path, reps=1) == t1
     assert k.tuning() == t1
+
+
+def test_grid_chain_stream_changes_nothing(pf, torch_mod, observations):
+    """The grid tenants' part of a fused interval runs on the context's second
+    stream, forked from the caller's stream and joined before the means; with
+    profiling on, both chains run in order on the caller's stream.  The two
+    schedules must give identical filters."""
+    y_all = torch_mod.from_numpy(np.ascontiguousarray(np.concatenate(observations, axis=1))).cuda()
+    tuning = {"vec_single_kernel": 0, "prop_tile": 128, "resample_bd_min": 256,
+              "grid_blocks_per_cu": 0}
+    runs = []
+    for profiling in (False, True):
+        f = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True)
+        f.set_tuning(tuning)
+        f.set_profiling(profiling)
+        for t in range(T):
+            f.step(y_all[t])
+        f.sync()
+        f.set_profiling(False)
+        f.read_profile()
+        runs.append(([_snapshot(f, e) for e in range(len(ENSEMBLES))],
+                     [x.cpu().numpy() for x in f.estimate()]))
+    (snap0, est0), (snap1, est1) = runs
+    for e in range(len(ENSEMBLES)):
+        for a, b in zip(snap0[e], snap1[e]):
+            assert np.array_equal(a, b, equal_nan=True), f"ensemble {e}"
+    for a, b in zip(est0, est1):
+        assert np.array_equal(a, b, equal_nan=True)
