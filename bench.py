@@ -474,7 +474,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              "(the ensemble shards by whole filters, see DESIGN.md)", file=sys.stderr)
+              "(the ensemble would shard by whole filters, one group of filters per GPU)", file=sys.stderr)
         sys.exit(2)
     if a.workload == "fhn40_learned_64x128":
         learned_main(a)
