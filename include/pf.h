@@ -36,7 +36,7 @@ extern "C" {
 typedef enum pf_status {
   PF_OK = 0,
   PF_ERR_INVALID_ARG = 1, /* bad descriptor, size, index or NULL pointer    */
-  PF_ERR_UNSUPPORTED = 2, /* valid request this build does not implement    */
+  PF_ERR_UNSUPPORTED = 2, /* valid request the library does not implement   */
   PF_ERR_WORKSPACE = 3,   /* workspace too small or misaligned              */
   PF_ERR_DEVICE = 4,      /* a HIP runtime call failed                      */
   PF_ERR_STATE = 5        /* call out of order (e.g. step before init)      */
