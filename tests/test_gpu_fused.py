@@ -189,3 +189,31 @@ def test_fused_end_to_end_mse_32_seeds(pf, orc, torch_mod):
     se = ora.std(ddof=1) / np.sqrt(len(seeds))
     print(f"fused MSE gpu {gpu.mean():.5f} oracle {ora.mean():.5f} (2 SE = {2 * se:.5f})")
     assert abs(gpu.mean() - ora.mean()) <= 2 * se
+
+
+def test_ensemble_means_are_the_average_of_filter_means(pf, orc, torch_mod):
+    """The cross-filter average (Definition 3's ensemble estimator) over
+    ensembles of very different M in one batch: the 1024-thread form of the
+    means kernel (some ensemble has more than 256 filters) for dx = 3 and
+    dx = 1, and a small ensemble in the same launch."""
+    ou = pf_inputs.ou1d(theta=1.0, sd=1.0, h=0.01, S=10, obs_var=0.3)
+    specs = [L63, ou]
+    ens = [(0, 4096, 64, 7), (1, 600, 32, 8), (0, 3, 100, 9)]
+    ys = []
+    for e, (mi, M, N, seed) in enumerate(ens):
+        _, y = orc.simulate(orc.Model(specs[mi]), 60 + e, 2)
+        ys.append(y.astype(np.float32))
+    y_all = _dev(np.ascontiguousarray(np.concatenate(ys, axis=1)))
+    f = pf.ParticleFilter(specs, ens, fused=True)
+    for t in range(2):
+        f.step(y_all[t])
+    f.sync()
+    mean, _, _, fmean = [x.cpu().numpy() for x in f.estimate()]
+    off_e = off_f = 0
+    for mi, M, N, seed in ens:
+        dx = specs[mi]["dx"]
+        fm = fmean[off_f:off_f + M * dx].reshape(M, dx)
+        assert np.all(np.isfinite(fm))
+        assert np.allclose(mean[off_e:off_e + dx], fm.mean(axis=0), rtol=1e-13, atol=1e-13)
+        off_e += dx
+        off_f += M * dx
