@@ -56,15 +56,23 @@ def _strict_ancestors(orc, A, lw, seed, t):
     assert n_diff <= max(4, 1e-5 * M * N), n_diff
 
 
-@pytest.mark.parametrize("M,N", [(1, 1), (3, 7), (4, 256), (2, 4097), (16, 5000), (1, 70001),
-                                 (1, 1 << 20)])
-def test_fused_resampling_matches_oracle(pf, orc, torch_mod, M, N):
+OU = pf_inputs.ou1d(theta=1.0, sd=1.0, h=0.01, S=10, obs_var=0.3)
+
+
+# (N = 4096 and 8192 take the resampler's 16-byte span loads: 4 and 8
+# elements per thread, N a multiple of 4; OU is its one-component form)
+@pytest.mark.parametrize("spec,M,N", [(L63, 1, 1), (L63, 3, 7), (L63, 4, 256), (L63, 2, 4097),
+                                      (L63, 16, 5000), (L63, 1, 70001), (L63, 1, 1 << 20),
+                                      (L63, 2, 4096), (L63, 2, 8192), (OU, 3, 4096),
+                                      (OU, 2, 8192)])
+def test_fused_resampling_matches_oracle(pf, orc, torch_mod, spec, M, N):
     seed, t = 40 + N, 23
+    dx = spec["dx"]
     lw = pf_inputs.logweights(7 + N, M, N, scale=4.0)
     if N > 10:
         lw[:, 2] = -np.inf
-    Xb = pf_inputs.particles(seed, L63, M, N).astype(np.float32)
-    f = pf.ParticleFilter([L63], [(0, M, N, seed)], fused=True)
+    Xb = pf_inputs.particles(seed, spec, M, N).astype(np.float32)
+    f = pf.ParticleFilter([spec], [(0, M, N, seed)], fused=True)
     f.set_predicted(0, _dev(oracle_to_vec(Xb)))
     f.set_logweights(0, _dev(lw))
     f.set_interval(t)
@@ -74,7 +82,7 @@ def test_fused_resampling_matches_oracle(pf, orc, torch_mod, M, N):
     _strict_ancestors(orc, A, lw, seed, t)
     st = f.get_filter_stats(0).cpu().numpy()
     mean, mean_w, _, fmean = [x.cpu().numpy() for x in f.estimate()]
-    fmean = fmean.reshape(M, 3)
+    fmean = fmean.reshape(M, dx)
     for k in range(min(M, 4)):
         lwk = lw[k].astype(np.float64)
         Ao, Co, Uo, (mx, W, s2, deg) = orc.resample(seed, k, t, lwk)
