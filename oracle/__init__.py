@@ -80,6 +80,7 @@ def lib():
             "or_propagate_particle": (None, [M, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int, _D]),
             "or_weights": (None, [M, C.c_int, _D, _D, _D]),
             "or_normalise": (C.c_int, [C.c_int, _D, _D, _D, _D]),
+            "or_ess": (C.c_double, [C.c_int, _D]),
             "or_cdf": (None, [C.c_int, _D, C.c_double, C.c_int, _D]),
             "or_sorted_uniforms": (None, [C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D]),
             "or_ancestors": (None, [C.c_int, _D, _D, _I32]),
@@ -101,6 +102,8 @@ def lib():
             "or_ou_features": (None, [M, _D, _D, C.c_int, _D]),
             "or_propagate_learned": (None, [M, _D, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D,
                                             _D, _D, C.c_int]),
+            "or_propagate_learned_particle": (C.c_double, [M, _D, C.c_uint64, C.c_uint32,
+                                                           C.c_uint32, C.c_int, _D, _D, C.c_int]),
             "or_filter_interval_learned": (C.c_int, [M, _D, C.c_uint64, C.c_uint32, C.c_int,
                                                      C.c_int, _D, _D, _D, _D, _I32, _D, _D, _D,
                                                      C.c_int]),
@@ -273,6 +276,12 @@ def normalise(lw):
     mx, W, s2 = C.c_double(), C.c_double(), C.c_double()
     deg = lib().or_normalise(lw.size, _d(lw), C.byref(mx), C.byref(W), C.byref(s2))
     return mx.value, W.value, s2.value, bool(deg)
+
+
+def ess(lw) -> float:
+    """Effective sample size (sum w)^2 / sum w^2 of the weights exp(lw)."""
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    return float(lib().or_ess(lw.size, _d(lw)))
 
 
 def cdf(lw, mx, degenerate=False) -> np.ndarray:
@@ -465,6 +474,17 @@ def propagate_learned(m: Model, p, seed, filt, t, X, y, bf16_mode=True):
     lib().or_propagate_learned(m.ref, _d(p), C.c_uint64(seed), filt, X.shape[0], t, _d(X),
                                _d(y), _d(dlw), int(bf16_mode))
     return X, dlw
+
+
+def propagate_learned_particle(m: Model, p, seed, filt, index, t, x, y, bf16_mode=True):
+    """Interval t of one particle (Philox counter word 0 = index) under the
+    learned proposal: returns (x', its log increment-density ratio)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    r = lib().or_propagate_learned_particle(m.ref, _d(p), C.c_uint64(seed), filt, index, t,
+                                            _d(x), _d(y), int(bf16_mode))
+    return x, float(r)
 
 
 def filter_interval_learned(m: Model, p, seed, filt, t, X, y, logZ=0.0, bf16_mode=True):

@@ -308,6 +308,14 @@ int or_normalise(int N, const double *lw, double *mx, double *W, double *sumw2) 
   return 0;
 }
 
+/* Effective sample size of the normalised weights, (sum w)^2 / sum w^2
+   (N when no weight is positive: the weights are then taken as uniform). */
+double or_ess(int N, const double *lw) {
+  double mx, W, s2;
+  or_normalise(N, lw, &mx, &W, &s2);
+  return W * W / s2;
+}
+
 /* Cumulative weights C_i = sum_{j<=i} exp(lw_j - mx) (uniform if degenerate). */
 void or_cdf(int N, const double *lw, double mx, int degenerate, double *C) {
   double acc = 0.0;
@@ -527,31 +535,42 @@ double or_bf16(double x) {
 
 static double relu(double a) { return a > 0.0 ? a : 0.0; }
 
-void or_mlp_forward(int in_dim, int out_dim, const double *p, const double *x,
-                    double *h1_out, double *h2_out, double *out, int bf16) {
+/* Forward pass; `rin` rounds inputs and hidden activations, `rw` the
+   parameters (both 0 in FP64 mode, both 1 in bfloat16 mode; a caller that has
+   rounded the parameters once already passes rw = 0, which gives the same
+   values since rounding a bfloat16 number returns it unchanged). */
+static void mlp_forward(int in_dim, int out_dim, const double *p, const double *x,
+                        double *h1_out, double *h2_out, double *out, int rin, int rw) {
   const int H = OR_MLP_HIDDEN;
   const double *W1 = p, *b1 = W1 + H * in_dim, *W2 = b1 + H, *b2 = W2 + H * H;
   const double *W3 = b2 + H, *b3 = W3 + out_dim * H;
   double h1[OR_MLP_HIDDEN], h2[OR_MLP_HIDDEN];
-#define Q(v) (bf16 ? or_bf16(v) : (v))
+#define QI(v) (rin ? or_bf16(v) : (v))
+#define QW(v) (rw ? or_bf16(v) : (v))
   for (int j = 0; j < H; ++j) {
-    double a = Q(b1[j]);
-    for (int i = 0; i < in_dim; ++i) a += Q(W1[j * in_dim + i]) * Q(x[i]);
-    h1[j] = Q(relu(a));
+    double a = QW(b1[j]);
+    for (int i = 0; i < in_dim; ++i) a += QW(W1[j * in_dim + i]) * QI(x[i]);
+    h1[j] = QI(relu(a));
   }
   for (int j = 0; j < H; ++j) {
-    double a = Q(b2[j]);
-    for (int i = 0; i < H; ++i) a += Q(W2[j * H + i]) * h1[i];
-    h2[j] = Q(relu(a));
+    double a = QW(b2[j]);
+    for (int i = 0; i < H; ++i) a += QW(W2[j * H + i]) * h1[i];
+    h2[j] = QI(relu(a));
   }
   for (int c = 0; c < out_dim; ++c) {
-    double a = Q(b3[c]);
-    for (int i = 0; i < H; ++i) a += Q(W3[c * H + i]) * h2[i];
+    double a = QW(b3[c]);
+    for (int i = 0; i < H; ++i) a += QW(W3[c * H + i]) * h2[i];
     out[c] = a;
   }
-#undef Q
+#undef QI
+#undef QW
   if (h1_out) memcpy(h1_out, h1, sizeof h1);
   if (h2_out) memcpy(h2_out, h2, sizeof h2);
+}
+
+void or_mlp_forward(int in_dim, int out_dim, const double *p, const double *x,
+                    double *h1_out, double *h2_out, double *out, int bf16) {
+  mlp_forward(in_dim, out_dim, p, x, h1_out, h2_out, out, bf16, bf16);
 }
 
 /* Reverse-mode derivative of dout . out, layer by layer (chain rule; the
@@ -650,6 +669,7 @@ void or_ou_features(const or_model *m, const double *x, const double *y, int k,
 
 /* u_theta for every state component at step k (FHN: out 0 drives v, out 1
    drives w of the node; OU: the single output). */
+/* (p is already rounded to bfloat16 in bfloat16 mode) */
 static void learned_drift(const or_model *m, const double *p, const double *x,
                           const double *y, const int *nearest, int k, double *u,
                           int bf16) {
@@ -658,15 +678,52 @@ static void learned_drift(const or_model *m, const double *p, const double *x,
     int nn = m->J * m->J;
     for (int n = 0; n < nn; ++n) {
       or_fhn_features(m, x, y, nearest, k, n, feat);
-      or_mlp_forward(22, 2, p, feat, NULL, NULL, o, bf16);
+      mlp_forward(22, 2, p, feat, NULL, NULL, o, bf16, 0);
       u[n] = o[0];
       u[nn + n] = o[1];
     }
   } else {
     or_ou_features(m, x, y, k, feat);
-    or_mlp_forward(3, 1, p, feat, NULL, NULL, o, bf16);
+    mlp_forward(3, 1, p, feat, NULL, NULL, o, bf16, 0);
     u[0] = o[0];
   }
+}
+
+/* One particle (Philox counter word 0 = index) through interval t under the
+   learned proposal; returns the sum of its log increment-density ratios.
+   pr: the parameters (rounded to bfloat16 in bfloat16 mode), nearest: each
+   node's nearest observation (FH-N; NULL otherwise). */
+static double propagate_learned_one(const or_model *m, const double *pr, const uint32_t key[2],
+                                    uint32_t filter, uint32_t index, int t, double *x,
+                                    const double *y, const int *nearest, int bf16) {
+  int d = m->dx;
+  int half = (m->kind == OR_FHN) ? m->J * m->J : d;
+  double *z = (double *)malloc(sizeof(double) * (size_t)d);
+  double *f = (double *)malloc(sizeof(double) * (size_t)d);
+  double *u = (double *)malloc(sizeof(double) * (size_t)d);
+  const double sh = sqrt(m->h);
+  double acc = 0.0;
+  for (int s = 0; s < m->S; ++s) {
+    uint32_t n = (uint32_t)((t - 1) * m->S + s);
+    or_step_noise(m, key, OR_P_PROP, index, filter, n, z);
+    or_drift(m, x, f);
+    learned_drift(m, pr, x, y, nearest, s, u, bf16);
+    for (int c = 0; c < d; ++c) {
+      double sd = (c < half) ? m->sd[0] : m->sd[1];
+      x[c] = (x[c] + m->h * (f[c] + u[c])) + sd * sh * z[c];
+      acc += -(sh / sd) * u[c] * z[c] - (m->h / (2.0 * sd * sd)) * u[c] * u[c];
+    }
+  }
+  free(z); free(f); free(u);
+  return acc;
+}
+
+/* The parameters as the network uses them: rounded once in bfloat16 mode. */
+static double *learned_params(const or_model *m, const double *p, int bf16) {
+  int np = (m->kind == OR_FHN) ? or_mlp_nparams(22, 2) : or_mlp_nparams(3, 1);
+  double *pr = (double *)malloc(sizeof(double) * (size_t)np);
+  for (int i = 0; i < np; ++i) pr[i] = bf16 ? or_bf16(p[i]) : p[i];
+  return pr;
 }
 
 void or_propagate_learned(const or_model *m, const double *p, uint64_t seed,
@@ -674,33 +731,32 @@ void or_propagate_learned(const or_model *m, const double *p, uint64_t seed,
                           const double *y, double *dlw, int bf16) {
   uint32_t key[2];
   or_key(seed, key);
-  int d = m->dx;
-  int half = (m->kind == OR_FHN) ? m->J * m->J : d;
-  double *z = (double *)malloc(sizeof(double) * (size_t)d);
-  double *f = (double *)malloc(sizeof(double) * (size_t)d);
-  double *u = (double *)malloc(sizeof(double) * (size_t)d);
   int *nearest = NULL;
   if (m->kind == OR_FHN) {
-    nearest = (int *)malloc(sizeof(int) * (size_t)half);
+    nearest = (int *)malloc(sizeof(int) * (size_t)(m->J * m->J));
     or_nearest_obs(m, nearest);
   }
-  const double sh = sqrt(m->h);
-  for (int i = 0; i < N; ++i) {
-    double *x = X + (size_t)i * d, acc = 0.0;
-    for (int s = 0; s < m->S; ++s) {
-      uint32_t n = (uint32_t)((t - 1) * m->S + s);
-      or_step_noise(m, key, OR_P_PROP, (uint32_t)i, filter, n, z);
-      or_drift(m, x, f);
-      learned_drift(m, p, x, y, nearest, s, u, bf16);
-      for (int c = 0; c < d; ++c) {
-        double sd = (c < half) ? m->sd[0] : m->sd[1];
-        x[c] = (x[c] + m->h * (f[c] + u[c])) + sd * sh * z[c];
-        acc += -(sh / sd) * u[c] * z[c] - (m->h / (2.0 * sd * sd)) * u[c] * u[c];
-      }
-    }
-    dlw[i] = acc;
+  double *pr = learned_params(m, p, bf16);
+  for (int i = 0; i < N; ++i)
+    dlw[i] = propagate_learned_one(m, pr, key, filter, (uint32_t)i, t, X + (size_t)i * m->dx, y,
+                                   nearest, bf16);
+  free(pr); free(nearest);
+}
+
+double or_propagate_learned_particle(const or_model *m, const double *p, uint64_t seed,
+                                     uint32_t filter, uint32_t index, int t, double *x,
+                                     const double *y, int bf16) {
+  uint32_t key[2];
+  or_key(seed, key);
+  int *nearest = NULL;
+  if (m->kind == OR_FHN) {
+    nearest = (int *)malloc(sizeof(int) * (size_t)(m->J * m->J));
+    or_nearest_obs(m, nearest);
   }
-  free(z); free(f); free(u); free(nearest);
+  double *pr = learned_params(m, p, bf16);
+  double r = propagate_learned_one(m, pr, key, filter, index, t, x, y, nearest, bf16);
+  free(pr); free(nearest);
+  return r;
 }
 
 int or_filter_interval_learned(const or_model *m, const double *p, uint64_t seed,

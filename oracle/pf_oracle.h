@@ -100,6 +100,8 @@ void or_weights(const or_model *m, int N, const double *X, const double *y,
                 double *lw);
 /* returns mx, W = sum exp(lw-mx), sumw2 = sum exp(2(lw-mx)); degenerate flag */
 int or_normalise(int N, const double *lw, double *mx, double *W, double *sumw2);
+/* effective sample size (sum w)^2 / sum w^2 of the weights exp(lw) */
+double or_ess(int N, const double *lw);
 void or_cdf(int N, const double *lw, double mx, int degenerate, double *C);
 void or_sorted_uniforms(uint64_t seed, uint32_t filter, int t, int N, double *U);
 void or_ancestors(int N, const double *C, const double *U, int32_t *A);
@@ -178,6 +180,11 @@ void or_ou_features(const or_model *m, const double *x, const double *y, int k,
 void or_propagate_learned(const or_model *m, const double *p, uint64_t seed,
                           uint32_t filter, int N, int t, double *X,
                           const double *y, double *dlw, int bf16);
+/* The same draw for one particle (Philox counter word 0 = index), in place on
+   x[dx]; returns its log increment-density ratio. */
+double or_propagate_learned_particle(const or_model *m, const double *p, uint64_t seed,
+                                     uint32_t filter, uint32_t index, int t, double *x,
+                                     const double *y, int bf16);
 /* One full interval of one filter under the learned proposal (as
    or_filter_interval). */
 int or_filter_interval_learned(const or_model *m, const double *p, uint64_t seed,

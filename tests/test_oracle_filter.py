@@ -154,3 +154,98 @@ def test_ensemble_is_equal_weight_average(orc):
             acc[t - 1] += r["mean_post"] / 3
         assert lz == pytest.approx(logZ[f], rel=1e-12)
     assert np.allclose(acc, est, rtol=1e-12, atol=1e-12)
+
+
+# ---- pins of the prior draw's scale and of the effective sample size ------
+# (Algorithm 1 step 1, eq. (eqPrior): x_0 ~ tau_0 = N(mean, diag(sd^2)).)
+
+def _chi2_ratio_ok(s2, var, dof, z=5.0):
+    """Sample variance with `dof` degrees of freedom against its law:
+    dof s2 / var ~ chi^2(dof), i.e. s2 / var = 1 +- z sqrt(2 / dof)."""
+    return abs(s2 / var - 1.0) <= z * np.sqrt(2.0 / dof)
+
+
+@pytest.mark.parametrize("spec", [
+    pf_inputs.ou1d(sd=0.5, prior_mean=3.0, prior_sd=0.5),
+    dict(pf_inputs.lorenz63(), prior_sd=[0.5, 2.0, 3.0]),
+])
+def test_prior_draw_scale(orc, spec):
+    """The per-component sample variance of 2e5 prior draws equals prior_sd^2
+    within chi-square bounds (a draw scaled by sd^2 or by another component's
+    sd fails), the means are the prior means, and the components are
+    uncorrelated."""
+    m = orc.Model(spec)
+    N = 200_000
+    X = orc.init(m, 123, 5, N)
+    mu = np.asarray(spec["prior_mean"])
+    sd = np.asarray(spec["prior_sd"])
+    for c in range(m.dx):
+        s2 = X[:, c].var(ddof=1)
+        assert _chi2_ratio_ok(s2, sd[c] ** 2, N - 1), (c, s2, sd[c] ** 2)
+        assert abs(X[:, c].mean() - mu[c]) < 5 * sd[c] / np.sqrt(N)
+    if m.dx > 1:
+        r = np.corrcoef(X.T)
+        assert np.all(np.abs(r[~np.eye(m.dx, dtype=bool)]) < 5 / np.sqrt(N))
+
+
+def test_prior_draw_scale_fhn_grid(orc):
+    """FH-N 4 x 4 grid, prior sd 0.05 on v and w around the stimulus pattern:
+    pooled chi-square of the 32 component variances, and the v/w lanes of one
+    Philox call independent."""
+    spec = pf_inputs.fhn(4)
+    m = orc.Model(spec)
+    N = 20_000
+    X = orc.init(m, 7, 1, N)
+    mu = np.asarray(spec["prior_mean"])
+    dev = (X - mu) / 0.05
+    pooled = (dev ** 2).sum() / (N * m.dx)
+    assert _chi2_ratio_ok(pooled, 1.0, N * m.dx)
+    assert np.all(np.abs(dev.mean(0)) < 5 / np.sqrt(N))
+    # v and w of node 0 come from lanes 0 and 1 of the same call
+    assert abs(np.corrcoef(X[:, 0], X[:, 16])[0, 1]) < 5 / np.sqrt(N)
+
+
+def test_prior_predictive_variance_ou(orc):
+    """N particles of one filter propagated without resampling from the
+    prior: after t intervals the sample variance is the closed form
+    a^2 var + q of the discrete OU recursion (pins the prior's scale together
+    with the Euler noise)."""
+    spec = pf_inputs.ou1d(theta=1.0, sd=0.5, h=0.01, S=10, prior_mean=3.0, prior_sd=0.5)
+    m = orc.Model(spec)
+    N = 200_000
+    X = orc.init(m, 9, 0, N)
+    phi = 1 - 0.01
+    a = phi ** 10
+    q = sum(0.5 ** 2 * 0.01 * phi ** (2 * i) for i in range(10))
+    var, mean = 0.25, 3.0
+    for t in range(1, 4):
+        X = orc.propagate(m, 9, 0, t, X)
+        var = a * a * var + q
+        mean = a * mean
+        assert _chi2_ratio_ok(X[:, 0].var(ddof=1), var, N - 1), (t, X[:, 0].var(), var)
+        assert abs(X[:, 0].mean() - mean) < 5 * np.sqrt(var / N)
+
+
+def test_ess_hand_values(orc):
+    """ESS = (sum w)^2 / sum w^2 on hand-computed weight vectors with N > 1."""
+    with np.errstate(divide="ignore"):
+        assert orc.ess(np.log([1.0, 1.0, 0.0, 0.0])) == pytest.approx(2.0, rel=1e-15)
+    assert orc.ess(np.log([1.0, 2.0, 3.0])) == pytest.approx(36.0 / 14.0, rel=1e-14)
+    assert orc.ess(np.zeros(7)) == pytest.approx(7.0, rel=1e-15)
+    assert orc.ess(np.array([0.0, -800.0, -900.0])) == pytest.approx(1.0, rel=1e-15)
+    # invariant to a common shift of the log-weights
+    lw = np.log([0.5, 0.25, 0.125, 0.125])
+    e = orc.ess(lw)
+    assert e == pytest.approx(1.0 / (0.25 + 0.0625 + 2 * 0.015625), rel=1e-14)
+    assert orc.ess(lw - 1000.0) == pytest.approx(e, rel=1e-14)
+    # no positive weight: uniform, ESS = N
+    assert orc.ess(np.full(5, -np.inf)) == pytest.approx(5.0)
+
+
+def test_filter_interval_reports_the_ess_of_its_weights(orc):
+    m = orc.Model(pf_inputs.lorenz63())
+    _, y = orc.simulate(m, 4, 1)
+    X = orc.init(m, 3, 0, 64)
+    r = orc.filter_interval(m, 3, 0, 1, X, y[0])
+    assert 1.0 < r["ess"] < 64.0
+    assert r["ess"] == pytest.approx(orc.ess(r["lw"]), rel=1e-14)
