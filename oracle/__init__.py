@@ -250,6 +250,14 @@ def init(m: Model, seed, filt, N) -> np.ndarray:
     return X
 
 
+def prior_particle(m: Model, seed, filt, index) -> np.ndarray:
+    """The prior draw x_0 of particle `index` of filter `filt` (Philox counter
+    word 0 = index), as or_init draws it."""
+    x = np.zeros(m.dx)
+    lib().or_prior_draw(m.ref, _u32(key(seed)), P_INIT, index, filt, _d(x))
+    return x
+
+
 def propagate(m: Model, seed, filt, t, X) -> np.ndarray:
     X = np.array(X, dtype=np.float64, order="C", copy=True)
     lib().or_propagate(m.ref, C.c_uint64(seed), filt, X.shape[0], t, _d(X))

@@ -4,9 +4,10 @@
 //
 // Each filter's N log-weights are cut into tiles of 4096 (256 threads x 16
 // consecutive elements).  The CDF is held in two levels: a tile-local
-// inclusive scan Cl (FP64) and per-tile offsets coff, with coff[q+1] =
-// coff[q] + Cl[last of tile q], so C_i = coff[tile(i)] + Cl[i] agrees exactly
-// with the offsets at every tile boundary.  The exponential spacings use the
+// inclusive scan Cl (FP64) and per-tile offsets coff, folded in tile order so
+// that coff[q+1] = coff[q] + Cl[last of tile q] holds exactly (the same FP64
+// addition): C_i = coff[tile(i)] + Cl[i] is non-decreasing across every tile
+// boundary and equals the next tile's offset at the last element of a tile.  The exponential spacings use the
 // same two-level layout (Sl, soff).  Uniforms come from exponential spacings:
 // E_j = -ln u_j (j = 0..N), S_k = sum_{j<=k} E_j, U_k = S_k / S_N, which are
 // the order statistics of N uniforms, so the ancestors come out ascending.
@@ -115,37 +116,50 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
 }
 
 // Per filter (one workgroup): tile offsets of the CDF and of the exponential
-// sums by a chunked block scan in tile order, the normaliser, ESS and the
-// log G_t^N update of (eqGtN): log G += mx + log(W / N) - (d_y/2) log(2 pi s^2).
+// sums, the normaliser, ESS and the log G_t^N update of (eqGtN):
+// log G += mx + log(W / N) - (d_y/2) log(2 pi s^2).  The offsets are folded
+// in tile order by one thread, coff[q+1] = coff[q] + Cl[last of tile q] with
+// the very additions the searches repeat, so the two-level CDF is
+// non-decreasing across every tile boundary (a tree-ordered scan could leave
+// an offset one rounding above or below that sum, and a search could then
+// pick a zero-weight particle at a boundary).  The workgroup stages chunks of
+// the tile records in LDS for it.
+constexpr int FOLD_CHUNK = 1024;
 __global__ void __launch_bounds__(256)
 k_filter_reduce(int N, int T, double lognorm, const double *__restrict__ tile,
                 double *__restrict__ coff, double *__restrict__ soff,
                 double *__restrict__ fstat) {
   __shared__ double shd[8];
   __shared__ float shf[8];
+  __shared__ double cbuf[FOLD_CHUNK], ebuf[FOLD_CHUNK];
   const int m = blockIdx.x;
   const double *rec = tile + (size_t)m * T * TREC;
   double *co = coff + (size_t)m * (T + 1), *so = soff + (size_t)m * (T + 1);
   float lm = -INFINITY;
-  for (int q = threadIdx.x; q < T; q += blockDim.x) lm = fmaxf(lm, (float)rec[(size_t)q * TREC]);
-  const double mx = (double)block_max(lm, shf);
-  double cc = 0.0, sc = 0.0, s2 = 0.0;
-  for (int base = 0; base < T; base += blockDim.x) {
-    const int q = base + threadIdx.x;
-    const double c = q < T ? rec[(size_t)q * TREC + 1] : 0.0;
-    const double e = q < T ? rec[(size_t)q * TREC + 3] : 0.0;
-    if (q < T) s2 += rec[(size_t)q * TREC + 2];
-    double ct, et;
-    const double cx = block_exscan(c, shd, &ct);
-    const double ex = block_exscan(e, shd, &et);
-    if (q < T) {
-      co[q] = cc + cx;
-      so[q] = sc + ex;
-    }
-    cc += ct;
-    sc += et;
+  double s2 = 0.0;
+  for (int q = threadIdx.x; q < T; q += blockDim.x) {
+    lm = fmaxf(lm, (float)rec[(size_t)q * TREC]);
+    s2 += rec[(size_t)q * TREC + 2];
   }
+  const double mx = (double)block_max(lm, shf);
   s2 = block_sum(s2, shd);
+  double cc = 0.0, sc = 0.0;  // thread 0's running offsets
+  for (int base = 0; base < T; base += FOLD_CHUNK) {
+    const int n = min(FOLD_CHUNK, T - base);
+    __syncthreads();  // the previous chunk has been folded
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      cbuf[j] = rec[(size_t)(base + j) * TREC + 1];
+      ebuf[j] = rec[(size_t)(base + j) * TREC + 3];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int j = 0; j < n; ++j) {
+        co[base + j] = cc;
+        so[base + j] = sc;
+        cc += cbuf[j];
+        sc += ebuf[j];
+      }
+  }
   if (threadIdx.x == 0) {
     co[T] = cc;
     so[T] = sc;
@@ -240,7 +254,9 @@ k_ancestors(int N, int T, const double *__restrict__ Cl, const double *__restric
 // thread finds the tile by bisection over the offsets in LDS (the offset
 // after tile q is C at its last element), then bisects within that tile;
 // the others gallop onward.  The result is the same smallest i with
-// C_i > U_k C_{N-1} (clamped to N - 1).
+// C_i > U_k C_{N-1} (clamped to N - 1): the offset after tile q is exactly
+// coff[q] + Cl[last of q], the value the search inside tile q compares, so
+// the tile chosen always holds the answer.
 constexpr int ANC_PER_THREAD = 4, ANC_SPAN = TILE_THREADS * ANC_PER_THREAD;
 constexpr int ANC_LDS_TILES = 4096;  // tile offsets held in LDS: N <= 4096 * TILE
 

@@ -51,12 +51,13 @@ def test_workspace_bytes_and_validation(pf):
     assert st2 == 0 and n2 > n + (1 << 20) * 3 * 4 * 2
     bad = dict(l63, obs_idx=[0, 7])
     assert _bytes(pf, [bad], [(0, 1, 8, 0, 1)])[0] == 1
+    assert "obs_index[1] out of range" in pf.lib().pf_last_error().decode()
     assert _bytes(pf, [l63], [(0, 0, 8, 0, 1)])[0] == 1
     assert _bytes(pf, [l63], [(1, 1, 8, 0, 1)])[0] == 1
     assert _bytes(pf, [l63], [(0, 1, 8, 5, 1)])[0] == 1
     assert _bytes(pf, [dict(l63, obs_var=0.0)], [(0, 1, 8, 0, 1)])[0] == 1
     assert _bytes(pf, [dict(l63, dx=4)], [(0, 1, 8, 0, 1)])[0] == 1
-    assert "obs_index" in pf.lib().pf_last_error().decode() or True
+    assert "state_dim 3" in pf.lib().pf_last_error().decode()
 
 
 def test_learned_flag_validation(pf):

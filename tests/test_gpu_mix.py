@@ -175,3 +175,77 @@ def test_grid_chain_stream_changes_nothing(pf, torch_mod, observations):
             assert np.array_equal(a, b, equal_nan=True), f"ensemble {e}"
     for a, b in zip(est0, est1):
         assert np.array_equal(a, b, equal_nan=True)
+
+
+def _oracle_interval(orc, f, e, t, x_in, y_t):
+    """Interval t of batch member e against the oracle, from the particles
+    x_in [M, N, dx] it started from: states and log-weights within 1e-5
+    relative, ancestors equal outside the 1e-6 CDF band on the GPU's own
+    log-weights.  Returns the member's pre-resampling particles [M, N, dx]
+    and ancestors."""
+    from pf_testlib import assert_rel_close, band_mask, vec_to_oracle
+    mi, M, N, seed = ENSEMBLES[e]
+    spec = SPECS[mi]
+    m = orc.Model(spec)
+    grid = spec["kind"] == "fhn"
+    xb = f.get_predicted(e).cpu().numpy()
+    if not grid:
+        xb = vec_to_oracle(xb)
+    lw = f.get_logweights(e).cpu().numpy()
+    A = f.get_ancestors(e).cpu().numpy()
+    yd = y_t.astype(np.float64)
+    n_diff = 0
+    for k in range(M):
+        ref = orc.propagate(m, seed, k, t, x_in[k].astype(np.float64))
+        assert_rel_close(xb[k], ref, floor=0.1 if grid else 1.0,
+                         what=f"member {e} filter {k} interval {t} states")
+        assert_rel_close(lw[k], orc.weights(m, ref, yd), floor=1.0,
+                         what=f"member {e} filter {k} interval {t} log-weights")
+        Ao, Co, Uo, _ = orc.resample(seed, k, t, lw[k].astype(np.float64))
+        assert not ((A[k] != Ao) & ~band_mask(Co, Uo)).any(), (e, k, t)
+        n_diff += int((A[k] != Ao).sum())
+    assert n_diff <= max(2, 1e-5 * M * N), (e, n_diff)
+    return xb, A
+
+
+@pytest.mark.parametrize("plan", ["autotuned", "autotuned_graph",
+                                  {"vec_single_kernel": 1, "prop_tile": 256, "resample_bd_min": 256,
+                                   "grid_blocks_per_cu": 0},
+                                  {"vec_single_kernel": 0, "prop_tile": 64, "resample_bd_min": 64,
+                                   "grid_blocks_per_cu": 1}])
+def test_batch_members_match_oracle(pf, orc, torch_mod, observations, plan):
+    """Every member of the uneven batch (Lorenz filters of every size class:
+    single workgroup, small-workgroup resampling, tiled; FH-N grids of two
+    sizes in batched launches; OU) against the oracle over two intervals, under
+    the autotuner's plan (launched directly and with the second interval
+    replayed from the captured graph), the single-kernel Lorenz path and the
+    small-workgroup resampler (Definition 3: each filter is independent of
+    the batch it runs in)."""
+    from pf_testlib import vec_to_oracle
+    graph = plan == "autotuned_graph"
+    y_all = torch_mod.from_numpy(np.ascontiguousarray(np.concatenate(observations, axis=1))).cuda()
+    f = pf.ParticleFilter(SPECS, ENSEMBLES, fused=True, graph=graph)
+    if isinstance(plan, dict):
+        f.set_tuning(plan)
+    else:
+        f.autotune(y_all[0], reps=2)
+        assert f.interval() == 1
+    print(f"plan {plan}: {f.tuning()}", flush=True)
+    x0 = []
+    for e, (mi, M, N, seed) in enumerate(ENSEMBLES):
+        x = f.get_particles(e).cpu().numpy()
+        x0.append(x if SPECS[mi]["kind"] == "fhn" else vec_to_oracle(x))
+    if graph:
+        f.set_observations(y_all)
+    f.step(None if graph else y_all[0])
+    f.sync()
+    x_in = []
+    for e in range(len(ENSEMBLES)):
+        xb, A = _oracle_interval(orc, f, e, 1, x0[e], observations[e][0])
+        x_in.append(np.stack([xb[k][A[k]] for k in range(xb.shape[0])]))
+    # interval 2: a graph replay when graph is set (the first interval ran
+    # directly: graphs replay from pending ancestors)
+    f.step(None if graph else y_all[1])
+    f.sync()
+    for e in range(len(ENSEMBLES)):
+        _oracle_interval(orc, f, e, 2, x_in[e], observations[e][1])
