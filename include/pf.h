@@ -361,6 +361,11 @@ pf_status pf_read_profile(pf_ctx *ctx, double *out_ms, int64_t *out_launches);
 /* Block until all work of the context's last stream is done; reports an
    asynchronous device error as PF_ERR_DEVICE. */
 pf_status pf_sync(pf_ctx *ctx);
+/* Wait for the context's queued work (on the last stream it was given and on
+   its own streams), then release its streams, events and captured graphs and
+   the host struct.  The caller's workspace may be freed afterwards.  Call it
+   while the HIP runtime is alive (not from a static destructor that runs
+   after the runtime's own teardown).  NULL is a no-op. */
 void pf_destroy(pf_ctx *ctx);
 const char *pf_status_str(pf_status s);
 const char *pf_last_error(void);

@@ -11,8 +11,10 @@ J, S, h, params, noise_sd, obs_idx, obs_var, prior_mean, prior_sd.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -166,6 +168,22 @@ class PFModel:
             self.prior_sd.ctypes.data_as(C.POINTER(C.c_double)))
 
 
+# Contexts still open.  They are closed by an exit handler, which runs
+# before the interpreter tears its modules down and before the HIP runtime's
+# own exit-time teardown, so that no context is destroyed from a finaliser
+# after the runtime has gone.
+_LIVE: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for f in list(_LIVE):
+        try:
+            f.close()
+        except Exception:
+            pass
+
+
 class ParticleFilter:
     """A context of one or more ensembles of independent bootstrap filters.
 
@@ -198,15 +216,20 @@ class ParticleFilter:
         _check(lib().pf_init(self._md, nm, self._ed, ne, self.options, self._ws,
                              nbytes.value, _stream(stream), C.byref(ctx)))
         self._ctx = ctx
+        _LIVE.add(self)
 
-    def __del__(self):
+    def close(self):
+        """Release the context (waits for its queued work); idempotent."""
         ctx = getattr(self, "_ctx", None)
         if ctx is not None and ctx.value:
-            try:
-                lib().pf_destroy(ctx)
-            except Exception:
-                pass
-            self._ctx = None
+            lib().pf_destroy(ctx)
+        self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     # ---- shapes ------------------------------------------------------------
     def dims(self, e: int):

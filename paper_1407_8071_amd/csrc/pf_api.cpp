@@ -1571,7 +1571,16 @@ pf_status pf_sync(pf_ctx *ctx) {
   return PF_OK;
 }
 
-void pf_destroy(pf_ctx *ctx) { delete ctx; }
+void pf_destroy(pf_ctx *ctx) {
+  if (!ctx) return;
+  // wait for everything the context queued before its streams, events and
+  // graphs go: the caller's last stream (which a replayed graph and the
+  // joined side stream end on) and the context's own streams
+  if (ctx->last_stream) (void)hipStreamSynchronize(ctx->last_stream);
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+  if (ctx->cap_stream) (void)hipStreamSynchronize(ctx->cap_stream);
+  delete ctx;
+}
 
 const char *pf_status_str(pf_status s) {
   switch (s) {
