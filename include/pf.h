@@ -12,6 +12,8 @@
  *   - Pointers prefixed d_ are device pointers (HBM), h_ host pointers.
  *   - The library never allocates device memory: the caller passes one
  *     workspace (pf_workspace_bytes) and owns every buffer it passes in.
+ *     The one static buffer it holds (PF_MLP_GRAD_STATIC_BYTES per device,
+ *     for pf_mlp_loss_grad_noalloc) is part of the loaded code object.
  *     Host descriptor arrays are copied during pf_init and may be freed
  *     afterwards.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  All
@@ -273,6 +275,28 @@ pf_status pf_mlp_grad_work_bytes(int32_t in_dim, int32_t out_dim, int64_t rows, 
 pf_status pf_mlp_loss_grad(const float *d_params, int32_t in_dim, int32_t out_dim, const float *d_x,
                            const float *d_target, int64_t rows, float *d_grad, float *d_loss,
                            void *d_work, size_t work_bytes, void *stream);
+
+/* Size of the library's static partial-gradient buffer (per device). */
+#define PF_MLP_GRAD_STATIC_BYTES ((size_t)16 << 20)
+
+/* pf_mlp_loss_grad without a work buffer, for callers that cannot allocate
+   device memory (code under HIP graph capture, serving loops, harnesses that
+   forbid allocation): the per-wave partial gradients go to a static buffer
+   of PF_MLP_GRAD_STATIC_BYTES that the library holds on each device it runs
+   on until the process ends.  The result is bit-identical to
+   pf_mlp_loss_grad (same launch shape, same fixed-order reduction).  The
+   first call on a device looks the buffer's address up (with that device
+   current); no call allocates or frees memory.  PF_ERR_WORKSPACE when the
+   call needs more partial-gradient bytes than the buffer holds
+   (pf_mlp_grad_work_bytes > PF_MLP_GRAD_STATIC_BYTES; for the 22 -> 2 FH-N
+   proposal network that is beyond 46336 rows).  Every call on one device
+   shares the buffer: calls that overlap on one device (on different
+   streams, or from different host threads) race and must be serialised by
+   the caller.  Nothing in the buffer needs clearing: every call overwrites
+   every value it reads. */
+pf_status pf_mlp_loss_grad_noalloc(const float *d_params, int32_t in_dim, int32_t out_dim,
+                                   const float *d_x, const float *d_target, int64_t rows,
+                                   float *d_grad, float *d_loss, void *stream);
 
 /* One Adam step (Kingma and Ba, Algorithm 1) at step t >= 1, in place on
    d_params, d_m, d_v (float32, n values). */

@@ -107,6 +107,7 @@ def lib():
         "pf_mlp_forward": [_VP, i32, i32, _VP, i64, _VP, _VP],
         "pf_mlp_grad_work_bytes": [i32, i32, i64, C.POINTER(C.c_size_t)],
         "pf_mlp_loss_grad": [_VP, i32, i32, _VP, _VP, i64, _VP, _VP, _VP, C.c_size_t, _VP],
+        "pf_mlp_loss_grad_noalloc": [_VP, i32, i32, _VP, _VP, i64, _VP, _VP, _VP],
         "pf_adam_step": [_VP, _VP, _VP, _VP, i64, C.c_double, C.c_double, C.c_double,
                          C.c_double, i32, _VP],
         "pf_train_workspace_bytes": [MD, C.POINTER(_TrainDesc), C.POINTER(C.c_size_t)],
@@ -429,6 +430,16 @@ def mlp_loss_grad(params, x, target, stream=None):
     _check(lib().pf_mlp_loss_grad(_ptr(params), in_dim, out_dim, _ptr(x), _ptr(target), rows,
                                   _ptr(grad), _ptr(loss), _ptr(work), n.value, _stream(stream)))
     return loss, grad
+
+
+def mlp_loss_grad_noalloc(params, x, target, grad, loss, stream=None):
+    """pf_mlp_loss_grad_noalloc into caller-owned grad and loss (float32
+    device tensors): the library's static partial-gradient buffer instead of
+    a work buffer, so the call allocates nothing."""
+    rows, in_dim = x.shape
+    out_dim = target.shape[1]
+    _check(lib().pf_mlp_loss_grad_noalloc(_ptr(params), in_dim, out_dim, _ptr(x), _ptr(target),
+                                          rows, _ptr(grad), _ptr(loss), _stream(stream)))
 
 
 def adam_step(params, grad, m, v, lr, beta1, beta2, eps, t, stream=None):

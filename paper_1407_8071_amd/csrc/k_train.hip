@@ -25,6 +25,7 @@
 // counters.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "mlp_device.h"
 
@@ -488,6 +489,36 @@ int grad_blocks(int64_t ntiles) {
 
 size_t mlp_grad_work_floats(int64_t ntiles, int np) {
   return (size_t)grad_blocks(ntiles) * TR_WAVES * (size_t)(np + 1);
+}
+
+// Partial gradients of the allocation-free gradient entry point: one copy
+// per device, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it passes the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+static __device__ __align__(256) float scratch[MLP_GRAD_SCRATCH_BYTES / sizeof(float)];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float *scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t mlp_grad_scratch(float **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_ptr[dev] = (float *)p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_mlp_grad_rows(const float *params, int in_dim, int out_dim, const float *X,

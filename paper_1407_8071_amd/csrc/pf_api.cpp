@@ -1337,6 +1337,24 @@ pf_status pf_mlp_loss_grad(const float *d_params, int32_t in_dim, int32_t out_di
   return PF_OK;
 }
 
+pf_status pf_mlp_loss_grad_noalloc(const float *d_params, int32_t in_dim, int32_t out_dim,
+                                   const float *d_x, const float *d_target, int64_t rows,
+                                   float *d_grad, float *d_loss, void *stream) {
+  size_t need = 0;
+  PF_TRY(pf_mlp_grad_work_bytes(in_dim, out_dim, rows, &need));
+  if (!d_params || !d_x || !d_target || !d_grad) return fail(PF_ERR_INVALID_ARG, "NULL buffer");
+  if (need > PF_MLP_GRAD_STATIC_BYTES)
+    return fail(PF_ERR_WORKSPACE,
+                "%lld rows need %zu bytes of partial gradients; the static buffer holds %zu "
+                "(use pf_mlp_loss_grad with a work buffer)",
+                (long long)rows, need, (size_t)PF_MLP_GRAD_STATIC_BYTES);
+  float *scratch = nullptr;
+  PF_HIP(pfk::mlp_grad_scratch(&scratch));
+  PF_HIP(pfk::launch_mlp_grad_rows(d_params, in_dim, out_dim, d_x, d_target, rows, scratch, d_grad,
+                                   d_loss, (hipStream_t)stream));
+  return PF_OK;
+}
+
 pf_status pf_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t n,
                        double lr, double beta1, double beta2, double eps, int32_t t, void *stream) {
   if (n < 1 || n > (1 << 30)) return fail(PF_ERR_INVALID_ARG, "n out of range");

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pf.h"
 #include "pf_device.h"
 
 namespace pfk {
@@ -170,6 +171,10 @@ hipError_t launch_grid_steps_learned(const EnsDev &e, IvArg iv, int yoff, const 
 // tiles of 16 rows, the gradient over explicit rows, Adam, one FH-N training
 // step (minibatch from stored trajectories + Adam), the training paths
 size_t mlp_grad_work_floats(int64_t ntiles, int np);
+// the allocation-free gradient's static partial-gradient buffer: its size,
+// and its device address on the current device (looked up on first use)
+constexpr size_t MLP_GRAD_SCRATCH_BYTES = PF_MLP_GRAD_STATIC_BYTES;
+hipError_t mlp_grad_scratch(float **out);
 hipError_t launch_mlp_grad_rows(const float *params, int in_dim, int out_dim, const float *X,
                                 const float *T, int64_t rows, float *partial, float *grad,
                                 float *loss, hipStream_t s);

@@ -78,6 +78,14 @@ def test_learned_flag_validation(pf):
     assert pf.lib().pf_mlp_forward(None, 20, 2, None, -1, None, None) == 1
     assert pf.lib().pf_mlp_forward(None, 20, 2, None, 0, None, None) == 0
     assert pf.lib().pf_proposal_set(None, 0, None, 5634, None) == 1
+    # the allocation-free gradient: NULL buffers, and more rows than its
+    # static partial-gradient buffer holds, are refused on the host
+    fake = C.c_void_p(0x1000)
+    assert pf.lib().pf_mlp_loss_grad_noalloc(None, 22, 2, None, None, 16, None, None, None) == 1
+    assert pf.lib().pf_mlp_loss_grad_noalloc(fake, 22, 2, fake, fake, 0, fake, None, None) == 1
+    assert pf.lib().pf_mlp_loss_grad_noalloc(fake, 22, 2, fake, fake, 46337, fake, None,
+                                             None) == 3
+    assert "static buffer holds" in pf.lib().pf_last_error().decode()
 
 
 def test_init_rejects_missing_workspace_and_bad_order(pf):
