@@ -90,6 +90,17 @@ def lib():
             "or_filter_interval": (C.c_int, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D, _D,
                                              _D, _D, _I32, _D, _D, _D]),
             "or_run_ensemble": (None, [M, C.c_uint64, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D, _D]),
+            "or_systematic_uniforms": (None, [C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D]),
+            "or_stratified_uniforms": (None, [C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D]),
+            "or_residual_ancestors": (None, [C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D,
+                                             C.c_double, C.c_int, _I32]),
+            "or_resample_scheme": (None, [C.c_int, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D,
+                                          _I32]),
+            "or_apf_interval": (C.c_int, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D, _D,
+                                          _D, _D, C.c_int, _D, _I32, _D, _D]),
+            "or_filter_interval_sched": (C.c_int, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D,
+                                                   _D, _D, _D, C.c_int, C.c_double, _D, _I32, _D,
+                                                   _D, _D, C.POINTER(C.c_int)]),
             "or_simulate": (None, [M, C.c_uint64, C.c_int, _D, _D]),
             "or_kalman_ou": (C.c_double, [M, C.c_int, _D, _D, _D]),
             "or_mlp_nparams": (C.c_int, [C.c_int, C.c_int]),
@@ -319,6 +330,73 @@ def resample(seed, filt, t, lw):
     Cdf = cdf(lw, mx, deg)
     U = sorted_uniforms(seed, filt, t, len(lw))
     return ancestors(Cdf, U), Cdf, U, (mx, W, s2, deg)
+
+
+# resampling schemes (Sec. 2.3): multinomial, systematic, stratified, residual
+SCHEMES = {"multinomial": 0, "systematic": 1, "stratified": 2, "residual": 3}
+
+
+def systematic_uniforms(seed, filt, t, N) -> np.ndarray:
+    U = np.zeros(N)
+    lib().or_systematic_uniforms(C.c_uint64(seed), filt, t, N, _d(U))
+    return U
+
+
+def stratified_uniforms(seed, filt, t, N) -> np.ndarray:
+    U = np.zeros(N)
+    lib().or_stratified_uniforms(C.c_uint64(seed), filt, t, N, _d(U))
+    return U
+
+
+def resample_scheme(scheme, seed, filt, t, lw) -> np.ndarray:
+    """Ancestors of the log-weights lw by `scheme` (name or number)."""
+    sc = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    A = np.zeros(lw.size, np.int32)
+    lib().or_resample_scheme(sc, C.c_uint64(seed), filt, t, lw.size, _d(lw), _i32(A))
+    return A
+
+
+def filter_interval_sched(m: "Model", seed, filt, t, X, lwc, y, logZ=0.0, scheme=0,
+                          ess_threshold=0.0):
+    """One interval with a resampling scheme and the ESS-triggered schedule
+    (carried log-weights lwc, normalised to mean weight 1)."""
+    sc = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    lwc = np.array(lwc, dtype=np.float64, copy=True)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    N = X.shape[0]
+    lz = C.c_double(logZ)
+    lw = np.zeros(N)
+    A = np.zeros(N, np.int32)
+    me = np.zeros(m.dx)
+    mw = np.zeros(m.dx)
+    ess = C.c_double()
+    rs = C.c_int()
+    deg = lib().or_filter_interval_sched(m.ref, C.c_uint64(seed), filt, N, t, _d(X), _d(lwc),
+                                         _d(y), C.byref(lz), sc, float(ess_threshold), _d(lw),
+                                         _i32(A), _d(me), _d(mw), C.byref(ess), C.byref(rs))
+    return dict(X=X, lwc=lwc, lw=lw, A=A, mean_est=me, mean_w=mw, logZ=lz.value,
+                ess=ess.value, resampled=bool(rs.value), degenerate=bool(deg))
+
+
+def apf_interval(m: "Model", seed, filt, t, X, lwc, y, logZ=0.0, scheme=0):
+    """One auxiliary-particle-filter interval (pilot, first-stage resampling,
+    propagation, second-stage weights carried in lwc)."""
+    sc = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    lwc = np.array(lwc, dtype=np.float64, copy=True)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    N = X.shape[0]
+    lz = C.c_double(logZ)
+    lw = np.zeros(N)
+    A = np.zeros(N, np.int32)
+    mw = np.zeros(m.dx)
+    ess = C.c_double()
+    deg = lib().or_apf_interval(m.ref, C.c_uint64(seed), filt, N, t, _d(X), _d(lwc), _d(y),
+                                C.byref(lz), sc, _d(lw), _i32(A), _d(mw), C.byref(ess))
+    return dict(X=X, lwc=lwc, lw=lw, A=A, mean_w=mw, logZ=lz.value, ess=ess.value,
+                degenerate=bool(deg))
 
 
 def mean(X) -> np.ndarray:

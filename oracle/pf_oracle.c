@@ -420,6 +420,204 @@ int or_filter_interval(const or_model *m, uint64_t seed, uint32_t filter, int N,
   return deg;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Other resampling schemes (Sec. 2.3) and the ESS-triggered schedule.       */
+
+static double rs_uniform(const uint32_t key[2], uint32_t c0, uint32_t filter, int t,
+                         uint32_t sub, int lane) {
+  uint32_t ctr[4], r[4];
+  make_ctr(ctr, c0, filter, (uint32_t)t, OR_P_RESAMPLE, sub);
+  or_philox4x32_10(ctr, key, r);
+  return or_u01(r[lane]);
+}
+
+/* Systematic resampling: the N points share one uniform offset. */
+void or_systematic_uniforms(uint64_t seed, uint32_t filter, int t, int N, double *U) {
+  uint32_t key[2];
+  or_key(seed, key);
+  double u = rs_uniform(key, 0u, filter, t, 1u, 0);
+  for (int k = 0; k < N; ++k) U[k] = ((double)k + u) / (double)N;
+}
+
+/* Stratified resampling: one uniform point in each stratum [k/N, (k+1)/N). */
+void or_stratified_uniforms(uint64_t seed, uint32_t filter, int t, int N, double *U) {
+  uint32_t key[2];
+  or_key(seed, key);
+  for (int k = 0; k < N; ++k) {
+    double u = rs_uniform(key, (uint32_t)(k / 4), filter, t, 2u, k % 4);
+    U[k] = ((double)k + u) / (double)N;
+  }
+}
+
+/* Residual resampling: the integer parts of N w_i / W deterministically,
+   the remainder multinomially from the fractional parts. */
+void or_residual_ancestors(uint64_t seed, uint32_t filter, int t, int N, const double *lw,
+                           double mx, int degenerate, int32_t *A) {
+  double *w = (double *)malloc(sizeof(double) * (size_t)N);
+  double *Cr = (double *)malloc(sizeof(double) * (size_t)N);
+  int *cnt = (int *)malloc(sizeof(int) * (size_t)N);
+  double W = 0.0;
+  for (int i = 0; i < N; ++i) {
+    w[i] = degenerate ? 1.0 : exp(lw[i] - mx);
+    W += w[i];
+  }
+  int R = N;
+  double acc = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double nw = (double)N * w[i] / W;
+    double fl = floor(nw);
+    cnt[i] = (int)fl;
+    R -= cnt[i];
+    acc += nw - fl;
+    Cr[i] = acc;
+  }
+  if (R > 0) {
+    /* R sorted uniforms from the spacings of R + 1 exponentials */
+    uint32_t key[2], ctr[4], r[4];
+    or_key(seed, key);
+    double *S = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+    double s = 0.0;
+    for (int j = 0; j <= R; ++j) {
+      if (j % 4 == 0) {
+        make_ctr(ctr, (uint32_t)(j / 4), filter, (uint32_t)t, OR_P_RESAMPLE, 0u);
+        or_philox4x32_10(ctr, key, r);
+      }
+      s += -log(or_u01(r[j % 4]));
+      S[j] = s;
+    }
+    int i = 0;
+    for (int k = 0; k < R; ++k) {
+      double v = (S[k] / S[R]) * Cr[N - 1];
+      while (i < N - 1 && Cr[i] <= v) ++i;
+      cnt[i] += 1;
+    }
+    free(S);
+  }
+  int k = 0;
+  for (int i = 0; i < N; ++i)
+    for (int c = 0; c < cnt[i]; ++c) A[k++] = i;
+  free(w); free(Cr); free(cnt);
+}
+
+void or_resample_scheme(int scheme, uint64_t seed, uint32_t filter, int t, int N,
+                        const double *lw, int32_t *A) {
+  double mx, W, s2;
+  int deg = or_normalise(N, lw, &mx, &W, &s2);
+  if (scheme == OR_RS_RESIDUAL) {
+    or_residual_ancestors(seed, filter, t, N, lw, mx, deg, A);
+    return;
+  }
+  double *C = (double *)malloc(sizeof(double) * (size_t)N);
+  double *U = (double *)malloc(sizeof(double) * (size_t)N);
+  or_cdf(N, lw, mx, deg, C);
+  if (scheme == OR_RS_SYSTEMATIC)
+    or_systematic_uniforms(seed, filter, t, N, U);
+  else if (scheme == OR_RS_STRATIFIED)
+    or_stratified_uniforms(seed, filter, t, N, U);
+  else
+    or_sorted_uniforms(seed, filter, t, N, U);
+  or_ancestors(N, C, U, A);
+  free(C); free(U);
+}
+
+int or_filter_interval_sched(const or_model *m, uint64_t seed, uint32_t filter, int N, int t,
+                             double *X, double *lwc, const double *y, double *logZ, int scheme,
+                             double ess_threshold, double *lw_out, int32_t *A_out,
+                             double *mean_est, double *mean_w, double *ess_out,
+                             int *resampled_out) {
+  int d = m->dx;
+  double *lw = (double *)malloc(sizeof(double) * (size_t)N);
+  int32_t *A = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  double *Xo = (double *)malloc(sizeof(double) * (size_t)N * d);
+  double mx, W, s2;
+
+  or_propagate(m, seed, filter, N, t, X);
+  or_weights(m, N, X, y, lw);
+  for (int i = 0; i < N; ++i) lw[i] += lwc[i];
+  int deg = or_normalise(N, lw, &mx, &W, &s2);
+  if (logZ) {
+    const double two_pi = 6.283185307179586476925286766559;
+    if (deg)
+      *logZ = -INFINITY;
+    else
+      *logZ += mx + log(W / (double)N) - 0.5 * m->dy * log(two_pi * m->obs_var);
+  }
+  double ess = W * W / s2;
+  if (ess_out) *ess_out = ess;
+  if (mean_w) or_weighted_mean(N, d, X, lw, mx, mean_w);
+  int resample = deg || ess_threshold <= 0.0 || ess < ess_threshold * (double)N;
+  if (resample) {
+    or_resample_scheme(scheme, seed, filter, t, N, lw, A);
+    or_gather(N, d, X, A, Xo);
+    memcpy(X, Xo, sizeof(double) * (size_t)N * d);
+    for (int i = 0; i < N; ++i) lwc[i] = 0.0;
+    if (mean_est) or_mean(N, d, X, mean_est);
+  } else {
+    double shift = mx + log(W / (double)N);
+    for (int i = 0; i < N; ++i) {
+      A[i] = i;
+      lwc[i] = lw[i] - shift;
+    }
+    if (mean_est) or_weighted_mean(N, d, X, lw, mx, mean_est);
+  }
+  if (resampled_out) *resampled_out = resample;
+  if (lw_out) memcpy(lw_out, lw, sizeof(double) * (size_t)N);
+  if (A_out) memcpy(A_out, A, sizeof(int32_t) * (size_t)N);
+  free(lw); free(A); free(Xo);
+  return deg;
+}
+
+int or_apf_interval(const or_model *m, uint64_t seed, uint32_t filter, int N, int t, double *X,
+                    double *lwc, const double *y, double *logZ, int scheme, double *lw_out,
+                    int32_t *A_out, double *mean_w, double *ess_out) {
+  const double two_pi = 6.283185307179586476925286766559;
+  int d = m->dx;
+  double *pil = (double *)calloc((size_t)N, sizeof(double));
+  double *lam = (double *)calloc((size_t)N, sizeof(double));
+  double *lw = (double *)malloc(sizeof(double) * (size_t)N);
+  int32_t *A = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  double *Xo = (double *)malloc(sizeof(double) * (size_t)N * d);
+  double *mu = (double *)malloc(sizeof(double) * (size_t)d);
+  double *nx = (double *)malloc(sizeof(double) * (size_t)d);
+  double *z0 = (double *)calloc((size_t)d, sizeof(double));
+  double mx, W, s2;
+  /* 1. the pilot: noise-free Euler path and its likelihood */
+  for (int i = 0; i < N; ++i) {
+    memcpy(mu, X + (size_t)i * d, sizeof(double) * (size_t)d);
+    for (int s = 0; s < m->S; ++s) {
+      or_em_step(m, mu, z0, nx);
+      memcpy(mu, nx, sizeof(double) * (size_t)d);
+    }
+    pil[i] = or_loglik(m, mu, y);
+    lam[i] = lwc[i] + pil[i];
+  }
+  /* 2. first-stage resampling */
+  int deg1 = or_normalise(N, lam, &mx, &W, &s2);
+  double lz1 = deg1 ? -INFINITY : mx + log(W / (double)N);
+  or_resample_scheme(scheme, seed, filter, t, N, lam, A);
+  /* 3. propagation of the selected particles, slot k */
+  or_gather(N, d, X, A, Xo);
+  or_propagate(m, seed, filter, N, t, Xo);
+  memcpy(X, Xo, sizeof(double) * (size_t)N * d);
+  /* 4. second-stage weights, carried */
+  or_weights(m, N, X, y, lw);
+  for (int k = 0; k < N; ++k) lw[k] -= pil[A[k]];
+  int deg2 = or_normalise(N, lw, &mx, &W, &s2);
+  if (logZ) {
+    if (deg1 || deg2)
+      *logZ = -INFINITY;
+    else
+      *logZ += lz1 + mx + log(W / (double)N) - 0.5 * m->dy * log(two_pi * m->obs_var);
+  }
+  if (ess_out) *ess_out = W * W / s2;
+  if (mean_w) or_weighted_mean(N, d, X, lw, mx, mean_w);
+  for (int k = 0; k < N; ++k) lwc[k] = deg2 ? 0.0 : lw[k] - (mx + log(W / (double)N));
+  if (lw_out) memcpy(lw_out, lw, sizeof(double) * (size_t)N);
+  if (A_out) memcpy(A_out, A, sizeof(int32_t) * (size_t)N);
+  free(pil); free(lam); free(lw); free(A); free(Xo); free(mu); free(nx); free(z0);
+  return deg1 || deg2;
+}
+
 /* Definition 3: M independent filters on the same y_{1:T}, averaged with
    equal weights 1/M. */
 void or_run_ensemble(const or_model *m, uint64_t seed, int M, int N, int T,

@@ -120,6 +120,64 @@ int or_filter_interval(const or_model *m, uint64_t seed, uint32_t filter, int N,
                        double *lw, int32_t *A, double *mean_post,
                        double *mean_w, double *ess);
 
+/* ---- other resampling schemes and the ESS-triggered schedule ------------
+   Sec. 2.3 notes that the convergence results also hold for other resampling
+   schemes than multinomial.  Each scheme turns the normalised weights into
+   ascending ancestors a_k = min{ i : C_i > U_k C_{N-1} } from sorted points
+   U_k in [0, 1):
+     systematic: U_k = (k + u) / N with one uniform u (counter (0, filter, t,
+                 RESAMPLE | sub-block 1), lane 0);
+     stratified: U_k = (k + u_k) / N with u_k from counter (k/4, filter, t,
+                 RESAMPLE | sub-block 2), lane k%4;
+     residual:   n_i = floor(N w_i / W) copies of particle i, then R = N -
+                 sum n_i multinomial draws from the residual weights
+                 N w_i / W - n_i (sorted uniforms from the exponentials
+                 E_0 .. E_R of the multinomial stream); the ancestors list
+                 particle i its total number of times, in index order. */
+enum { OR_RS_MULTINOMIAL = 0, OR_RS_SYSTEMATIC = 1, OR_RS_STRATIFIED = 2, OR_RS_RESIDUAL = 3 };
+void or_systematic_uniforms(uint64_t seed, uint32_t filter, int t, int N, double *U);
+void or_stratified_uniforms(uint64_t seed, uint32_t filter, int t, int N, double *U);
+void or_residual_ancestors(uint64_t seed, uint32_t filter, int t, int N, const double *lw,
+                           double mx, int degenerate, int32_t *A);
+/* ancestors A[N] of the log-weights lw[N] by `scheme` */
+void or_resample_scheme(int scheme, uint64_t seed, uint32_t filter, int t, int N,
+                        const double *lw, int32_t *A);
+
+/* One interval with a resampling scheme and schedule.  lwc[N] (in/out)
+   holds the carried log-weights of the particles, normalised so that
+   sum_i exp(lwc_i) = N (all zero after a resampling).  The particles'
+   log-weights are lw_i = lwc_i + log g(y | xbar_i); log G advances by
+   mx + log(W/N) + the Gaussian constant, as in or_filter_interval.  The
+   filter resamples (by `scheme`) when ess_threshold <= 0 (every interval,
+   Algorithm 1), when the weights are degenerate, or when the ESS
+   (sum w)^2 / sum w^2 is below ess_threshold * N; then lwc = 0 and
+   mean_est is the post-resampling mean.  Otherwise the particles stay
+   (A = identity), lwc_i = lw_i - mx - log(W/N) and mean_est is the weighted
+   mean.  *resampled receives the decision.  Outputs may be NULL. */
+int or_filter_interval_sched(const or_model *m, uint64_t seed, uint32_t filter, int N, int t,
+                             double *X, double *lwc, const double *y, double *logZ, int scheme,
+                             double ess_threshold, double *lw, int32_t *A, double *mean_est,
+                             double *mean_w, double *ess, int *resampled);
+
+/* Auxiliary particle filter interval (Pitt and Shephard's auxiliary filter,
+   the variant the paper runs on its FH-N network in Sec. 5.3; Sec. 3.3 notes
+   that the ensemble results extend to it).  From the particles X[N] with
+   carried log-weights lwc[N] (mean weight 1):
+     1. pilot: mu_i = the noise-free S-step Euler path of the model from x_i;
+        first-stage log-weights lambda_i = lwc_i + log g(y | mu_i);
+     2. ancestors a_k by `scheme` from lambda (counters of interval t);
+     3. propagation of x_{a_k} (the bootstrap's noise counters, slot k);
+     4. second-stage log-weights lw_k = log g(y | x_k) - log g(y | mu_{a_k}),
+        never resampled: lwc_k = lw_k - mx - log(W/N), and the estimate
+        mean_w is the weighted mean sum_k w_k x_k / W.
+   log G advances by the two stages' mx + log(W/N) and the Gaussian
+   constant, so that exp(log G) stays unbiased for p(y_{1:t}).  Outputs may
+   be NULL; A receives the first-stage ancestors.  Returns 1 if either
+   stage's weights were degenerate. */
+int or_apf_interval(const or_model *m, uint64_t seed, uint32_t filter, int N, int t, double *X,
+                    double *lwc, const double *y, double *logZ, int scheme, double *lw,
+                    int32_t *A, double *mean_w, double *ess);
+
 /* Whole ensemble run over T observations y[T][dy].  est[T][dx] receives the
    ensemble (equal-weight) post-resampling mean, est_w[T][dx] the ensemble of
    weighted pre-resampling means, logZ[M] the final log-evidence per filter,

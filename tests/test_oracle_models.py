@@ -156,3 +156,22 @@ def test_loglik_hand_values(orc):
     # residuals (2-1, 5-3) = (1, 2): -(1 + 4) / (2 * 0.5) = -5
     assert orc.loglik(m, [1.0, 2.0, 3.0], [2.0, 5.0]) == -5.0
     assert orc.loglik(m, [np.nan, 2.0, 3.0], [2.0, 5.0]) == -np.inf
+
+
+def test_paper_lorenz_observation_and_prior(orc):
+    # the paper's Lorenz experiment: y_t = X_{1,100t} + V_t with var(V) = 1/2
+    # (eqObservLorenz), so a particle's log-weight is -(y - x1)^2 and does not
+    # see x2, x3; the prior is N(x*, 10 I) (Sec. 4.1)
+    from scipy import stats
+    m = orc.Model(pf_inputs.lorenz63_paper())
+    X = np.array([[1.0, 2.0, 3.0], [1.0, -7.0, 40.0], [3.5, 0.0, 0.0]])
+    lw = orc.weights(m, X, np.array([2.0]))
+    assert lw == pytest.approx([-1.0, -1.0, -2.25], abs=1e-15)
+    n = 20000
+    x0 = orc.init(m, 5, 0, n)
+    dof = n - 1
+    lo, hi = stats.chi2.ppf([1e-5, 1 - 1e-5], dof)
+    for c, mu in enumerate([-10.2410, -1.3984, 23.6752]):
+        v = np.var(x0[:, c], ddof=1)
+        assert lo * 10.0 / dof < v < hi * 10.0 / dof, (c, v)
+        assert abs(np.mean(x0[:, c]) - mu) < 5 * np.sqrt(10.0 / n)
