@@ -13,7 +13,8 @@ roofline (timed live with HIP events around its launches in every
 PROF_EVERY-th timed interval), the FP64 oracle timed on a bounded sample on
 the host cores, and -- with the default workload -- the other measurements
 of the hot path in extra keys, each timed with the same warm-up and step
-counts:
+counts (they run before the headline, whose timed intervals then see the
+device at its sustained clock):
   sweep         every split M x N of K = 2^20 (M = 1, 16, 256, 4096): time per
                 interval, MSE against the truth and against a 64 x 2^20
                 reference filter, C_ipf = 1/M + 1/N;
@@ -24,7 +25,10 @@ counts:
                 autotuner's plan against the plain one-kernel-per-step path,
                 with the MSE of both;
   learned       the learned proposal against the bootstrap filter on the same
-                observations: time per interval at a stated equal MSE.
+                observations: time per interval at a stated equal MSE;
+  paper_l63     the paper's own Lorenz 63 experiment (Sec. 4): ensembles of
+                M = 20 filters against the centralised filter of K = M N,
+                MSE at t = 200 against a J = 1e5 proxy over 100 runs.
 """
 from __future__ import annotations
 
@@ -415,6 +419,66 @@ def mix_leg(pf, torch, a, n_compare=4):
             "roofline": rl}
 
 
+# ------------------------------------------------------ the paper's Lorenz --
+def paper_l63_leg(pf, torch, a):
+    """The paper's own Lorenz experiment (Sec. 4.2-4.3): one observation record
+    of 200 intervals (x1 every 100 Euler steps), the ensemble of M = 20
+    independent filters of N particles and the centralised filter of K = M N
+    particles, 100 runs each (independent seeds, the same observations) for
+    every N; per run the squared error of the posterior-mean estimate at
+    t = 200 against the estimate of one filter of J = 1e5 particles (the
+    paper's proxy), reported as the mean and the variance over the runs.  The
+    100 runs of a configuration are 100 ensembles of one graph-replayed
+    context; the time per run is that batch's time / 100, and the time of
+    one run alone is measured too."""
+    cfg = pf_inputs.PAPER_L63
+    spec = pf_inputs.lorenz63_paper()
+    T, R, M = cfg["T"], cfg["runs"], cfg["M"]
+    sim = pf.ParticleFilter([spec], [(0, 1, 1, 1)], fused=True)
+    xt, y = sim.simulate(0, 1, T)
+    sim.close()
+    stream = torch.cuda.current_stream()
+
+    def run(ens, timed=True):
+        """All intervals of a context of ensembles `ens` on the shared
+        observations; returns (ms, estimates at t = T [n_ens][3])."""
+        f = pf.ParticleFilter([spec], ens, graph=True)
+        f.set_observations(y.repeat(1, len(ens)).contiguous())
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for _ in range(T):
+            f.step()
+        e1.record(stream)
+        est = f.estimate()[0].view(len(ens), 3).clone()
+        torch.cuda.synchronize()
+        f.close()
+        return e0.elapsed_time(e1), est
+
+    _, proxy = run([(0, 1, cfg["proxy_J"], 99)])
+    proxy = proxy[0]
+    rows = []
+    for N in cfg["Ns"]:
+        r = {"N": N, "K": M * N}
+        for name, ens, single in (
+                ("ensemble", [(0, M, N, 1000 + i) for i in range(R)], (0, M, N, 1000)),
+                ("centralised", [(0, 1, M * N, 5000 + i) for i in range(R)], (0, 1, M * N, 5000))):
+            ms, est = run(ens)
+            err = torch.sum((est - proxy) ** 2, dim=1)     # squared error per run
+            ms1, _ = run([single])
+            r[name] = {"mse_mean": err.mean().item(), "mse_var": err.var().item(),
+                       "ms_per_run_batched": ms / R, "ms_per_run_alone": ms1,
+                       "particle_steps_per_s_batched":
+                           R * M * N * spec["S"] * T / (ms / 1e3)}
+        rows.append(r)
+    return {"model": "Lorenz 63, x1 observed every 100 steps (var 1/2), unit diffusion, "
+                     "prior N(x*, 10 I)", "T": T, "M": M, "runs": R,
+            "proxy": "one bootstrap filter of J = %d particles" % cfg["proxy_J"],
+            "error": "squared Euclidean error of E[X_t | y_1:t] at t = T against the proxy "
+                     "(mean and variance over the runs)",
+            "proxy_estimate": proxy.tolist(), "truth_at_T": xt[T].tolist(), "rows": rows}
+
+
 # ------------------------------------------------------ learned proposal ----
 def train_proposal(pf, torch, spec):
     tc = pf_inputs.LEARNED_TRAINING
@@ -612,6 +676,28 @@ def mix_main(a):
     print(json.dumps(line))
 
 
+def paper_main(a):
+    """The paper's Lorenz experiment as the headline: the value is the
+    batched ensemble runs' particle-steps/s at the largest N."""
+    import torch
+    import paper_1407_8071_amd as pf
+    torch.cuda.set_device(0)
+    out = paper_l63_leg(pf, torch, a)
+    last = out["rows"][-1]["ensemble"]
+    cfg = pf_inputs.PAPER_L63
+    line = {
+        "metric": "particle-steps/s", "value": last["particle_steps_per_s_batched"],
+        "unit": "particle-steps/s", "n_gpus": 1, "steps": cfg["T"], "warmup": 0,
+        "ms_per_step": last["ms_per_run_batched"] / cfg["T"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (GPU-simulated truth and observations)",
+        "config": {"workload": a.workload, "M": cfg["M"], "N": cfg["Ns"][-1],
+                   "runs": cfg["runs"], "path": "graph"},
+        "roofline": None, "cpu_baseline": None, "paper_l63": out,
+    }
+    print(json.dumps(line))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -625,6 +711,9 @@ def main():
     if a.workload == "mix_l63x1024_fhn20x32":
         mix_main(a)
         return
+    if a.workload == "l63_paper":
+        paper_main(a)
+        return
     import torch
     import paper_1407_8071_amd as pf
 
@@ -633,10 +722,26 @@ def main():
     grid = spec["kind"] == "fhn"
     torch.cuda.set_device(0)
     graph = a.path == "graph"
-    f = pf.ParticleFilter([spec], [(0, M, N, 1)], fused=(a.path == "fused"), graph=graph)
     T = a.warmup + a.steps
-    xt, y = f.simulate(0, 1, max(T, ACCURACY_INTERVALS))
+    sim = pf.ParticleFilter([spec], [(0, 1, 1, 1)], fused=True)
+    xt, y = sim.simulate(0, 1, max(T, ACCURACY_INTERVALS))
+    sim.close()
     torch.cuda.synchronize()
+    extras = {}
+    sweep = a.workload.startswith("l63_sweep")
+    if sweep and a.extras and a.path == "fused":
+        # the other measurements of the line first: the headline's timed
+        # intervals then see the device at its sustained clock (the first
+        # few hundred intervals of a cold device measured ~6% slower)
+        t0 = time.perf_counter()
+        extras["fhn40_64x512"] = fhn_leg(pf, torch, a)
+        extras["mix"] = mix_leg(pf, torch, a)
+        extras["learned"], _ = learned_leg(pf, torch, a)
+        extras["paper_l63"] = paper_l63_leg(pf, torch, a)
+        extras["sweep"] = sweep_leg(pf, torch, a, spec, xt, y, None)
+        extras["extras_wall_s"] = time.perf_counter() - t0
+        torch.cuda.empty_cache()
+    f = pf.ParticleFilter([spec], [(0, M, N, 1)], fused=(a.path == "fused"), graph=graph)
     if graph:
         f.set_observations(y)
     ms, k_ms, k_n, wall = timed_intervals(torch, f, y, a.warmup, a.steps, graph=graph)
@@ -679,16 +784,9 @@ def main():
                    "nodes_per_particle": nodes, "path": a.path, "wall_s": wall},
         "roofline": roofline, "cpu_baseline": cpu,
     }
-    torch.cuda.empty_cache()
-    sweep = a.workload.startswith("l63_sweep")
-    if sweep and a.extras and a.path == "fused":
-        t0 = time.perf_counter()
-        line["sweep"] = sweep_leg(pf, torch, a, spec, xt, y, (ms, k_ms, k_n))
-        line["fhn40_64x512"] = fhn_leg(pf, torch, a)
-        line["mix"] = mix_leg(pf, torch, a)
-        line["learned"], _ = learned_leg(pf, torch, a)
-        line["extras_wall_s"] = time.perf_counter() - t0
-    elif a.accuracy:
+    line.update(extras)
+    if not extras and a.accuracy:
+        torch.cuda.empty_cache()
         Ta = ACCURACY_INTERVALS
         comps = nodes if grid else spec["dx"]
         e = estimates(pf, torch, spec, M, N, y, Ta)

@@ -86,9 +86,39 @@ typedef struct pf_ensemble_desc {
   int32_t model;
   int32_t M;
   int32_t N;
-  uint32_t flags; /* 0 (bootstrap proposal) or PF_ENS_LEARNED */
+  uint32_t flags; /* 0 (bootstrap proposal), PF_ENS_LEARNED or PF_ENS_AUXILIARY */
   uint64_t seed;
+  /* Resampling (Sec. 2.3 notes that the convergence results also hold for
+     other schemes than the multinomial one of Algorithm 1):
+     scheme        PF_RESAMPLE_* (0 = multinomial, Algorithm 1);
+     ess_threshold 0 resamples at every observation (Algorithm 1); a value in
+                   (0, 1] resamples only when the effective sample size
+                   (sum w)^2 / sum w^2 is below ess_threshold * N, and
+                   otherwise keeps the particles with their weights carried
+                   into the next interval (the filter's estimate is then the
+                   weighted mean).  Anything but (multinomial, 0) needs a
+                   PF_OPT_FUSED context and N <= 8192 (PF_ERR_UNSUPPORTED
+                   otherwise). */
+  int32_t scheme;
+  int32_t reserved; /* 0 */
+  double ess_threshold;
 } pf_ensemble_desc;
+
+/* Resampling schemes: each turns the normalised weights into ascending
+   ancestors a_k = min{ i : C_i > U_k C_{N-1} } from sorted points U_k.
+   MULTINOMIAL: U_k from N + 1 exponential spacings (Algorithm 1);
+   SYSTEMATIC:  U_k = (k + u) / N, one uniform u (Philox counter (0, filter,
+                t, RESAMPLE << 24 | 1), lane 0);
+   STRATIFIED:  U_k = (k + u_k) / N, u_k from counter (k/4, filter, t,
+                RESAMPLE << 24 | 2), lane k%4;
+   RESIDUAL:    floor(N w_i / W) copies of particle i, then the remaining
+                R draws multinomially from the fractional parts (sorted
+                uniforms from the spacings of the exponentials E_0 .. E_R of
+                the multinomial stream), ancestors in index order. */
+#define PF_RESAMPLE_MULTINOMIAL 0
+#define PF_RESAMPLE_SYSTEMATIC 1
+#define PF_RESAMPLE_STRATIFIED 2
+#define PF_RESAMPLE_RESIDUAL 3
 
 /* Ensemble flag: draw the particles from the learned proposal instead of
    the model's transition (FH-N models with J <= 48 only).  Every Euler-
@@ -99,6 +129,21 @@ typedef struct pf_ensemble_desc {
    Sec. 6 extend the results to).  Until pf_proposal_set is called the
    network is zero and the filter is the bootstrap filter. */
 #define PF_ENS_LEARNED 1u
+
+/* Ensemble flag: run every filter of the ensemble as an auxiliary particle
+   filter (Pitt and Shephard's auxiliary filter, the variant the paper runs
+   on its FH-N network in Sec. 5.3; Sec. 3.3 notes that the ensemble results
+   extend to it).  Each interval: a pilot mu_i, the noise-free S-step Euler
+   path of the model from particle i; first-stage log-weights lambda_i =
+   lwc_i + log g(y_t | mu_i) (lwc: carried log-weights, mean weight 1);
+   ancestors by the ensemble's scheme from lambda; propagation of the
+   selected particles; second-stage log-weights log g(y_t | x_k) -
+   log g(y_t | mu_{a_k}), normalised and carried to the next interval (the
+   filter's estimate is their weighted mean; no resampling at the end of the
+   interval).  log G advances by both stages' factors, so exp(log G) stays
+   unbiased for p(y_{1:t}).  Needs PF_OPT_FUSED, N <= 8192, the bootstrap
+   transition (not PF_ENS_LEARNED) and ess_threshold 0. */
+#define PF_ENS_AUXILIARY 2u
 
 /* Context options (pf_init `options`). */
 #define PF_OPT_PLAIN 0u /* one kernel per method step (reference path)     */
@@ -191,7 +236,9 @@ pf_status pf_run_stages(pf_ctx *ctx, uint32_t stages, const float *d_y, void *st
    d_logZ:   float64 [sum_e M(e)]: log G_t^N per filter including the Gaussian
              normalising constant, so that exp(d_logZ) is unbiased for
              p(y_{1:t}) (Lemma 2); -inf once a filter degenerated.
-   d_filter_mean: float64 [sum_e M(e)*state_dim(e)]: per-filter means. */
+   d_filter_mean: float64 [sum_e M(e)*state_dim(e)]: per-filter means.
+   A filter that kept its particles in the last interval (ESS threshold)
+   contributes its weighted mean to d_mean and d_filter_mean. */
 pf_status pf_estimate(pf_ctx *ctx, double *d_mean, double *d_mean_w, double *d_logZ,
                       double *d_filter_mean, void *stream);
 
@@ -203,11 +250,19 @@ pf_status pf_get_particles(pf_ctx *ctx, int32_t ens, float *d_x, void *stream);
 /* pre-resampling particles xbar_t of the current interval (get / overwrite) */
 pf_status pf_get_predicted(pf_ctx *ctx, int32_t ens, float *d_x, void *stream);
 pf_status pf_set_predicted(pf_ctx *ctx, int32_t ens, const float *d_x, void *stream);
-/* log-weights float32 [M][N] of the current interval */
+/* log-weights float32 [M][N] of the current interval (with an ESS threshold:
+   the carried log-weight plus the log-likelihood, once the interval ran) */
 pf_status pf_get_logweights(pf_ctx *ctx, int32_t ens, float *d_lw, void *stream);
 pf_status pf_set_logweights(pf_ctx *ctx, int32_t ens, const float *d_lw, void *stream);
 /* ancestors int32 [M][N] of the current interval, ascending per filter */
 pf_status pf_get_ancestors(pf_ctx *ctx, int32_t ens, int32_t *d_a, void *stream);
+/* carried log-weights float32 [M][N] of an ensemble with an ESS threshold:
+   log-weights of particles that were kept at the end of the last interval,
+   normalised so that their exponentials average 1 (all zero after a
+   resampling); the next interval adds them to the log-likelihoods
+   (get / overwrite) */
+pf_status pf_get_carried_logweights(pf_ctx *ctx, int32_t ens, float *d_lwc, void *stream);
+pf_status pf_set_carried_logweights(pf_ctx *ctx, int32_t ens, const float *d_lwc, void *stream);
 /* per-filter float64 [M][4]: max log-weight, sum exp(lw - max),
    sum exp(2(lw - max)), degenerate flag (1.0 if no weight was positive) */
 pf_status pf_get_filter_stats(pf_ctx *ctx, int32_t ens, double *d_stats, void *stream);

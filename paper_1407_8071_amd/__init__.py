@@ -26,6 +26,7 @@ OPT_PLAIN, OPT_FUSED, OPT_GRAPH = 0, 1, 2
 STAGE_PROPAGATE, STAGE_WEIGHT, STAGE_RESAMPLE, STAGE_GATHER, STAGE_ESTIMATE = 1, 2, 4, 8, 16
 STAGE_ALL = 31
 ENS_LEARNED = 1
+ENS_AUXILIARY = 2
 
 
 class PFError(RuntimeError):
@@ -60,7 +61,12 @@ class _TrainDesc(C.Structure):
 
 class _EnsDesc(C.Structure):
     _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32),
-                ("flags", C.c_uint32), ("seed", C.c_uint64)]
+                ("flags", C.c_uint32), ("seed", C.c_uint64), ("scheme", C.c_int32),
+                ("reserved", C.c_int32), ("ess_threshold", C.c_double)]
+
+
+# resampling schemes of pf_ensemble_desc.scheme
+RESAMPLE = {"multinomial": 0, "systematic": 1, "stratified": 2, "residual": 3}
 
 
 _lib = None
@@ -90,6 +96,8 @@ def lib():
         "pf_set_predicted": [_VP, i32, _VP, _VP],
         "pf_get_logweights": [_VP, i32, _VP, _VP],
         "pf_set_logweights": [_VP, i32, _VP, _VP],
+        "pf_get_carried_logweights": [_VP, i32, _VP, _VP],
+        "pf_set_carried_logweights": [_VP, i32, _VP, _VP],
         "pf_get_ancestors": [_VP, i32, _VP, _VP],
         "pf_get_filter_stats": [_VP, i32, _VP, _VP],
         "pf_set_interval": [_VP, i32],
@@ -188,8 +196,9 @@ def _close_all():
 class ParticleFilter:
     """A context of one or more ensembles of independent bootstrap filters.
 
-    ``ensembles`` is a list of (model_index, M, N, seed) or
-    (model_index, M, N, seed, flags) with flags 0 or ENS_LEARNED.  ``fused``
+    ``ensembles`` is a list of (model_index, M, N, seed[, flags[, scheme[,
+    ess_threshold]]]) with flags 0 or ENS_LEARNED, scheme a name of RESAMPLE
+    or its number, ess_threshold 0 (resample every interval) or in (0, 1].  ``fused``
     selects the persistent fused interval kernel instead of one kernel per
     step.
     """
@@ -203,7 +212,10 @@ class ParticleFilter:
         def desc(e):
             mi, M, N, seed = e[:4]
             flags = e[4] if len(e) > 4 else 0
-            return _EnsDesc(int(mi), int(M), int(N), int(flags), int(seed))
+            scheme = e[5] if len(e) > 5 else 0
+            scheme = RESAMPLE[scheme] if isinstance(scheme, str) else int(scheme)
+            ess = float(e[6]) if len(e) > 6 else 0.0
+            return _EnsDesc(int(mi), int(M), int(N), int(flags), int(seed), scheme, 0, ess)
         self._ed = (_EnsDesc * ne)(*[desc(e) for e in self.ens])
         self.options = (OPT_FUSED if fused or graph else OPT_PLAIN) | (OPT_GRAPH if graph else 0)
         nbytes = C.c_size_t()
@@ -308,6 +320,18 @@ class ParticleFilter:
         _, M, N = self.dims(e)
         assert lw.dtype == torch.float32 and lw.is_cuda and tuple(lw.shape) == (M, N)
         _check(lib().pf_set_logweights(self._ctx, e, _ptr(lw.contiguous()), _stream(stream)))
+
+    def get_carried_logweights(self, e: int, stream=None):
+        import torch
+        _, M, N = self.dims(e)
+        return self._get(lib().pf_get_carried_logweights, e, (M, N), torch.float32, stream)
+
+    def set_carried_logweights(self, e: int, lwc, stream=None):
+        import torch
+        _, M, N = self.dims(e)
+        assert lwc.dtype == torch.float32 and lwc.is_cuda and tuple(lwc.shape) == (M, N)
+        _check(lib().pf_set_carried_logweights(self._ctx, e, _ptr(lwc.contiguous()),
+                                               _stream(stream)))
 
     def get_ancestors(self, e: int, stream=None):
         import torch

@@ -310,10 +310,13 @@ __device__ __forceinline__ void load_span(const gmem<float> *row, int k0, int N,
 
 // PM: elements per thread the registers hold, at least ceil(N / BD) for every
 // filter of the launch (1 below 1024 threads, which serve filters of N <= BD).
-template <int BD, int D, int PM>
+// CUSTOM: the launch serves ensembles with another scheme or the ESS schedule
+// (compiled apart, so that the multinomial body keeps its registers).
+template <int BD, int D, int PM, bool CUSTOM>
 __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
                                             const FusedEns *__restrict__ ens, IvArg iv,
-                                            int32_t *const *__restrict__ counts, int xb_parity) {
+                                            int32_t *const *__restrict__ counts, int xb_parity,
+                                            int stage) {
   const int t = iv_t(iv);
   extern __shared__ double lds[];
   constexpr int NW = BD / 64;
@@ -341,32 +344,50 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
   // 4) they are 16-byte loads: one instruction per 4 elements instead of 4
   // lane-strided ones that each touch 4 times the cache lines they use.
   const bool vec4 = PM % 4 == 0 && P % 4 == 0 && N % 4 == 0;
-  float lw[PM];
+  // the ensemble's scheme and schedule (uniform over the workgroup)
+  const int scheme = CUSTOM ? E.scheme : RS_MULTINOMIAL;
+  // ESS schedule: the carried log-weights join the interval's ones here.
+  // Auxiliary filters: stage 1 resamples from the pilot weights (which carry
+  // them already), stage 0 normalises the second-stage weights and carries
+  // them (never resamples)
+  const bool sched = CUSTOM && E.ess_thr > 0.0;
+  const bool apf = CUSTOM && E.apf != 0;
+  float lw[PM], lc[PM];
   load_span<PM>(lwg, k0, N, vec4, lw);
+  if (sched) load_span<PM>(gptr(E.lwc + (size_t)m * N), k0, N, vec4, lc);
 #pragma unroll
   for (int e = 0; e < PM; ++e)
     if (k0 + e < k1) cnt[k0 + e] = 0;
   // 2. exponential spacings over the same elements (they do not depend on
-  // the weights: computed while the loads are in flight)
+  // the weights: computed while the loads are in flight); multinomial and
+  // residual resampling draw from them
   ExpoWG ex{E.key, (uint32_t)m, (uint32_t)t};
   double eg[PM], es = 0.0;
+  const bool spacings = scheme == RS_MULTINOMIAL || scheme == RS_RESIDUAL;
 #pragma unroll
   for (int e = 0; e < PM; ++e) {
-    eg[e] = (k0 + e < k1) ? ex(k0 + e) : 0.0;
+    eg[e] = (spacings && k0 + e < k1) ? ex(k0 + e) : 0.0;
     es += eg[e];
   }
   // the last thread, whose range is last (or empty), adds E_N: it enters
   // the total S_N but no thread's exclusive prefix
-  if (tid == BD - 1) {
+  if (spacings && tid == BD - 1) {
     ExpoWG tail{E.key, (uint32_t)m, (uint32_t)t};
     es += tail(N);
   }
   // 3. the filter maximum, the weights and their thread-local inclusive
-  // scan; one block scan of the weights and the spacings -> CDF, S_N
+  // scan; one block scan of the weights and the spacings -> CDF, S_N.  With
+  // the ESS schedule a particle's log-weight is its carried log-weight plus
+  // the interval's log-likelihood, and the sum replaces the stored value
   float lmax = -INFINITY;
 #pragma unroll
   for (int e = 0; e < PM; ++e) {
     lw[e] = (k0 + e < k1 && lw[e] == lw[e]) ? lw[e] : -INFINITY;
+    if (sched) {
+      lw[e] += lc[e];
+      lw[e] = lw[e] == lw[e] ? lw[e] : -INFINITY;
+      if (k0 + e < k1) gptr(E.lw)[(size_t)m * N + k0 + e] = lw[e];
+    }
     lmax = fmaxf(lmax, lw[e]);
   }
   const float mxf = block_max(lmax, shf);
@@ -401,18 +422,146 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
   const double eoff = sc[1], SN = tot[1];
   __syncthreads();  // publishes C
   const double W = C[N - 1];
-  // 4. ancestors in the LDS CDF and the offspring counts
-  double sacc = eoff;
-  int i = 0;
+  // the schedule's decision: resample every interval, or only when the ESS
+  // (sum w)^2 / sum w^2 falls below ess_thr N (and always when degenerate)
+  bool resample = true;
+  if (sched) {
+    const double w2 = block_sum(s2, shd);
+    resample = deg || W * W / w2 < E.ess_thr * (double)N;
+  }
+  if (apf) resample = stage == 1;
+  gmem<int32_t> *Ag = gptr(E.A + (size_t)m * N);
+  if (!resample) {
+    // 4'. the particles stay (identity ancestors, one offspring each) and
+    // carry their log-weights, normalised to mean weight 1
+    const double shift = mx + log(W / (double)N);
 #pragma unroll
-  for (int e = 0; e < PM; ++e) {
-    const int k = k0 + e;
-    if (k < k1) {
-      sacc += eg[e];
-      const double v = (sacc / SN) * W;
-      i = e == 0 ? lds_search_blocked(C, N, v) : lds_search(C, N, i, v);
-      gptr(E.A)[(size_t)m * N + k] = i;
-      atomicAdd(cnt + i, 1);
+    for (int e = 0; e < PM; ++e) {
+      const int k = k0 + e;
+      if (k < k1) {
+        Ag[k] = k;
+        cnt[k] = 1;
+        gptr(E.lwc)[(size_t)m * N + k] = deg ? 0.f : (float)((double)lw[e] - shift);
+      }
+    }
+  } else {
+    if (sched) {
+#pragma unroll
+      for (int e = 0; e < PM; ++e)
+        if (k0 + e < k1) gptr(E.lwc)[(size_t)m * N + k0 + e] = 0.f;
+    }
+    if (scheme == RS_RESIDUAL) {
+      // 4r. residual resampling: floor(N w_i / W) copies of particle i, then
+      // R = N - sum of the floors multinomial draws from the fractional
+      // parts (sorted uniforms from the spacings of E_0 .. E_R), the
+      // ancestors listed in index order
+      double nsum = 0.0, rsum = 0.0;
+#pragma unroll
+      for (int e = 0; e < PM; ++e)
+        if (k0 + e < k1) {
+          const double nw = (double)N * w[e] / W;
+          const double fl = floor(nw);
+          nsum += fl;
+          rsum += nw - fl;
+        }
+      double sc2[2], tot2[2];
+      block_exscan2(nsum, rsum, shd, sc2, tot2);  // (its first barrier: C[N-1] was read)
+      const int R = N - (int)tot2[0];
+      {
+        double c = sc2[1];
+#pragma unroll
+        for (int e = 0; e < PM; ++e)
+          if (k0 + e < k1) {
+            const double nw = (double)N * w[e] / W;
+            c += nw - floor(nw);
+            C[k0 + e] = c;  // the residual CDF replaces the CDF
+          }
+      }
+      // S_R, the spacings' prefix at R, from the thread that owns index R
+      double *sR = (double *)(((uintptr_t)(cnt + N) + 7) & ~(uintptr_t)7);
+      if (R < N) {
+        if (k0 <= R && R < k1) {
+          double a = eoff;
+#pragma unroll
+          for (int e = 0; e < PM; ++e)
+            if (k0 + e <= R) a += eg[e];
+          *sR = a;
+        }
+      } else if (tid == 0) {
+        *sR = SN;
+      }
+      __syncthreads();
+      const double SR = *sR, Wr = C[N - 1];
+      double sacc = eoff;
+      int i = 0;
+#pragma unroll
+      for (int e = 0; e < PM; ++e) {
+        const int k = k0 + e;
+        if (k < k1 && k < R) {
+          sacc += eg[e];
+          const double v = (sacc / SR) * Wr;
+          i = e == 0 ? lds_search_blocked(C, N, v) : lds_search(C, N, i, v);
+          atomicAdd(cnt + i, 1);
+        }
+      }
+      __syncthreads();
+      // total offspring of each particle; positions from one block scan
+      int o[PM];
+      double osum = 0.0;
+#pragma unroll
+      for (int e = 0; e < PM; ++e) {
+        o[e] = 0;
+        if (k0 + e < k1) o[e] = (int)floor((double)N * w[e] / W) + cnt[k0 + e];
+        osum += (double)o[e];
+      }
+      double otot;
+      int pos = (int)block_exscan(osum, shd, &otot);
+#pragma unroll
+      for (int e = 0; e < PM; ++e) {
+        const int k = k0 + e;
+        if (k < k1) {
+          for (int j = 0; j < o[e]; ++j) Ag[pos++] = k;
+          cnt[k] = o[e];
+        }
+      }
+    } else {
+      // 4. ancestors in the LDS CDF and the offspring counts: the sorted
+      // points are exponential spacings (multinomial), one uniform offset on
+      // the lattice k / N (systematic) or one uniform in each stratum
+      // [k / N, (k + 1) / N) (stratified)
+      double sacc = eoff;
+      int i = 0;
+      const double usys =
+          scheme == RS_SYSTEMATIC
+              ? u01d(philox(0u, (uint32_t)m, (uint32_t)t, (P_RESAMPLE << 24) | 1u, E.key).x)
+              : 0.0;
+      int cached = -1;
+      uint4 rq = make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < PM; ++e) {
+        const int k = k0 + e;
+        if (k < k1) {
+          double v;
+          if (scheme == RS_MULTINOMIAL) {
+            sacc += eg[e];
+            v = (sacc / SN) * W;
+          } else if (scheme == RS_SYSTEMATIC) {
+            v = (((double)k + usys) / (double)N) * W;
+          } else {
+            if ((k >> 2) != cached) {
+              cached = k >> 2;
+              rq = philox((uint32_t)cached, (uint32_t)m, (uint32_t)t, (P_RESAMPLE << 24) | 2u,
+                          E.key);
+            }
+            const int l = k & 3;
+            const uint32_t wq = l == 0 ? rq.x : l == 1 ? rq.y : l == 2 ? rq.z : rq.w;
+            v = (((double)k + u01d(wq)) / (double)N) * W;
+          }
+          i = e == 0 ? lds_search_blocked(C, N, v) : lds_search(C, N, i, v);
+          Ag[k] = i;
+          atomicAdd(cnt + i, 1);
+        }
+      }
     }
   }
   __syncthreads();
@@ -428,7 +577,7 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
         if (k0 + e < k1) px += (double)cnt[k0 + e] * (double)xb[c][e];
         wx += w[e] * (double)xb[c][e];
       }
-      red[1 + c] = px;
+      red[1 + c] = resample ? px : wx;  // kept particles: the weighted estimate
       red[1 + D + c] = wx;
     }
   } else {
@@ -448,7 +597,7 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
       num = W * W;  // ESS = W^2 / sum w^2
       den = a;
     } else if (tid <= D) {
-      den = (double)N;
+      den = resample ? (double)N : W;
       dst = gptr(E.fmean + (size_t)m * D + (tid - 1));
     } else {
       dst = gptr(E.fmeanw + (size_t)m * D + (tid - 1 - D));
@@ -460,31 +609,36 @@ __device__ __forceinline__ void resample_wg(const WgJob *__restrict__ jobs,
       f[2] = a;  // sum w^2
       f[3] = deg ? 1.0 : 0.0;
       f[4] = SN;
+      f[FREC_KEPT] = resample ? 0.0 : 1.0;
     }
   }
-  if (tid == T5) f[5] = deg ? -INFINITY : lg_prev + mx + log(W / (double)N) + E.lognorm;
+  // (the first stage of an auxiliary filter adds its factor of the
+  // evidence without the Gaussian constant, which the second stage adds)
+  if (tid == T5)
+    f[5] = deg ? -INFINITY
+               : lg_prev + mx + log(W / (double)N) + (stage == 1 ? 0.0 : E.lognorm);
 }
 
 // The kernel: PMAX is the largest ceil(N / BD) of the launch's filters; each
 // workgroup runs the body compiled for its own filter's count (a uniform
 // branch), so that small filters in a launch with large ones read no more
 // than they need.
-template <int BD, int D, int PMAX>
+template <int BD, int D, int PMAX, bool CUSTOM>
 __global__ void __launch_bounds__(BD)
 k_resample_wg(const WgJob *__restrict__ jobs, const FusedEns *__restrict__ ens, IvArg iv,
-              int32_t *const *__restrict__ counts, int xb_parity) {
+              int32_t *const *__restrict__ counts, int xb_parity, int stage) {
   if constexpr (PMAX == 1) {
-    resample_wg<BD, D, 1>(jobs, ens, iv, counts, xb_parity);
+    resample_wg<BD, D, 1, CUSTOM>(jobs, ens, iv, counts, xb_parity, stage);
   } else {
     const int P = (ens[jobs[blockIdx.x].ens].N + BD - 1) / BD;
     if (P <= 1)
-      resample_wg<BD, D, 1>(jobs, ens, iv, counts, xb_parity);
+      resample_wg<BD, D, 1, CUSTOM>(jobs, ens, iv, counts, xb_parity, stage);
     else if (P <= 2 || PMAX == 2)
-      resample_wg<BD, D, (PMAX >= 2 ? 2 : 1)>(jobs, ens, iv, counts, xb_parity);
+      resample_wg<BD, D, (PMAX >= 2 ? 2 : 1), CUSTOM>(jobs, ens, iv, counts, xb_parity, stage);
     else if (P <= 4 || PMAX == 4)
-      resample_wg<BD, D, (PMAX >= 4 ? 4 : 1)>(jobs, ens, iv, counts, xb_parity);
+      resample_wg<BD, D, (PMAX >= 4 ? 4 : 1), CUSTOM>(jobs, ens, iv, counts, xb_parity, stage);
     else
-      resample_wg<BD, D, PMAX>(jobs, ens, iv, counts, xb_parity);
+      resample_wg<BD, D, PMAX, CUSTOM>(jobs, ens, iv, counts, xb_parity, stage);
   }
 }
 
@@ -508,14 +662,19 @@ size_t resample_wg_lds(int N, int BD) {
 
 hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                               const FusedEns *d_ens, IvArg iv, int32_t *const *d_counts,
-                              int xb_parity, hipStream_t s) {
+                              int xb_parity, bool custom, int stage, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
   const size_t lds = resample_wg_lds(max_n, BD);
   const int pm = BD < 1024 ? 1 : (max_n <= 1024 ? 1 : max_n <= 2048 ? 2 : max_n <= 4096 ? 4 : 8);
   if (BD < 1024 && max_n > BD) return hipErrorInvalidValue;
   if (max_n > RS_MAX_P * 1024) return hipErrorInvalidValue;
-#define PF_RS_LAUNCH(B, DD, P) \
-  k_resample_wg<B, DD, P><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, d_counts, xb_parity)
+#define PF_RS_LAUNCH(B, DD, P)                                                                  \
+  do {                                                                                          \
+    if (custom)                                                                                 \
+      k_resample_wg<B, DD, P, true><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, d_counts, xb_parity, stage);  \
+    else                                                                                        \
+      k_resample_wg<B, DD, P, false><<<n_jobs, B, lds, s>>>(d_jobs, d_ens, iv, d_counts, xb_parity, stage); \
+  } while (0)
 #define PF_RS_BD(DD)                 \
   if (BD == 64) PF_RS_LAUNCH(64, DD, 1); \
   else if (BD == 128) PF_RS_LAUNCH(128, DD, 1); \
@@ -586,15 +745,15 @@ hipError_t set_filter_wg_lds_limit() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_filter_wg<1, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  const void *rs[] = {(const void *)k_resample_wg<256, 0, 1>,  (const void *)k_resample_wg<512, 0, 1>,
-                      (const void *)k_resample_wg<1024, 0, 1>, (const void *)k_resample_wg<1024, 0, 2>,
-                      (const void *)k_resample_wg<1024, 0, 4>, (const void *)k_resample_wg<1024, 0, 8>,
-                      (const void *)k_resample_wg<256, 1, 1>,  (const void *)k_resample_wg<512, 1, 1>,
-                      (const void *)k_resample_wg<1024, 1, 1>, (const void *)k_resample_wg<1024, 1, 2>,
-                      (const void *)k_resample_wg<1024, 1, 4>, (const void *)k_resample_wg<1024, 1, 8>,
-                      (const void *)k_resample_wg<256, 3, 1>,  (const void *)k_resample_wg<512, 3, 1>,
-                      (const void *)k_resample_wg<1024, 3, 1>, (const void *)k_resample_wg<1024, 3, 2>,
-                      (const void *)k_resample_wg<1024, 3, 4>, (const void *)k_resample_wg<1024, 3, 8>};
+#define PF_RS_PAIR(B, DD, P) \
+  (const void *)k_resample_wg<B, DD, P, false>, (const void *)k_resample_wg<B, DD, P, true>
+  const void *rs[] = {PF_RS_PAIR(256, 0, 1),  PF_RS_PAIR(512, 0, 1),  PF_RS_PAIR(1024, 0, 1),
+                      PF_RS_PAIR(1024, 0, 2), PF_RS_PAIR(1024, 0, 4), PF_RS_PAIR(1024, 0, 8),
+                      PF_RS_PAIR(256, 1, 1),  PF_RS_PAIR(512, 1, 1),  PF_RS_PAIR(1024, 1, 1),
+                      PF_RS_PAIR(1024, 1, 2), PF_RS_PAIR(1024, 1, 4), PF_RS_PAIR(1024, 1, 8),
+                      PF_RS_PAIR(256, 3, 1),  PF_RS_PAIR(512, 3, 1),  PF_RS_PAIR(1024, 3, 1),
+                      PF_RS_PAIR(1024, 3, 2), PF_RS_PAIR(1024, 3, 4), PF_RS_PAIR(1024, 3, 8)};
+#undef PF_RS_PAIR
   for (const void *f : rs) {
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

@@ -217,8 +217,11 @@ __device__ __forceinline__ void grid_steps(const int4 *__restrict__ ptab, int n_
     const float *Xin = parity ? E.X1 : E.X0;
     float *Xout = parity ? E.X0 : E.X1;
     Slot4 S;
+    // (an auxiliary filter's particles always come through the ancestors its
+    // first stage has just drawn)
+    const bool thru = pending || E.apf;
     if (on) {
-      const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
+      const int src = thru ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
       const gmem<f4v> *in = gptr((const f4v *)(Xin + ((size_t)m * N + src) * dx));
       const f4v a = in[sl], b = in[slots + sl];
       S.v = make_float4(a.x, a.y, a.z, a.w);
@@ -244,7 +247,13 @@ __device__ __forceinline__ void grid_steps(const int4 *__restrict__ ptab, int n_
       for (int qq = wid; qq < ppb; qq += nwaves) {
         const int4 pq = ptab[p0 + qq];
         if (pq.x >= 0) {
-          const float l = wave_loglik(md, planes + qq * nn, yb + E.yoff, lane);
+          float l = wave_loglik(md, planes + qq * nn, yb + E.yoff, lane);
+          // auxiliary filter: divided by the pilot likelihood of the ancestor
+          if (E.apf && lane == 0) {
+            const int a = min(max(gptr(E.A)[(size_t)pq.y * N + pq.z], 0), N - 1);
+            l -= gptr(E.lpil)[(size_t)pq.y * N + a];
+            l = l == l ? l : -INFINITY;
+          }
           if (lane == 0) gptr(E.lw)[(size_t)pq.y * N + pq.z] = l;
         }
       }
@@ -336,6 +345,70 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
       if (threadIdx.x == 0) lw[(size_t)m * N + i] = l;
     }
     __syncthreads();
+  }
+}
+
+// Auxiliary filters: the pilot of one particle per workgroup -- its
+// noise-free S-step Euler path on the grid (v planes double-buffered in LDS,
+// w in LDS, updated in place: a node's w step reads only its own v and w)
+// -- its log-likelihood, kept for the second stage, and the first-stage
+// log-weight lwc + log g(y | mu).
+constexpr int PILOT_THREADS = 256;
+__global__ void __launch_bounds__(PILOT_THREADS)
+k_grid_pilot(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pending) {
+  const int t = iv_t(iv);
+  const float *y = iv_y(iv, t);
+  const FusedEns &E = ens[e];
+  const ModelDev md = E.md;
+  const int J = md.J, nn = J * J, N = E.N;
+  const int p = blockIdx.x, m = p / N, i = p - m * N;
+  extern __shared__ float sh[];
+  float *v = sh, *vn = sh + nn, *w = sh + 2 * nn, *red = sh + 3 * nn;
+  const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
+  const gmem<float> *x = gptr((parity ? E.X1 : E.X0) + ((size_t)m * N + src) * 2 * nn);
+  for (int n = threadIdx.x; n < nn; n += PILOT_THREADS) {
+    v[n] = x[n];
+    w[n] = x[nn + n];
+  }
+  __syncthreads();
+  const float a = md.p0, D = md.p1, eps = md.p2, gam = md.p3, h = md.h;
+  for (int st = 0; st < md.S; ++st) {
+    for (int n = threadIdx.x; n < nn; n += PILOT_THREADS) {
+      const int r = n / J, c = n - r * J;
+      const float vc = v[n], wc = w[n];
+      float lap = 0.f;
+      if (r > 0) lap += v[n - J] - vc;
+      if (r < J - 1) lap += v[n + J] - vc;
+      if (c > 0) lap += v[n - 1] - vc;
+      if (c < J - 1) lap += v[n + 1] - vc;
+      const float fv = vc * (vc - a) * (1.f - vc) - wc + D * lap;
+      const float fw = eps * (vc - gam * wc);
+      vn[n] = fmaf(h, fv, vc);
+      w[n] = fmaf(h, fw, wc);
+    }
+    __syncthreads();
+    float *tmp = v;
+    v = vn;
+    vn = tmp;
+  }
+  float acc = 0.f;
+  for (int k = threadIdx.x; k < md.dy; k += PILOT_THREADS) {
+    const float rr = gptr(y)[E.yoff + k] - v[gptr(md.obs_idx)[k]];
+    acc = fmaf(rr, rr, acc);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float tot = 0.f;
+    for (int k = 0; k < PILOT_THREADS / 64; ++k) tot += red[k];
+    float pl = -tot * md.inv2var;
+    pl = pl == pl ? pl : -INFINITY;
+    const size_t o = (size_t)m * N + i;
+    gptr(E.lpil)[o] = pl;
+    const float lam = pl + gptr(E.lwc)[o];
+    gptr(E.lw)[o] = lam == lam ? lam : -INFINITY;
   }
 }
 
@@ -431,8 +504,11 @@ k_grid_filter_fold(int N, int dx, int nch, const double *__restrict__ part,
     a += o[c];
     b += o[(size_t)dx + c];
   }
-  fmean[(size_t)m * dx + c] = a / (double)N;
-  fmeanw[(size_t)m * dx + c] = b / fstat[(size_t)m * FREC + 1];
+  const double W = fstat[(size_t)m * FREC + 1];
+  // a filter that kept its particles (ESS schedule) reports the weighted mean
+  const bool kept = fstat[(size_t)m * FREC + FREC_KEPT] != 0.0;
+  fmean[(size_t)m * dx + c] = kept ? b / W : a / (double)N;
+  fmeanw[(size_t)m * dx + c] = b / W;
 }
 
 // Ensemble means: one thread per state element, filters in a fixed order.
@@ -502,8 +578,11 @@ k_grid_filter_fold_b(const int4 *__restrict__ jobs, const FusedEns *__restrict__
     a += o[c];
     b += o[(size_t)dx + c];
   }
-  gptr(E.fmean)[(size_t)m * dx + c] = a / (double)E.N;
-  gptr(E.fmeanw)[(size_t)m * dx + c] = b / gptr(E.fstat)[(size_t)m * FREC + 1];
+  const double W = gptr(E.fstat)[(size_t)m * FREC + 1];
+  // a filter that kept its particles (ESS schedule) reports the weighted mean
+  const bool kept = gptr(E.fstat)[(size_t)m * FREC + FREC_KEPT] != 0.0;
+  gptr(E.fmean)[(size_t)m * dx + c] = kept ? b / W : a / (double)E.N;
+  gptr(E.fmeanw)[(size_t)m * dx + c] = b / W;
 }
 
 __global__ void __launch_bounds__(GB)
@@ -673,6 +752,13 @@ int grid_resident_blocks(const ModelDev &md) {
                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_stream_step<4>, threads, lds);
   if (e != hipSuccess) return 1024;
   return std::max(1, per_cu) * prop.multiProcessorCount;
+}
+
+hipError_t launch_grid_pilot(const FusedEns *d_ens, int e, int M, int N, int J, IvArg iv,
+                             int parity, int pending, hipStream_t s) {
+  const size_t lds = sizeof(float) * (3 * (size_t)J * J + PILOT_THREADS / 64);
+  k_grid_pilot<<<(unsigned)((size_t)M * N), PILOT_THREADS, lds, s>>>(d_ens, e, iv, parity, pending);
+  return hipGetLastError();
 }
 
 hipError_t launch_grid_init(const EnsDev &e, float *X, hipStream_t s) {

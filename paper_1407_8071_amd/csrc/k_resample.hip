@@ -11,6 +11,8 @@
 // same two-level layout (Sl, soff).  Uniforms come from exponential spacings:
 // E_j = -ln u_j (j = 0..N), S_k = sum_{j<=k} E_j, U_k = S_k / S_N, which are
 // the order statistics of N uniforms, so the ancestors come out ascending.
+#include <algorithm>
+
 #include "pf_internal.h"
 
 namespace pfk {
@@ -431,9 +433,21 @@ hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, in
 
 namespace {
 __global__ void k_set_i32(int *p, int v) { *p = v; }
+
+__global__ void __launch_bounds__(256) k_fill_f32(float *p, float v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    p[i] = v;
+}
 }  // namespace
 
 // a one-thread kernel instead of a memset, so that it is safe in graphs
+hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+  k_fill_f32<<<(unsigned)blocks, 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_i32(int *p, int v, hipStream_t s) {
   k_set_i32<<<1, 1, 0, s>>>(p, v);
   return hipGetLastError();

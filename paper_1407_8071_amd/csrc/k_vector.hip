@@ -130,14 +130,59 @@ k_vec_prop_batched(const int4 *__restrict__ tiles, const FusedEns *__restrict__ 
   // (pointers from the ensemble table: global-address-space accesses)
   const gmem<float> *Xin = gptr(parity ? E.X1 : E.X0);
   gmem<float> *Xout = gptr(parity ? E.X0 : E.X1);
-  const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
+  // (an auxiliary filter's particles always come through the ancestors its
+  // first stage has just drawn)
+  const bool thru = pending || E.apf;
+  const int src = thru ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
   float x[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) x[c] = Xin[((size_t)m * D + c) * N + src];
   em_steps<D>(E.md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * E.md.S, E.md.S, x);
 #pragma unroll
   for (int c = 0; c < D; ++c) Xout[((size_t)m * D + c) * N + i] = x[c];
-  gptr(E.lw)[(size_t)m * N + i] = loglik<D>(E.md, x, y + E.yoff);
+  float l = loglik<D>(E.md, x, y + E.yoff);
+  // auxiliary filter: the second-stage weight divides by the pilot
+  // likelihood of the particle's ancestor
+  if (E.apf) l -= gptr(E.lpil)[(size_t)m * N + src];
+  gptr(E.lw)[(size_t)m * N + i] = l == l ? l : -INFINITY;
+}
+
+// Auxiliary filters: the pilot of particle i -- its noise-free S-step Euler
+// path mu_i, summed in the same FP32 offset form as the stochastic steps --
+// and the first-stage log-weight lwc_i + log g(y | mu_i); the pilot
+// log-likelihood is kept for the second stage.
+template <int D>
+__global__ void __launch_bounds__(VEC_BLOCK)
+k_vec_pilot(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pending) {
+  const int t = iv_t(iv);
+  const float *y = iv_y(iv, t);
+  const FusedEns &E = ens[e];
+  const int m = blockIdx.y, i = blockIdx.x * VEC_BLOCK + threadIdx.x, N = E.N;
+  if (i >= N) return;
+  const gmem<float> *Xin = gptr(parity ? E.X1 : E.X0);
+  const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
+  const ModelDev md = E.md;
+  float x0[D], off[D], x[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    x0[c] = Xin[((size_t)m * D + c) * N + src];
+    off[c] = 0.f;
+  }
+  for (int st = 0; st < md.S; ++st) {
+    float f[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) x[c] = x0[c] + off[c];
+    drift<D>(md, x, f);
+#pragma unroll
+    for (int c = 0; c < D; ++c) off[c] = fmaf(md.h, f[c], off[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) x[c] = x0[c] + off[c];
+  const float pl = loglik<D>(md, x, y + E.yoff);
+  const size_t o = (size_t)m * N + i;
+  gptr(E.lpil)[o] = pl;
+  const float lam = pl + gptr(E.lwc)[o];
+  gptr(E.lw)[o] = lam == lam ? lam : -INFINITY;
 }
 
 template <int D>
@@ -279,6 +324,16 @@ hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, int 
     k_vec_prop_batched<3><<<n_tiles, tile_width, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
   else
     k_vec_prop_batched<1><<<n_tiles, tile_width, 0, s>>>(d_tiles, d_ens, iv, parity, pending);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_pilot(int D, const FusedEns *d_ens, int e, int M, int N, IvArg iv,
+                            int parity, int pending, hipStream_t s) {
+  const dim3 g((unsigned)((N + VEC_BLOCK - 1) / VEC_BLOCK), (unsigned)M);
+  if (D == 3)
+    k_vec_pilot<3><<<g, VEC_BLOCK, 0, s>>>(d_ens, e, iv, parity, pending);
+  else
+    k_vec_pilot<1><<<g, VEC_BLOCK, 0, s>>>(d_ens, e, iv, parity, pending);
   return hipGetLastError();
 }
 

@@ -58,6 +58,8 @@ struct Ens {
   int blocks = 1024;       // grid model: resident workgroups of the stepping kernels
   int32_t *cnt = nullptr;  // grid model: offspring counts [M][N]
   double *gpart = nullptr; // grid model: estimator partial sums
+  float *lwc = nullptr;    // ESS schedule, auxiliary filter: carried log-weights [M][N]
+  bool apf = false;        // auxiliary particle filter
   // learned proposal (FH-N): FP32 parameters and each node's nearest observation
   bool learned = false;
   float *params = nullptr;
@@ -69,10 +71,11 @@ struct Ens {
 // One launch of the filter-per-workgroup kernel: every filter of the
 // ensembles of one (state dimension, workgroup size) class.
 // kinds of workgroup-per-filter launches
-enum { CLASS_FILTER_WG = 0, CLASS_RESAMPLE_VEC = 1, CLASS_RESAMPLE_GRID = 2 };
+enum { CLASS_FILTER_WG = 0, CLASS_RESAMPLE_VEC = 1, CLASS_RESAMPLE_GRID = 2, CLASS_APF_FIRST = 3 };
 struct WgClass {
   int kind;
   int D, BD, max_n;  // D = 0: grid-model resampling class
+  bool custom = false;  // resampling classes: another scheme or the ESS schedule
   std::vector<pfk::WgJob> jobs;
   pfk::WgJob *d_jobs = nullptr;
 };
@@ -88,13 +91,14 @@ int wg_block(int N, int bd_min = 256) {
 // Offsets of every array of one ensemble inside the workspace.
 struct Layout {
   size_t obs, pmean, psd, X0, X1, lw, A, Cl, Sl, tile, coff, soff, fstat, mpart, wpart, fmean,
-      fmeanw, emean, cnt, gpart, params, nearest, end;
+      fmeanw, emean, cnt, gpart, params, nearest, lwc, lpil, end;
 };
 
 constexpr int LEARNED_IN = 22, LEARNED_OUT = 2;  // FH-N node features, (u_v, u_w)
 constexpr int LEARNED_MAX_J = 48;
 
-Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bool learned) {
+Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bool learned,
+                 bool carried, bool auxiliary) {
   Layout L{};
   size_t o = base;
   auto take = [&](size_t bytes) {
@@ -126,6 +130,10 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bo
   L.gpart = take(grid ? sizeof(double) * (size_t)M * pfk::grid_est_chunks(N) * 2 * dx : 0);
   L.params = take(learned ? sizeof(float) * (size_t)pfk::mlp_nparams(LEARNED_IN, LEARNED_OUT) : 0);
   L.nearest = take(learned ? sizeof(int32_t) * (size_t)(dx / 2) : 0);
+  // ESS schedule: the carried log-weights
+  L.lwc = take(carried ? sizeof(float) * MN : 0);
+  // auxiliary filter: the pilot log-likelihoods
+  L.lpil = take(auxiliary ? sizeof(float) * MN : 0);
   L.end = o;
   return L;
 }
@@ -134,7 +142,7 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bo
 // launch plan's tables sized for any tuning (workgroup job lists, at most one
 // job per filter per class; batched propagation tiles of the narrowest
 // width; the batched grid tables) and the device interval counter.
-constexpr int MAX_CLASSES = 32;
+constexpr int MAX_CLASSES = 40;
 constexpr int MIN_PROP_TILE = 64;
 
 struct CtxSizes {
@@ -225,13 +233,44 @@ pf_status check_all(const pf_model_desc *models, int n_models, const pf_ensemble
     if (d.M < 1 || d.N < 1 || d.N > (1 << 26) || (int64_t)d.M * d.N > (int64_t)1 << 30)
       return fail(PF_ERR_INVALID_ARG, "ensemble %d: bad M=%d N=%d", e, d.M, d.N);
     if (d.M > 65535) return fail(PF_ERR_INVALID_ARG, "ensemble %d: M > 65535", e);
-    if (d.flags & ~PF_ENS_LEARNED)
+    if (d.flags & ~(PF_ENS_LEARNED | PF_ENS_AUXILIARY))
       return fail(PF_ERR_INVALID_ARG, "ensemble %d: unknown flags 0x%x", e, d.flags);
+    if ((d.flags & PF_ENS_AUXILIARY) && ((d.flags & PF_ENS_LEARNED) || d.ess_threshold != 0.0))
+      return fail(PF_ERR_UNSUPPORTED,
+                  "ensemble %d: the auxiliary filter runs the bootstrap transition and resamples "
+                  "at every interval (no PF_ENS_LEARNED, ess_threshold 0)", e);
     if ((d.flags & PF_ENS_LEARNED) &&
         (models[d.model].kind != PF_MODEL_FHN || models[d.model].grid_j > LEARNED_MAX_J))
       return fail(PF_ERR_UNSUPPORTED, "ensemble %d: the learned proposal needs an FH-N model with J <= %d",
                   e, LEARNED_MAX_J);
+    if (d.scheme < PF_RESAMPLE_MULTINOMIAL || d.scheme > PF_RESAMPLE_RESIDUAL)
+      return fail(PF_ERR_INVALID_ARG, "ensemble %d: unknown resampling scheme %d", e, d.scheme);
+    if (d.reserved != 0) return fail(PF_ERR_INVALID_ARG, "ensemble %d: reserved must be 0", e);
+    if (!(d.ess_threshold >= 0.0 && d.ess_threshold <= 1.0))
+      return fail(PF_ERR_INVALID_ARG, "ensemble %d: ess_threshold must be in [0, 1]", e);
   }
+  return PF_OK;
+}
+
+// An ensemble with another scheme or an ESS schedule runs on the fused
+// path's per-filter resampling kernel only.
+bool custom_resampling(const pf_ensemble_desc &d) {
+  return d.scheme != PF_RESAMPLE_MULTINOMIAL || d.ess_threshold > 0.0 ||
+         (d.flags & PF_ENS_AUXILIARY) != 0;
+}
+
+// carried log-weights: the ESS schedule and the auxiliary filter
+bool carried_weights(const pf_ensemble_desc &d) {
+  return d.ess_threshold > 0.0 || (d.flags & PF_ENS_AUXILIARY) != 0;
+}
+
+pf_status check_resampling(const pf_ensemble_desc *ens, int n_ens, uint32_t options) {
+  for (int e = 0; e < n_ens; ++e)
+    if (custom_resampling(ens[e]) && (!(options & PF_OPT_FUSED) || ens[e].N > pfk::WG_MAX_N))
+      return fail(PF_ERR_UNSUPPORTED,
+                  "ensemble %d: resampling schemes other than multinomial, the ESS schedule and "
+                  "the auxiliary filter need a PF_OPT_FUSED context and N <= %d", e,
+                  pfk::WG_MAX_N);
   return PF_OK;
 }
 
@@ -248,7 +287,8 @@ size_t total_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int
     const pf_model_desc &m = models[ens[e].model];
     const int T = (ens[e].N + pfk::TILE - 1) / pfk::TILE;
     o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T, m.kind == PF_MODEL_FHN,
-                  (ens[e].flags & PF_ENS_LEARNED) != 0)
+                  (ens[e].flags & PF_ENS_LEARNED) != 0, carried_weights(ens[e]),
+                  (ens[e].flags & PF_ENS_AUXILIARY) != 0)
             .end;
   }
   return o + ctx_bytes(models, ens, n_ens);
@@ -477,6 +517,25 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     PF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     g = ctx->side;
   }
+  // 0. auxiliary filters: the pilot of every particle and the first-stage
+  //    resampling from its weights (the grid ensembles' on the grid chain)
+  if (!resample_only) {
+    for (size_t e = 0; e < ctx->ens.size(); ++e) {
+      const Ens &E = ctx->ens[e];
+      if (!E.apf) continue;
+      if (E.grid)
+        PF_HIP(pfk::launch_grid_pilot(ctx->d_fens, (int)e, E.d.M, E.d.N, E.dev.md.J, iv, parity,
+                                      pending, g));
+      else
+        PF_HIP(pfk::launch_vec_pilot(E.dx, ctx->d_fens, (int)e, E.d.M, E.d.N, iv, parity, pending,
+                                     s));
+    }
+    for (const WgClass &c : ctx->classes)
+      if (c.kind == CLASS_APF_FIRST)
+        PF_HIP(pfk::launch_resample_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n,
+                                       ctx->d_fens, iv, ctx->d_counts, parity, true, 1,
+                                       c.D == 0 ? g : s));
+  }
   // 1. propagation + weighting: the batched vector tiles (profiled: the
   //    kernel that carries the interval), the single-kernel classes, and the
   //    grid model's stepping kernel (profiled)
@@ -519,10 +578,10 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
   for (const WgClass &c : ctx->classes) {
     if (c.kind == CLASS_RESAMPLE_VEC)
       PF_HIP(pfk::launch_resample_wg(c.D, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                     iv, ctx->d_counts, out, s));
+                                     iv, ctx->d_counts, out, c.custom, 0, s));
     else if (c.kind == CLASS_RESAMPLE_GRID)
       PF_HIP(pfk::launch_resample_wg(0, c.BD, c.d_jobs, (int)c.jobs.size(), c.max_n, ctx->d_fens,
-                                     iv, ctx->d_counts, out, g));
+                                     iv, ctx->d_counts, out, c.custom, 0, g));
   }
   for (const auto &gg : ctx->ggroups)
     PF_HIP(pfk::launch_grid_estimate_batched(gg.J, gg.d_part, (int)gg.part_jobs.size(), gg.d_fold,
@@ -630,20 +689,24 @@ pf_status materialise(pf_ctx *ctx, hipStream_t s) {
 pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
   PF_TRY(check_tuning(u));
   const int n_ens = (int)ctx->ens.size();
-  for (Ens &E : ctx->ens) E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N && u.vec_single_kernel;
+  // (the single-kernel path resamples multinomially at every interval)
+  for (Ens &E : ctx->ens)
+    E.wg = !E.grid && E.d.N <= pfk::WG_MAX_N && u.vec_single_kernel && !custom_resampling(E.d);
   ctx->classes.clear();
   int next_class = 0;
   const int BDs[5] = {1024, 512, 256, 128, 64};
-  auto add_class = [&](int kind, int D, int BD, int bd_min, auto member) {
+  auto add_class = [&](int kind, int D, int BD, int bd_min, bool custom, auto member) {
     WgClass c;
     c.kind = kind;
     c.D = D;
     c.BD = BD;
+    c.custom = custom;
     c.max_n = 0;
     std::vector<std::pair<int, int>> order;  // (N, ensemble)
     for (int e = 0; e < n_ens; ++e) {
       const Ens &E = ctx->ens[(size_t)e];
-      if (member(E) && wg_block(E.d.N, bd_min) == BD) order.push_back({E.d.N, e});
+      if (member(E) && custom_resampling(E.d) == custom && wg_block(E.d.N, bd_min) == BD)
+        order.push_back({E.d.N, e});
     }
     if (order.empty()) return;
     std::stable_sort(order.begin(), order.end(),
@@ -663,15 +726,26 @@ pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
   const int wg_min = std::max(256, u.resample_bd_min);
   for (int D : {3, 1}) {
     for (int BD : BDs) {
-      if (BD >= 256) add_class(CLASS_FILTER_WG, D, BD, wg_min, [D](const Ens &E) { return E.wg && E.dx == D; });
-      add_class(CLASS_RESAMPLE_VEC, D, BD, u.resample_bd_min, [D](const Ens &E) {
-        return !E.grid && !E.wg && !E.tiled && E.dx == D;
-      });
+      if (BD >= 256)
+        add_class(CLASS_FILTER_WG, D, BD, wg_min, false,
+                  [D](const Ens &E) { return E.wg && E.dx == D; });
+      for (bool custom : {false, true})
+        add_class(CLASS_RESAMPLE_VEC, D, BD, u.resample_bd_min, custom, [D](const Ens &E) {
+          return !E.grid && !E.wg && !E.tiled && E.dx == D;
+        });
     }
   }
   for (int BD : BDs)
-    add_class(CLASS_RESAMPLE_GRID, 0, BD, u.resample_bd_min,
-              [](const Ens &E) { return E.grid && E.d.N <= pfk::WG_MAX_N; });
+    for (bool custom : {false, true})
+      add_class(CLASS_RESAMPLE_GRID, 0, BD, u.resample_bd_min, custom,
+                [](const Ens &E) { return E.grid && E.d.N <= pfk::WG_MAX_N; });
+  // the first-stage resampling of auxiliary filters (its estimates are
+  // overwritten by the second stage's)
+  for (int D : {3, 1, 0})
+    for (int BD : BDs)
+      add_class(CLASS_APF_FIRST, D, BD, u.resample_bd_min, true, [D](const Ens &E) {
+        return E.apf && (E.grid ? 0 : E.dx) == D;
+      });
   if (next_class > MAX_CLASSES) return fail(PF_ERR_STATE, "too many launch classes");
   // batched propagation tiles of the vector ensembles not run by the single
   // filter-per-workgroup kernel
@@ -759,6 +833,7 @@ pf_status reset_filters(pf_ctx *ctx, hipStream_t s) {
     PF_HIP(hipMemsetAsync(D.fstat, 0, sizeof(double) * (size_t)E.d.M * pfk::FREC, s));
     PF_HIP(hipMemsetAsync(D.emean, 0, sizeof(double) * 2 * (size_t)E.dx, s));
     PF_HIP(hipMemsetAsync(D.A, 0, sizeof(int32_t) * (size_t)E.d.M * E.d.N, s));
+    if (E.lwc) PF_HIP(pfk::launch_fill_f32(E.lwc, 0.f, (size_t)E.d.M * E.d.N, s));
     if (E.grid)
       PF_HIP(pfk::launch_grid_init(D, D.X[0], s));
     else
@@ -788,6 +863,7 @@ pf_status pf_workspace_bytes(const pf_model_desc *h_models, int32_t n_models,
   if (options > (PF_OPT_FUSED | PF_OPT_GRAPH)) return fail(PF_ERR_INVALID_ARG, "unknown options");
   PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
   if (options & PF_OPT_FUSED) PF_TRY(check_fused(h_models, h_ens, n_ens));
+  PF_TRY(check_resampling(h_ens, n_ens, options));
   *out_bytes = total_bytes(h_models, h_ens, n_ens);
   return PF_OK;
 }
@@ -802,6 +878,7 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     return fail(PF_ERR_INVALID_ARG, "PF_OPT_GRAPH needs PF_OPT_FUSED");
   PF_TRY(check_all(h_models, n_models, h_ens, n_ens));
   if (options & PF_OPT_FUSED) PF_TRY(check_fused(h_models, h_ens, n_ens));
+  PF_TRY(check_resampling(h_ens, n_ens, options));
   const size_t need = total_bytes(h_models, h_ens, n_ens);
   if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0)
     return fail(PF_ERR_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
@@ -833,7 +910,9 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
       E.prior_sd[(size_t)k] = (float)m.h_prior_sd[k];
     }
     E.learned = (E.d.flags & PF_ENS_LEARNED) != 0;
-    const Layout L = layout_of(base, E.d.M, E.d.N, E.dx, E.dy, E.T, E.grid, E.learned);
+    E.apf = (E.d.flags & PF_ENS_AUXILIARY) != 0;
+    const Layout L = layout_of(base, E.d.M, E.d.N, E.dx, E.dy, E.T, E.grid, E.learned,
+                               carried_weights(E.d), E.apf);
     base = L.end;
     pfk::EnsDev &D = E.dev;
     pfk::ModelDev &md = D.md;
@@ -896,6 +975,12 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     F.cnt = nullptr;
     F.gpart = nullptr;
     F.nch = 0;
+    F.scheme = E.d.scheme;
+    F.ess_thr = E.d.ess_threshold;
+    F.lwc = carried_weights(E.d) ? (float *)(ws + L.lwc) : nullptr;
+    E.lwc = F.lwc;
+    F.apf = E.apf ? 1 : 0;
+    F.lpil = E.apf ? (float *)(ws + L.lpil) : nullptr;
     if (E.grid) {
       E.cnt = (int32_t *)(ws + L.cnt);
       E.gpart = (double *)(ws + L.gpart);
@@ -947,6 +1032,7 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     INIT_TRY(hipMemsetAsync(D.emean, 0, sizeof(double) * 2 * (size_t)E.dx, s));
     // every ancestor index is valid from the start
     INIT_TRY(hipMemsetAsync(D.A, 0, sizeof(int32_t) * (size_t)E.d.M * E.d.N, s));
+    if (E.lwc) INIT_TRY(pfk::launch_fill_f32(E.lwc, 0.f, (size_t)E.d.M * E.d.N, s));
     if (E.grid)
       INIT_TRY(pfk::launch_grid_init(D, D.X[0], s));
     else
@@ -1139,6 +1225,24 @@ pf_status pf_set_logweights(pf_ctx *ctx, int32_t ens, const float *d_lw, void *s
   Ens *E = get_ens(ctx, ens);
   if (!E || !d_lw) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
   PF_HIP(hipMemcpyAsync(E->dev.lw, d_lw, sizeof(float) * (size_t)E->d.M * E->d.N,
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_get_carried_logweights(pf_ctx *ctx, int32_t ens, float *d_lwc, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_lwc) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  if (!E->lwc) return fail(PF_ERR_STATE, "ensemble %d has no ESS threshold", ens);
+  PF_HIP(hipMemcpyAsync(d_lwc, E->lwc, sizeof(float) * (size_t)E->d.M * E->d.N,
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_set_carried_logweights(pf_ctx *ctx, int32_t ens, const float *d_lwc, void *stream) {
+  Ens *E = get_ens(ctx, ens);
+  if (!E || !d_lwc) return fail(PF_ERR_INVALID_ARG, "bad context, ensemble or pointer");
+  if (!E->lwc) return fail(PF_ERR_STATE, "ensemble %d has no ESS threshold", ens);
+  PF_HIP(hipMemcpyAsync(E->lwc, d_lwc, sizeof(float) * (size_t)E->d.M * E->d.N,
                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return PF_OK;
 }

@@ -19,7 +19,8 @@ constexpr int TILE = TILE_THREADS * TILE_PER_THREAD;
 // 2 sum w^2, 3 sum of the tile's exponential variates (incl. E_N on the last).
 constexpr int TREC = 4;
 // Per-filter record (doubles): 0 mx, 1 W, 2 sum w^2, 3 degenerate flag,
-// 4 S_N, 5 log G_t^N (running), 6 ESS of the last interval.
+// 4 S_N, 5 log G_t^N (running), 6 ESS of the last interval, 7 kept flag
+// (FREC_KEPT).
 constexpr int FREC = 8;
 
 struct EnsDev {
@@ -72,7 +73,21 @@ struct FusedEns {
   int32_t *cnt;
   double *gpart;
   int32_t nch;
+  // resampling scheme (RS_*), and the ESS-triggered schedule: resample when
+  // ESS < ess_thr N (ess_thr > 0); lwc [M][N] holds the carried log-weights
+  // of particles that were not resampled (normalised to mean weight 1)
+  int32_t scheme;
+  double ess_thr;
+  float *lwc;
+  // auxiliary particle filter: pilot log-likelihoods [M][N] of the particles
+  // at the start of the interval (the first stage's weights are lwc + lpil)
+  int32_t apf;
+  float *lpil;
 };
+enum { RS_MULTINOMIAL = 0, RS_SYSTEMATIC = 1, RS_STRATIFIED = 2, RS_RESIDUAL = 3 };
+// per-filter record slot 7: 1.0 when the last interval kept its particles
+// (ESS above the threshold), so that the filter's estimate is the weighted one
+constexpr int FREC_KEPT = 7;
 
 // ---- vector models (OU, Lorenz 63): particles [M][dx][N] ------------------
 hipError_t launch_vec_init(const EnsDev &e, float *X, hipStream_t s);
@@ -104,9 +119,18 @@ hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int 
                             int resample_only, hipStream_t s);
 // resampling of each job's filter from its log-weights; offspring counts to
 // d_counts[ensemble] (an array of per-ensemble device pointers)
+// stage 0: the interval's resampling (or, for auxiliary filters, the
+// normalisation of the second-stage weights, which are carried); stage 1:
+// the first-stage resampling of auxiliary filters from their pilot weights
 hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                               const FusedEns *d_ens, IvArg iv, int32_t *const *d_counts,
-                              int xb_parity, hipStream_t s);
+                              int xb_parity, bool custom, int stage, hipStream_t s);
+// auxiliary filters: the pilot -- the noise-free S-step Euler path of every
+// particle and its log-likelihood -- and the first-stage log-weights
+hipError_t launch_vec_pilot(int D, const FusedEns *d_ens, int e, int M, int N, IvArg iv,
+                            int parity, int pending, hipStream_t s);
+hipError_t launch_grid_pilot(const FusedEns *d_ens, int e, int M, int N, int J, IvArg iv,
+                             int parity, int pending, hipStream_t s);
 // batched propagation + weighting of vector-model tiles {ens, filter, i0, -}
 hipError_t launch_vec_prop_batched(int D, const int4 *d_tiles, int n_tiles, int tile_width,
                                   const FusedEns *d_ens, IvArg iv, int parity, int pending,
@@ -148,6 +172,8 @@ int grid_steps_ppb(int J);
 hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, int *t_inc,
                                  hipStream_t s);
 hipError_t launch_set_i32(int *p, int v, hipStream_t s);
+// p[0 .. n) = v (a kernel, not a memset node, so that it may be captured)
+hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
 
 // ---- learned proposal (MLP in -> 64 -> 64 -> out, FP32 master parameters) ---
 constexpr int MLP_HIDDEN = 64;

@@ -88,6 +88,34 @@ def test_learned_flag_validation(pf):
     assert "static buffer holds" in pf.lib().pf_last_error().decode()
 
 
+def test_resampling_scheme_validation(pf):
+    l63 = pf_inputs.lorenz63()
+    ok = _bytes(pf, [l63], [(0, 2, 64, 0, 1, 2, 0, 0.5)], options=1)
+    assert ok[0] == 0
+    # the carried log-weights take M N floats more
+    base = _bytes(pf, [l63], [(0, 2, 64, 0, 1)], options=1)[1]
+    assert ok[1] >= base + 2 * 64 * 4
+    assert _bytes(pf, [l63], [(0, 2, 64, 0, 1, 4, 0, 0.0)], options=1)[0] == 1
+    assert "unknown resampling scheme" in pf.lib().pf_last_error().decode()
+    assert _bytes(pf, [l63], [(0, 2, 64, 0, 1, 0, 0, 1.5)], options=1)[0] == 1
+    assert _bytes(pf, [l63], [(0, 2, 64, 0, 1, 0, 0, -0.1)], options=1)[0] == 1
+    assert _bytes(pf, [l63], [(0, 2, 64, 0, 1, 0, 7, 0.0)], options=1)[0] == 1
+    # other schemes and the ESS schedule: fused path, N <= 8192 only
+    assert _bytes(pf, [l63], [(0, 2, 64, 0, 1, 1, 0, 0.0)], options=0)[0] == 2
+    assert _bytes(pf, [l63], [(0, 2, 64, 0, 1, 0, 0, 0.5)], options=0)[0] == 2
+    assert _bytes(pf, [l63], [(0, 1, 8193, 0, 1, 3, 0, 0.0)], options=1)[0] == 2
+    assert "PF_OPT_FUSED" in pf.lib().pf_last_error().decode()
+    # the auxiliary filter: fused, bootstrap transition, no ESS threshold
+    assert _bytes(pf, [l63], [(0, 2, 64, 2, 1)], options=1)[0] == 0
+    assert _bytes(pf, [l63], [(0, 2, 64, 2, 1)], options=0)[0] == 2
+    assert _bytes(pf, [l63], [(0, 2, 64, 2, 1, 0, 0, 0.5)], options=1)[0] == 2
+    f20 = pf_inputs.fhn(20)
+    assert _bytes(pf, [f20], [(0, 2, 64, 3, 1)], options=1)[0] == 2
+    assert _bytes(pf, [l63], [(0, 2, 64, 4, 1)], options=1)[0] == 1
+    # the default (multinomial at every interval) runs everywhere
+    assert _bytes(pf, [l63], [(0, 1, 8193, 0, 1, 0, 0, 0.0)], options=0)[0] == 0
+
+
 def test_init_rejects_missing_workspace_and_bad_order(pf):
     l63 = pf.PFModel(pf_inputs.lorenz63())
     md = (pf._ModelDesc * 1)(l63.desc)
