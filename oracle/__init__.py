@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KINDS = {"ou1d": 0, "lorenz63": 1, "fhn": 2}
+KINDS = {"ou1d": 0, "lorenz63": 1, "fhn": 2, "fhn_paper": 3}
 P_INIT, P_PROP, P_RESAMPLE, P_TRUTH_INIT, P_TRUTH_NOISE, P_OBS_NOISE, P_TRAIN, P_CONFIG = range(1, 9)
 TRUTH_STREAM = 0xFFFFFFFF
 
@@ -44,6 +44,7 @@ class _Model(C.Structure):
         ("h", C.c_double), ("p", C.c_double * 4), ("sd", C.c_double * 2),
         ("dy", C.c_int), ("obs_idx", C.POINTER(C.c_int)), ("obs_var", C.c_double),
         ("prior_mean", C.POINTER(C.c_double)), ("prior_sd", C.POINTER(C.c_double)),
+        ("q", C.c_double * 8),
     ]
 
 
@@ -98,6 +99,11 @@ def lib():
                                           _I32]),
             "or_apf_interval": (C.c_int, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D, _D,
                                           _D, _D, C.c_int, _D, _I32, _D, _D]),
+            "or_fhnp_region": (C.c_int, [M, _D, _I32]),
+            "or_fhnp_step": (C.c_int, [M, _U32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                       _D, _D]),
+            "or_transition": (None, [M, _U32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _D,
+                                     _D]),
             "or_filter_interval_sched": (C.c_int, [M, C.c_uint64, C.c_uint32, C.c_int, C.c_int, _D,
                                                    _D, _D, _D, C.c_int, C.c_double, _D, _I32, _D,
                                                    _D, _D, C.POINTER(C.c_int)]),
@@ -168,11 +174,12 @@ class Model:
         assert self.prior_mean.size == self.dx and self.prior_sd.size == self.dx
         p = list(spec["params"]) + [0.0] * (4 - len(spec["params"]))
         sd = list(spec["noise_sd"]) + [0.0] * (2 - len(spec["noise_sd"]))
+        q = list(spec.get("params_ext", ())) + [0.0] * (8 - len(spec.get("params_ext", ())))
         self.c = _Model(
             KINDS[self.kind], self.dx, self.J, self.S, float(spec["h"]),
             (C.c_double * 4)(*p), (C.c_double * 2)(*sd), self.dy,
             self.obs_idx.ctypes.data_as(C.POINTER(C.c_int)), float(spec["obs_var"]),
-            _d(self.prior_mean), _d(self.prior_sd))
+            _d(self.prior_mean), _d(self.prior_sd), (C.c_double * 8)(*q))
 
     @property
     def ref(self):
@@ -397,6 +404,22 @@ def apf_interval(m: "Model", seed, filt, t, X, lwc, y, logZ=0.0, scheme=0):
                                 C.byref(lz), sc, _d(lw), _i32(A), _d(mw), C.byref(ess))
     return dict(X=X, lwc=lwc, lw=lw, A=A, mean_w=mw, logZ=lz.value, ess=ess.value,
                 degenerate=bool(deg))
+
+
+def fhnp_region(m: "Model", U):
+    """Stimulus region of the paper's network from the U plane: (count, mask)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    reg = np.zeros(U.size, np.int32)
+    c = lib().or_fhnp_region(m.ref, _d(U), _i32(reg))
+    return int(c), reg.astype(bool)
+
+
+def fhnp_step(m: "Model", seed, purpose, c0, c1, n, x):
+    """One step of the paper's network: (next state, event centre or -1)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xo = np.zeros_like(x)
+    ev = lib().or_fhnp_step(m.ref, _u32(key(seed)), purpose, c0, c1, n, _d(x), _d(xo))
+    return xo, int(ev)
 
 
 def mean(X) -> np.ndarray:

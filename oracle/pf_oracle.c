@@ -159,7 +159,7 @@ void or_step_noise(const or_model *m, const uint32_t key[2], uint32_t purpose,
                    uint32_t c0, uint32_t c1, uint32_t n, double *z) {
   uint32_t ctr[4];
   double q[4];
-  if (m->kind == OR_FHN) {
+  if (m->kind == OR_FHN || m->kind == OR_FHN_PAPER) {
     int nn = m->J * m->J;
     for (int p = 0; 2 * p < nn; ++p) {
       make_ctr(ctr, c0, c1, n, purpose, (uint32_t)p);
@@ -183,6 +183,107 @@ void or_step_noise(const or_model *m, const uint32_t key[2], uint32_t purpose,
   }
 }
 
+/* ---- the paper's modified FH-N network (Sec. 5.1, 5.2) ------------------ */
+
+/* 4-neighbours of node k inside the grid; returns how many */
+static int grid_nbrs(int J, int k, int *nb) {
+  int i = k / J, j = k % J, c = 0;
+  if (i > 0) nb[c++] = k - J;
+  if (i < J - 1) nb[c++] = k + J;
+  if (j > 0) nb[c++] = k - 1;
+  if (j < J - 1) nb[c++] = k + 1;
+  return c;
+}
+
+int or_fhnp_region(const or_model *m, const double *U, int *region) {
+  int J = m->J, nn = J * J, count = 0, nb[4];
+  double lo = m->q[3], hi = m->q[4];
+  for (int k = 0; k < nn; ++k) {
+    int in = U[k] > lo && U[k] < hi;
+    int c = grid_nbrs(J, k, nb);
+    for (int e = 0; e < c && !in; ++e) in = U[nb[e]] > lo && U[nb[e]] < hi;
+    region[k] = in;
+    count += in;
+  }
+  return count;
+}
+
+static int fhnp_step(const or_model *m, const uint32_t key[2], uint32_t purpose, uint32_t c0,
+                     uint32_t c1, uint32_t n, const double *x, double *xo, int pilot) {
+  int J = m->J, nn = J * J, nb[4];
+  int l0 = (int)m->q[5];
+  const double *U = x, *V = x + nn;
+  double a2 = m->p[0], cpl = m->p[1], b0 = m->p[2], b1 = m->p[3], b2 = m->q[0];
+  double amp = m->q[1], eps = m->q[2];
+  int *region = (int *)malloc(sizeof(int) * (size_t)nn);
+  double *z = (double *)malloc(sizeof(double) * (size_t)m->dx);
+  /* 1.-2. stimulus region, Bernoulli event and its centre */
+  int count = or_fhnp_region(m, U, region);
+  uint32_t ctr[4], r[4];
+  make_ctr(ctr, c0, c1, n, purpose, (uint32_t)(nn / 2));
+  or_philox4x32_10(ctr, key, r);
+  int event = -1;
+  if (!pilot && count > 0 && or_u01(r[0]) < eps) {
+    int kth = (int)floor(or_u01(r[1]) * (double)count);
+    if (kth > count - 1) kth = count - 1;
+    for (int k = 0; k < nn; ++k)
+      if (region[k] && kth-- == 0) {
+        event = k;
+        break;
+      }
+  }
+  /* 3. the event history */
+  memcpy(xo + 2 * nn, x + 2 * nn, sizeof(double) * (size_t)(m->dx - 2 * nn));
+  xo[2 * nn + (int)(n % (uint32_t)l0)] = (double)event;
+  /* 4.-6. stimulus, forcing and the Euler step */
+  if (pilot)
+    memset(z, 0, sizeof(double) * (size_t)m->dx);
+  else
+    or_step_noise(m, key, purpose, c0, c1, n, z);
+  double sq0 = m->sd[0] * sqrt(m->h), sq1 = m->sd[1] * sqrt(m->h);
+  int forcing = (int)(n % (uint32_t)m->q[6]) < (int)m->q[7];
+  for (int k = 0; k < nn; ++k) {
+    int c = grid_nbrs(J, k, nb);
+    double sum = 0.0;
+    for (int e = 0; e < c; ++e) sum += U[nb[e]];
+    int covered = 0;
+    for (int l = 0; l < l0 && !covered; ++l) {
+      int ev = (int)xo[2 * nn + l];
+      if (ev < 0) continue;
+      covered = ev == k;
+      int cn = grid_nbrs(J, ev, nb);
+      for (int e = 0; e < cn && !covered; ++e) covered = nb[e] == k;
+    }
+    double psi = covered ? amp : 0.0;
+    double mf = (forcing && k / J < 2 && k % J < 2) ? amp : 0.0;
+    double u = U[k], v = V[k];
+    double p3 = a2 * u - u * u * u;
+    xo[k] = ((u + m->h * (p3 - v)) + m->h * (cpl * sum + mf + psi)) + sq0 * z[k];
+    xo[nn + k] = (v + m->h * (b0 * u + b1 * v + b2)) + sq1 * z[nn + k];
+  }
+  free(region);
+  free(z);
+  return event;
+}
+
+int or_fhnp_step(const or_model *m, const uint32_t key[2], uint32_t purpose, uint32_t c0,
+                 uint32_t c1, uint32_t n, const double *x, double *xo) {
+  return fhnp_step(m, key, purpose, c0, c1, n, x, xo, 0);
+}
+
+/* The noise-free continuation of one step: no new stimulus event (the
+   ring's active stimuli and the forcing still act) and no noise. */
+void or_pilot_step(const or_model *m, uint32_t n, const double *x, double *xo) {
+  if (m->kind == OR_FHN_PAPER) {
+    uint32_t key[2] = {0u, 0u};
+    fhnp_step(m, key, 0u, 0u, 0u, n, x, xo, 1);
+    return;
+  }
+  double *z = (double *)calloc((size_t)m->dx, sizeof(double));
+  or_em_step(m, x, z, xo);
+  free(z);
+}
+
 /* Euler-Maruyama: x' = x + h f(x) + sd sqrt(h) z (drift first, then the
    deterministic update, then the noise). */
 void or_em_step(const or_model *m, const double *x, const double *z, double *xo) {
@@ -197,6 +298,18 @@ void or_em_step(const or_model *m, const double *x, const double *z, double *xo)
     xo[k] = (x[k] + m->h * f[k]) + sq * z[k];
   }
   free(f);
+}
+
+void or_transition(const or_model *m, const uint32_t key[2], uint32_t purpose, uint32_t c0,
+                   uint32_t c1, uint32_t n, const double *x, double *xo) {
+  if (m->kind == OR_FHN_PAPER) {
+    or_fhnp_step(m, key, purpose, c0, c1, n, x, xo);
+    return;
+  }
+  double *z = (double *)malloc(sizeof(double) * (size_t)m->dx);
+  or_step_noise(m, key, purpose, c0, c1, n, z);
+  or_em_step(m, x, z, xo);
+  free(z);
 }
 
 void or_prior_draw(const or_model *m, const uint32_t key[2], uint32_t purpose,
@@ -243,18 +356,15 @@ void or_propagate(const or_model *m, uint64_t seed, uint32_t filter, int N,
   uint32_t key[2];
   or_key(seed, key);
   int d = m->dx;
-  double *z = (double *)malloc(sizeof(double) * (size_t)d);
   double *xn = (double *)malloc(sizeof(double) * (size_t)d);
   for (int i = 0; i < N; ++i) {
     double *x = X + (size_t)i * d;
     for (int s = 0; s < m->S; ++s) {
       uint32_t n = (uint32_t)((t - 1) * m->S + s);
-      or_step_noise(m, key, OR_P_PROP, (uint32_t)i, filter, n, z);
-      or_em_step(m, x, z, xn);
+      or_transition(m, key, OR_P_PROP, (uint32_t)i, filter, n, x, xn);
       memcpy(x, xn, sizeof(double) * (size_t)d);
     }
   }
-  free(z);
   free(xn);
 }
 
@@ -265,15 +375,12 @@ void or_propagate_particle(const or_model *m, uint64_t seed, uint32_t filter,
   uint32_t key[2];
   or_key(seed, key);
   int d = m->dx;
-  double *z = (double *)malloc(sizeof(double) * (size_t)d);
   double *xn = (double *)malloc(sizeof(double) * (size_t)d);
   for (int s = 0; s < m->S; ++s) {
     uint32_t n = (uint32_t)((t - 1) * m->S + s);
-    or_step_noise(m, key, OR_P_PROP, index, filter, n, z);
-    or_em_step(m, x, z, xn);
+    or_transition(m, key, OR_P_PROP, index, filter, n, x, xn);
     memcpy(x, xn, sizeof(double) * (size_t)d);
   }
-  free(z);
   free(xn);
 }
 
@@ -579,13 +686,12 @@ int or_apf_interval(const or_model *m, uint64_t seed, uint32_t filter, int N, in
   double *Xo = (double *)malloc(sizeof(double) * (size_t)N * d);
   double *mu = (double *)malloc(sizeof(double) * (size_t)d);
   double *nx = (double *)malloc(sizeof(double) * (size_t)d);
-  double *z0 = (double *)calloc((size_t)d, sizeof(double));
   double mx, W, s2;
   /* 1. the pilot: noise-free Euler path and its likelihood */
   for (int i = 0; i < N; ++i) {
     memcpy(mu, X + (size_t)i * d, sizeof(double) * (size_t)d);
     for (int s = 0; s < m->S; ++s) {
-      or_em_step(m, mu, z0, nx);
+      or_pilot_step(m, (uint32_t)((t - 1) * m->S + s), mu, nx);
       memcpy(mu, nx, sizeof(double) * (size_t)d);
     }
     pil[i] = or_loglik(m, mu, y);
@@ -614,7 +720,7 @@ int or_apf_interval(const or_model *m, uint64_t seed, uint32_t filter, int N, in
   for (int k = 0; k < N; ++k) lwc[k] = deg2 ? 0.0 : lw[k] - (mx + log(W / (double)N));
   if (lw_out) memcpy(lw_out, lw, sizeof(double) * (size_t)N);
   if (A_out) memcpy(A_out, A, sizeof(int32_t) * (size_t)N);
-  free(pil); free(lam); free(lw); free(A); free(Xo); free(mu); free(nx); free(z0);
+  free(pil); free(lam); free(lw); free(A); free(Xo); free(mu); free(nx);
   return deg1 || deg2;
 }
 
@@ -663,8 +769,7 @@ void or_simulate(const or_model *m, uint64_t seed, int T, double *x_true,
   for (int t = 1; t <= T; ++t) {
     for (int s = 0; s < m->S; ++s) {
       uint32_t n = (uint32_t)((t - 1) * m->S + s);
-      or_step_noise(m, key, OR_P_TRUTH_NOISE, 0u, OR_TRUTH_STREAM, n, z);
-      or_em_step(m, x, z, xn);
+      or_transition(m, key, OR_P_TRUTH_NOISE, 0u, OR_TRUTH_STREAM, n, x, xn);
       memcpy(x, xn, sizeof(double) * (size_t)d);
     }
     memcpy(x_true + (size_t)t * d, x, sizeof(double) * (size_t)d);

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-enum { OR_OU1D = 0, OR_LORENZ63 = 1, OR_FHN = 2 };
+enum { OR_OU1D = 0, OR_LORENZ63 = 1, OR_FHN = 2, OR_FHN_PAPER = 3 };
 
 /* Counter "purpose" tags (top byte of counter word 3). */
 enum {
@@ -65,7 +65,49 @@ typedef struct {
   double obs_var;           /* observation noise variance                      */
   const double *prior_mean; /* [dx]                                            */
   const double *prior_sd;   /* [dx]                                            */
+  double q[8];              /* OR_FHN_PAPER: beta2, stimulus amplitude F~,
+                               Bernoulli parameter eps, thresholds u-, u+,
+                               stimulus duration l0 (steps), forcing period and
+                               pulse width (steps)                             */
 } or_model;
+
+/* ---- the paper's modified FH-N network (Sec. 5.1, 5.2) -----------------
+   State of a particle: the U plane [J*J], the V plane [J*J], then a ring of
+   the last l0 stimulus events (slot n mod l0 holds the event of step n: the
+   centre node i*J+j of the stimulated group, or -1), padded with -1 to a
+   multiple of 4 (dx = 2 J^2 + 4 ceil(l0/4)).  p = (a2, c, beta0, beta1) with
+   p3(u) = a2 u - u^3 (read with a negative leading coefficient: the printed
+   sign gives no rest state), c = 1/D the coupling of the neighbour sum
+   (eqUd), (beta0, beta1, beta2) the recovery (eqVd); sd = (sigma~, 0).
+   Step n (0-based; the paper's t = n + 1) from U, V:
+     1. the stimulus region S (eqStimulusRegion): nodes with U in (u-, u+)
+        at the node or one of its 4 grid neighbours;
+     2. one Philox call (c0, c1, n, purpose | sub-block J*J/2): u0 < eps is
+        the Bernoulli event (eqBernu), u1 picks the centre uniformly from S
+        in row-major order, floor(u1 |S|) (eqUnifStimulus); no event when S
+        is empty;
+     3. the event enters the ring, replacing the event of step n - l0;
+     4. Psi = F~ on every node covered by an event of the ring (the centre or
+        one of its 4 neighbours), else 0 -- F~ min{1, sum_l Q} (eqPsi_ijt,
+        whose max is read as min: the printed max keeps every node
+        stimulated);
+     5. forcing m F_n: F~ on the 2 x 2 corner block (i, j < 2) while
+        (n mod period) < width, else 0 (the printed square pulse spans the
+        whole period);
+     6. Euler (eqUd, eqVd): U' = U + h (p3(U) - V) + h (c sum_nbr U + m F +
+        Psi) + sigma~ sqrt(h) z, V' = V + h (beta0 U + beta1 V + beta2). */
+int or_fhnp_region(const or_model *m, const double *U, int *region);
+/* one step of the network (x, xo of dx); returns the event centre or -1 */
+int or_fhnp_step(const or_model *m, const uint32_t key[2], uint32_t purpose, uint32_t c0,
+                 uint32_t c1, uint32_t n, const double *x, double *xo);
+/* the noise-free continuation of step n (the auxiliary filter's pilot):
+   the Euler step with z = 0; for the FH-N network also no new stimulus
+   event (active stimuli and the forcing still act) */
+void or_pilot_step(const or_model *m, uint32_t n, const double *x, double *xo);
+/* one step of any model: normals and the Euler-Maruyama step, and the
+   stimulus process of the paper's network */
+void or_transition(const or_model *m, const uint32_t key[2], uint32_t purpose, uint32_t c0,
+                   uint32_t c1, uint32_t n, const double *x, double *xo);
 
 /* ---- random numbers ---------------------------------------------------- */
 void or_key(uint64_t seed, uint32_t key[2]);
@@ -163,7 +205,8 @@ int or_filter_interval_sched(const or_model *m, uint64_t seed, uint32_t filter, 
    the variant the paper runs on its FH-N network in Sec. 5.3; Sec. 3.3 notes
    that the ensemble results extend to it).  From the particles X[N] with
    carried log-weights lwc[N] (mean weight 1):
-     1. pilot: mu_i = the noise-free S-step Euler path of the model from x_i;
+     1. pilot: mu_i = the noise-free S-step Euler path of the model from x_i
+        (or_pilot_step);
         first-stage log-weights lambda_i = lwc_i + log g(y | mu_i);
      2. ancestors a_k by `scheme` from lambda (counters of interval t);
      3. propagation of x_{a_k} (the bootstrap's noise counters, slot k);

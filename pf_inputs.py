@@ -75,6 +75,46 @@ def fhn(J: int = 40, S: int = 20) -> dict:
                 prior_mean=mean.tolist(), prior_sd=[0.05] * (2 * nn))
 
 
+def fhn_paper_obs_nodes(J: int = 32) -> list:
+    """The paper's observation zones (Sec. 5.2): a 5 x 5 grid of 2 x 2 node
+    squares, equally spaced -- read as top-left corners at rows and columns
+    6k + 3 (k = 0..4, 0-based), which leaves three unobserved rows and
+    columns on each border of the 32 x 32 grid; row-major U-plane indices."""
+    starts = [6 * k + 3 for k in range(5)]
+    rows = sorted(r + d for r in starts for d in (0, 1))
+    return [i * J + j for i in rows for j in rows]
+
+
+def fhn_paper(J: int = 32, S: int = 1, eps: float = 1e-3) -> dict:
+    """The paper's modified stochastic FitzHugh-Nagumo network (Sec. 5.1, 5.2):
+    p3(u) = 3.6 u - u^3 (read with a negative leading coefficient), coupling
+    (1/D) sum of the 4 neighbours' U with 1/D = 4.5e-3, recovery (2.1, -0.6,
+    0.6), noise variance 1/2 on U only, T_d = 5e-3; random stimuli of
+    amplitude 200 for l0 = 25 steps at a uniform node of the region where
+    U (or a neighbour's U) lies in (-1.8, -1.6), with probability eps = 1e-3
+    per step; periodic forcing of amplitude 200 every 20 time units (4000
+    steps) on the 2 x 2 corner block, read as a pulse of l0 steps; U observed
+    at every step on the 100 nodes of the 2 x 2 zones with variance 1/2.
+    Prior: U, V near the node's rest point (-1.033, -2.616) with sd 0.05, no
+    past stimuli.  The state is U, V and the ring of the last l0 stimulus
+    events (padded to 28 entries)."""
+    nn = J * J
+    l0 = 25
+    ring = 4 * ((l0 + 3) // 4)
+    mean = [-1.0332] * nn + [-2.6162] * nn + [-1.0] * ring
+    sd = [0.05] * (2 * nn) + [0.0] * ring
+    return dict(kind="fhn_paper", dx=2 * nn + ring, J=J, S=S, h=5e-3,
+                params=(3.6, 4.5e-3, 2.1, -0.6), noise_sd=(0.5 ** 0.5, 0.0),
+                params_ext=(0.6, 200.0, eps, -1.8, -1.6, float(l0), 4000.0, float(l0)),
+                obs_idx=fhn_paper_obs_nodes(J), obs_var=0.5,
+                prior_mean=mean, prior_sd=sd)
+
+
+# the paper's FH-N network experiment (Sec. 5.3): M = 10 filters with N per
+# filter (the paper's auxiliary filters, here bootstrap filters)
+PAPER_FHN = dict(M=10, Ns=(100, 500, 1000, 2000, 5000))
+
+
 def ou1d(theta=1.0, sd=1.0, h=0.01, S=10, obs_var=0.05, prior_mean=0.0,
          prior_sd=1.0) -> dict:
     """1-D Ornstein-Uhlenbeck test model, x' = x - theta h x + sd sqrt(h) z,
