@@ -28,7 +28,10 @@ device at its sustained clock):
                 observations: time per interval at a stated equal MSE;
   paper_l63     the paper's own Lorenz 63 experiment (Sec. 4): ensembles of
                 M = 20 filters against the centralised filter of K = M N,
-                MSE at t = 200 against a J = 1e5 proxy over 100 runs.
+                MSE at t = 200 against a J = 1e5 proxy over 100 runs;
+  paper_fhn     the paper's FH-N network (Sec. 5): ensembles of M = 10
+                bootstrap filters against the centralised filter, MSE per
+                node and time per discrete step.
 """
 from __future__ import annotations
 
@@ -479,6 +482,72 @@ def paper_l63_leg(pf, torch, a):
             "proxy_estimate": proxy.tolist(), "truth_at_T": xt[T].tolist(), "rows": rows}
 
 
+def paper_fhn_leg(pf, torch, a, datasets=5, T=300):
+    """The paper's FH-N network experiment (Sec. 5.3) with the auxiliary
+    filter the paper runs and with the bootstrap filter: ensembles of M = 10
+    independent filters of N particles against
+    the centralised filter of K = M N particles (K <= 8192, the per-filter
+    resampler's limit), on `datasets` independent truth records of T
+    discrete steps (one observation per step); the MSE per node of the U
+    estimate against the truth over the steps after the first 50, averaged
+    over the records, and the time per discrete step (all records' filters
+    batched in one graph-replayed context, and one filter ensemble alone)."""
+    spec = pf_inputs.fhn_paper(32)
+    nn = spec["J"] ** 2
+    M = pf_inputs.PAPER_FHN["M"]
+    skip = 50
+    sim = pf.ParticleFilter([spec], [(0, 1, 1, 1)], fused=True)
+    recs = [sim.simulate(0, 900 + r, T) for r in range(datasets)]
+    sim.close()
+    truth = torch.stack([x[1:, :nn] for x, _ in recs]).double()    # [R][T][nn]
+    y_all = torch.cat([y for _, y in recs], dim=1).contiguous()
+    stream = torch.cuda.current_stream()
+
+    import ctypes as C
+
+    def run(Mf, N, flags=0):
+        """(ms per step of the timed pass, MSE of an untimed pass that
+        copies the ensemble estimates out at every step)."""
+        ens = [(0, Mf, N, 70 + r, flags) for r in range(datasets)]
+        f = pf.ParticleFilter([spec], ens, graph=True)
+        f.set_observations(y_all)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for t in range(T):
+            f.step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        f.close()
+        ms = e0.elapsed_time(e1) / T
+        f = pf.ParticleFilter([spec], ens, graph=True)
+        f.set_observations(y_all)
+        est = torch.empty((T, datasets, spec["dx"]), dtype=torch.float64, device="cuda")
+        for t in range(T):
+            f.step()
+            pf._check(pf.lib().pf_estimate(f._ctx, C.c_void_p(est[t].data_ptr()), None, None,
+                                           None, pf._stream(None)))
+        torch.cuda.synchronize()
+        f.close()
+        err = (est[skip:, :, :nn].permute(1, 0, 2) - truth[:, skip:]) ** 2
+        return ms, err.mean().item()
+
+    rows = []
+    for N in pf_inputs.PAPER_FHN["Ns"]:
+        r = {"N": N, "K": M * N}
+        for name, flags in (("bootstrap", 0), ("auxiliary", pf.ENS_AUXILIARY)):
+            ms_e, mse_e = run(M, N, flags)
+            r[name + "_ensemble"] = {"mse_per_node": mse_e, "ms_per_step_all_records": ms_e}
+            if M * N <= 8192:
+                ms_c, mse_c = run(1, M * N, flags)
+                r[name + "_centralised"] = {"mse_per_node": mse_c,
+                                            "ms_per_step_all_records": ms_c}
+        rows.append(r)
+    return {"model": "the paper's FH-N network (32 x 32, stimuli, forcing)",
+            "filters": "bootstrap and auxiliary (the paper's), ensembles of M and centralised",
+            "M": M, "records": datasets, "steps": T, "mse_after_step": skip, "rows": rows}
+
+
 # ------------------------------------------------------ learned proposal ----
 def train_proposal(pf, torch, spec):
     tc = pf_inputs.LEARNED_TRAINING
@@ -738,6 +807,7 @@ def main():
         extras["mix"] = mix_leg(pf, torch, a)
         extras["learned"], _ = learned_leg(pf, torch, a)
         extras["paper_l63"] = paper_l63_leg(pf, torch, a)
+        extras["paper_fhn"] = paper_fhn_leg(pf, torch, a)
         extras["sweep"] = sweep_leg(pf, torch, a, spec, xt, y, None)
         extras["extras_wall_s"] = time.perf_counter() - t0
         torch.cuda.empty_cache()

@@ -57,12 +57,38 @@ typedef enum pf_model_kind {
      additive noise on both variables; lap is the 5-point Laplacian over the
      truncated neighbourhoods of Sec. 5.2 (no flux).
      params = (a, D, eps, gam). */
-  PF_MODEL_FHN = 2
+  PF_MODEL_FHN = 2,
+  /* The paper's modified stochastic FH-N network, Sec. 5.1 eqs. (eqUd),
+     (eqVd), (eqStimulusRegion)-(eqPsi_ijt), (eqObservFHN), with Sec. 5.2's
+     constants in the descriptor:
+       params     = (a2, c, beta0, beta1): p3(u) = a2 u - u^3 (the cubic read
+                    with a negative leading coefficient), c = 1/D the weight
+                    of the sum of the 4 neighbours' U, the recovery
+                    V' = V + h (beta0 U + beta1 V + beta2);
+       params_ext = (beta2, stimulus amplitude F~, Bernoulli parameter eps,
+                    band u-, u+ of the stimulus region, duration l0 <= 32
+                    (steps), forcing period, forcing pulse width (steps));
+       noise_sd   = (sigma~ on U, on V).
+     State (float32, state_dim = 2 J^2 + 4 ceil(l0/4)): the U plane, the V
+     plane, then the ring of the last l0 stimulus events (slot n mod l0:
+     centre node of the event of Euler step n, or -1; padding -1).  Step n:
+     the region of nodes whose U or a 4-neighbour's U lies in (u-, u+); one
+     Philox call (particle, filter, n, PROP << 24 | J*J/2): its first uniform
+     < eps makes an event, centred on the floor(u |region|)-th region node
+     (row-major), that stimulates the centre and its neighbours with F~ for
+     l0 steps (F~ min{1, sum Q}: the printed max is read as min); forcing F~
+     on the 2 x 2 corner block while (n mod period) < width; then Euler-
+     Maruyama with the noise layout of the FH-N grid.  Observations read U
+     nodes (< J*J).  Not with PF_ENS_LEARNED; with PF_ENS_AUXILIARY the
+     pilot is the noise-free continuation without new stimulus events (the
+     active stimuli and the forcing still act). */
+  PF_MODEL_FHN_PAPER = 3
 } pf_model_kind;
 
 typedef struct pf_model_desc {
   int32_t kind;          /* pf_model_kind                                   */
-  int32_t state_dim;     /* d_x: 1 (OU), 3 (Lorenz), 2*J*J (FH-N)            */
+  int32_t state_dim;     /* d_x: 1 (OU), 3 (Lorenz), 2*J*J (FH-N), 2*J*J + the
+                            event ring (the paper's FH-N network)           */
   int32_t grid_j;        /* J for FH-N, else 0                              */
   int32_t steps_per_obs; /* S Euler-Maruyama steps per observation interval */
   double h;              /* Euler step                                      */
@@ -77,6 +103,7 @@ typedef struct pf_model_desc {
                             eqObservFHN)                                    */
   const double *h_prior_mean; /* [state_dim] tau_0 = N(mean, diag(sd^2))    */
   const double *h_prior_sd;   /* [state_dim]                                */
+  double params_ext[8];  /* PF_MODEL_FHN_PAPER only (see pf_model_kind)     */
 } pf_model_desc;
 
 /* One ensemble of M independent filters with N particles each, on model

@@ -21,7 +21,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpf.so")
 
-KIND = {"ou1d": 0, "lorenz63": 1, "fhn": 2}
+KIND = {"ou1d": 0, "lorenz63": 1, "fhn": 2, "fhn_paper": 3}
 OPT_PLAIN, OPT_FUSED, OPT_GRAPH = 0, 1, 2
 STAGE_PROPAGATE, STAGE_WEIGHT, STAGE_RESAMPLE, STAGE_GATHER, STAGE_ESTIMATE = 1, 2, 4, 8, 16
 STAGE_ALL = 31
@@ -42,6 +42,7 @@ class _ModelDesc(C.Structure):
         ("noise_sd", C.c_double * 2), ("obs_dim", C.c_int32),
         ("h_obs_index", C.POINTER(C.c_int32)), ("obs_var", C.c_double),
         ("h_prior_mean", C.POINTER(C.c_double)), ("h_prior_sd", C.POINTER(C.c_double)),
+        ("params_ext", C.c_double * 8),
     ]
 
 
@@ -174,7 +175,9 @@ class PFModel:
             float(spec["h"]), (C.c_double * 4)(*p), (C.c_double * 2)(*sd), self.dy,
             self.obs_idx.ctypes.data_as(C.POINTER(C.c_int32)), float(spec["obs_var"]),
             self.prior_mean.ctypes.data_as(C.POINTER(C.c_double)),
-            self.prior_sd.ctypes.data_as(C.POINTER(C.c_double)))
+            self.prior_sd.ctypes.data_as(C.POINTER(C.c_double)),
+            (C.c_double * 8)(*(list(spec.get("params_ext", ())) +
+                               [0.0] * (8 - len(spec.get("params_ext", ()))))))
 
 
 # Contexts still open.  They are closed by an exit handler, which runs
@@ -251,7 +254,7 @@ class ParticleFilter:
 
     def particle_shape(self, e: int):
         m, M, N = self.dims(e)
-        if m.spec["kind"] == "fhn":
+        if m.spec["kind"] in ("fhn", "fhn_paper"):
             return (M, N, m.dx)
         return (M, m.dx, N)
 

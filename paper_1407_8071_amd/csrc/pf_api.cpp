@@ -60,6 +60,7 @@ struct Ens {
   double *gpart = nullptr; // grid model: estimator partial sums
   float *lwc = nullptr;    // ESS schedule, auxiliary filter: carried log-weights [M][N]
   bool apf = false;        // auxiliary particle filter
+  bool paper = false;      // the paper's FH-N network (kind 3)
   // learned proposal (FH-N): FP32 parameters and each node's nearest observation
   bool learned = false;
   float *params = nullptr;
@@ -154,7 +155,8 @@ CtxSizes ctx_sizes(const pf_model_desc *models, const pf_ensemble_desc *ens, int
   for (int e = 0; e < n_ens; ++e) {
     z.jobs += (size_t)ens[e].M;
     z.tiles += (size_t)ens[e].M * (((size_t)ens[e].N + MIN_PROP_TILE - 1) / MIN_PROP_TILE);
-    if (models[ens[e].model].kind == PF_MODEL_FHN) {
+    if (models[ens[e].model].kind == PF_MODEL_FHN ||
+        models[ens[e].model].kind == PF_MODEL_FHN_PAPER) {
       // room for the padding of the stepping kernel's groups (at most 7)
       z.gparticles += (size_t)ens[e].M * ens[e].N + 7;
       z.gpart_jobs += (size_t)ens[e].M * pfk::grid_est_chunks(ens[e].N);
@@ -196,6 +198,22 @@ pf_status check_model(const pf_model_desc &m, int idx) {
     if (m.grid_j < 2 || m.grid_j > 64 || (m.grid_j & 1) || m.state_dim != 2 * m.grid_j * m.grid_j)
       return fail(PF_ERR_INVALID_ARG,
                   "model %d: FH-N needs an even J in [2, 64] and state_dim 2*J*J", idx);
+  } else if (m.kind == PF_MODEL_FHN_PAPER) {
+    const double l0 = m.params_ext[5];
+    if (!(l0 >= 1.0 && l0 <= 32.0) || l0 != std::floor(l0))
+      return fail(PF_ERR_INVALID_ARG, "model %d: stimulus duration l0 must be an integer in [1, 32]", idx);
+    const int ring = 4 * (((int)l0 + 3) / 4);
+    if (m.grid_j < 2 || m.grid_j > 64 || (m.grid_j & 1) ||
+        m.state_dim != 2 * m.grid_j * m.grid_j + ring)
+      return fail(PF_ERR_INVALID_ARG,
+                  "model %d: the FH-N network needs an even J in [2, 64] and state_dim "
+                  "2*J*J + %d", idx, ring);
+    if (!(m.params_ext[2] >= 0.0 && m.params_ext[2] <= 1.0) || !(m.params_ext[3] < m.params_ext[4]) ||
+        !(m.params_ext[6] >= 1.0 && m.params_ext[6] < 2147483647.0) || !(m.params_ext[7] >= 0.0) ||
+        !(m.params_ext[6] == std::floor(m.params_ext[6])) ||
+        !(m.params_ext[7] == std::floor(m.params_ext[7])))
+      return fail(PF_ERR_INVALID_ARG,
+                  "model %d: eps in [0, 1], u- < u+, integer forcing period >= 1 and width >= 0", idx);
   } else {
     return fail(PF_ERR_INVALID_ARG, "model %d: unknown kind %d", idx, m.kind);
   }
@@ -208,7 +226,7 @@ pf_status check_model(const pf_model_desc &m, int idx) {
     if (m.h_obs_index[k] < 0 || m.h_obs_index[k] >= m.state_dim)
       return fail(PF_ERR_INVALID_ARG, "model %d: obs_index[%d] out of range", idx, k);
   // FH-N: the observation operator reads v (the kernels stage only v for it)
-  if (m.kind == PF_MODEL_FHN)
+  if (m.kind == PF_MODEL_FHN || m.kind == PF_MODEL_FHN_PAPER)
     for (int k = 0; k < m.obs_dim; ++k)
       if (m.h_obs_index[k] >= m.grid_j * m.grid_j)
         return fail(PF_ERR_INVALID_ARG, "model %d: FH-N obs_index[%d] is not a v node", idx, k);
@@ -276,7 +294,8 @@ pf_status check_resampling(const pf_ensemble_desc *ens, int n_ens, uint32_t opti
 
 pf_status check_fused(const pf_model_desc *models, const pf_ensemble_desc *ens, int n_ens) {
   for (int e = 0; e < n_ens; ++e)
-    if (models[ens[e].model].kind == PF_MODEL_FHN && ens[e].N > pfk::WG_MAX_N)
+    if ((models[ens[e].model].kind == PF_MODEL_FHN ||
+         models[ens[e].model].kind == PF_MODEL_FHN_PAPER) && ens[e].N > pfk::WG_MAX_N)
       return fail(PF_ERR_UNSUPPORTED, "fused path: FH-N ensemble %d has N > %d", e, pfk::WG_MAX_N);
   return PF_OK;
 }
@@ -286,7 +305,8 @@ size_t total_bytes(const pf_model_desc *models, const pf_ensemble_desc *ens, int
   for (int e = 0; e < n_ens; ++e) {
     const pf_model_desc &m = models[ens[e].model];
     const int T = (ens[e].N + pfk::TILE - 1) / pfk::TILE;
-    o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T, m.kind == PF_MODEL_FHN,
+    o = layout_of(o, ens[e].M, ens[e].N, m.state_dim, m.obs_dim, T,
+                  m.kind == PF_MODEL_FHN || m.kind == PF_MODEL_FHN_PAPER,
                   (ens[e].flags & PF_ENS_LEARNED) != 0, carried_weights(ens[e]),
                   (ens[e].flags & PF_ENS_AUXILIARY) != 0)
             .end;
@@ -411,10 +431,17 @@ pf_status stage_run(pf_ctx *ctx, uint32_t stages, const float *d_y, hipStream_t 
     return fail(PF_ERR_INVALID_ARG, "weighting needs observations");
   if (stages & PF_STAGE_PROPAGATE) {
     const int out = 1 - ctx->cur;
-    for (Ens &E : ctx->ens) {
+    for (size_t e = 0; e < ctx->ens.size(); ++e) {
+      Ens &E = ctx->ens[e];
       pfk::EnsDev &D = E.dev;
       const int32_t *anc = ctx->pending ? D.A : nullptr;
-      if (E.learned) {
+      if (E.paper) {
+        const long ev = prof_begin(ctx, s);
+        PF_HIP(pfk::launch_fhnp_steps(ctx->d_fens, (int)e, E.d.M, E.d.N, D.md.J,
+                                      pfk::IvArg{t, nullptr, nullptr, 0}, ctx->cur,
+                                      ctx->pending ? 1 : 0, s));
+        prof_end(ctx, ev, s);
+      } else if (E.learned) {
         if (!d_y) return fail(PF_ERR_INVALID_ARG, "the learned proposal needs the observations");
         const long ev = prof_begin(ctx, s);
         PF_HIP(pfk::launch_grid_steps_learned(D, pfk::IvArg{t, nullptr, d_y, 0}, learned_yoff(ctx, E),
@@ -507,7 +534,7 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     if (c.kind == CLASS_RESAMPLE_GRID) grid_work = true;
   }
   for (const Ens &E : ctx->ens) {
-    if (E.learned) grid_work = true;
+    if (E.learned || E.paper) grid_work = true;
     else if (E.tiled) vec_work = true;
   }
   hipStream_t g = s;  // the grid chain's stream
@@ -523,7 +550,10 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     for (size_t e = 0; e < ctx->ens.size(); ++e) {
       const Ens &E = ctx->ens[e];
       if (!E.apf) continue;
-      if (E.grid)
+      if (E.paper)
+        PF_HIP(pfk::launch_fhnp_pilot(ctx->d_fens, (int)e, E.d.M, E.d.N, E.dev.md.J, iv, parity,
+                                      pending, g));
+      else if (E.grid)
         PF_HIP(pfk::launch_grid_pilot(ctx->d_fens, (int)e, E.d.M, E.d.N, E.dev.md.J, iv, parity,
                                       pending, g));
       else
@@ -561,6 +591,14 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
                                             parity, pending, gg.blocks, g));
       prof_end(ctx, eg, g);
     }
+    for (size_t e = 0; e < ctx->ens.size(); ++e) {
+      const Ens &E = ctx->ens[e];
+      if (!E.paper) continue;
+      const long eg = prof ? prof_begin(ctx, g) : -1;
+      PF_HIP(pfk::launch_fhnp_steps(ctx->d_fens, (int)e, E.d.M, E.d.N, E.dev.md.J, iv, parity,
+                                    pending, g));
+      prof_end(ctx, eg, g);
+    }
     int yo = 0;
     for (Ens &E : ctx->ens) {
       const int yoff = yo;
@@ -589,7 +627,7 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
                                              ctx->d_fens, out, g));
   for (Ens &E : ctx->ens) {
     pfk::EnsDev &D = E.dev;
-    if (E.learned) {
+    if (E.learned || E.paper) {
       PF_HIP(pfk::launch_grid_estimate(D, D.X[out], E.cnt, E.gpart, g));
     } else if (E.tiled) {
       PF_HIP(pfk::launch_resample(D, iv.t, s, iv.tp));
@@ -764,7 +802,7 @@ pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
   size_t op = 0, oj = 0, of = 0, og = 0;
   for (int e = 0; e < n_ens; ++e) {
     const Ens &E = ctx->ens[(size_t)e];
-    if (!E.grid || E.learned) continue;
+    if (!E.grid || E.learned || E.paper) continue;
     const int J = E.dev.md.J;
     pf_ctx::GridGroup *g = nullptr;
     for (auto &gg : ctx->ggroups)
@@ -900,7 +938,8 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     const pf_model_desc &m = h_models[E.d.model];
     E.dx = m.state_dim;
     E.dy = m.obs_dim;
-    E.grid = m.kind == PF_MODEL_FHN;
+    E.grid = m.kind == PF_MODEL_FHN || m.kind == PF_MODEL_FHN_PAPER;
+    E.paper = m.kind == PF_MODEL_FHN_PAPER;
     E.T = (E.d.N + pfk::TILE - 1) / pfk::TILE;
     E.obs_idx.assign(m.h_obs_index, m.h_obs_index + m.obs_dim);
     E.prior_mean.resize((size_t)E.dx);
@@ -929,6 +968,14 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     md.sq0 = (float)(m.noise_sd[0] * std::sqrt(m.h));
     md.sq1 = (float)(m.noise_sd[1] * std::sqrt(m.h));
     md.inv2var = (float)(1.0 / (2.0 * m.obs_var));
+    md.stim_b2 = (float)m.params_ext[0];
+    md.stim_amp = (float)m.params_ext[1];
+    md.stim_eps = m.params_ext[2];
+    md.stim_lo = (float)m.params_ext[3];
+    md.stim_hi = (float)m.params_ext[4];
+    md.stim_l0 = (int32_t)m.params_ext[5];
+    md.force_period = E.paper ? (int32_t)m.params_ext[6] : 1;
+    md.force_width = (int32_t)m.params_ext[7];
     md.obs_sd = (float)std::sqrt(m.obs_var);
     md.obs_idx = (const int32_t *)(ws + L.obs);
     md.prior_mean = (const float *)(ws + L.pmean);
@@ -1294,7 +1341,9 @@ pf_status pf_simulate(pf_ctx *ctx, int32_t ens, uint64_t seed, int32_t T, float 
                       float *d_y, void *stream) {
   Ens *E = get_ens(ctx, ens);
   if (!E || !d_x_true || !d_y || T < 1) return fail(PF_ERR_INVALID_ARG, "bad simulate arguments");
-  if (E->grid)
+  if (E->paper)
+    PF_HIP(pfk::launch_fhnp_simulate(E->dev, seed, T, d_x_true, d_y, (hipStream_t)stream));
+  else if (E->grid)
     PF_HIP(pfk::launch_grid_simulate(E->dev, seed, T, d_x_true, d_y, (hipStream_t)stream));
   else
     PF_HIP(pfk::launch_vec_simulate(E->dev, seed, T, d_x_true, d_y, (hipStream_t)stream));

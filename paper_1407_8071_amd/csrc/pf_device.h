@@ -115,7 +115,7 @@ __device__ __forceinline__ void normals4(uint4 w, float z[4]) {
 // ---------------------------------------------------------------------------
 // Model record handed to kernels by value.
 struct ModelDev {
-  int32_t kind;      // 0 OU, 1 Lorenz 63, 2 FH-N
+  int32_t kind;      // 0 OU, 1 Lorenz 63, 2 FH-N, 3 the paper's FH-N network
   int32_t dx, J, S, dy;
   float h;
   float p0, p1, p2, p3;   // model parameters
@@ -124,6 +124,12 @@ struct ModelDev {
   float obs_sd;           // sqrt(obs_var)
   const int32_t *obs_idx; // [dy]
   const float *prior_mean, *prior_sd; // [dx]
+  // the paper's network (kind 3): recovery constant, stimulus amplitude,
+  // band (lo, hi) of the stimulus region, Bernoulli parameter, stimulus
+  // duration l0 (steps), forcing period and pulse width (steps)
+  float stim_b2, stim_amp, stim_lo, stim_hi;
+  double stim_eps;
+  int32_t stim_l0, force_period, force_width;
 };
 
 // One Euler-Maruyama step of one FH-N node from its v (c), w, the 5-point

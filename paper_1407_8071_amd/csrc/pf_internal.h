@@ -125,6 +125,15 @@ hipError_t launch_filter_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int 
 hipError_t launch_resample_wg(int D, int BD, const WgJob *d_jobs, int n_jobs, int max_n,
                               const FusedEns *d_ens, IvArg iv, int32_t *const *d_counts,
                               int xb_parity, bool custom, int stage, hipStream_t s);
+// the paper's FH-N network (kind 3): interval t of every particle of fused
+// ensemble e (log-weights when iv carries observations), and the truth path
+hipError_t launch_fhnp_steps(const FusedEns *d_ens, int e, int M, int N, int J, IvArg iv,
+                             int parity, int pending, hipStream_t s);
+hipError_t launch_fhnp_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,
+                                hipStream_t s);
+// its auxiliary-filter pilot (S noise-free steps without new stimuli)
+hipError_t launch_fhnp_pilot(const FusedEns *d_ens, int e, int M, int N, int J, IvArg iv,
+                             int parity, int pending, hipStream_t s);
 // auxiliary filters: the pilot -- the noise-free S-step Euler path of every
 // particle and its log-likelihood -- and the first-stage log-weights
 hipError_t launch_vec_pilot(int D, const FusedEns *d_ens, int e, int M, int N, IvArg iv,
