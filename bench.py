@@ -788,7 +788,7 @@ def main():
 
     factory, M, N, T_cfg = pf_inputs.WORKLOADS[a.workload]
     spec = factory()
-    grid = spec["kind"] == "fhn"
+    grid = spec["kind"] in ("fhn", "fhn_paper")
     torch.cuda.set_device(0)
     graph = a.path == "graph"
     T = a.warmup + a.steps
@@ -824,7 +824,17 @@ def main():
     nodes = spec["J"] ** 2 if grid else 1
     value = M * N * S * a.steps / (ms / 1e3)
     k_avg_s = (k_ms / max(k_n, 1)) / 1e3
-    if grid and a.path == "plain":
+    if spec["kind"] == "fhn_paper":
+        # dominant kernel: every particle's interval with the planes in LDS;
+        # its HBM bytes are one read and one write of each particle's state
+        nbytes = 2.0 * 4 * spec["dx"] * M * N
+        achieved = nbytes / k_avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "k_fhnp_steps", "algorithmic_bytes_per_launch": nbytes,
+                    "kernel_avg_us": k_avg_s * 1e6, "launches": k_n,
+                    "timed_intervals": f"every {PROF_EVERY}th of the timed region"}
+    elif grid and a.path == "plain":
         # dominant kernel: one streaming Euler step of every particle per launch
         nbytes = FHN_BYTES_PER_NODE_STEP * M * N * nodes
         achieved = nbytes / k_avg_s / 1e9

@@ -8,363 +8,606 @@
 // the event of Euler step n: the centre node of the stimulated group, or
 // -1), padded with -1 to a multiple of 4.
 //
-// One workgroup advances one particle at a time with the planes in LDS.
+// One workgroup of 256 threads advances one particle at a time.  Thread t
+// owns the 4Q consecutive nodes 4Q t .. 4Q t + 4Q - 1 (Q = ceil(J*J / 1024)):
+// their U, V and stimulus coverage counts stay in registers for the whole
+// interval, and only the U plane (read by the neighbours) goes through LDS.
 // Per Euler step n:
-//   (a) the stimulus region: nodes whose U, or a 4-neighbour's U, lies in
-//       (u-, u+) -- each thread flags its contiguous nodes, and one block
-//       scan of the per-thread counts orders the region row-major;
-//   (b) one Philox call (particle, filter, n, PROP | sub-block J*J/2): its
-//       first uniform against eps decides the Bernoulli event, its second
-//       picks the floor(u |S|)-th node of the region as the centre; the
-//       thread whose range holds that node publishes it;
-//   (c) the event enters the ring; a per-node count of the ring's coverage
-//       (centre and its neighbours) is kept in LDS, so the stimulus of a
-//       node is F~ when its count is positive (F~ min{1, sum Q});
-//   (d) the Euler step of every node: U' = U + h (p3(U) - V) + h (c sum_nbr
-//       U + m F + Psi) + sigma~ sqrt(h) z, V' = V + h (b0 U + b1 V + b2),
-//       the normals of node pair p from the FH-N grid layout (call (particle,
-//       filter, n, PROP | p): lanes 0, 1 for node 2p, lanes 2, 3 for 2p + 1).
-// The first read goes through the ancestors (fused gather); the last step
-// ends with the log-likelihood of the observed U nodes.
+//   (A) [barrier: the plane is complete] every thread reads the four
+//       neighbours of its nodes once, for the coupling sum and for the
+//       stimulus region (nodes whose U, or a 4-neighbour's U, lies in the
+//       open band (u-, u+)), and counts its region nodes; a wave scan of the
+//       counts and the wave totals in LDS order the region row-major;
+//   (B) [barrier] one Philox call (particle, filter, n, PROP | sub-block
+//       J*J/2), the same in every thread: its first uniform against eps
+//       decides the Bernoulli event, its second picks the floor(u |S|)-th
+//       node of the region as the centre; on an event step (rare) the thread
+//       whose range holds that node publishes it [barrier];
+//   (C) the event replaces the ring's entry of step n - l0: every thread
+//       updates the coverage counts of its nodes (centre and neighbours of
+//       the entering and the leaving event), so that the stimulus of a node
+//       is F~ when its count is positive (F~ min{1, sum Q});
+//   (D) the Euler step of every node in registers: U' = U + h (p3(U) - V) +
+//       h (c sum_nbr U + m F + Psi) + sigma~ sqrt(h) z, V' = V + h (b0 U +
+//       b1 V + b2), the normals of node pair p from the FH-N grid layout
+//       (call (particle, filter, n, PROP | p): lanes 0, 1 for node 2p, lanes
+//       2, 3 for 2p + 1); U' goes back into the plane.
+// The next particle's state is fetched into registers while this one steps
+// (its ancestor index one particle earlier still).  The log-likelihood of
+// the observed U nodes is summed from the final plane, which stays intact
+// (the planes alternate by particle) until the next particle's first step.
 #include "pf_internal.h"
 
 namespace pfk {
 namespace {
 
-constexpr int FP_THREADS = 256;
+constexpr int FP_THREADS = 256, FP_WAVES = FP_THREADS / 64;
 
-struct FhnpLds {
-  float *u, *un, *v;  // [nn] each
-  int *inr, *cov;     // [nn] each
-  int *ring;          // [32]
-  int *scan;          // [FP_THREADS / 64 + 4]: wave sums, then broadcast slots
+// streaming access to a particle's state (touched once per interval)
+typedef float fp4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4(const gmem<float> *p) {
+  const fp4v v = __builtin_nontemporal_load((const gmem<fp4v> *)p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4(gmem<float> *p, float a, float b, float c, float d) {
+  const fp4v v = {a, b, c, d};
+  __builtin_nontemporal_store(v, (gmem<fp4v> *)p);
+}
+
+// per-node bits (fixed for a thread): which grid neighbours exist, whether
+// the node is in the forced 2 x 2 corner block, whether it is a node at all
+constexpr int NB_UP = 1, NB_DOWN = 2, NB_LEFT = 4, NB_RIGHT = 8, NB_CORNER = 16, NB_VALID = 32;
+
+struct FpLds {
+  float *plane[2];  // U planes [J*J], alternating by particle
+  int *ring;        // [32] the current particle's event ring
+  int *wsum;        // [FP_WAVES] wave totals of the region count
+  int *ev;          // [1] centre of the step's event
+  float *lwp;       // [FP_WAVES] wave sums of the squared residuals
 };
 
-__device__ __forceinline__ FhnpLds fhnp_lds(int nn) {
-  extern __shared__ float fp_lds[];
-  FhnpLds L;
-  L.u = fp_lds;
-  L.un = L.u + nn;
-  L.v = L.un + nn;
-  L.inr = (int *)(L.v + nn);
-  L.cov = L.inr + nn;
-  L.ring = L.cov + nn;
-  L.scan = L.ring + 32;
+__device__ __forceinline__ FpLds fp_lds(int nn) {
+  extern __shared__ float4 fp_mem4[];
+  float *fp_mem = (float *)fp_mem4;
+  FpLds L;
+  L.plane[0] = fp_mem;
+  L.plane[1] = fp_mem + nn;
+  L.ring = (int *)(fp_mem + 2 * nn);
+  L.wsum = L.ring + 32;
+  L.ev = L.wsum + FP_WAVES;
+  L.lwp = (float *)(L.ev + 4);
   return L;
 }
 
-// the centre node and its neighbours inside the grid: +d to the coverage
-__device__ __forceinline__ void cover(int *cov, int J, int c, int d) {
-  if (c < 0) return;
-  const int i = c / J, j = c - i * J;
-  cov[c] += d;
-  if (i > 0) cov[c - J] += d;
-  if (i < J - 1) cov[c + J] += d;
-  if (j > 0) cov[c - 1] += d;
-  if (j < J - 1) cov[c + 1] += d;
+size_t fhnp_lds_bytes(int J) {
+  const size_t nn = (size_t)J * J;
+  return sizeof(float) * (2 * nn + 32 + FP_WAVES + 4 + FP_WAVES);
+}
+
+template <int Q>
+__device__ __forceinline__ void node_bits(int J, int nb[4 * Q]) {
+  const int nn = J * J, k0 = 4 * Q * (int)threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < 4 * Q; ++e) {
+    const int k = k0 + e, i = k / J, j = k - i * J;
+    nb[e] = k >= nn ? 0
+                    : NB_VALID | (i > 0 ? NB_UP : 0) | (i < J - 1 ? NB_DOWN : 0) |
+                          (j > 0 ? NB_LEFT : 0) | (j < J - 1 ? NB_RIGHT : 0) |
+                          (i < 2 && j < 2 ? NB_CORNER : 0);
+  }
+}
+
+// 1 when node k is the centre c or one of its grid neighbours (c < 0: none)
+__device__ __forceinline__ int covers(int J, int c, int k) {
+  if (c < 0) return 0;
+  const int ci = c / J, cj = c - ci * J, i = k / J, j = k - i * J;
+  return ((ci == i && abs(cj - j) <= 1) || (cj == j && abs(ci - i) == 1)) ? 1 : 0;
+}
+
+// the first normal of a Box-Muller pair alone: r cos 2 pi u1, as box_muller
+// computes it
+__device__ __forceinline__ float box_muller_cos(uint32_t a, uint32_t b) {
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01f(a)));
+  return r * __builtin_amdgcn_cosf(u01f(b));
 }
 
 __device__ __forceinline__ bool in_band(const ModelDev &md, float u) {
   return u > md.stim_lo && u < md.stim_hi;
 }
 
-// Node range of a thread: P consecutive nodes, P even (whole noise pairs).
-__device__ __forceinline__ int fhnp_per_thread(int nn) {
-  return 2 * ((nn + 2 * FP_THREADS - 1) / (2 * FP_THREADS));
+// inclusive scan of small integers across the 64 lanes (DPP row shifts,
+// then the row broadcasts)
+__device__ __forceinline__ int wave_scan_i32(int v) {
+  v += dpp_i32<DPP_ROW_SHR1, 0xf>(v, 0);
+  v += dpp_i32<DPP_ROW_SHR2, 0xf>(v, 0);
+  v += dpp_i32<DPP_ROW_SHR4, 0xf>(v, 0);
+  v += dpp_i32<DPP_ROW_SHR8, 0xf>(v, 0);
+  v += dpp_i32<DPP_ROW_BCAST15, 0xa>(v, 0);
+  v += dpp_i32<DPP_ROW_BCAST31, 0xc>(v, 0);
+  return v;
 }
 
-// S Euler steps n0 .. n0 + S - 1 of the particle in LDS (u, v, ring, cov).
-// c0, c1, purpose: its Philox stream.  Leaves the state in L.u, L.v, L.ring.
-// PILOT: the noise-free continuation (the auxiliary filter's pilot): no new
-// stimulus event and no noise; the ring's active stimuli and the forcing act.
-template <bool PILOT>
-__device__ void fhnp_steps(const ModelDev &md, Key key, uint32_t purpose, uint32_t c0,
-                           uint32_t c1, int n0, FhnpLds &L) {
-  const int J = md.J, nn = J * J, tid = threadIdx.x;
-  const int P = fhnp_per_thread(nn), k0 = tid * P;
-  const int lane = tid & 63, wid = tid >> 6;
+// Coverage counts of a thread's nodes from the ring in LDS (entries
+// 0..l0-1, l0 <= 32): all 32 entries in eight broadcast reads, then the
+// active ones (usually none) one by one.
+template <int Q>
+__device__ __forceinline__ void build_cover(int J, int l0, const int nb[4 * Q], const int *ring,
+                                            int cov[4 * Q]) {
+  const int k0 = 4 * Q * (int)threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < 4 * Q; ++e) cov[e] = 0;
+  unsigned act = 0;
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    const int4 c = ((const int4 *)ring)[g];
+    act |= (c.x >= 0 ? 1u : 0u) << (4 * g);
+    act |= (c.y >= 0 ? 1u : 0u) << (4 * g + 1);
+    act |= (c.z >= 0 ? 1u : 0u) << (4 * g + 2);
+    act |= (c.w >= 0 ? 1u : 0u) << (4 * g + 3);
+  }
+  if (l0 < 32) act &= (1u << l0) - 1u;
+  act = __builtin_amdgcn_readfirstlane(act);
+  while (act) {
+    const int l = __builtin_ctz(act);
+    act &= act - 1u;
+    const int c = __builtin_amdgcn_readfirstlane(ring[l]);
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e)
+      if (nb[e] & NB_VALID) cov[e] += covers(J, c, k0 + e);
+  }
+}
+
+// S Euler steps n0 .. n0 + S - 1 of the particle whose nodes this thread
+// holds in (u, v, cov), with the whole U plane in `pl` and the ring in LDS;
+// the caller has made the plane and the ring visible (a barrier).  PILOT:
+// the auxiliary filter's noise-free continuation -- no new stimulus events
+// and no noise; the ring's active stimuli and the forcing act, and the ring
+// advances.  hook.before_b() / hook.after_b() run in step 0 just before and
+// after its second barrier.  Leaves U' in the plane (not yet synchronised)
+// and the ring updated.
+template <int Q, bool PILOT, class Hook>
+__device__ __forceinline__ void fhnp_steps(const ModelDev &md, Key key, uint32_t purpose,
+                                           uint32_t c0, uint32_t c1, int n0, const int nb[4 * Q],
+                                           float u[4 * Q], float v[4 * Q], int cov[4 * Q],
+                                           float *pl, const FpLds &L, Hook &hook) {
+  const int J = md.J, nn = J * J, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int k0 = 4 * Q * tid;
   for (int st = 0; st < md.S; ++st) {
     const uint32_t n = (uint32_t)(n0 + st);
-    if (PILOT) {
-      if (tid == 0) L.scan[FP_THREADS / 64 + 1] = -1;
-      __syncthreads();
-    } else {
-      // (a) stimulus region
-      for (int e = 0; e < P; ++e) {
-        const int k = k0 + e;
-        if (k < nn) L.inr[k] = in_band(md, L.u[k]) ? 1 : 0;
+    if (st > 0) __syncthreads();  // (A) U' of the previous step is in the plane
+    const int slot = (int)(n % (uint32_t)md.stim_l0);
+    const int old = __builtin_amdgcn_readfirstlane(L.ring[slot]);
+    // neighbours: coupling sums (up, down, left, right) and region flags
+    float sum[4 * Q];
+    unsigned rm = 0;
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e) {
+      const int k = k0 + e, b = nb[e];
+      float s = 0.f;
+      bool r = in_band(md, u[e]);
+      if (b & NB_UP) {
+        const float x = pl[k - J];
+        s += x;
+        r |= in_band(md, x);
       }
-      __syncthreads();
-      int cnt = 0;
-      for (int e = 0; e < P; ++e) {
-        const int k = k0 + e;
-        if (k < nn) {
-          const int i = k / J, j = k - i * J;
-          const int r = L.inr[k] | (i > 0 ? L.inr[k - J] : 0) | (i < J - 1 ? L.inr[k + J] : 0) |
-                        (j > 0 ? L.inr[k - 1] : 0) | (j < J - 1 ? L.inr[k + 1] : 0);
-          cnt += r;
-        }
+      if (b & NB_DOWN) {
+        const float x = pl[k + J];
+        s += x;
+        r |= in_band(md, x);
       }
-      // exclusive scan of the counts over the workgroup
-      int inc = cnt;
-  #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += y;
+      if (b & NB_LEFT) {
+        const float x = pl[k - 1];
+        s += x;
+        r |= in_band(md, x);
       }
-      if (lane == 63) L.scan[wid] = inc;
-      __syncthreads();
+      if (b & NB_RIGHT) {
+        const float x = pl[k + 1];
+        s += x;
+        r |= in_band(md, x);
+      }
+      sum[e] = s;
+      if ((b & NB_VALID) && r) rm |= 1u << e;
+    }
+    int ev = -1;
+    if (!PILOT) {
+      const int cnt = __builtin_popcount(rm);
+      const int inc = wave_scan_i32(cnt);
+      if (lane == 63) L.wsum[wid] = inc;
+      if (st == 0) hook.before_b();
+      __syncthreads();  // (B)
+      if (st == 0) hook.after_b();
       int off = inc - cnt, total = 0;
-      for (int w = 0; w < FP_THREADS / 64; ++w) {
-        if (w < wid) off += L.scan[w];
-        total += L.scan[w];
+#pragma unroll
+      for (int w = 0; w < FP_WAVES; ++w) {
+        const int ws = L.wsum[w];
+        off += w < wid ? ws : 0;
+        total += ws;
       }
-      // (b) the Bernoulli event and its centre
-      if (tid == 0) {
-        const uint4 r = philox(c0, c1, n, (purpose << 24) | (uint32_t)(nn / 2), key);
-        int kth = -1;
-        if (total > 0 && u01d(r.x) < md.stim_eps) {
-          kth = (int)floor(u01d(r.y) * (double)total);
-          kth = min(kth, total - 1);
+      total = __builtin_amdgcn_readfirstlane(total);
+      const uint4 r = philox(c0, c1, n, (purpose << 24) | (uint32_t)(nn / 2), key);
+      int kth = -1;
+      if (total > 0 && u01d(r.x) < md.stim_eps)
+        kth = min((int)floor(u01d(r.y) * (double)total), total - 1);
+      kth = __builtin_amdgcn_readfirstlane(kth);
+      if (kth >= 0) {  // an event (the same decision in every thread)
+        if (kth >= off && kth < off + cnt) {
+          int want = kth - off;
+#pragma unroll
+          for (int e = 0; e < 4 * Q; ++e)
+            if ((rm >> e) & 1u) {
+              if (want == 0) L.ev[0] = k0 + e;
+              --want;
+            }
         }
-        L.scan[FP_THREADS / 64] = kth;
-        L.scan[FP_THREADS / 64 + 1] = -1;
+        __syncthreads();
+        ev = __builtin_amdgcn_readfirstlane(L.ev[0]);
       }
-      __syncthreads();
-      const int kth = L.scan[FP_THREADS / 64];
-      if (kth >= off && kth < off + cnt) {
-        int want = kth - off;
-        for (int e = 0; e < P; ++e) {
-          const int k = k0 + e;
-          if (k < nn) {
-            const int i = k / J, j = k - i * J;
-            const int r = L.inr[k] | (i > 0 ? L.inr[k - J] : 0) | (i < J - 1 ? L.inr[k + J] : 0) |
-                          (j > 0 ? L.inr[k - 1] : 0) | (j < J - 1 ? L.inr[k + 1] : 0);
-            if (r && want-- == 0) L.scan[FP_THREADS / 64 + 1] = k;
-          }
-        }
-      }
-      __syncthreads();
+    } else {
+      if (st == 0) hook.before_b();
+      __syncthreads();  // (B)
+      if (st == 0) hook.after_b();
     }
-    // (c) the ring and the coverage counts
-    if (tid == 0) {
-      const int slot = (int)(n % (uint32_t)md.stim_l0);
-      const int ev = L.scan[FP_THREADS / 64 + 1];
-      cover(L.cov, J, L.ring[slot], -1);
-      L.ring[slot] = ev;
-      cover(L.cov, J, ev, +1);
+    // (C) the ring: ev enters slot n mod l0, the event of step n - l0 leaves
+    if (old >= 0 || ev >= 0) {
+#pragma unroll
+      for (int e = 0; e < 4 * Q; ++e)
+        if (nb[e] & NB_VALID) cov[e] += covers(J, ev, k0 + e) - covers(J, old, k0 + e);
+      if (tid == (slot >> 2)) L.ring[slot] = ev;  // the thread that loaded that slot
     }
-    __syncthreads();
-    // (d) Euler step of this thread's node pairs
+    // (D) Euler step of this thread's node pairs
+    const bool vnoise = md.sq1 != 0.f;
     const bool forcing = (int)(n % (uint32_t)md.force_period) < md.force_width;
-    for (int e = 0; e < P; e += 2) {
-      const int k = k0 + e;
-      if (k >= nn) break;
+#pragma unroll
+    for (int pp = 0; pp < 2 * Q; ++pp) {
       float z[4] = {0.f, 0.f, 0.f, 0.f};
-      if (!PILOT) normals4(philox(c0, c1, n, (purpose << 24) | (uint32_t)(k >> 1), key), z);
+      if (!PILOT && (nb[2 * pp] & NB_VALID)) {
+        const uint4 w = philox(c0, c1, n, (purpose << 24) | (uint32_t)((k0 >> 1) + pp), key);
+        if (vnoise) {
+          normals4(w, z);
+        } else {
+          // V without noise: only the U normals (lanes 0 and 2), the same values
+          z[0] = box_muller_cos(w.x, w.y);
+          z[2] = box_muller_cos(w.z, w.w);
+        }
+      }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int kk = k + q;
-        const int i = kk / J, j = kk - i * J;
-        float sum = 0.f;
-        if (i > 0) sum += L.u[kk - J];
-        if (i < J - 1) sum += L.u[kk + J];
-        if (j > 0) sum += L.u[kk - 1];
-        if (j < J - 1) sum += L.u[kk + 1];
-        const float u = L.u[kk], v = L.v[kk];
-        const float psi = L.cov[kk] > 0 ? md.stim_amp : 0.f;
-        const float mf = (forcing && i < 2 && j < 2) ? md.stim_amp : 0.f;
-        const float p3 = md.p0 * u - u * u * u;
-        const float un = (u + md.h * (p3 - v)) + md.h * (md.p1 * sum + mf + psi);
-        L.un[kk] = fmaf(md.sq0, z[2 * q], un);
-        const float vn = v + md.h * (md.p2 * u + md.p3 * v + md.stim_b2);
-        L.v[kk] = fmaf(md.sq1, z[2 * q + 1], vn);
+        const int e = 2 * pp + q;
+        const float uu = u[e], vv = v[e];
+        const float psi = cov[e] > 0 ? md.stim_amp : 0.f;
+        const float mf = (forcing && (nb[e] & NB_CORNER)) ? md.stim_amp : 0.f;
+        const float p3 = md.p0 * uu - uu * uu * uu;
+        const float un = (uu + md.h * (p3 - vv)) + md.h * (md.p1 * sum[e] + mf + psi);
+        u[e] = fmaf(md.sq0, z[2 * q], un);
+        const float vn = vv + md.h * (md.p2 * uu + md.p3 * vv + md.stim_b2);
+        v[e] = fmaf(md.sq1, z[2 * q + 1], vn);
       }
     }
-    __syncthreads();
-    float *tmp = L.u;
-    L.u = L.un;
-    L.un = tmp;
-  }
-}
-
-// Load the particle (U, V, ring) into LDS and build the coverage counts.
-__device__ __forceinline__ void fhnp_load(const ModelDev &md, const float *x, FhnpLds &L) {
-  const int nn = md.J * md.J, l0 = md.stim_l0;
-  for (int k = threadIdx.x; k < nn; k += FP_THREADS) {
-    L.u[k] = x[k];
-    L.v[k] = x[nn + k];
-    L.cov[k] = 0;
-  }
-  if (threadIdx.x < 32) L.ring[threadIdx.x] = threadIdx.x < l0 ? (int)x[2 * nn + threadIdx.x] : -1;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int l = 0; l < l0; ++l) cover(L.cov, md.J, L.ring[l], +1);
-  __syncthreads();
-}
-
-__device__ __forceinline__ void fhnp_store(const ModelDev &md, float *x, const FhnpLds &L) {
-  const int nn = md.J * md.J, ring = md.dx - 2 * nn;
-  for (int k = threadIdx.x; k < nn; k += FP_THREADS) {
-    x[k] = L.u[k];
-    x[nn + k] = L.v[k];
-  }
-  if (threadIdx.x < ring) x[2 * nn + threadIdx.x] = threadIdx.x < md.stim_l0 ? (float)L.ring[threadIdx.x] : -1.f;
-}
-
-// Interval t of every particle of one ensemble (fused path): read through
-// the ancestors when `pending`, S steps, state out, log-likelihood.
-__global__ void __launch_bounds__(FP_THREADS)
-k_fhnp_steps(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pending) {
-  const int t = iv_t(iv);
-  const float *y = iv_y(iv, t);
-  const FusedEns &E = ens[e];
-  const ModelDev md = E.md;
-  const int nn = md.J * md.J, dx = md.dx, N = E.N, MN = E.M * N;
-  FhnpLds L = fhnp_lds(nn);
-  const float *Xin = parity ? E.X1 : E.X0;
-  float *Xout = parity ? E.X0 : E.X1;
-  for (int p = blockIdx.x; p < MN; p += gridDim.x) {
-    const int m = p / N, i = p - m * N;
-    // (an auxiliary filter's particles always come through the ancestors its
-    // first stage has just drawn)
-    const bool thru = pending || E.apf;
-    const int src = thru ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
-    fhnp_load(md, Xin + ((size_t)m * N + src) * dx, L);
-    fhnp_steps<false>(md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * md.S, L);
-    fhnp_store(md, Xout + ((size_t)m * N + i) * dx, L);
-    if (y) {
-      float acc = 0.f;
-      for (int k = threadIdx.x; k < md.dy; k += FP_THREADS) {
-        const float r = gptr(y)[E.yoff + k] - L.u[gptr(md.obs_idx)[k]];
-        acc = fmaf(r, r, acc);
-      }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-      __syncthreads();
-      if ((threadIdx.x & 63) == 0) L.scan[threadIdx.x >> 6] = __float_as_int(acc);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float a = 0.f;
-        for (int w = 0; w < FP_THREADS / 64; ++w) a += __int_as_float(L.scan[w]);
-        float l = -a * md.inv2var;
-        // auxiliary filter: divided by the pilot likelihood of the ancestor
-        if (E.apf) l -= gptr(E.lpil)[(size_t)m * N + src];
-        gptr(E.lw)[(size_t)m * N + i] = l == l ? l : -INFINITY;
-      }
-    }
-    __syncthreads();
+    for (int g = 0; g < Q; ++g)
+      if (nb[4 * g] & NB_VALID)
+        *(float4 *)(pl + k0 + 4 * g) = make_float4(u[4 * g], u[4 * g + 1], u[4 * g + 2], u[4 * g + 3]);
   }
 }
 
-// Auxiliary filters: the pilot of every particle -- S noise-free steps
-// without new stimuli -- its log-likelihood, kept for the second stage, and
-// the first-stage log-weight lwc + log g(y | mu).
-__global__ void __launch_bounds__(FP_THREADS)
-k_fhnp_pilot(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pending) {
-  const int t = iv_t(iv);
-  const float *y = iv_y(iv, t);
-  const FusedEns &E = ens[e];
-  const ModelDev md = E.md;
-  const int nn = md.J * md.J, dx = md.dx, N = E.N, MN = E.M * N;
-  FhnpLds L = fhnp_lds(nn);
-  const float *Xin = parity ? E.X1 : E.X0;
-  for (int p = blockIdx.x; p < MN; p += gridDim.x) {
-    const int m = p / N, i = p - m * N;
-    const int src = pending ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
-    fhnp_load(md, Xin + ((size_t)m * N + src) * dx, L);
-    fhnp_steps<true>(md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * md.S, L);
+struct NoHook {
+  __device__ void before_b() {}
+  __device__ void after_b() {}
+};
+
+// The previous particle's log-likelihood: the squared residuals of the
+// observed U nodes summed from its final plane before the second barrier of
+// the next particle's first step, finished by thread 0 after it (after the
+// last particle, between two barriers of their own).
+template <bool PILOT>
+struct LikHook {
+  const gmem<float> *y;      // this ensemble's observations (null: none)
+  const gmem<int32_t> *obs;  // observed nodes [dy]
+  gmem<float> *lw, *lpil;
+  const gmem<float> *lwc;
+  float inv2var;
+  int dy, apf, N;
+  float *lwp;          // LDS wave sums
+  const float *plane;  // the previous particle's final plane
+  int m, i, src;       // the previous particle and its ancestor
+  bool active;
+  int o0;    // this thread's first observation (k = thread index): its node
+  float y0;  // and value
+  float lpil_src;  // (thread 0, auxiliary filter) the pilot log-likelihood of the ancestor
+  __device__ void set_prev(bool on, const float *pl, int pm, int pi, int psrc) {
+    active = on;
+    plane = pl;
+    m = pm;
+    i = pi;
+    src = psrc;
+    // read now, used at the next particle's second barrier
+    if (!PILOT && on && apf && threadIdx.x == 0) lpil_src = lpil[(size_t)pm * N + psrc];
+  }
+  __device__ void init_obs() {
+    const int k = threadIdx.x;
+    o0 = y && k < dy ? obs[k] : 0;
+    y0 = y && k < dy ? y[k] : 0.f;
+  }
+  __device__ void before_b() {
+    if (!active) return;
     float acc = 0.f;
-    for (int k = threadIdx.x; k < md.dy; k += FP_THREADS) {
-      const float r = gptr(y)[E.yoff + k] - L.u[gptr(md.obs_idx)[k]];
+    if ((int)threadIdx.x < dy) {
+      const float r = y0 - plane[o0];
+      acc = r * r;
+    }
+    for (int k = threadIdx.x + FP_THREADS; k < dy; k += FP_THREADS) {
+      const float r = y[k] - plane[obs[k]];
       acc = fmaf(r, r, acc);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) L.scan[threadIdx.x >> 6] = __float_as_int(acc);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float a = 0.f;
-      for (int w = 0; w < FP_THREADS / 64; ++w) a += __int_as_float(L.scan[w]);
-      float pl = -a * md.inv2var;
-      pl = pl == pl ? pl : -INFINITY;
-      const size_t o = (size_t)m * N + i;
-      gptr(E.lpil)[o] = pl;
-      const float lam = pl + gptr(E.lwc)[o];
-      gptr(E.lw)[o] = lam == lam ? lam : -INFINITY;
+    if ((threadIdx.x & 63) == 0) lwp[threadIdx.x >> 6] = acc;
+  }
+  __device__ void after_b() {
+    if (!active || threadIdx.x != 0) return;
+    float a = 0.f;
+#pragma unroll
+    for (int w = 0; w < FP_WAVES; ++w) a += lwp[w];
+    float l = -a * inv2var;
+    const size_t o = (size_t)m * N + i;
+    if (PILOT) {
+      // auxiliary filter: the pilot likelihood, kept for the second stage,
+      // and the first-stage log-weight lwc + log g(y | mu)
+      l = l == l ? l : -INFINITY;
+      lpil[o] = l;
+      const float lam = l + lwc[o];
+      lw[o] = lam == lam ? lam : -INFINITY;
+    } else {
+      // auxiliary filter: divided by the pilot likelihood of the ancestor
+      if (apf) l -= lpil_src;
+      lw[o] = l == l ? l : -INFINITY;
     }
+  }
+};
+
+// Interval t of every particle of fused ensemble e: the state read through
+// the ancestors when `pending` (always for an auxiliary filter, whose first
+// stage has just drawn them), S steps, state out, log-likelihood when iv
+// carries observations.  PILOT: the auxiliary filter's pilot -- S noise-free
+// steps without new stimuli, no state out, the pilot likelihood and the
+// first-stage log-weight.
+template <int Q, bool PILOT>
+__global__ void __launch_bounds__(FP_THREADS)
+k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pending) {
+  const int t = iv_t(iv);
+  const float *y = iv_y(iv, t);
+  const FusedEns &E = ens[e];
+  const ModelDev md = E.md;
+  const int J = md.J, nn = J * J, dx = md.dx, N = E.N, MN = E.M * N, G = gridDim.x;
+  const int tid = threadIdx.x, k0 = 4 * Q * tid, nr4 = (dx - 2 * nn) / 4;
+  const FpLds L = fp_lds(nn);
+  const gmem<float> *Xin = gptr(parity ? E.X1 : E.X0);
+  gmem<float> *Xout = gptr(parity ? E.X0 : E.X1);
+  const gmem<int32_t> *A = gptr(E.A);
+  const bool thru = PILOT ? (pending != 0) : (pending || E.apf);
+  int nb[4 * Q];
+  node_bits<Q>(J, nb);
+
+  // The next particle's state is fetched into registers while this one
+  // steps, its ancestor index one particle earlier still.  Both fetches are
+  // unconditional (past the end they repeat the last particle, unused), and
+  // the index stays raw in a vector register until it is used: the compiler
+  // would otherwise move it to a scalar register at once, and waiting for it
+  // would also wait for every load issued before it.
+  int vzero;
+  asm("v_mov_b32 %0, 0" : "=v"(vzero));
+  auto anc_raw = [&](int p) {
+    p = min(p, MN - 1);
+    return thru ? A[(size_t)p + vzero] : p - (p / N) * N;
+  };
+  auto src_of = [&](int raw) { return min(max(raw, 0), N - 1); };
+  float4 fu[Q], fv[Q], fr = make_float4(-1.f, -1.f, -1.f, -1.f);
+#pragma unroll
+  for (int g = 0; g < Q; ++g) fu[g] = fv[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto fetch = [&](int p, int src) {
+    const int m = min(p, MN - 1) / N;
+    const gmem<float> *x = Xin + ((size_t)m * N + src) * dx;
+#pragma unroll
+    for (int g = 0; g < Q; ++g)
+      if (nb[4 * g] & NB_VALID) {
+        fu[g] = ld4(x + k0 + 4 * g);
+        fv[g] = ld4(x + nn + k0 + 4 * g);
+      }
+    if (tid < nr4) fr = ld4(x + 2 * nn + 4 * tid);
+  };
+
+  int p = blockIdx.x;
+  int src = src_of(anc_raw(p));
+  fetch(p, src);
+  int raw_nx = anc_raw(p + G);
+  LikHook<PILOT> hook{y ? gptr(y) + E.yoff : nullptr, gptr(md.obs_idx), gptr(E.lw), gptr(E.lpil),
+                      gptr((const float *)E.lwc), md.inv2var, md.dy, E.apf, N, L.lwp,
+                      L.plane[1], 0, 0, 0, false, 0, 0.f, 0.f};
+  hook.init_obs();
+  // A particle's new state is written out at the start of the next
+  // iteration, after the prefetched state has been taken from its registers
+  // and before the next prefetch is issued: with loads and stores both
+  // outstanding, a wait for one kind is a wait for all, and here the only
+  // wait for a load comes before the stores and a particle's time after it.
+  float u[4 * Q], v[4 * Q];
+  int m = 0, i = 0;
+  auto store = [&]() {
+    gmem<float> *x = Xout + ((size_t)m * N + i) * dx;
+#pragma unroll
+    for (int g = 0; g < Q; ++g)
+      if (nb[4 * g] & NB_VALID) {
+        st4(x + k0 + 4 * g, u[4 * g], u[4 * g + 1], u[4 * g + 2], u[4 * g + 3]);
+        st4(x + nn + k0 + 4 * g, v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
+      }
+    if (tid < nr4) {
+      // (this thread's own ring slots: no other thread writes them)
+      float r[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) r[c] = 4 * tid + c < md.stim_l0 ? (float)L.ring[4 * tid + c] : -1.f;
+      st4(x + 2 * nn + 4 * tid, r[0], r[1], r[2], r[3]);
+    }
+  };
+  int par = 0;
+  for (; p < MN; p += G) {
+    // every load issued in the previous iteration (this particle's state and
+    // the next ancestor index) has arrived, issued a particle's time ago; the
+    // wait comes before the previous particle's stores, so it never waits
+    // for them (s_waitcnt vmcnt(0), the other counters left alone)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    float *pl = par ? L.plane[1] : L.plane[0];
+    float4 cu[Q], cv[Q];
+#pragma unroll
+    for (int g = 0; g < Q; ++g) {
+      cu[g] = fu[g], cv[g] = fv[g];
+      if (nb[4 * g] & NB_VALID) *(float4 *)(pl + k0 + 4 * g) = cu[g];
+    }
+    const int r0 = (int)fr.x, r1 = (int)fr.y, r2 = (int)fr.z, r3 = (int)fr.w;
+    // the previous particle's state out (its ring slots are read from LDS
+    // before this thread overwrites them)
+    if (!PILOT && p != (int)blockIdx.x) store();
+    m = p / N;
+    i = p - m * N;
+    int cov[4 * Q];
+#pragma unroll
+    for (int g = 0; g < Q; ++g) {
+      u[4 * g] = cu[g].x, u[4 * g + 1] = cu[g].y, u[4 * g + 2] = cu[g].z, u[4 * g + 3] = cu[g].w;
+      v[4 * g] = cv[g].x, v[4 * g + 1] = cv[g].y, v[4 * g + 2] = cv[g].z, v[4 * g + 3] = cv[g].w;
+    }
+    if (tid < nr4) {
+      L.ring[4 * tid] = r0;
+      L.ring[4 * tid + 1] = r1;
+      L.ring[4 * tid + 2] = r2;
+      L.ring[4 * tid + 3] = r3;
+    }
+    const int src_cur = src;
+    src = src_of(raw_nx);
+    fetch(p + G, src);
+    raw_nx = anc_raw(p + 2 * G);
+    __syncthreads();  // (A) of step 0: plane and ring complete
+    build_cover<Q>(J, md.stim_l0, nb, L.ring, cov);
+    fhnp_steps<Q, PILOT>(md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * md.S, nb, u, v, cov,
+                         pl, L, hook);
+    hook.set_prev(y != nullptr, pl, m, i, src_cur);
+    par ^= 1;
+  }
+  if (!PILOT) store();
+  if (hook.active) {
     __syncthreads();
+    hook.before_b();
+    __syncthreads();
+    hook.after_b();
   }
 }
 
 // Truth path and observations on the truth stream: one workgroup, T
 // intervals of S steps from x_0 ~ tau_0.
+template <int Q>
 __global__ void __launch_bounds__(FP_THREADS)
 k_fhnp_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *__restrict__ y) {
-  const int nn = md.J * md.J, dx = md.dx;
-  FhnpLds L = fhnp_lds(nn);
-  for (int s = threadIdx.x; s < dx; s += FP_THREADS) {
+  const int J = md.J, nn = J * J, dx = md.dx;
+  const int tid = threadIdx.x, k0 = 4 * Q * tid, nr4 = (dx - 2 * nn) / 4;
+  const FpLds L = fp_lds(nn);
+  for (int s = tid; s < dx; s += FP_THREADS) {
     float z[4];
     normals4(philox(0u, TRUTH_STREAM, 0u, (P_TRUTH_INIT << 24) | (uint32_t)(s >> 2), key), z);
     xtrue[s] = md.prior_mean[s] + md.prior_sd[s] * z[s & 3];
   }
   __syncthreads();
-  fhnp_load(md, xtrue, L);
+  int nb[4 * Q], cov[4 * Q];
+  float u[4 * Q], v[4 * Q];
+  node_bits<Q>(J, nb);
+  float *pl = L.plane[0];
+#pragma unroll
+  for (int e = 0; e < 4 * Q; ++e) {
+    const bool ok = nb[e] & NB_VALID;
+    u[e] = ok ? xtrue[k0 + e] : 0.f;
+    v[e] = ok ? xtrue[nn + k0 + e] : 0.f;
+    if (ok) pl[k0 + e] = u[e];
+  }
+  if (tid < nr4)
+    for (int c = 0; c < 4; ++c) L.ring[4 * tid + c] = (int)xtrue[2 * nn + 4 * tid + c];
+  __syncthreads();
+  build_cover<Q>(J, md.stim_l0, nb, L.ring, cov);
+  NoHook none;
   for (int t = 1; t <= T; ++t) {
-    fhnp_steps<false>(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, (t - 1) * md.S, L);
-    fhnp_store(md, xtrue + (size_t)t * dx, L);
-    for (int k4 = threadIdx.x; 4 * k4 < md.dy; k4 += FP_THREADS) {
+    fhnp_steps<Q, false>(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, (t - 1) * md.S, nb, u, v, cov,
+                         pl, L, none);
+    float *x = xtrue + (size_t)t * dx;
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e)
+      if (nb[e] & NB_VALID) {
+        x[k0 + e] = u[e];
+        x[nn + k0 + e] = v[e];
+      }
+    if (tid < nr4)
+      for (int c = 0; c < 4; ++c)
+        x[2 * nn + 4 * tid + c] = 4 * tid + c < md.stim_l0 ? (float)L.ring[4 * tid + c] : -1.f;
+    __syncthreads();  // the plane holds U at the observation time
+    for (int k4 = tid; 4 * k4 < md.dy; k4 += FP_THREADS) {
       float z[4];
       normals4(philox(0u, TRUTH_STREAM, (uint32_t)t, (P_OBS_NOISE << 24) | (uint32_t)k4, key), z);
       for (int l = 0; l < 4 && 4 * k4 + l < md.dy; ++l)
-        y[(size_t)(t - 1) * md.dy + 4 * k4 + l] = L.u[md.obs_idx[4 * k4 + l]] + md.obs_sd * z[l];
+        y[(size_t)(t - 1) * md.dy + 4 * k4 + l] = pl[md.obs_idx[4 * k4 + l]] + md.obs_sd * z[l];
     }
-    __syncthreads();
+    // (the next step writes the plane only after its second barrier)
   }
 }
 
-size_t fhnp_lds_bytes(int J) {
-  const size_t nn = (size_t)J * J;
-  return sizeof(float) * 3 * nn + sizeof(int) * (2 * nn + 32 + FP_THREADS / 64 + 4);
+template <bool PILOT, int Q>
+hipError_t launch_q(const FusedEns *d_ens, int e, int MN, int J, IvArg iv, int parity, int pending,
+                    hipStream_t s) {
+  int per_cu = 0, dev = 0, cus = 256;
+  const size_t lds = fhnp_lds_bytes(J);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fhnp<Q, PILOT>,
+                                                   FP_THREADS, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int blocks = std::min(MN, per_cu * cus);
+  k_fhnp<Q, PILOT><<<blocks, FP_THREADS, lds, s>>>(d_ens, e, iv, parity, pending);
+  return hipGetLastError();
+}
+
+// nodes per thread / 4 on a J x J grid (J even, at most 64)
+int fhnp_q(int J) { return (J * J + 4 * FP_THREADS - 1) / (4 * FP_THREADS); }
+
+template <bool PILOT>
+hipError_t launch_any(const FusedEns *d_ens, int e, int M, int N, int J, IvArg iv, int parity,
+                      int pending, hipStream_t s) {
+  if (M * N <= 0) return hipSuccess;
+  switch (fhnp_q(J)) {
+    case 1: return launch_q<PILOT, 1>(d_ens, e, M * N, J, iv, parity, pending, s);
+    case 2: return launch_q<PILOT, 2>(d_ens, e, M * N, J, iv, parity, pending, s);
+    case 3: return launch_q<PILOT, 3>(d_ens, e, M * N, J, iv, parity, pending, s);
+    case 4: return launch_q<PILOT, 4>(d_ens, e, M * N, J, iv, parity, pending, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 hipError_t launch_fhnp_steps(const FusedEns *d_ens, int e, int M, int N, int J, IvArg iv,
                              int parity, int pending, hipStream_t s) {
-  int per_cu = 0, dev = 0, cus = 256;
-  const size_t lds = fhnp_lds_bytes(J);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fhnp_steps, FP_THREADS,
-                                                   lds) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  if (hipGetDevice(&dev) == hipSuccess)
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int blocks = std::min(M * N, per_cu * cus);
-  k_fhnp_steps<<<blocks, FP_THREADS, lds, s>>>(d_ens, e, iv, parity, pending);
-  return hipGetLastError();
+  return launch_any<false>(d_ens, e, M, N, J, iv, parity, pending, s);
 }
 
 hipError_t launch_fhnp_pilot(const FusedEns *d_ens, int e, int M, int N, int J, IvArg iv,
                              int parity, int pending, hipStream_t s) {
-  int per_cu = 0, dev = 0, cus = 256;
-  const size_t lds = fhnp_lds_bytes(J);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fhnp_pilot, FP_THREADS,
-                                                   lds) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  if (hipGetDevice(&dev) == hipSuccess)
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int blocks = std::min(M * N, per_cu * cus);
-  k_fhnp_pilot<<<blocks, FP_THREADS, lds, s>>>(d_ens, e, iv, parity, pending);
-  return hipGetLastError();
+  return launch_any<true>(d_ens, e, M, N, J, iv, parity, pending, s);
 }
 
 hipError_t launch_fhnp_simulate(const EnsDev &e, uint64_t seed, int T, float *xtrue, float *y,
                                 hipStream_t s) {
-  k_fhnp_simulate<<<1, FP_THREADS, fhnp_lds_bytes(e.md.J), s>>>(e.md, make_key(seed), T, xtrue,
-                                                                 y);
+  const size_t lds = fhnp_lds_bytes(e.md.J);
+  const Key key = make_key(seed);
+  switch (fhnp_q(e.md.J)) {
+    case 1: k_fhnp_simulate<1><<<1, FP_THREADS, lds, s>>>(e.md, key, T, xtrue, y); break;
+    case 2: k_fhnp_simulate<2><<<1, FP_THREADS, lds, s>>>(e.md, key, T, xtrue, y); break;
+    case 3: k_fhnp_simulate<3><<<1, FP_THREADS, lds, s>>>(e.md, key, T, xtrue, y); break;
+    case 4: k_fhnp_simulate<4><<<1, FP_THREADS, lds, s>>>(e.md, key, T, xtrue, y); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -386,7 +386,8 @@ k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
   // every earlier kernel of the interval has read the counter
   if (t_inc && blockIdx.x == 0 && threadIdx.x == 0) *t_inc += 1;
   const FusedEns &E = ens[blockIdx.x];
-  if (E.md.kind == 2) return;  // grid model: folded by its own estimator
+  // grid models (both FH-N forms): folded by their own state-wide estimator
+  if (E.md.kind >= 2) return;
   const int dx = E.md.dx;
   if (dx <= 3) {
     double v[6];

@@ -138,6 +138,8 @@ WORKLOADS = {
     "fhn20_4x64": (lambda: fhn(20), 4, 64, 20),
     # learned proposal, compared with the bootstrap filter at N = 512
     "fhn40_learned_64x128": (fhn, 64, 128, 200),
+    # the paper's FH-N network, its largest ensemble (M = 10 x N = 5000)
+    "fhn_paper_10x5000": (fhn_paper, 10, 5000, 300),
     # uneven serving mix (see mixed_batch): 1024 Lorenz + 32 FH-N 20 x 20 tenants
     "mix_l63x1024_fhn20x32": (None, None, None, 100),
 }
