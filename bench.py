@@ -56,9 +56,10 @@ import pf_inputs  # noqa: E402
 #   157.3 TFLOP/s FP32 is this rate at 2 FLOP per FMA).  Work is counted in
 #   full-rate issue slots: half-rate instructions (32x32-bit integer
 #   multiply, v_mad_u64_u32, FP64 FMA, int->float conversion) take 2 slots,
-#   transcendentals (log2, sqrt, sin, cos, exp) take 4 -- the rates measured
-#   on the device.  Beside the slot fraction the line reports the pure FP32
-#   FLOP fraction of the model arithmetic against 157.3 TFLOP/s.
+#   transcendentals (log2, sqrt, sin, cos, exp) take 4, their issue rates
+#   relative to a 32-bit FMA.  Beside the slot fraction the line reports the
+#   slots the compiled kernel issues (hardware counters, below) and the pure
+#   FP32 FLOP fraction of the model arithmetic against 157.3 TFLOP/s.
 HBM_PEAK_GBS = 8000.0
 VALU_SLOTS_PER_S = 256 * 128 * 2.4e9
 FP32_PEAK_TFLOPS = 157.3
@@ -95,6 +96,20 @@ FHN_SLOTS_PER_NODE_STEP = 0.5 * PHILOX_SLOTS + BOXMULLER_SLOTS + 7 + 8 + 4
 # reaction v(v - a)(1 - v) - w + D lap (7), recovery eps (v - gam w) (3),
 # two updates x + h f + sd sqrt(h) z (2 FMAs each: 8).
 FHN_FP32_FLOP_PER_NODE_STEP = 25.0
+# Issued VALU work per unit from rocprofv3 counters of one launch
+# (SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_INSTS_VALU_INT64, x 64 lanes /
+# units; profiles/valu_instruction_mix.md): instructions per unit, and slots
+# = instructions + 3 per transcendental + 1 per 64-bit multiply-add.
+L63_ISSUED = {"valu": 60.30, "trans": 6.00, "int64": 11.85}
+FHN_ISSUED = {"valu": 62.01, "trans": 4.48, "int64": 8.50}
+# 64 lanes per CU per clock: the basis of the plain instruction-issue fraction
+VALU_LANE_OPS_64_PER_S = 256 * 64 * 2.4e9
+
+
+def issued_slots(mix):
+    return mix["valu"] + 3 * mix["trans"] + mix["int64"]
+
+
 # FH-N streaming Euler step: every node's v and w read and written once.
 FHN_BYTES_PER_NODE_STEP = 16.0
 
@@ -104,12 +119,14 @@ MLP_FLOP_PER_NODE_STEP = 2.0 * (22 * 64 + 64 * 64 + 64 * 2)
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB; fetch scaled x2, write x1 by the same counters on a 1 GiB
-# copy), recorded in profiles/hbm_counters_fhn_stream_step_and_lorenz_propagation.md
-# for the kernels as they are now.
+# WRITE_SIZE (KiB per dispatch of a timed-type interval, i.e. one that reads
+# through the ancestors; fetch scaled x2, write x1 by the same counters on a
+# 1 GiB copy), recorded in profiles/hbm_counters.md for the kernels as they
+# are now.
 MEASURED_TRAFFIC_BYTES = {
-    ("lorenz63", "fused", 256, 4096): (15618 + 16384) * 1024,
-    ("fhn", "plain", 64, 512): (409688 + 409610) * 1024,
+    ("lorenz63", "fused", 256, 4096): (2 * 9183.5 + 16384) * 1024,
+    ("fhn", "plain", 64, 512): (2 * 204841.5 + 409609) * 1024,
+    ("fhn_paper", "fused", 10, 5000): (2 * 199440 + 418640) * 1024,
 }
 
 SWEEP = (("l63_sweep_M1", 1, 1 << 20), ("l63_sweep_M16", 16, 1 << 16),
@@ -237,19 +254,27 @@ def estimates(pf, torch, spec, M, N, y, T, flags=0, params=None):
     return est
 
 
-def valu_roofline(kernel, slots, flop, k_avg_s, launches):
+def valu_roofline(kernel, slots, flop, k_avg_s, launches, units=None, issued=None):
     """VALU issue-slot fraction of a kernel against 7.86e13 slots/s, with the
-    pure FP32 FLOP fraction of its model arithmetic beside it."""
+    pure FP32 FLOP fraction of its model arithmetic beside it; with the
+    counter-measured instruction mix of the kernel (per unit) also the slots
+    it issues and its instruction count against 64 lanes per CU per clock."""
     achieved = slots / k_avg_s / 1e12
     peak = VALU_SLOTS_PER_S / 1e12
     tflops = flop / k_avg_s / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU-slots/s",
-            "frac": achieved / peak, "traffic": None, "kernel": kernel,
-            "algorithmic_slots_per_launch": slots,
-            "fp32_flop_per_launch": flop, "fp32_tflops": tflops,
-            "fp32_flop_frac": tflops / FP32_PEAK_TFLOPS,
-            "kernel_avg_us": k_avg_s * 1e6, "launches": launches,
-            "timed_intervals": f"every {PROF_EVERY}th of the timed region"}
+    r = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU-slots/s",
+         "frac": achieved / peak, "traffic": None, "kernel": kernel,
+         "algorithmic_slots_per_launch": slots,
+         "fp32_flop_per_launch": flop, "fp32_tflops": tflops,
+         "fp32_flop_frac": tflops / FP32_PEAK_TFLOPS,
+         "kernel_avg_us": k_avg_s * 1e6, "launches": launches,
+         "timed_intervals": f"every {PROF_EVERY}th of the timed region"}
+    if issued is not None and units:
+        s_issued = issued_slots(issued) * units
+        r["issued_slots_per_launch_counters"] = s_issued
+        r["issued_slot_frac"] = s_issued / k_avg_s / VALU_SLOTS_PER_S
+        r["valu_instr_frac_64_lanes"] = issued["valu"] * units / k_avg_s / VALU_LANE_OPS_64_PER_S
+    return r
 
 
 # ------------------------------------------------------ Lorenz sweep --------
@@ -313,7 +338,8 @@ def fhn_leg(pf, torch, a):
             units = M * N * nn * spec["S"]
             r["roofline"] = valu_roofline("k_grid_steps (all S steps, plane in LDS)",
                                           FHN_SLOTS_PER_NODE_STEP * units,
-                                          FHN_FP32_FLOP_PER_NODE_STEP * units, k_avg_s, k_n)
+                                          FHN_FP32_FLOP_PER_NODE_STEP * units, k_avg_s, k_n,
+                                          units, FHN_ISSUED)
             out["blocked"] = r
         else:
             nbytes = FHN_BYTES_PER_NODE_STEP * M * N * nn
@@ -850,7 +876,9 @@ def main():
         per_flop = FHN_FP32_FLOP_PER_NODE_STEP if grid else L63_FP32_FLOP_PER_PARTICLE_STEP
         kname = {"fused": "k_grid_steps" if grid else "k_vec_prop_batched",
                  "graph": "interval graph", "plain": "k_vec_propagate"}[a.path]
-        roofline = valu_roofline(kname, per_slots * units, per_flop * units, k_avg_s, k_n)
+        issued = (FHN_ISSUED if grid else L63_ISSUED) if a.path == "fused" else None
+        roofline = valu_roofline(kname, per_slots * units, per_flop * units, k_avg_s, k_n,
+                                 units, issued)
     roofline["traffic"] = MEASURED_TRAFFIC_BYTES.get((spec["kind"], a.path, M, N))
     cpu = None
     if a.cpu_seconds > 0:
