@@ -20,9 +20,11 @@ namespace {
 
 __device__ __forceinline__ float sane_lw(float v) { return (v == v) ? v : -INFINITY; }
 
-// Tile maximum of the log-weights.
+// Tile maximum of the log-weights, as the tile's order-preserving key (0 when
+// every weight of the tile is zero).  The fused path's propagation raises the
+// same keys as it writes the log-weights, and this launch is then skipped.
 __global__ void __launch_bounds__(TILE_THREADS)
-k_tile_max(int N, int T, const float *__restrict__ lw, double *__restrict__ tile) {
+k_tile_maxkey(int N, int T, const float *__restrict__ lw, uint32_t *__restrict__ key) {
   __shared__ float sh[TILE_THREADS / 64];
   const int m = blockIdx.y, q = blockIdx.x;
   float v = -INFINITY;
@@ -31,15 +33,14 @@ k_tile_max(int N, int T, const float *__restrict__ lw, double *__restrict__ tile
     if (i < N) v = fmaxf(v, sane_lw(lw[(size_t)m * N + i]));
   }
   v = block_max(v, sh);
-  if (threadIdx.x == 0) tile[((size_t)m * T + q) * TREC + 0] = (double)v;
+  if (threadIdx.x == 0) key[(size_t)m * T + q] = v > -INFINITY ? ord_key(v) : 0u;
 }
 
 // mx of a filter from its tile maxima (exact, order-free).
-__device__ __forceinline__ double filter_max(const double *__restrict__ tile, int m, int T,
+__device__ __forceinline__ double filter_max(const uint32_t *__restrict__ key, int m, int T,
                                              float *sh) {
   float v = -INFINITY;
-  for (int q = threadIdx.x; q < T; q += blockDim.x)
-    v = fmaxf(v, (float)tile[((size_t)m * T + q) * TREC + 0]);
+  for (int q = threadIdx.x; q < T; q += blockDim.x) v = fmaxf(v, key_float(key[(size_t)m * T + q]));
   return (double)block_max(v, sh);
 }
 
@@ -50,15 +51,19 @@ __device__ __forceinline__ double filter_max(const double *__restrict__ tile, in
 // elements [4t, 4t+4) (one Philox call): with a tile per workgroup a
 // single-filter launch has few workgroups, and 16 waves per workgroup hide
 // the latency of the FP64 exponentials and logarithms.  The exponentials
-// come first since they need no other launch's result.
+// come first since they need no other launch's result.  With X (the fused
+// path) it also sums the weighted particles w_i x_i of the tile for the
+// weighted estimator (D <= 3 components, component-major [M][D][N]).
 constexpr int CDF_THREADS = 1024, CDF_PER_THREAD = TILE / CDF_THREADS;
 static_assert(CDF_PER_THREAD % 4 == 0, "whole Philox calls per thread");
 __global__ void __launch_bounds__(CDF_THREADS)
 k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float *__restrict__ lw,
-                    double *__restrict__ tile, double *__restrict__ Cl, double *__restrict__ Sl) {
+                    const uint32_t *__restrict__ mxkey, double *__restrict__ tile,
+                    double *__restrict__ Cl, double *__restrict__ Sl, const float *__restrict__ X,
+                    int D, double *__restrict__ wpart) {
   const int t = tp ? *tp : t_arg;
   __shared__ float shf[CDF_THREADS / 64];
-  __shared__ double shd[CDF_THREADS / 64];
+  __shared__ double shd[3 * (CDF_THREADS / 64)];
   const int m = blockIdx.y, q = blockIdx.x;
   const int base = q * TILE + threadIdx.x * CDF_PER_THREAD;
   // exponential variates first: they need no other launch's result
@@ -76,10 +81,10 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
       s[4 * g + l] = srun;
     }
   }
-  const double mx = filter_max(tile, m, T, shf);
+  const double mx = filter_max(mxkey, m, T, shf);
   const bool deg = !(mx > -INFINITY);
   double w[CDF_PER_THREAD];
-  double run = 0.0, sq = 0.0;
+  double run = 0.0, sq = 0.0, wx[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int e = 0; e < CDF_PER_THREAD; ++e) {
     const int i = base + e;
@@ -88,6 +93,8 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
     run += we;
     sq += we * we;
     w[e] = run;
+    if (X && i < N)
+      for (int c = 0; c < D; ++c) wx[c] += we * (double)X[((size_t)m * D + c) * N + i];
   }
   double tot, stot;
   const double off = block_exscan(run, shd, &tot);
@@ -115,6 +122,11 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
   }
   const double s2 = block_sum(sq, shd);
   if (threadIdx.x == 0) tile[((size_t)m * T + q) * TREC + 2] = s2;
+  if (X) {
+    block_sum_multi_t0<3>(wx, shd);
+    if (threadIdx.x == 0)
+      for (int c = 0; c < D; ++c) wpart[((size_t)m * T + q) * D + c] = wx[c];
+  }
 }
 
 // Per filter (one workgroup): tile offsets of the CDF and of the exponential
@@ -129,8 +141,8 @@ k_cdf_uniform_tiles(Key key, int N, int T, int t_arg, const int *tp, const float
 constexpr int FOLD_CHUNK = 1024;
 __global__ void __launch_bounds__(256)
 k_filter_reduce(int N, int T, double lognorm, const double *__restrict__ tile,
-                double *__restrict__ coff, double *__restrict__ soff,
-                double *__restrict__ fstat) {
+                uint32_t *__restrict__ mxkey, double *__restrict__ coff,
+                double *__restrict__ soff, double *__restrict__ fstat) {
   __shared__ double shd[8];
   __shared__ float shf[8];
   __shared__ double cbuf[FOLD_CHUNK], ebuf[FOLD_CHUNK];
@@ -140,11 +152,13 @@ k_filter_reduce(int N, int T, double lognorm, const double *__restrict__ tile,
   float lm = -INFINITY;
   double s2 = 0.0;
   for (int q = threadIdx.x; q < T; q += blockDim.x) {
-    lm = fmaxf(lm, (float)rec[(size_t)q * TREC]);
+    lm = fmaxf(lm, key_float(mxkey[(size_t)m * T + q]));
     s2 += rec[(size_t)q * TREC + 2];
   }
   const double mx = (double)block_max(lm, shf);
   s2 = block_sum(s2, shd);
+  // every thread has read the keys: cleared for the next interval
+  for (int q = threadIdx.x; q < T; q += blockDim.x) mxkey[(size_t)m * T + q] = 0u;
   double cc = 0.0, sc = 0.0;  // thread 0's running offsets
   for (int base = 0; base < T; base += FOLD_CHUNK) {
     const int n = min(FOLD_CHUNK, T - base);
@@ -259,7 +273,6 @@ k_ancestors(int N, int T, const double *__restrict__ Cl, const double *__restric
 // C_i > U_k C_{N-1} (clamped to N - 1): the offset after tile q is exactly
 // coff[q] + Cl[last of q], the value the search inside tile q compares, so
 // the tile chosen always holds the answer.
-constexpr int ANC_PER_THREAD = 4, ANC_SPAN = TILE_THREADS * ANC_PER_THREAD;
 constexpr int ANC_LDS_TILES = 4096;  // tile offsets held in LDS: N <= 4096 * TILE
 
 struct Cdf2L {
@@ -316,6 +329,124 @@ k_ancestors_lds(int N, int T, const double *__restrict__ Cl, const double *__res
     i = gallop(c, i, v);
     A[(size_t)m * N + k] = i;
   }
+}
+
+// The fused path's ancestor search for filters of at most FOLD_MAX_TILES
+// tiles, with the per-filter fold inside it: every workgroup folds the
+// filter's tile totals into the CDF and spacing offsets in LDS (one thread,
+// in tile order -- the additions of k_filter_reduce, so every workgroup holds
+// the same offsets and the two-level CDF is non-decreasing across tile
+// boundaries), the filter's first workgroup writes its record (mx, W, sum w^2,
+// S_N, log G_t^N, ESS) and clears its tile maximum keys, and each workgroup
+// sums the post-resampling particles x^(a_k) of its 1024 k for the
+// estimator (span partial sums, folded with the cross-filter means).  Search
+// as in k_ancestors_lds.
+template <int D>
+__global__ void __launch_bounds__(TILE_THREADS)
+k_ancestors_fold(int N, int T, int G, double lognorm, const double *__restrict__ tile,
+                 uint32_t *__restrict__ mxkey, const double *__restrict__ Cl,
+                 const double *__restrict__ Sl, double *__restrict__ fstat,
+                 int32_t *__restrict__ A, const float *__restrict__ X,
+                 double *__restrict__ mpart) {
+  // (tile totals and offsets in separate arrays, so that the fold's loads
+  // run ahead of its stores)
+  __shared__ double ct[FOLD_MAX_TILES], st[FOLD_MAX_TILES];
+  __shared__ double co[FOLD_MAX_TILES + 1], so[FOLD_MAX_TILES + 1];
+  __shared__ double shd[D * (TILE_THREADS / 64)];
+  __shared__ float shf[TILE_THREADS / 64];
+  const int m = blockIdx.y, g = blockIdx.x;
+  const double *rec = tile + (size_t)m * T * TREC;
+  for (int j = threadIdx.x; j < T; j += TILE_THREADS) {
+    ct[j] = rec[(size_t)j * TREC + 1];
+    st[j] = rec[(size_t)j * TREC + 3];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double cc = 0.0, sc = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < T; ++j) {
+      co[j] = cc;
+      so[j] = sc;
+      cc += ct[j];
+      sc += st[j];
+    }
+    co[T] = cc;
+    so[T] = sc;
+  }
+  __syncthreads();
+  const double W = co[T], SN = so[T];
+  if (g == 0) {
+    float lm = -INFINITY;
+    double s2 = 0.0;
+    for (int q = threadIdx.x; q < T; q += TILE_THREADS) {
+      lm = fmaxf(lm, key_float(mxkey[(size_t)m * T + q]));
+      s2 += rec[(size_t)q * TREC + 2];
+    }
+    const double mx = (double)block_max(lm, shf);
+    s2 = block_sum(s2, shd);
+    // every thread has read the keys: cleared for the next interval
+    for (int q = threadIdx.x; q < T; q += TILE_THREADS) mxkey[(size_t)m * T + q] = 0u;
+    if (threadIdx.x == 0) {
+      double *f = fstat + (size_t)m * FREC;
+      const bool deg = !(mx > -INFINITY);
+      f[0] = mx;
+      f[1] = W;
+      f[2] = s2;
+      f[3] = deg ? 1.0 : 0.0;
+      f[4] = SN;
+      f[5] = deg ? -INFINITY : f[5] + mx + log(W / (double)N) + lognorm;
+      f[6] = W * W / s2;
+    }
+  }
+  double acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+  const int base = g * ANC_SPAN + threadIdx.x * ANC_PER_THREAD;
+  if (base < N) {
+    const double sot = so[base / TILE];  // the 4 k share a tile
+    const double *cl = Cl + (size_t)m * N;
+    const Cdf2L c{cl, co, N};
+    auto take = [&](int k, int i) {
+      A[(size_t)m * N + k] = i;
+#pragma unroll
+      for (int d = 0; d < D; ++d) acc[d] += (double)X[((size_t)m * D + d) * N + i];
+    };
+    int i;
+    {
+      const double v = ((sot + Sl[(size_t)m * N + base]) / SN) * W;
+      int a = 0, b = T - 1;
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (co[mid + 1] > v)
+          b = mid;
+        else
+          a = mid + 1;
+      }
+      const double off = co[a];
+      int lo = a * TILE, hi = min(N - 1, (a + 1) * TILE - 1);
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (off + cl[mid] > v)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      i = lo;
+      take(base, i);
+    }
+#pragma unroll
+    for (int e = 1; e < ANC_PER_THREAD; ++e) {
+      const int k = base + e;
+      if (k >= N) break;
+      const double v = ((sot + Sl[(size_t)m * N + k]) / SN) * W;
+      i = gallop(c, i, v);
+      take(k, i);
+    }
+  }
+  block_sum_multi_t0<D>(acc, shd);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int d = 0; d < D; ++d) mpart[((size_t)m * G + g) * D + d] = acc[d];
 }
 
 // Per-filter means from the tile partial sums (one workgroup per filter,
@@ -389,6 +520,47 @@ k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
   // grid models (both FH-N forms): folded by their own state-wide estimator
   if (E.md.kind >= 2) return;
   const int dx = E.md.dx;
+  if (E.mpart) {
+    // a tiled ensemble: its filters' means from the estimator's partial sums
+    // (post-resampling ones per ancestor span, weighted ones per tile); a
+    // group of waves per filter, each wave summing every component over a
+    // strided share of the partials, the group's sums added in LDS
+    __shared__ double part[16][6];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int per = max(1, nw / E.M);  // waves per filter
+    for (int m0 = 0; m0 < E.M; m0 += nw / per) {
+      const int m = m0 + wid / per, sub = wid % per;
+      const bool on = wid / per < nw / per && m < E.M;
+      double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+      if (on) {
+        for (int j = sub * 64 + lane; j < E.G; j += per * 64)
+          for (int c = 0; c < dx; ++c) a[c] += gptr(E.mpart)[((size_t)m * E.G + j) * dx + c];
+        for (int j = sub * 64 + lane; j < E.T; j += per * 64)
+          for (int c = 0; c < dx; ++c) b[c] += gptr(E.wpart)[((size_t)m * E.T + j) * dx + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a[c] = wave_sum(a[c]);
+        b[c] = wave_sum(b[c]);
+      }
+      if (lane == 0)
+        for (int c = 0; c < 3; ++c) {
+          part[wid][c] = a[c];
+          part[wid][3 + c] = b[c];
+        }
+      __syncthreads();
+      if (on && sub == 0 && lane < 2 * dx) {
+        const int c = lane % dx, r = lane < dx ? c : 3 + c;
+        double v = 0.0;
+        for (int k = 0; k < per; ++k) v += part[wid + k][r];
+        if (lane < dx)
+          gptr(E.fmean)[(size_t)m * dx + c] = v / (double)E.N;
+        else
+          gptr(E.fmeanw)[(size_t)m * dx + c] = v / gptr(E.fstat)[(size_t)m * FREC + 1];
+      }
+      __syncthreads();  // (part is reused; the filter means are read below)
+    }
+  }
   if (dx <= 3) {
     double v[6];
 #pragma unroll
@@ -456,15 +628,35 @@ hipError_t launch_set_i32(int *p, int v, hipStream_t s) {
 
 hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s, const int *tp) {
   const dim3 g((unsigned)e.T, (unsigned)e.M);
-  k_tile_max<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.tile);
-  k_cdf_uniform_tiles<<<g, CDF_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.lw, e.tile, e.Cl, e.Sl);
-  k_filter_reduce<<<e.M, 256, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.coff, e.soff, e.fstat);
+  k_tile_maxkey<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.mxkey);
+  k_cdf_uniform_tiles<<<g, CDF_THREADS, 0, s>>>(e.key, e.N, e.T, t, tp, e.lw, e.mxkey, e.tile, e.Cl,
+                                                 e.Sl, nullptr, 0, nullptr);
+  k_filter_reduce<<<e.M, 256, 0, s>>>(e.N, e.T, e.lognorm, e.tile, e.mxkey, e.coff, e.soff,
+                                      e.fstat);
   if (e.T <= ANC_LDS_TILES) {
     const dim3 ga((unsigned)((e.N + ANC_SPAN - 1) / ANC_SPAN), (unsigned)e.M);
     k_ancestors_lds<<<ga, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
   } else {
     k_ancestors<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.Cl, e.coff, e.Sl, e.soff, e.fstat, e.A);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_resample_fused(const EnsDev &e, IvArg iv, const float *X, bool key_ready,
+                                 hipStream_t s) {
+  if (e.T > FOLD_MAX_TILES || e.md.dx > 3) return hipErrorInvalidValue;
+  const dim3 g((unsigned)e.T, (unsigned)e.M);
+  if (!key_ready) k_tile_maxkey<<<g, TILE_THREADS, 0, s>>>(e.N, e.T, e.lw, e.mxkey);
+  k_cdf_uniform_tiles<<<g, CDF_THREADS, 0, s>>>(e.key, e.N, e.T, iv.t, iv.tp, e.lw, e.mxkey, e.tile,
+                                                 e.Cl, e.Sl, X, e.md.dx, e.wpart);
+  const int G = (e.N + ANC_SPAN - 1) / ANC_SPAN;
+  const dim3 ga((unsigned)G, (unsigned)e.M);
+  if (e.md.dx == 3)
+    k_ancestors_fold<3><<<ga, TILE_THREADS, 0, s>>>(e.N, e.T, G, e.lognorm, e.tile, e.mxkey, e.Cl,
+                                                     e.Sl, e.fstat, e.A, X, e.mpart);
+  else
+    k_ancestors_fold<1><<<ga, TILE_THREADS, 0, s>>>(e.N, e.T, G, e.lognorm, e.tile, e.mxkey, e.Cl,
+                                                     e.Sl, e.fstat, e.A, X, e.mpart);
   return hipGetLastError();
 }
 

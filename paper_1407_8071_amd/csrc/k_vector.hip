@@ -116,7 +116,10 @@ k_vec_propagate(ModelDev md, Key key, int N, int t, const float *__restrict__ Xi
 
 // Batched propagation and weighting for the fused path: tile g of the table
 // is (ensemble, filter, first particle) and holds up to 256 particles; every
-// particle is read through the previous ancestors when `pending`.
+// particle is read through the previous ancestors when `pending`.  For a
+// tiled ensemble the workgroup also raises the maximum key of the resampling
+// tile that holds its particles (a propagation tile of 64..1024 never
+// straddles one of 4096) with one atomic.
 template <int D>
 __global__ void __launch_bounds__(VEC_BLOCK)
 k_vec_prop_batched(const int4 *__restrict__ tiles, const FusedEns *__restrict__ ens, IvArg iv,
@@ -126,25 +129,42 @@ k_vec_prop_batched(const int4 *__restrict__ tiles, const FusedEns *__restrict__ 
   const int4 tl = tiles[blockIdx.x];
   const FusedEns &E = ens[tl.x];
   const int m = tl.y, i = tl.z + threadIdx.x, N = E.N;
-  if (i >= N) return;
-  // (pointers from the ensemble table: global-address-space accesses)
-  const gmem<float> *Xin = gptr(parity ? E.X1 : E.X0);
-  gmem<float> *Xout = gptr(parity ? E.X0 : E.X1);
-  // (an auxiliary filter's particles always come through the ancestors its
-  // first stage has just drawn)
-  const bool thru = pending || E.apf;
-  const int src = thru ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
-  float x[D];
+  float l = -INFINITY;
+  if (i < N) {
+    // (pointers from the ensemble table: global-address-space accesses)
+    const gmem<float> *Xin = gptr(parity ? E.X1 : E.X0);
+    gmem<float> *Xout = gptr(parity ? E.X0 : E.X1);
+    // (an auxiliary filter's particles always come through the ancestors its
+    // first stage has just drawn)
+    const bool thru = pending || E.apf;
+    const int src = thru ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
+    float x[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) x[c] = Xin[((size_t)m * D + c) * N + src];
-  em_steps<D>(E.md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * E.md.S, E.md.S, x);
+    for (int c = 0; c < D; ++c) x[c] = Xin[((size_t)m * D + c) * N + src];
+    em_steps<D>(E.md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * E.md.S, E.md.S, x);
 #pragma unroll
-  for (int c = 0; c < D; ++c) Xout[((size_t)m * D + c) * N + i] = x[c];
-  float l = loglik<D>(E.md, x, y + E.yoff);
-  // auxiliary filter: the second-stage weight divides by the pilot
-  // likelihood of the particle's ancestor
-  if (E.apf) l -= gptr(E.lpil)[(size_t)m * N + src];
-  gptr(E.lw)[(size_t)m * N + i] = l == l ? l : -INFINITY;
+    for (int c = 0; c < D; ++c) Xout[((size_t)m * D + c) * N + i] = x[c];
+    l = loglik<D>(E.md, x, y + E.yoff);
+    // auxiliary filter: the second-stage weight divides by the pilot
+    // likelihood of the particle's ancestor
+    if (E.apf) l -= gptr(E.lpil)[(size_t)m * N + src];
+    l = l == l ? l : -INFINITY;
+    gptr(E.lw)[(size_t)m * N + i] = l;
+  }
+  if (E.mxkey) {  // (the same for the whole workgroup)
+    // every lane takes part: lanes past N carry -inf
+    __shared__ float wmax[VEC_BLOCK / 64];
+    const float wm = wave_max(l);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = wm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float v = wmax[0];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmaxf(v, wmax[w]);
+      if (v > -INFINITY)
+        __hip_atomic_fetch_max(gptr(E.mxkey) + (size_t)m * E.T + tl.z / TILE, ord_key(v),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // Auxiliary filters: the pilot of particle i -- its noise-free S-step Euler

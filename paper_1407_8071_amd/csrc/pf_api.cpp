@@ -91,8 +91,8 @@ int wg_block(int N, int bd_min = 256) {
 
 // Offsets of every array of one ensemble inside the workspace.
 struct Layout {
-  size_t obs, pmean, psd, X0, X1, lw, A, Cl, Sl, tile, coff, soff, fstat, mpart, wpart, fmean,
-      fmeanw, emean, cnt, gpart, params, nearest, lwc, lpil, end;
+  size_t obs, pmean, psd, X0, X1, lw, A, Cl, Sl, tile, mxkey, coff, soff, fstat, mpart, wpart,
+      fmean, fmeanw, emean, cnt, gpart, params, nearest, lwc, lpil, end;
 };
 
 constexpr int LEARNED_IN = 22, LEARNED_OUT = 2;  // FH-N node features, (u_v, u_w)
@@ -118,10 +118,12 @@ Layout layout_of(size_t base, int M, int N, int dx, int dy, int T, bool grid, bo
   L.Cl = take(sizeof(double) * MN);
   L.Sl = take(sizeof(double) * MN);
   L.tile = take(sizeof(double) * (size_t)M * T * pfk::TREC);
+  L.mxkey = take(sizeof(uint32_t) * (size_t)M * T);
   L.coff = take(sizeof(double) * (size_t)M * (T + 1));
   L.soff = take(sizeof(double) * (size_t)M * (T + 1));
   L.fstat = take(sizeof(double) * (size_t)M * pfk::FREC);
-  L.mpart = take(sizeof(double) * (size_t)M * T * dx);
+  // post-resampling partial sums: per tile (T) or per ancestor span (G >= T)
+  L.mpart = take(sizeof(double) * (size_t)M * ((N + pfk::ANC_SPAN - 1) / pfk::ANC_SPAN) * dx);
   L.wpart = take(sizeof(double) * (size_t)M * T * dx);
   L.fmean = take(sizeof(double) * (size_t)M * dx);
   L.fmeanw = take(sizeof(double) * (size_t)M * dx);
@@ -629,6 +631,9 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     pfk::EnsDev &D = E.dev;
     if (E.learned || E.paper) {
       PF_HIP(pfk::launch_grid_estimate(D, D.X[out], E.cnt, E.gpart, g));
+    } else if (E.tiled && E.fz.mpart) {
+      // (in a resampling-only interval no propagation has raised the keys)
+      PF_HIP(pfk::launch_resample_fused(D, iv, D.X[out], !resample_only, s));
     } else if (E.tiled) {
       PF_HIP(pfk::launch_resample(D, iv.t, s, iv.tp));
       PF_HIP(pfk::launch_vec_estimate(D, D.X[out], D.X[out], D.A, false, s));
@@ -992,6 +997,7 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     D.Cl = (double *)(ws + L.Cl);
     D.Sl = (double *)(ws + L.Sl);
     D.tile = (double *)(ws + L.tile);
+    D.mxkey = (uint32_t *)(ws + L.mxkey);
     D.coff = (double *)(ws + L.coff);
     D.soff = (double *)(ws + L.soff);
     D.fstat = (double *)(ws + L.fstat);
@@ -1019,6 +1025,15 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     F.emean = D.emean;
     E.wg = false;  // set by the launch plan
     E.tiled = !E.grid && E.d.N > pfk::WG_MAX_N;
+    // tiled filters on the fused path: propagation raises the tile maximum
+    // keys; up to FOLD_MAX_TILES tiles the resampler folds the tile offsets
+    // and the cross-filter means fold the estimator's partial sums
+    F.T = E.T;
+    F.G = (E.d.N + pfk::ANC_SPAN - 1) / pfk::ANC_SPAN;
+    F.mxkey = E.tiled ? D.mxkey : nullptr;
+    const bool fold = E.tiled && E.T <= pfk::FOLD_MAX_TILES;
+    F.mpart = fold ? D.mpart : nullptr;
+    F.wpart = fold ? D.wpart : nullptr;
     F.cnt = nullptr;
     F.gpart = nullptr;
     F.nch = 0;
@@ -1080,6 +1095,8 @@ pf_status pf_init(const pf_model_desc *h_models, int32_t n_models, const pf_ense
     // every ancestor index is valid from the start
     INIT_TRY(hipMemsetAsync(D.A, 0, sizeof(int32_t) * (size_t)E.d.M * E.d.N, s));
     if (E.lwc) INIT_TRY(pfk::launch_fill_f32(E.lwc, 0.f, (size_t)E.d.M * E.d.N, s));
+    // tile maximum keys start empty (key 0; the bits of 0.0f)
+    INIT_TRY(pfk::launch_fill_f32((float *)D.mxkey, 0.f, (size_t)E.d.M * E.T, s));
     if (E.grid)
       INIT_TRY(pfk::launch_grid_init(D, D.X[0], s));
     else

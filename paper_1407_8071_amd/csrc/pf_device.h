@@ -23,6 +23,20 @@ __device__ __forceinline__ gmem<T> *gptr(T *p) {
   return (gmem<T> *)p;
 }
 
+// Order-preserving 32-bit keys of floats, for a maximum taken with integer
+// atomics: a non-negative float gets its sign bit set, a negative one all its
+// bits flipped, so the unsigned order of keys is the order of the values
+// (-inf -> 0x007FFFFF).  Key 0 stands for "no value yet" (it is the key of no
+// float that is not a NaN) and reads back as -inf.
+__device__ __forceinline__ uint32_t ord_key(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key_float(uint32_t k) {
+  if (k == 0u) return -INFINITY;
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
 // ---------------------------------------------------------------------------
 // Random numbers.  Philox4x32-10 (Salmon et al., SC'11): per round two 32x32
 // -> 64-bit products of counter words 0 and 2 with the published multipliers,

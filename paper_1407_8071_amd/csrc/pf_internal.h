@@ -18,6 +18,13 @@ constexpr int TILE = TILE_THREADS * TILE_PER_THREAD;
 // Per-tile record (doubles): 0 max lw, 1 sum w (= last local CDF value),
 // 2 sum w^2, 3 sum of the tile's exponential variates (incl. E_N on the last).
 constexpr int TREC = 4;
+// Ancestor searches of the tiled resampler: 4 consecutive k per thread of a
+// 256-thread workgroup, so 1024 k per workgroup ("span").
+constexpr int ANC_PER_THREAD = 4, ANC_SPAN = TILE_THREADS * ANC_PER_THREAD;
+// The fused path folds a filter's tile offsets inside every ancestor
+// workgroup up to this many tiles (N <= 4 Mi); larger filters take the
+// separate per-filter fold.
+constexpr int FOLD_MAX_TILES = 1024;
 // Per-filter record (doubles): 0 mx, 1 W, 2 sum w^2, 3 degenerate flag,
 // 4 S_N, 5 log G_t^N (running), 6 ESS of the last interval, 7 kept flag
 // (FREC_KEPT).
@@ -35,10 +42,11 @@ struct EnsDev {
   double *Cl;       // [M][N] tile-local inclusive CDF
   double *Sl;       // [M][N] tile-local inclusive sums of exponentials
   double *tile;     // [M][T][TREC]
+  uint32_t *mxkey;  // [M][T] order-preserving key of each tile's maximum log-weight (0: empty)
   double *coff;     // [M][T+1] CDF tile offsets
   double *soff;     // [M][T+1] exponential-sum tile offsets
   double *fstat;    // [M][FREC]
-  double *mpart;    // [M][T][dx] partial sums of post-resampling particles
+  double *mpart;    // [M][G][dx] partial sums of post-resampling particles (G = spans >= T)
   double *wpart;    // [M][T][dx] partial sums of weighted particles
   double *fmean;    // [M][dx]
   double *fmeanw;   // [M][dx]
@@ -83,6 +91,13 @@ struct FusedEns {
   // at the start of the interval (the first stage's weights are lwc + lpil)
   int32_t apf;
   float *lpil;
+  // tiled vector ensembles on the fused path (else null): the tile maximum
+  // keys that propagation raises, and the estimator's partial sums that the
+  // cross-filter means fold -- per ancestor span (post-resampling, G per
+  // filter) and per tile (weighted, T per filter)
+  uint32_t *mxkey;
+  double *mpart, *wpart;
+  int32_t T, G;
 };
 enum { RS_MULTINOMIAL = 0, RS_SYSTEMATIC = 1, RS_STRATIFIED = 2, RS_RESIDUAL = 3 };
 // per-filter record slot 7: 1.0 when the last interval kept its particles
@@ -104,6 +119,13 @@ hipError_t launch_vec_simulate(const EnsDev &e, uint64_t seed, int T, float *xtr
 
 // ---- resampling (any model): lw [M][N] -> A [M][N] ------------------------
 hipError_t launch_resample(const EnsDev &e, int t, hipStream_t s, const int *tp = nullptr);
+// The fused path's tiled resampling (T <= FOLD_MAX_TILES): the CDF and
+// spacings with the weighted estimator's tile sums, then the ancestor search
+// with the tile offsets folded in every workgroup, the filter records and
+// the post-resampling estimator's span sums; the tile maximum keys come from
+// propagation (key_ready) or from a key launch here.
+hipError_t launch_resample_fused(const EnsDev &e, IvArg iv, const float *X, bool key_ready,
+                                 hipStream_t s);
 hipError_t launch_combine_means(const EnsDev &e, bool ensemble_mean, hipStream_t s);
 
 // ---- filter-per-workgroup interval kernel (vector models, N <= WG_MAX_N) ---
