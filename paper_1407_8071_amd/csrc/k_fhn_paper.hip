@@ -62,7 +62,7 @@ struct FpLds {
   float *plane[2];  // U planes [J*J], alternating by particle
   int *ring;        // [32] the current particle's event ring
   int *wsum;        // [FP_WAVES] wave totals of the region count
-  int *ev;          // [1] centre of the step's event
+  int *ev;          // [1] centre of the step's event; [1]: whether the loaded ring holds any
   float *lwp;       // [FP_WAVES] wave sums of the squared residuals
 };
 
@@ -132,10 +132,11 @@ __device__ __forceinline__ int wave_scan_i32(int v) {
 // active ones (usually none) one by one.
 template <int Q>
 __device__ __forceinline__ void build_cover(int J, int l0, const int nb[4 * Q], const int *ring,
-                                            int cov[4 * Q]) {
+                                            bool any, int cov[4 * Q]) {
   const int k0 = 4 * Q * (int)threadIdx.x;
 #pragma unroll
   for (int e = 0; e < 4 * Q; ++e) cov[e] = 0;
+  if (!any) return;  // (no entry of the loaded ring holds an event: the usual case)
   unsigned act = 0;
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
@@ -172,41 +173,79 @@ __device__ __forceinline__ void fhnp_steps(const ModelDev &md, Key key, uint32_t
                                            float *pl, const FpLds &L, Hook &hook) {
   const int J = md.J, nn = J * J, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int k0 = 4 * Q * tid;
+  // a thread's 4Q nodes in one row (every thread's, or none is a node)
+  const bool row = J % (4 * Q) == 0;
   for (int st = 0; st < md.S; ++st) {
     const uint32_t n = (uint32_t)(n0 + st);
     if (st > 0) __syncthreads();  // (A) U' of the previous step is in the plane
     const int slot = (int)(n % (uint32_t)md.stim_l0);
     const int old = __builtin_amdgcn_readfirstlane(L.ring[slot]);
-    // neighbours: coupling sums (up, down, left, right) and region flags
+    // neighbours: coupling sums (up, down, left, right, those that exist,
+    // in that order) and region flags
     float sum[4 * Q];
     unsigned rm = 0;
+    if (row) {
+      // the thread's nodes lie in one row: the rows above and below in
+      // 16-byte reads, the outer left and right neighbours in two scalar
+      // reads, the inner ones from the thread's own registers
+      const bool hu = nb[0] & NB_UP, hd = nb[0] & NB_DOWN;
+      const bool hl = nb[0] & NB_LEFT, hr = nb[4 * Q - 1] & NB_RIGHT;
+      float up[4 * Q], dn[4 * Q];
 #pragma unroll
-    for (int e = 0; e < 4 * Q; ++e) {
-      const int k = k0 + e, b = nb[e];
-      float s = 0.f;
-      bool r = in_band(md, u[e]);
-      if (b & NB_UP) {
-        const float x = pl[k - J];
-        s += x;
-        r |= in_band(md, x);
+      for (int g = 0; g < Q; ++g) {
+        const float4 a = *(const float4 *)(pl + (hu ? k0 - J : k0) + 4 * g);
+        const float4 b = *(const float4 *)(pl + (hd ? k0 + J : k0) + 4 * g);
+        up[4 * g] = a.x, up[4 * g + 1] = a.y, up[4 * g + 2] = a.z, up[4 * g + 3] = a.w;
+        dn[4 * g] = b.x, dn[4 * g + 1] = b.y, dn[4 * g + 2] = b.z, dn[4 * g + 3] = b.w;
       }
-      if (b & NB_DOWN) {
-        const float x = pl[k + J];
-        s += x;
-        r |= in_band(md, x);
+      const float lft = pl[hl ? k0 - 1 : k0], rgt = pl[hr ? k0 + 4 * Q : k0];
+      bool ib[4 * Q];
+#pragma unroll
+      for (int e = 0; e < 4 * Q; ++e) ib[e] = in_band(md, u[e]);
+      const bool il = hl && in_band(md, lft), ir = hr && in_band(md, rgt);
+#pragma unroll
+      for (int e = 0; e < 4 * Q; ++e) {
+        float s = 0.f;
+        if (hu) s += up[e];
+        if (hd) s += dn[e];
+        if (e > 0) s += u[e - 1];
+        else if (hl) s += lft;
+        if (e < 4 * Q - 1) s += u[e + 1];
+        else if (hr) s += rgt;
+        sum[e] = s;
+        const bool r = ib[e] || (hu && in_band(md, up[e])) || (hd && in_band(md, dn[e])) ||
+                       (e > 0 ? ib[e - 1] : il) || (e < 4 * Q - 1 ? ib[e + 1] : ir);
+        if ((nb[e] & NB_VALID) && r) rm |= 1u << e;
       }
-      if (b & NB_LEFT) {
-        const float x = pl[k - 1];
-        s += x;
-        r |= in_band(md, x);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4 * Q; ++e) {
+        const int k = k0 + e, b = nb[e];
+        float s = 0.f;
+        bool r = in_band(md, u[e]);
+        if (b & NB_UP) {
+          const float x = pl[k - J];
+          s += x;
+          r |= in_band(md, x);
+        }
+        if (b & NB_DOWN) {
+          const float x = pl[k + J];
+          s += x;
+          r |= in_band(md, x);
+        }
+        if (b & NB_LEFT) {
+          const float x = pl[k - 1];
+          s += x;
+          r |= in_band(md, x);
+        }
+        if (b & NB_RIGHT) {
+          const float x = pl[k + 1];
+          s += x;
+          r |= in_band(md, x);
+        }
+        sum[e] = s;
+        if ((b & NB_VALID) && r) rm |= 1u << e;
       }
-      if (b & NB_RIGHT) {
-        const float x = pl[k + 1];
-        s += x;
-        r |= in_band(md, x);
-      }
-      sum[e] = s;
-      if ((b & NB_VALID) && r) rm |= 1u << e;
     }
     int ev = -1;
     if (!PILOT) {
@@ -394,11 +433,14 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
   // the index stays raw in a vector register until it is used: the compiler
   // would otherwise move it to a scalar register at once, and waiting for it
   // would also wait for every load issued before it.
-  int vzero;
-  asm("v_mov_b32 %0, 0" : "=v"(vzero));
   auto anc_raw = [&](int p) {
     p = min(p, MN - 1);
-    return thru ? A[(size_t)p + vzero] : p - (p / N) * N;
+    if (!thru) return p - (p / N) * N;
+    // (a fresh opaque zero at every use: kept live across the loop it
+    // would be spilled, and its reload would wait for the prefetch)
+    int vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+    return A[p + vzero];
   };
   auto src_of = [&](int raw) { return min(max(raw, 0), N - 1); };
   float4 fu[Q], fv[Q], fr = make_float4(-1.f, -1.f, -1.f, -1.f);
@@ -462,6 +504,11 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
       if (nb[4 * g] & NB_VALID) *(float4 *)(pl + k0 + 4 * g) = cu[g];
     }
     const int r0 = (int)fr.x, r1 = (int)fr.y, r2 = (int)fr.z, r3 = (int)fr.w;
+    // whether any loaded ring entry holds an event (the loading threads are
+    // lanes of wave 0; read after the barrier below)
+    const bool mine = tid < nr4 && (r0 >= 0 || r1 >= 0 || r2 >= 0 || r3 >= 0);
+    const unsigned long long anyb = __ballot(mine);
+    if (tid == 0) L.ev[1] = anyb != 0ull;
     // the previous particle's state out (its ring slots are read from LDS
     // before this thread overwrites them)
     if (!PILOT && p != (int)blockIdx.x) store();
@@ -484,7 +531,7 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
     fetch(p + G, src);
     raw_nx = anc_raw(p + 2 * G);
     __syncthreads();  // (A) of step 0: plane and ring complete
-    build_cover<Q>(J, md.stim_l0, nb, L.ring, cov);
+    build_cover<Q>(J, md.stim_l0, nb, L.ring, L.ev[1] != 0, cov);
     fhnp_steps<Q, PILOT>(md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * md.S, nb, u, v, cov,
                          pl, L, hook);
     hook.set_prev(y != nullptr, pl, m, i, src_cur);
@@ -527,7 +574,7 @@ k_fhnp_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
   if (tid < nr4)
     for (int c = 0; c < 4; ++c) L.ring[4 * tid + c] = (int)xtrue[2 * nn + 4 * tid + c];
   __syncthreads();
-  build_cover<Q>(J, md.stim_l0, nb, L.ring, cov);
+  build_cover<Q>(J, md.stim_l0, nb, L.ring, true, cov);
   NoHook none;
   for (int t = 1; t <= T; ++t) {
     fhnp_steps<Q, false>(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, (t - 1) * md.S, nb, u, v, cov,

@@ -46,21 +46,23 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def _cloud(seed, spec, M, N):
+def _cloud(seed, spec, M, N, nn=NN, empty_rings=False):
     """Particles near the rest point with 8 nodes each in the middle of the
     stimulus band (so that the region is never empty), and random event
-    rings."""
+    rings (or rings without events)."""
     rng = np.random.default_rng(seed)
     dx = spec["dx"]
     X = np.full((M, N, dx), -1.0)
-    X[:, :, :NN] = -1.03 + 0.05 * rng.standard_normal((M, N, NN))
+    X[:, :, :nn] = -1.03 + 0.05 * rng.standard_normal((M, N, nn))
     for k in range(M):
         for i in range(N):
-            X[k, i, rng.choice(NN, 8, replace=False)] = -1.7 + 0.02 * rng.standard_normal(8)
-    X[:, :, NN:2 * NN] = -2.6 + 0.1 * rng.standard_normal((M, N, NN))
-    ring = rng.integers(-1, NN, size=(M, N, 25))
+            X[k, i, rng.choice(nn, 8, replace=False)] = -1.7 + 0.02 * rng.standard_normal(8)
+    X[:, :, nn:2 * nn] = -2.6 + 0.1 * rng.standard_normal((M, N, nn))
+    ring = rng.integers(-1, nn, size=(M, N, 25))
     ring[rng.random((M, N, 25)) < 0.6] = -1
-    X[:, :, 2 * NN:2 * NN + 25] = ring
+    if empty_rings:
+        ring[:] = -1
+    X[:, :, 2 * nn:2 * nn + 25] = ring
     return X.astype(np.float32).astype(np.float64)
 
 
@@ -68,7 +70,7 @@ def _near_band(U, lo=-1.8, hi=-1.6, tol=2e-5):
     return np.any(np.abs(U - lo) < tol) or np.any(np.abs(U - hi) < tol)
 
 
-def _oracle_particle(orc, m, seed, k, i, t, x):
+def _oracle_particle(orc, m, seed, k, i, t, x, nn=NN):
     """The particle's S steps with the oracle, and whether a step after the
     first (whose input both sides share exactly) started with a U within
     the threshold tolerance of the states' FP32/FP64 difference."""
@@ -76,7 +78,7 @@ def _oracle_particle(orc, m, seed, k, i, t, x):
     amb = False
     for s in range(S):
         if s > 0:
-            amb |= _near_band(x[:NN])
+            amb |= _near_band(x[:nn])
         x, _ = orc.fhnp_step(m, seed, 2, i, k, (t - 1) * S + s, x)
     return x, amb
 
@@ -112,6 +114,43 @@ def test_interval_matches_oracle(pf, orc, torch_mod, S, fused):
     print(f"exempt {n_amb} of {M * N}; ring slots changed {n_ev}")
     assert n_amb <= 0.05 * M * N
     assert n_ev > 0
+
+
+# Other grid sizes: each thread owns 4Q consecutive nodes (Q = ceil(J^2 / 1024));
+# where J is a multiple of 4Q they lie in one row and the neighbours come from
+# row reads (J = 40, Q = 2), otherwise from per-node reads (J = 30: threads
+# beyond the last node idle; J = 36, Q = 2); some particles start with no
+# event in their ring.
+@pytest.mark.parametrize("Jg", [30, 36, 40])
+def test_interval_other_grids(pf, orc, torch_mod, Jg):
+    spec = pf_inputs.fhn_paper(Jg, S=2, eps=0.5)
+    nn = Jg * Jg
+    M, N, seed, t = 2, 24, 800 + Jg, 3
+    print(f"FH-N network J {Jg}", flush=True)
+    m = orc.Model(spec)
+    X0 = _cloud(seed, spec, M, N, nn)
+    X0[:, ::2] = _cloud(seed + 1, spec, M, N, nn, empty_rings=True)[:, ::2]
+    rng = np.random.default_rng(seed)
+    y = (-1.5 + 0.5 * rng.standard_normal(len(spec["obs_idx"]))).astype(np.float32)
+    f = pf.ParticleFilter([spec], [(0, M, N, seed)], fused=True)
+    f.set_particles(0, _dev(X0))
+    f.set_interval(t)
+    f.step(_dev(y))
+    xb = f.get_predicted(0).cpu().numpy()
+    lw = f.get_logweights(0).cpu().numpy()
+    f.close()
+    n_amb = 0
+    for k in range(M):
+        for i in range(N):
+            xo, amb = _oracle_particle(orc, m, seed, k, i, t, X0[k, i].copy(), nn)
+            if amb:
+                n_amb += 1
+                continue
+            assert np.array_equal(xb[k, i, 2 * nn:], xo[2 * nn:].astype(np.float32)), (k, i)
+            assert_rel_close(xb[k, i, :2 * nn], xo[:2 * nn], floor=0.1, what=f"particle {k},{i}")
+            assert_rel_close(lw[k, i], orc.loglik(m, xo, y.astype(np.float64)), floor=1.0,
+                             what=f"log-weight {k},{i}")
+    assert n_amb <= 0.05 * M * N
 
 
 def test_prior_draw(pf, orc, torch_mod):
