@@ -794,12 +794,52 @@ pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
   // filter-per-workgroup kernel
   ctx->prop_tile = u.prop_tile;
   for (int w = 0; w < 2; ++w) ctx->tiles_host[w].clear();
-  for (int e = 0; e < n_ens; ++e) {
-    const Ens &E = ctx->ens[(size_t)e];
-    if (E.grid || E.wg) continue;
-    const int which = E.dx == 3 ? 1 : 0;
-    for (int mm = 0; mm < E.d.M; ++mm)
-      for (int i0 = 0; i0 < E.d.N; i0 += u.prop_tile) ctx->tiles_host[which].push_back(int4{e, mm, i0, 0});
+  {
+    // Workgroups of a launch go to the 8 XCDs in turn (workgroup b to XCD
+    // b mod 8), and each XCD has its own L2.  A filter resampled by
+    // workgroup j of its class runs there on XCD j mod 8; its propagation
+    // tiles are placed on the positions of that same XCD, so that the
+    // resampler's reads of the log-weights and predicted states and the
+    // next interval's reads through the ancestors find the lines in the L2
+    // that wrote them.  (Any order is correct; this one is the locality.)
+    constexpr int XCDS = 8;
+    std::vector<std::vector<int>> xpos((size_t)n_ens);
+    for (int e = 0; e < n_ens; ++e) xpos[(size_t)e].assign((size_t)ctx->ens[(size_t)e].d.M, -1);
+    for (const WgClass &c : ctx->classes)
+      if (c.kind == CLASS_RESAMPLE_VEC)
+        for (size_t j = 0; j < c.jobs.size(); ++j)
+          xpos[(size_t)c.jobs[j].ens][(size_t)c.jobs[j].filter] = (int)(j % XCDS);
+    auto xcd = [&](int e, int mm) {
+      const int x = xpos[(size_t)e][(size_t)mm];
+      return x >= 0 ? x : mm % XCDS;
+    };
+    std::vector<int4> bucket[2][XCDS];
+    for (int e = 0; e < n_ens; ++e) {
+      const Ens &E = ctx->ens[(size_t)e];
+      if (E.grid || E.wg) continue;
+      const int which = E.dx == 3 ? 1 : 0;
+      for (int mm = 0; mm < E.d.M; ++mm) {
+        const int x = xcd(e, mm);
+        for (int i0 = 0; i0 < E.d.N; i0 += u.prop_tile) bucket[which][x].push_back(int4{e, mm, i0, 0});
+      }
+    }
+    for (int w = 0; w < 2; ++w) {
+      size_t total = 0, next[XCDS] = {};
+      for (int x = 0; x < XCDS; ++x) total += bucket[w][x].size();
+      for (size_t b = 0; b < total; ++b) {
+        // position b's own XCD while it has tiles, else the fullest other
+        int x = (int)(b % XCDS);
+        if (next[x] == bucket[w][x].size()) {
+          size_t most = 0;
+          for (int q = 0; q < XCDS; ++q)
+            if (bucket[w][q].size() - next[q] > most) {
+              most = bucket[w][q].size() - next[q];
+              x = q;
+            }
+        }
+        ctx->tiles_host[w].push_back(bucket[w][x][next[x]++]);
+      }
+    }
   }
   for (int w = 0; w < 2; ++w) ctx->n_tiles[w] = (int)ctx->tiles_host[w].size();
   // batched grid tables, one group per grid size
