@@ -13,29 +13,37 @@
 // their U, V and stimulus coverage counts stay in registers for the whole
 // interval, and only the U plane (read by the neighbours) goes through LDS.
 // Per Euler step n:
-//   (A) [barrier: the plane is complete] every thread reads the four
-//       neighbours of its nodes once, for the coupling sum and for the
-//       stimulus region (nodes whose U, or a 4-neighbour's U, lies in the
-//       open band (u-, u+)), and counts its region nodes; a wave scan of the
-//       counts and the wave totals in LDS order the region row-major;
-//   (B) [barrier] one Philox call (particle, filter, n, PROP | sub-block
-//       J*J/2), the same in every thread: its first uniform against eps
-//       decides the Bernoulli event, its second picks the floor(u |S|)-th
-//       node of the region as the centre; on an event step (rare) the thread
-//       whose range holds that node publishes it [barrier];
+//   (A) [barrier: the step's input plane is complete] every thread reads the
+//       four neighbours of its nodes once, for the coupling sums;
+//   (B) one Philox call (particle, filter, n, PROP | sub-block J*J/2), the
+//       same in every thread: its first uniform against eps decides the
+//       Bernoulli event.  Only when it falls below eps (rare) is the
+//       stimulus region formed -- the nodes whose U, or a 4-neighbour's U,
+//       lies in the open band (u-, u+) -- and ordered row-major by a wave
+//       scan of each thread's count and the wave totals in LDS [barrier];
+//       the second uniform picks its floor(u |S|)-th node as the centre
+//       (no event when the region is empty), and the thread whose range
+//       holds that node publishes it [barrier];
 //   (C) the event replaces the ring's entry of step n - l0: every thread
 //       updates the coverage counts of its nodes (centre and neighbours of
 //       the entering and the leaving event), so that the stimulus of a node
-//       is F~ when its count is positive (F~ min{1, sum Q});
+//       is F~ when its count is positive (F~ min{1, sum Q}); the owner of
+//       the ring slot writes it after the next barrier, when every wave has
+//       read the leaving entry;
 //   (D) the Euler step of every node in registers: U' = U + h (p3(U) - V) +
 //       h (c sum_nbr U + m F + Psi) + sigma~ sqrt(h) z, V' = V + h (b0 U +
 //       b1 V + b2), the normals of node pair p from the FH-N grid layout
 //       (call (particle, filter, n, PROP | p): lanes 0, 1 for node 2p, lanes
-//       2, 3 for 2p + 1); U' goes back into the plane.
-// The next particle's state is fetched into registers while this one steps
-// (its ancestor index one particle earlier still).  The log-likelihood of
-// the observed U nodes is summed from the final plane, which stays intact
-// (the planes alternate by particle) until the next particle's first step.
+//       2, 3 for 2p + 1); U' goes into the other plane of the particle's
+//       pair, the next step's input.
+// One barrier per step when no event is drawn.  A particle has two planes
+// (a step's input and output) and a ring, and two particles' sets alternate,
+// so that the next particle's plane and ring are written while a slower
+// wave still reads this particle's.  The next particle's state is fetched
+// into registers while this one steps (its ancestor index one particle
+// earlier still); the previous particle's log-likelihood of the observed U
+// nodes is summed by wave 0 from its final plane during the next particle's
+// first step.
 #include "pf_internal.h"
 
 namespace pfk {
@@ -59,30 +67,38 @@ __device__ __forceinline__ void st4(gmem<float> *p, float a, float b, float c, f
 constexpr int NB_UP = 1, NB_DOWN = 2, NB_LEFT = 4, NB_RIGHT = 8, NB_CORNER = 16, NB_VALID = 32;
 
 struct FpLds {
-  float *plane[2];  // U planes [J*J], alternating by particle
-  int *ring;        // [32] the current particle's event ring
-  int *wsum;        // [FP_WAVES] wave totals of the region count
-  int *ev;          // [1] centre of the step's event; [1]: whether the loaded ring holds any
-  float *lwp;       // [FP_WAVES] wave sums of the squared residuals
+  float *planes;  // 4 U planes [J*J]: the pair 2 q, 2 q + 1 for particles of parity q
+  int nn;
+  int *rings;     // 2 event rings [32], by particle parity
+  int *wsum;      // [FP_WAVES] wave totals of the region count
+  int *ev;        // [0]: centre of the step's event; [1 + q]: whether ring q as loaded holds any
+  // (offsets, not arrays of pointers: an index into a pointer array that is
+  // not a compile-time constant would put the array in scratch memory)
+  __device__ float *plane(int k) const { return planes + k * nn; }
+  __device__ int *ring(int q) const { return rings + 32 * q; }
 };
 
 __device__ __forceinline__ FpLds fp_lds(int nn) {
   extern __shared__ float4 fp_mem4[];
   float *fp_mem = (float *)fp_mem4;
   FpLds L;
-  L.plane[0] = fp_mem;
-  L.plane[1] = fp_mem + nn;
-  L.ring = (int *)(fp_mem + 2 * nn);
-  L.wsum = L.ring + 32;
+  L.planes = fp_mem;
+  L.nn = nn;
+  L.rings = (int *)(fp_mem + 4 * nn);
+  L.wsum = L.rings + 64;
   L.ev = L.wsum + FP_WAVES;
-  L.lwp = (float *)(L.ev + 4);
   return L;
 }
 
 size_t fhnp_lds_bytes(int J) {
   const size_t nn = (size_t)J * J;
-  return sizeof(float) * (2 * nn + 32 + FP_WAVES + 4 + FP_WAVES);
+  return sizeof(float) * (4 * nn + 64 + FP_WAVES + 4);
 }
+
+// A thread's deferred write of a ring slot (slot -1: none)
+struct RingPend {
+  int slot, ev;
+};
 
 template <int Q>
 __device__ __forceinline__ void node_bits(int J, int nb[4 * Q]) {
@@ -158,140 +174,197 @@ __device__ __forceinline__ void build_cover(int J, int l0, const int nb[4 * Q], 
   }
 }
 
+// Coupling sums of a thread's nodes (up, down, left, right, those that
+// exist, in that order) from the plane pl.  row: the thread's 4Q nodes lie
+// in one row (every thread's, or none is a node): the rows above and below
+// in 16-byte reads, the outer left and right neighbours in two scalar
+// reads, the inner ones from the thread's own registers.
+template <int Q>
+__device__ __forceinline__ void nbr_sums(int J, int k0, const int nb[4 * Q], const float u[4 * Q],
+                                         const float *pl, bool row, float sum[4 * Q]) {
+  if (row) {
+    if (!(nb[0] & NB_VALID)) {  // (a thread past the last node reads nothing)
+#pragma unroll
+      for (int e = 0; e < 4 * Q; ++e) sum[e] = 0.f;
+      return;
+    }
+    const bool hu = nb[0] & NB_UP, hd = nb[0] & NB_DOWN;
+    const bool hl = nb[0] & NB_LEFT, hr = nb[4 * Q - 1] & NB_RIGHT;
+    float up[4 * Q], dn[4 * Q];
+#pragma unroll
+    for (int g = 0; g < Q; ++g) {
+      const float4 a = *(const float4 *)(pl + (hu ? k0 - J : k0) + 4 * g);
+      const float4 b = *(const float4 *)(pl + (hd ? k0 + J : k0) + 4 * g);
+      up[4 * g] = a.x, up[4 * g + 1] = a.y, up[4 * g + 2] = a.z, up[4 * g + 3] = a.w;
+      dn[4 * g] = b.x, dn[4 * g + 1] = b.y, dn[4 * g + 2] = b.z, dn[4 * g + 3] = b.w;
+    }
+    const float lft = pl[hl ? k0 - 1 : k0], rgt = pl[hr ? k0 + 4 * Q : k0];
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e) {
+      float s = 0.f;
+      if (hu) s += up[e];
+      if (hd) s += dn[e];
+      if (e > 0) s += u[e - 1];
+      else if (hl) s += lft;
+      if (e < 4 * Q - 1) s += u[e + 1];
+      else if (hr) s += rgt;
+      sum[e] = s;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e) {
+      const int k = k0 + e, b = nb[e];
+      float s = 0.f;
+      if (b & NB_UP) s += pl[k - J];
+      if (b & NB_DOWN) s += pl[k + J];
+      if (b & NB_LEFT) s += pl[k - 1];
+      if (b & NB_RIGHT) s += pl[k + 1];
+      sum[e] = s;
+    }
+  }
+}
+
+// Bit e set when node k0 + e is in the stimulus region: its U or a
+// 4-neighbour's U lies in the open band (the neighbours read again from pl:
+// only on a step that draws an event).
+template <int Q>
+__device__ __forceinline__ unsigned region_mask(const ModelDev &md, int J, int k0,
+                                                const int nb[4 * Q], const float u[4 * Q],
+                                                const float *pl, bool row) {
+  unsigned rm = 0;
+  if (row) {
+    if (!(nb[0] & NB_VALID)) return 0u;
+    const bool hu = nb[0] & NB_UP, hd = nb[0] & NB_DOWN;
+    const bool hl = nb[0] & NB_LEFT, hr = nb[4 * Q - 1] & NB_RIGHT;
+    bool ib[4 * Q], bu[4 * Q], bd[4 * Q];
+#pragma unroll
+    for (int g = 0; g < Q; ++g) {
+      const float4 a = *(const float4 *)(pl + (hu ? k0 - J : k0) + 4 * g);
+      const float4 b = *(const float4 *)(pl + (hd ? k0 + J : k0) + 4 * g);
+      bu[4 * g] = in_band(md, a.x), bu[4 * g + 1] = in_band(md, a.y);
+      bu[4 * g + 2] = in_band(md, a.z), bu[4 * g + 3] = in_band(md, a.w);
+      bd[4 * g] = in_band(md, b.x), bd[4 * g + 1] = in_band(md, b.y);
+      bd[4 * g + 2] = in_band(md, b.z), bd[4 * g + 3] = in_band(md, b.w);
+    }
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e) ib[e] = in_band(md, u[e]);
+    const bool il = hl && in_band(md, pl[k0 - 1 + (hl ? 0 : 1)]);
+    const bool ir = hr && in_band(md, pl[k0 + 4 * Q - (hr ? 0 : 1)]);
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e) {
+      const bool r = ib[e] || (hu && bu[e]) || (hd && bd[e]) || (e > 0 ? ib[e - 1] : il) ||
+                     (e < 4 * Q - 1 ? ib[e + 1] : ir);
+      if ((nb[e] & NB_VALID) && r) rm |= 1u << e;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4 * Q; ++e) {
+      const int k = k0 + e, b = nb[e];
+      bool r = in_band(md, u[e]);
+      if (b & NB_UP) r |= in_band(md, pl[k - J]);
+      if (b & NB_DOWN) r |= in_band(md, pl[k + J]);
+      if (b & NB_LEFT) r |= in_band(md, pl[k - 1]);
+      if (b & NB_RIGHT) r |= in_band(md, pl[k + 1]);
+      if ((b & NB_VALID) && r) rm |= 1u << e;
+    }
+  }
+  return rm;
+}
+
+// sum over the 64 lanes (DPP row shifts and broadcasts, as wave_scan_i32),
+// in every lane
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  v += __int_as_float(dpp_i32<DPP_ROW_SHR1, 0xf>(__float_as_int(v), 0));
+  v += __int_as_float(dpp_i32<DPP_ROW_SHR2, 0xf>(__float_as_int(v), 0));
+  v += __int_as_float(dpp_i32<DPP_ROW_SHR4, 0xf>(__float_as_int(v), 0));
+  v += __int_as_float(dpp_i32<DPP_ROW_SHR8, 0xf>(__float_as_int(v), 0));
+  v += __int_as_float(dpp_i32<DPP_ROW_BCAST15, 0xa>(__float_as_int(v), 0));
+  v += __int_as_float(dpp_i32<DPP_ROW_BCAST31, 0xc>(__float_as_int(v), 0));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // S Euler steps n0 .. n0 + S - 1 of the particle whose nodes this thread
-// holds in (u, v, cov), with the whole U plane in `pl` and the ring in LDS;
-// the caller has made the plane and the ring visible (a barrier).  PILOT:
-// the auxiliary filter's noise-free continuation -- no new stimulus events
-// and no noise; the ring's active stimuli and the forcing act, and the ring
-// advances.  hook.before_b() / hook.after_b() run in step 0 just before and
-// after its second barrier.  Leaves U' in the plane (not yet synchronised)
-// and the ring updated.
-template <int Q, bool PILOT, class Hook>
+// holds in (u, v, cov), with its input U plane in pa, pb the particle's
+// other plane and its ring in LDS; the caller has made pa and the ring
+// visible (a barrier).  Step s reads the plane it starts from (pa, pb, pa,
+// ...) and writes U' into the other one, so the final U lies in pb for odd
+// S and in pa for even S (not yet synchronised).  The ring slot of the last
+// step is left in pend (its owner's register pair) for the caller to write.
+// PILOT: the auxiliary filter's noise-free continuation -- no new stimulus
+// events and no noise; the ring's active stimuli and the forcing act, and
+// the ring advances.
+template <int Q, bool PILOT>
 __device__ __forceinline__ void fhnp_steps(const ModelDev &md, Key key, uint32_t purpose,
                                            uint32_t c0, uint32_t c1, int n0, const int nb[4 * Q],
                                            float u[4 * Q], float v[4 * Q], int cov[4 * Q],
-                                           float *pl, const FpLds &L, Hook &hook) {
+                                           float *pa, float *pb, int *ring, const FpLds &L,
+                                           RingPend &pend) {
   const int J = md.J, nn = J * J, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int k0 = 4 * Q * tid;
-  // a thread's 4Q nodes in one row (every thread's, or none is a node)
   const bool row = J % (4 * Q) == 0;
   for (int st = 0; st < md.S; ++st) {
     const uint32_t n = (uint32_t)(n0 + st);
-    if (st > 0) __syncthreads();  // (A) U' of the previous step is in the plane
-    const int slot = (int)(n % (uint32_t)md.stim_l0);
-    const int old = __builtin_amdgcn_readfirstlane(L.ring[slot]);
-    // neighbours: coupling sums (up, down, left, right, those that exist,
-    // in that order) and region flags
-    float sum[4 * Q];
-    unsigned rm = 0;
-    if (row) {
-      // the thread's nodes lie in one row: the rows above and below in
-      // 16-byte reads, the outer left and right neighbours in two scalar
-      // reads, the inner ones from the thread's own registers
-      const bool hu = nb[0] & NB_UP, hd = nb[0] & NB_DOWN;
-      const bool hl = nb[0] & NB_LEFT, hr = nb[4 * Q - 1] & NB_RIGHT;
-      float up[4 * Q], dn[4 * Q];
-#pragma unroll
-      for (int g = 0; g < Q; ++g) {
-        const float4 a = *(const float4 *)(pl + (hu ? k0 - J : k0) + 4 * g);
-        const float4 b = *(const float4 *)(pl + (hd ? k0 + J : k0) + 4 * g);
-        up[4 * g] = a.x, up[4 * g + 1] = a.y, up[4 * g + 2] = a.z, up[4 * g + 3] = a.w;
-        dn[4 * g] = b.x, dn[4 * g + 1] = b.y, dn[4 * g + 2] = b.z, dn[4 * g + 3] = b.w;
+    const float *pin = (st & 1) ? pb : pa;
+    float *pout = (st & 1) ? pa : pb;
+    if (st > 0) {
+      __syncthreads();  // (A) U' of the previous step is complete in pin
+      // the previous step's ring entry: every wave has read the one it
+      // replaces (with l0 = 1 this step reads that same slot: one more
+      // barrier)
+      if (pend.slot >= 0) {
+        ring[pend.slot] = pend.ev;
+        pend.slot = -1;
       }
-      const float lft = pl[hl ? k0 - 1 : k0], rgt = pl[hr ? k0 + 4 * Q : k0];
-      bool ib[4 * Q];
-#pragma unroll
-      for (int e = 0; e < 4 * Q; ++e) ib[e] = in_band(md, u[e]);
-      const bool il = hl && in_band(md, lft), ir = hr && in_band(md, rgt);
-#pragma unroll
-      for (int e = 0; e < 4 * Q; ++e) {
-        float s = 0.f;
-        if (hu) s += up[e];
-        if (hd) s += dn[e];
-        if (e > 0) s += u[e - 1];
-        else if (hl) s += lft;
-        if (e < 4 * Q - 1) s += u[e + 1];
-        else if (hr) s += rgt;
-        sum[e] = s;
-        const bool r = ib[e] || (hu && in_band(md, up[e])) || (hd && in_band(md, dn[e])) ||
-                       (e > 0 ? ib[e - 1] : il) || (e < 4 * Q - 1 ? ib[e + 1] : ir);
-        if ((nb[e] & NB_VALID) && r) rm |= 1u << e;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4 * Q; ++e) {
-        const int k = k0 + e, b = nb[e];
-        float s = 0.f;
-        bool r = in_band(md, u[e]);
-        if (b & NB_UP) {
-          const float x = pl[k - J];
-          s += x;
-          r |= in_band(md, x);
-        }
-        if (b & NB_DOWN) {
-          const float x = pl[k + J];
-          s += x;
-          r |= in_band(md, x);
-        }
-        if (b & NB_LEFT) {
-          const float x = pl[k - 1];
-          s += x;
-          r |= in_band(md, x);
-        }
-        if (b & NB_RIGHT) {
-          const float x = pl[k + 1];
-          s += x;
-          r |= in_band(md, x);
-        }
-        sum[e] = s;
-        if ((b & NB_VALID) && r) rm |= 1u << e;
-      }
+      if (md.stim_l0 < 2) __syncthreads();
     }
+    const int slot = (int)(n % (uint32_t)md.stim_l0);
+    const int old = __builtin_amdgcn_readfirstlane(ring[slot]);
+    float sum[4 * Q];
+    nbr_sums<Q>(J, k0, nb, u, pin, row, sum);
     int ev = -1;
     if (!PILOT) {
-      const int cnt = __builtin_popcount(rm);
-      const int inc = wave_scan_i32(cnt);
-      if (lane == 63) L.wsum[wid] = inc;
-      if (st == 0) hook.before_b();
-      __syncthreads();  // (B)
-      if (st == 0) hook.after_b();
-      int off = inc - cnt, total = 0;
-#pragma unroll
-      for (int w = 0; w < FP_WAVES; ++w) {
-        const int ws = L.wsum[w];
-        off += w < wid ? ws : 0;
-        total += ws;
-      }
-      total = __builtin_amdgcn_readfirstlane(total);
       const uint4 r = philox(c0, c1, n, (purpose << 24) | (uint32_t)(nn / 2), key);
-      int kth = -1;
-      if (total > 0 && u01d(r.x) < md.stim_eps)
-        kth = min((int)floor(u01d(r.y) * (double)total), total - 1);
-      kth = __builtin_amdgcn_readfirstlane(kth);
-      if (kth >= 0) {  // an event (the same decision in every thread)
-        if (kth >= off && kth < off + cnt) {
-          int want = kth - off;
-#pragma unroll
-          for (int e = 0; e < 4 * Q; ++e)
-            if ((rm >> e) & 1u) {
-              if (want == 0) L.ev[0] = k0 + e;
-              --want;
-            }
-        }
+      if (u01d(r.x) < md.stim_eps) {  // (the same decision in every thread)
+        const unsigned rm = region_mask<Q>(md, J, k0, nb, u, pin, row);
+        const int cnt = __builtin_popcount(rm);
+        const int inc = wave_scan_i32(cnt);
+        if (lane == 63) L.wsum[wid] = inc;
         __syncthreads();
-        ev = __builtin_amdgcn_readfirstlane(L.ev[0]);
+        int off = inc - cnt, total = 0;
+#pragma unroll
+        for (int w = 0; w < FP_WAVES; ++w) {
+          const int ws = L.wsum[w];
+          off += w < wid ? ws : 0;
+          total += ws;
+        }
+        total = __builtin_amdgcn_readfirstlane(total);
+        int kth = -1;
+        if (total > 0) kth = min((int)floor(u01d(r.y) * (double)total), total - 1);
+        kth = __builtin_amdgcn_readfirstlane(kth);
+        if (kth >= 0) {  // an event
+          if (kth >= off && kth < off + cnt) {
+            int want = kth - off;
+#pragma unroll
+            for (int e = 0; e < 4 * Q; ++e)
+              if ((rm >> e) & 1u) {
+                if (want == 0) L.ev[0] = k0 + e;
+                --want;
+              }
+          }
+          __syncthreads();
+          ev = __builtin_amdgcn_readfirstlane(L.ev[0]);
+        }
       }
-    } else {
-      if (st == 0) hook.before_b();
-      __syncthreads();  // (B)
-      if (st == 0) hook.after_b();
     }
     // (C) the ring: ev enters slot n mod l0, the event of step n - l0 leaves
     if (old >= 0 || ev >= 0) {
 #pragma unroll
       for (int e = 0; e < 4 * Q; ++e)
         if (nb[e] & NB_VALID) cov[e] += covers(J, ev, k0 + e) - covers(J, old, k0 + e);
-      if (tid == (slot >> 2)) L.ring[slot] = ev;  // the thread that loaded that slot
+      if (tid == (slot >> 2)) {  // the thread that loaded that slot
+        pend.slot = slot;
+        pend.ev = ev;
+      }
     }
     // (D) Euler step of this thread's node pairs
     const bool vnoise = md.sq1 != 0.f;
@@ -325,68 +398,62 @@ __device__ __forceinline__ void fhnp_steps(const ModelDev &md, Key key, uint32_t
 #pragma unroll
     for (int g = 0; g < Q; ++g)
       if (nb[4 * g] & NB_VALID)
-        *(float4 *)(pl + k0 + 4 * g) = make_float4(u[4 * g], u[4 * g + 1], u[4 * g + 2], u[4 * g + 3]);
+        *(float4 *)(pout + k0 + 4 * g) =
+            make_float4(u[4 * g], u[4 * g + 1], u[4 * g + 2], u[4 * g + 3]);
   }
 }
 
-struct NoHook {
-  __device__ void before_b() {}
-  __device__ void after_b() {}
-};
-
 // The previous particle's log-likelihood: the squared residuals of the
-// observed U nodes summed from its final plane before the second barrier of
-// the next particle's first step, finished by thread 0 after it (after the
-// last particle, between two barriers of their own).
+// observed U nodes summed by wave 0 alone from that particle's final plane
+// (complete: a barrier has passed since its last step), lane 0 writing it.
 template <bool PILOT>
-struct LikHook {
+struct LikPrev {
   const gmem<float> *y;      // this ensemble's observations (null: none)
   const gmem<int32_t> *obs;  // observed nodes [dy]
   gmem<float> *lw, *lpil;
   const gmem<float> *lwc;
   float inv2var;
   int dy, apf, N;
-  float *lwp;          // LDS wave sums
   const float *plane;  // the previous particle's final plane
   int m, i, src;       // the previous particle and its ancestor
   bool active;
-  int o0;    // this thread's first observation (k = thread index): its node
-  float y0;  // and value
-  float lpil_src;  // (thread 0, auxiliary filter) the pilot log-likelihood of the ancestor
-  __device__ void set_prev(bool on, const float *pl, int pm, int pi, int psrc) {
+  int o0, o1;          // this lane's first two observations (k = lane, lane + 64): nodes
+  float y0, y1;        // and values
+  float lpil_src;      // (lane 0, auxiliary filter) the pilot log-likelihood of the ancestor
+  __device__ void init_obs() {
+    const int k = threadIdx.x & 63;
+    o0 = y && k < dy ? obs[k] : 0;
+    y0 = y && k < dy ? y[k] : 0.f;
+    o1 = y && k + 64 < dy ? obs[k + 64] : 0;
+    y1 = y && k + 64 < dy ? y[k + 64] : 0.f;
+  }
+  __device__ void set(bool on, const float *pl, int pm, int pi, int psrc) {
     active = on;
     plane = pl;
     m = pm;
     i = pi;
     src = psrc;
-    // read now, used at the next particle's second barrier
+    // read now, used at the next particle's first step
     if (!PILOT && on && apf && threadIdx.x == 0) lpil_src = lpil[(size_t)pm * N + psrc];
   }
-  __device__ void init_obs() {
+  __device__ void run() {
+    if (!active || threadIdx.x >= 64) return;
     const int k = threadIdx.x;
-    o0 = y && k < dy ? obs[k] : 0;
-    y0 = y && k < dy ? y[k] : 0.f;
-  }
-  __device__ void before_b() {
-    if (!active) return;
     float acc = 0.f;
-    if ((int)threadIdx.x < dy) {
+    if (k < dy) {
       const float r = y0 - plane[o0];
       acc = r * r;
     }
-    for (int k = threadIdx.x + FP_THREADS; k < dy; k += FP_THREADS) {
-      const float r = y[k] - plane[obs[k]];
+    if (k + 64 < dy) {
+      const float r = y1 - plane[o1];
       acc = fmaf(r, r, acc);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) lwp[threadIdx.x >> 6] = acc;
-  }
-  __device__ void after_b() {
-    if (!active || threadIdx.x != 0) return;
-    float a = 0.f;
-#pragma unroll
-    for (int w = 0; w < FP_WAVES; ++w) a += lwp[w];
+    for (int kk = k + 128; kk < dy; kk += 64) {
+      const float r = y[kk] - plane[obs[kk]];
+      acc = fmaf(r, r, acc);
+    }
+    const float a = wave_sum_f32(acc);
+    if (k != 0) return;
     float l = -a * inv2var;
     const size_t o = (size_t)m * N + i;
     if (PILOT) {
@@ -462,10 +529,10 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
   int src = src_of(anc_raw(p));
   fetch(p, src);
   int raw_nx = anc_raw(p + G);
-  LikHook<PILOT> hook{y ? gptr(y) + E.yoff : nullptr, gptr(md.obs_idx), gptr(E.lw), gptr(E.lpil),
-                      gptr((const float *)E.lwc), md.inv2var, md.dy, E.apf, N, L.lwp,
-                      L.plane[1], 0, 0, 0, false, 0, 0.f, 0.f};
-  hook.init_obs();
+  LikPrev<PILOT> lik{y ? gptr(y) + E.yoff : nullptr, gptr(md.obs_idx), gptr(E.lw), gptr(E.lpil),
+                     gptr((const float *)E.lwc), md.inv2var, md.dy, E.apf, N, L.plane(0),
+                     0, 0, 0, false, 0, 0, 0.f, 0.f, 0.f};
+  lik.init_obs();
   // A particle's new state is written out at the start of the next
   // iteration, after the prefetched state has been taken from its registers
   // and before the next prefetch is issued: with loads and stores both
@@ -473,7 +540,8 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
   // wait for a load comes before the stores and a particle's time after it.
   float u[4 * Q], v[4 * Q];
   int m = 0, i = 0;
-  auto store = [&]() {
+  RingPend pend{-1, -1};
+  auto store = [&](const int *ring) {
     gmem<float> *x = Xout + ((size_t)m * N + i) * dx;
 #pragma unroll
     for (int g = 0; g < Q; ++g)
@@ -482,10 +550,14 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
         st4(x + nn + k0 + 4 * g, v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
       }
     if (tid < nr4) {
-      // (this thread's own ring slots: no other thread writes them)
+      // (this thread's own ring slots, its deferred write of the last step
+      // among them: no other thread writes them)
       float r[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) r[c] = 4 * tid + c < md.stim_l0 ? (float)L.ring[4 * tid + c] : -1.f;
+      for (int c = 0; c < 4; ++c) {
+        const int sl = 4 * tid + c;
+        r[c] = sl < md.stim_l0 ? (float)(sl == pend.slot ? pend.ev : ring[sl]) : -1.f;
+      }
       st4(x + 2 * nn + 4 * tid, r[0], r[1], r[2], r[3]);
     }
   };
@@ -496,22 +568,25 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
     // wait comes before the previous particle's stores, so it never waits
     // for them (s_waitcnt vmcnt(0), the other counters left alone)
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    float *pl = par ? L.plane[1] : L.plane[0];
+    float *pa = L.plane(2 * par), *pb = L.plane(2 * par + 1);
+    int *ring = L.ring(par);
     float4 cu[Q], cv[Q];
 #pragma unroll
     for (int g = 0; g < Q; ++g) {
       cu[g] = fu[g], cv[g] = fv[g];
-      if (nb[4 * g] & NB_VALID) *(float4 *)(pl + k0 + 4 * g) = cu[g];
+      if (nb[4 * g] & NB_VALID) *(float4 *)(pa + k0 + 4 * g) = cu[g];
     }
     const int r0 = (int)fr.x, r1 = (int)fr.y, r2 = (int)fr.z, r3 = (int)fr.w;
     // whether any loaded ring entry holds an event (the loading threads are
     // lanes of wave 0; read after the barrier below)
     const bool mine = tid < nr4 && (r0 >= 0 || r1 >= 0 || r2 >= 0 || r3 >= 0);
     const unsigned long long anyb = __ballot(mine);
-    if (tid == 0) L.ev[1] = anyb != 0ull;
-    // the previous particle's state out (its ring slots are read from LDS
-    // before this thread overwrites them)
-    if (!PILOT && p != (int)blockIdx.x) store();
+    if (tid == 0) L.ev[1 + par] = anyb != 0ull;
+    // the previous particle's state out (its ring, of the other parity, is
+    // read from LDS before the set of this parity is overwritten two
+    // particles on)
+    if (!PILOT && p != (int)blockIdx.x) store(L.ring(par ^ 1));
+    pend.slot = -1;
     m = p / N;
     i = p - m * N;
     int cov[4 * Q];
@@ -521,28 +596,27 @@ k_fhnp(const FusedEns *__restrict__ ens, int e, IvArg iv, int parity, int pendin
       v[4 * g] = cv[g].x, v[4 * g + 1] = cv[g].y, v[4 * g + 2] = cv[g].z, v[4 * g + 3] = cv[g].w;
     }
     if (tid < nr4) {
-      L.ring[4 * tid] = r0;
-      L.ring[4 * tid + 1] = r1;
-      L.ring[4 * tid + 2] = r2;
-      L.ring[4 * tid + 3] = r3;
+      ring[4 * tid] = r0;
+      ring[4 * tid + 1] = r1;
+      ring[4 * tid + 2] = r2;
+      ring[4 * tid + 3] = r3;
     }
     const int src_cur = src;
     src = src_of(raw_nx);
     fetch(p + G, src);
     raw_nx = anc_raw(p + 2 * G);
     __syncthreads();  // (A) of step 0: plane and ring complete
-    build_cover<Q>(J, md.stim_l0, nb, L.ring, L.ev[1] != 0, cov);
+    lik.run();        // (wave 0) the previous particle's log-likelihood
+    build_cover<Q>(J, md.stim_l0, nb, ring, L.ev[1 + par] != 0, cov);
     fhnp_steps<Q, PILOT>(md, E.key, P_PROP, (uint32_t)i, (uint32_t)m, (t - 1) * md.S, nb, u, v, cov,
-                         pl, L, hook);
-    hook.set_prev(y != nullptr, pl, m, i, src_cur);
+                         pa, pb, ring, L, pend);
+    lik.set(y != nullptr, (md.S & 1) ? pb : pa, m, i, src_cur);
     par ^= 1;
   }
-  if (!PILOT) store();
-  if (hook.active) {
+  if (!PILOT) store(L.ring(par ^ 1));
+  if (lik.active) {
     __syncthreads();
-    hook.before_b();
-    __syncthreads();
-    hook.after_b();
+    lik.run();
   }
 }
 
@@ -563,22 +637,28 @@ k_fhnp_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
   int nb[4 * Q], cov[4 * Q];
   float u[4 * Q], v[4 * Q];
   node_bits<Q>(J, nb);
-  float *pl = L.plane[0];
+  float *pa = L.plane(0), *pb = L.plane(1);  // pa: the plane that holds U
+  int *ring = L.ring(0);
 #pragma unroll
   for (int e = 0; e < 4 * Q; ++e) {
     const bool ok = nb[e] & NB_VALID;
     u[e] = ok ? xtrue[k0 + e] : 0.f;
     v[e] = ok ? xtrue[nn + k0 + e] : 0.f;
-    if (ok) pl[k0 + e] = u[e];
+    if (ok) pa[k0 + e] = u[e];
   }
   if (tid < nr4)
-    for (int c = 0; c < 4; ++c) L.ring[4 * tid + c] = (int)xtrue[2 * nn + 4 * tid + c];
+    for (int c = 0; c < 4; ++c) ring[4 * tid + c] = (int)xtrue[2 * nn + 4 * tid + c];
   __syncthreads();
-  build_cover<Q>(J, md.stim_l0, nb, L.ring, true, cov);
-  NoHook none;
+  build_cover<Q>(J, md.stim_l0, nb, ring, true, cov);
+  RingPend pend{-1, -1};
   for (int t = 1; t <= T; ++t) {
     fhnp_steps<Q, false>(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, (t - 1) * md.S, nb, u, v, cov,
-                         pl, L, none);
+                         pa, pb, ring, L, pend);
+    if (md.S & 1) {
+      float *tmp = pa;
+      pa = pb;
+      pb = tmp;
+    }
     float *x = xtrue + (size_t)t * dx;
 #pragma unroll
     for (int e = 0; e < 4 * Q; ++e)
@@ -587,16 +667,24 @@ k_fhnp_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
         x[nn + k0 + e] = v[e];
       }
     if (tid < nr4)
-      for (int c = 0; c < 4; ++c)
-        x[2 * nn + 4 * tid + c] = 4 * tid + c < md.stim_l0 ? (float)L.ring[4 * tid + c] : -1.f;
-    __syncthreads();  // the plane holds U at the observation time
+      for (int c = 0; c < 4; ++c) {
+        const int sl = 4 * tid + c;
+        x[2 * nn + sl] = sl < md.stim_l0 ? (float)(sl == pend.slot ? pend.ev : ring[sl]) : -1.f;
+      }
+    __syncthreads();  // pa holds U at the observation time; every wave has read the last step's ring
+    if (pend.slot >= 0) {
+      ring[pend.slot] = pend.ev;
+      pend.slot = -1;
+    }
+    if (md.stim_l0 < 2) __syncthreads();  // (the next step reads that same slot)
     for (int k4 = tid; 4 * k4 < md.dy; k4 += FP_THREADS) {
       float z[4];
       normals4(philox(0u, TRUTH_STREAM, (uint32_t)t, (P_OBS_NOISE << 24) | (uint32_t)k4, key), z);
       for (int l = 0; l < 4 && 4 * k4 + l < md.dy; ++l)
-        y[(size_t)(t - 1) * md.dy + 4 * k4 + l] = pl[md.obs_idx[4 * k4 + l]] + md.obs_sd * z[l];
+        y[(size_t)(t - 1) * md.dy + 4 * k4 + l] = pa[md.obs_idx[4 * k4 + l]] + md.obs_sd * z[l];
     }
-    // (the next step writes the plane only after its second barrier)
+    // (the next interval's first step writes pb; pa is written again only
+    // after that step's barrier)
   }
 }
 
@@ -605,6 +693,12 @@ hipError_t launch_q(const FusedEns *d_ens, int e, int MN, int J, IvArg iv, int p
                     hipStream_t s) {
   int per_cu = 0, dev = 0, cus = 256;
   const size_t lds = fhnp_lds_bytes(J);
+  // (J = 64: four 16 KB planes, past the default 64 KB of dynamic LDS)
+  if (lds > 65536) {
+    const hipError_t a = hipFuncSetAttribute((const void *)k_fhnp<Q, PILOT>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (a != hipSuccess) return a;
+  }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fhnp<Q, PILOT>,
                                                    FP_THREADS, lds) != hipSuccess ||
       per_cu < 1)
@@ -648,6 +742,16 @@ hipError_t launch_fhnp_simulate(const EnsDev &e, uint64_t seed, int T, float *xt
                                 hipStream_t s) {
   const size_t lds = fhnp_lds_bytes(e.md.J);
   const Key key = make_key(seed);
+  if (lds > 65536) {
+    const void *f = nullptr;
+    switch (fhnp_q(e.md.J)) {
+      case 3: f = (const void *)k_fhnp_simulate<3>; break;
+      case 4: f = (const void *)k_fhnp_simulate<4>; break;
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t a = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (a != hipSuccess) return a;
+  }
   switch (fhnp_q(e.md.J)) {
     case 1: k_fhnp_simulate<1><<<1, FP_THREADS, lds, s>>>(e.md, key, T, xtrue, y); break;
     case 2: k_fhnp_simulate<2><<<1, FP_THREADS, lds, s>>>(e.md, key, T, xtrue, y); break;

@@ -153,6 +153,48 @@ def test_interval_other_grids(pf, orc, torch_mod, Jg):
     assert n_amb <= 0.05 * M * N
 
 
+# Many particles per workgroup: the launch holds only the resident
+# workgroups (a few per CU), so each walks the particles p, p + G, ... with
+# the next state prefetched, the planes and rings reused, and the previous
+# particle's log-likelihood formed during the next particle's first step.
+# 4200 particles (four or five per workgroup); a sample, the last particles
+# included, against the oracle.
+@pytest.mark.parametrize("S,fused", [(1, True), (2, True), (1, False)])
+def test_interval_many_particles_per_workgroup(pf, orc, torch_mod, S, fused):
+    spec = pf_inputs.fhn_paper(J, S=S, eps=0.5)
+    M, N, seed, t = 2, 2100, 950 + S, 5
+    print(f"FH-N network {M}x{N} S {S} fused {fused}", flush=True)
+    m = orc.Model(spec)
+    X0 = _cloud(seed, spec, M, N)
+    X0[:, 1::3] = _cloud(seed + 1, spec, M, N, empty_rings=True)[:, 1::3]
+    rng = np.random.default_rng(seed)
+    y = (-1.5 + 0.5 * rng.standard_normal(len(spec["obs_idx"]))).astype(np.float32)
+    f = pf.ParticleFilter([spec], [(0, M, N, seed)], fused=fused)
+    f.set_particles(0, _dev(X0))
+    f.set_interval(t)
+    f.run_stages(pf.STAGE_PROPAGATE | pf.STAGE_WEIGHT, _dev(y))
+    xb = f.get_predicted(0).cpu().numpy()
+    lw = f.get_logweights(0).cpu().numpy()
+    f.close()
+    picks = sorted(set(rng.integers(0, M * N, 56).tolist()) | {0, 1, M * N - 2, M * N - 1,
+                                                                N - 1, N})
+    n_amb = n_ev = 0
+    for p in picks:
+        k, i = divmod(p, N)
+        xo, amb = _oracle_particle(orc, m, seed, k, i, t, X0[k, i].copy())
+        if amb:
+            n_amb += 1
+            continue
+        n_ev += int(np.sum(xo[2 * NN:2 * NN + 25] != X0[k, i, 2 * NN:2 * NN + 25]))
+        assert np.array_equal(xb[k, i, 2 * NN:], xo[2 * NN:].astype(np.float32)), (k, i)
+        assert_rel_close(xb[k, i, :2 * NN], xo[:2 * NN], floor=0.1, what=f"particle {k},{i}")
+        assert_rel_close(lw[k, i], orc.loglik(m, xo, y.astype(np.float64)), floor=1.0,
+                         what=f"log-weight {k},{i}")
+    print(f"exempt {n_amb} of {len(picks)}; ring slots changed {n_ev}")
+    assert n_amb <= 0.05 * len(picks) + 1
+    assert n_ev > 0
+
+
 def test_prior_draw(pf, orc, torch_mod):
     spec = pf_inputs.fhn_paper(J)
     M, N, seed = 2, 16, 5
@@ -250,14 +292,17 @@ def test_batch_members_equal_runs_alone(pf, torch_mod):
             g.close()
 
 
-def test_auxiliary_filter_interval_matches_oracle(pf, orc, torch_mod):
+@pytest.mark.parametrize("N", [64, 2100])
+def test_auxiliary_filter_interval_matches_oracle(pf, orc, torch_mod, N):
     # the paper's filter on its network: pilot = the noise-free continuation
     # with the active stimuli of the ring (eps = 0: no new events, so no
     # threshold decision is involved), first stage, propagation, carried
-    # second-stage weights
+    # second-stage weights (N = 2100: several particles per workgroup in
+    # both the pilot and the propagation kernel)
     from pf_testlib import rel_close
     spec = pf_inputs.fhn_paper(J, S=2, eps=0.0)
-    M, N, seed, t = 2, 64, 909, 4
+    M, seed, t = 2, 909, 4
+    print(f"FH-N network auxiliary {M}x{N}", flush=True)
     m = orc.Model(spec)
     X0 = _cloud(seed, spec, M, N)
     rng = np.random.default_rng(seed)
