@@ -491,18 +491,35 @@ k_grid_estimate_part(int N, int dx4, const float4 *__restrict__ Xb,
   }
 }
 
-// Filter means from the chunk partials: one thread per (state element, filter).
+// Filter means from the chunk partials: a workgroup per (64 state elements,
+// filter), its four waves each summing every fourth chunk of the filter's
+// (ch = slice, slice + 4, ...: one coalesced 512-byte row per wave and
+// chunk), the four slices added in LDS in slice order.
+constexpr int FOLD_COLS = 64, FOLD_SLICES = GB / FOLD_COLS;
 __global__ void __launch_bounds__(GB)
 k_grid_filter_fold(int N, int dx, int nch, const double *__restrict__ part,
                    const double *__restrict__ fstat, double *__restrict__ fmean,
                    double *__restrict__ fmeanw) {
-  const int c = blockIdx.x * GB + threadIdx.x, m = blockIdx.y;
-  if (c >= dx) return;
+  __shared__ double sa[FOLD_SLICES][FOLD_COLS], sb[FOLD_SLICES][FOLD_COLS];
+  const int cl = threadIdx.x % FOLD_COLS, sl = threadIdx.x / FOLD_COLS;
+  const int c = blockIdx.x * FOLD_COLS + cl, m = blockIdx.y;
   double a = 0.0, b = 0.0;
-  for (int ch = 0; ch < nch; ++ch) {
-    const double *o = part + (((size_t)m * nch + ch) * 2) * (size_t)dx;
-    a += o[c];
-    b += o[(size_t)dx + c];
+  if (c < dx) {
+#pragma unroll 4
+    for (int ch = sl; ch < nch; ch += FOLD_SLICES) {
+      const double *o = part + (((size_t)m * nch + ch) * 2) * (size_t)dx;
+      a += o[c];
+      b += o[(size_t)dx + c];
+    }
+  }
+  sa[sl][cl] = a;
+  sb[sl][cl] = b;
+  __syncthreads();
+  if (sl != 0 || c >= dx) return;
+#pragma unroll
+  for (int q = 1; q < FOLD_SLICES; ++q) {
+    a += sa[q][cl];
+    b += sb[q][cl];
   }
   const double W = fstat[(size_t)m * FREC + 1];
   // a filter that kept its particles (ESS schedule) reports the weighted mean
@@ -836,7 +853,7 @@ hipError_t launch_grid_estimate(const EnsDev &e, const float *Xb, const int32_t 
   const int dx4 = e.md.dx / 4, nch = grid_est_chunks(e.N);
   dim3 g((unsigned)((dx4 + GB - 1) / GB), (unsigned)nch, (unsigned)e.M);
   k_grid_estimate_part<<<g, GB, 0, s>>>(e.N, dx4, (const float4 *)Xb, cnt, e.lw, e.fstat, part);
-  const dim3 gf((unsigned)((e.md.dx + GB - 1) / GB), (unsigned)e.M);
+  const dim3 gf((unsigned)((e.md.dx + FOLD_COLS - 1) / FOLD_COLS), (unsigned)e.M);
   k_grid_filter_fold<<<gf, GB, 0, s>>>(e.N, e.md.dx, nch, part, e.fstat, e.fmean, e.fmeanw);
   k_grid_ensemble_fold<<<(e.md.dx + GB - 1) / GB, GB, 0, s>>>(e.M, e.md.dx, e.fmean, e.fmeanw,
                                                                e.emean);

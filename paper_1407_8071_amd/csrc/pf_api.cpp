@@ -643,11 +643,18 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
     PF_HIP(hipEventRecord(ctx->ev_join, g));
     PF_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
-  // 3. the cross-filter averages (and, in a graph, the interval counter)
+  // 3. the cross-filter averages (and, in a graph, the interval counter);
+  //    grid ensembles have theirs from their own estimator, so a batch of
+  //    grid ensembles only needs the launch for the counter
   int max_m = 1;
-  for (const Ens &E : ctx->ens) max_m = std::max(max_m, (int)E.d.M);
-  PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), max_m,
-                                    iv.tp ? const_cast<int *>(iv.tp) : nullptr, s));
+  bool any_vec = false;
+  for (const Ens &E : ctx->ens) {
+    max_m = std::max(max_m, (int)E.d.M);
+    any_vec |= !E.grid;
+  }
+  if (any_vec || iv.tp)
+    PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), max_m,
+                                      iv.tp ? const_cast<int *>(iv.tp) : nullptr, s));
   return PF_OK;
 }
 
