@@ -598,9 +598,12 @@ k_ensemble_means_batched(const FusedEns *__restrict__ ens, int *t_inc) {
 
 }  // namespace
 
-hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, int *t_inc,
-                                 hipStream_t s) {
-  if (n_ens > 0) k_ensemble_means_batched<<<n_ens, max_m > 256 ? 1024 : 256, 0, s>>>(d_ens, t_inc);
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, bool tiled,
+                                 int *t_inc, hipStream_t s) {
+  // 1024 threads for many filters, or where the partial sums of more than
+  // four tiled filters are folded (a wave per filter, in one round)
+  if (n_ens > 0)
+    k_ensemble_means_batched<<<n_ens, (max_m > 256 || tiled) ? 1024 : 256, 0, s>>>(d_ens, t_inc);
   return hipGetLastError();
 }
 

@@ -647,13 +647,15 @@ pf_status fused_launch(pf_ctx *ctx, pfk::IvArg iv, int parity, int pending, bool
   //    grid ensembles have theirs from their own estimator, so a batch of
   //    grid ensembles only needs the launch for the counter
   int max_m = 1;
-  bool any_vec = false;
+  bool any_vec = false, any_tiled = false;
   for (const Ens &E : ctx->ens) {
     max_m = std::max(max_m, (int)E.d.M);
     any_vec |= !E.grid;
+    // (four waves fold up to four tiled filters in one round; more take 16)
+    any_tiled |= E.tiled && E.fz.mpart != nullptr && E.d.M > 4;
   }
   if (any_vec || iv.tp)
-    PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), max_m,
+    PF_HIP(pfk::launch_ensemble_means(ctx->d_fens, (int)ctx->ens.size(), max_m, any_tiled,
                                       iv.tp ? const_cast<int *>(iv.tp) : nullptr, s));
   return PF_OK;
 }

@@ -200,8 +200,8 @@ int grid_steps_ppb(int J);
 // cross-filter averages of many ensembles at once (one workgroup each)
 // t_inc (optional): device interval counter advanced once the means are done
 // max_m: the largest filter count of the ensembles (sets the workgroup size)
-hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, int *t_inc,
-                                 hipStream_t s);
+hipError_t launch_ensemble_means(const FusedEns *d_ens, int n_ens, int max_m, bool tiled,
+                                 int *t_inc, hipStream_t s);
 hipError_t launch_set_i32(int *p, int v, hipStream_t s);
 // p[0 .. n) = v (a kernel, not a memset node, so that it may be captured)
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
