@@ -118,10 +118,10 @@ def test_interval_matches_oracle(pf, orc, torch_mod, S, fused):
 
 # Other grid sizes: each thread owns 4Q consecutive nodes (Q = ceil(J^2 / 1024));
 # where J is a multiple of 4Q they lie in one row and the neighbours come from
-# row reads (J = 40, Q = 2), otherwise from per-node reads (J = 30: threads
-# beyond the last node idle; J = 36, Q = 2); some particles start with no
-# event in their ring.
-@pytest.mark.parametrize("Jg", [30, 36, 40])
+# row reads (J = 40, Q = 2; J = 64, Q = 4, whose four planes exceed 64 KB of
+# LDS), otherwise from per-node reads (J = 30: threads beyond the last node
+# idle; J = 36, Q = 2); some particles start with no event in their ring.
+@pytest.mark.parametrize("Jg", [30, 36, 40, 64])
 def test_interval_other_grids(pf, orc, torch_mod, Jg):
     spec = pf_inputs.fhn_paper(Jg, S=2, eps=0.5)
     nn = Jg * Jg
@@ -208,8 +208,12 @@ def test_prior_draw(pf, orc, torch_mod):
         assert np.all(X[k, :, 2 * NN:] == -1.0)
 
 
-def test_truth_simulation_matches_oracle(pf, orc, torch_mod):
-    spec = pf_inputs.fhn_paper(J, eps=0.05)
+# J = 64 with two steps per observation: the planes take more than 64 KB of
+# LDS, and the plane holding U alternates with S even and odd
+@pytest.mark.parametrize("Jt,S", [(32, 1), (64, 2)])
+def test_truth_simulation_matches_oracle(pf, orc, torch_mod, Jt, S):
+    spec = pf_inputs.fhn_paper(Jt, S=S, eps=0.05)
+    nn = Jt * Jt
     T, seed = 40, 12
     m = orc.Model(spec)
     xo, yo = orc.simulate(m, seed, T)
@@ -219,10 +223,10 @@ def test_truth_simulation_matches_oracle(pf, orc, torch_mod):
     sim.close()
     # compare up to the first step whose start is ambiguous at a threshold
     for t in range(T + 1):
-        if t > 0 and _near_band(xo[t - 1, :NN]):
+        if t > 0 and _near_band(xo[t - 1, :nn]):
             break
-        assert np.array_equal(xt[t, 2 * NN:], xo[t, 2 * NN:].astype(np.float32)), t
-        assert_rel_close(xt[t, :2 * NN], xo[t, :2 * NN], floor=0.1, rel=5e-5, what=f"truth {t}")
+        assert np.array_equal(xt[t, 2 * nn:], xo[t, 2 * nn:].astype(np.float32)), t
+        assert_rel_close(xt[t, :2 * nn], xo[t, :2 * nn], floor=0.1, rel=5e-5, what=f"truth {t}")
         if t > 0:
             assert_rel_close(y[t - 1], yo[t - 1], floor=1.0, rel=5e-5, what=f"y {t}")
     assert t >= 10
