@@ -464,13 +464,13 @@ k_grid_estimate_part(int N, int dx4, const float4 *__restrict__ Xb,
                      const double *__restrict__ fstat, double *__restrict__ part) {
   // the chunk's offspring counts and weights, computed once per workgroup
   __shared__ double nsh[EST_CHUNK], wsh[EST_CHUNK];
-  const int g = blockIdx.x * GB + threadIdx.x;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y, m = blockIdx.z;
   const int nch = gridDim.y;
   const double mx = fstat[(size_t)m * FREC + 0];
   const bool deg = fstat[(size_t)m * FREC + 3] != 0.0;
   const int i0 = ch * EST_CHUNK, i1 = min(N, i0 + EST_CHUNK);
-  for (int k = threadIdx.x; k < i1 - i0; k += GB) {
+  for (int k = threadIdx.x; k < i1 - i0; k += blockDim.x) {
     nsh[k] = (double)cnt[(size_t)m * N + i0 + k];
     wsh[k] = deg ? 1.0 : exp((double)lw[(size_t)m * N + i0 + k] - mx);
   }
@@ -528,16 +528,31 @@ k_grid_filter_fold(int N, int dx, int nch, const double *__restrict__ part,
   fmeanw[(size_t)m * dx + c] = b / W;
 }
 
-// Ensemble means: one thread per state element, filters in a fixed order.
+// Ensemble means: a workgroup per 64 state elements, its four waves each
+// summing every fourth filter's means (m = slice, slice + 4, ...), the four
+// slices added in LDS in slice order.
 __global__ void __launch_bounds__(GB)
 k_grid_ensemble_fold(int M, int dx, const double *__restrict__ fmean,
                      const double *__restrict__ fmeanw, double *__restrict__ emean) {
-  const int c = blockIdx.x * GB + threadIdx.x;
-  if (c >= dx) return;
+  __shared__ double sa[FOLD_SLICES][FOLD_COLS], sb[FOLD_SLICES][FOLD_COLS];
+  const int cl = threadIdx.x % FOLD_COLS, sl = threadIdx.x / FOLD_COLS;
+  const int c = blockIdx.x * FOLD_COLS + cl;
   double a = 0.0, b = 0.0;
-  for (int m = 0; m < M; ++m) {
-    a += fmean[(size_t)m * dx + c];
-    b += fmeanw[(size_t)m * dx + c];
+  if (c < dx) {
+#pragma unroll 4
+    for (int m = sl; m < M; m += FOLD_SLICES) {
+      a += fmean[(size_t)m * dx + c];
+      b += fmeanw[(size_t)m * dx + c];
+    }
+  }
+  sa[sl][cl] = a;
+  sb[sl][cl] = b;
+  __syncthreads();
+  if (sl != 0 || c >= dx) return;
+#pragma unroll
+  for (int q = 1; q < FOLD_SLICES; ++q) {
+    a += sa[q][cl];
+    b += sb[q][cl];
   }
   emean[c] = a / (double)M;
   emean[dx + c] = b / (double)M;
@@ -851,12 +866,16 @@ int grid_est_chunks(int N) { return (N + EST_CHUNK - 1) / EST_CHUNK; }
 hipError_t launch_grid_estimate(const EnsDev &e, const float *Xb, const int32_t *cnt,
                                 double *part, hipStream_t s) {
   const int dx4 = e.md.dx / 4, nch = grid_est_chunks(e.N);
-  dim3 g((unsigned)((dx4 + GB - 1) / GB), (unsigned)nch, (unsigned)e.M);
-  k_grid_estimate_part<<<g, GB, 0, s>>>(e.N, dx4, (const float4 *)Xb, cnt, e.lw, e.fstat, part);
+  // the state's float4 groups split evenly over the fewest workgroups of at
+  // most GB threads (e.g. 519 groups: 3 x 192 threads rather than 3 x 256)
+  const int ngr = (dx4 + GB - 1) / GB;
+  const int th = std::min(GB, 64 * (((dx4 + ngr - 1) / ngr + 63) / 64));
+  dim3 g((unsigned)((dx4 + th - 1) / th), (unsigned)nch, (unsigned)e.M);
+  k_grid_estimate_part<<<g, th, 0, s>>>(e.N, dx4, (const float4 *)Xb, cnt, e.lw, e.fstat, part);
   const dim3 gf((unsigned)((e.md.dx + FOLD_COLS - 1) / FOLD_COLS), (unsigned)e.M);
   k_grid_filter_fold<<<gf, GB, 0, s>>>(e.N, e.md.dx, nch, part, e.fstat, e.fmean, e.fmeanw);
-  k_grid_ensemble_fold<<<(e.md.dx + GB - 1) / GB, GB, 0, s>>>(e.M, e.md.dx, e.fmean, e.fmeanw,
-                                                               e.emean);
+  k_grid_ensemble_fold<<<(e.md.dx + FOLD_COLS - 1) / FOLD_COLS, GB, 0, s>>>(e.M, e.md.dx, e.fmean,
+                                                                             e.fmeanw, e.emean);
   return hipGetLastError();
 }
 
