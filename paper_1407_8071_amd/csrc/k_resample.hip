@@ -354,7 +354,19 @@ k_ancestors_fold(int N, int T, int G, double lognorm, const double *__restrict__
   __shared__ double co[FOLD_MAX_TILES + 1], so[FOLD_MAX_TILES + 1];
   __shared__ double shd[D * (TILE_THREADS / 64)];
   __shared__ float shf[TILE_THREADS / 64];
-  const int m = blockIdx.y, g = blockIdx.x;
+  const int m = blockIdx.y;
+  // Workgroup b = blockIdx.x + G m runs on XCD b mod 8, and resampling tile
+  // q of filter m was formed on XCD (q + T m) mod 8 (workgroup q + T m of
+  // the CDF launch).  The span of targets g lies mostly in tile g / 4
+  // (ANC_SPAN = TILE / 4), so where G is a multiple of 32 each workgroup
+  // takes a span of the tiles formed on its own XCD (a bijection of the
+  // spans), and its searches read that XCD's L2.
+  int g = blockIdx.x;
+  if (G % 32 == 0 && 4 * ANC_SPAN == TILE) {
+    const int r = g & 7, a = g >> 3;
+    const int x = (int)(((long)r + (long)(G - T) * m) & 7);
+    g = 32 * (a >> 2) + 4 * x + (a & 3);
+  }
   const double *rec = tile + (size_t)m * T * TREC;
   for (int j = threadIdx.x; j < T; j += TILE_THREADS) {
     ct[j] = rec[(size_t)j * TREC + 1];

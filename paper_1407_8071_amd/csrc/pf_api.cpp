@@ -827,10 +827,15 @@ pf_status build_plan(pf_ctx *ctx, const pf_tuning &u, hipStream_t s) {
       const Ens &E = ctx->ens[(size_t)e];
       if (E.grid || E.wg) continue;
       const int which = E.dx == 3 ? 1 : 0;
-      for (int mm = 0; mm < E.d.M; ++mm) {
-        const int x = xcd(e, mm);
-        for (int i0 = 0; i0 < E.d.N; i0 += u.prop_tile) bucket[which][x].push_back(int4{e, mm, i0, 0});
-      }
+      for (int mm = 0; mm < E.d.M; ++mm)
+        for (int i0 = 0; i0 < E.d.N; i0 += u.prop_tile) {
+          // a tiled ensemble: resampling tile q of filter m is workgroup
+          // q + T m of its CDF launch, so the propagation tiles of its
+          // particles go to that workgroup's XCD
+          const int x = E.tiled ? (int)(((long)(i0 / pfk::TILE) + (long)E.T * mm) % XCDS)
+                                : xcd(e, mm);
+          bucket[which][x].push_back(int4{e, mm, i0, 0});
+        }
     }
     for (int w = 0; w < 2; ++w) {
       size_t total = 0, next[XCDS] = {};
