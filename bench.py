@@ -199,7 +199,9 @@ def cpu_baseline(spec, M, N, y_host, target_s):
     return {"value": steps / wall, "unit": "particle-steps/s", "cores": n_filters,
             "wall_s": wall, "kind": "oracle",
             "sample": f"{n_filters} filters x N={N} x {intervals} intervals "
-                      f"({steps:.3g} particle-steps, FP64, one filter per core)"}
+                      f"({steps:.3g} particle-steps, FP64, one filter per core)",
+            # the calibration run: one filter's interval on one core
+            "single_core_value": N * spec["S"] / per_filter_interval}
 
 
 # ------------------------------------------------------------- helpers ------
