@@ -5,8 +5,10 @@ reads the interval index and the observations from device memory.  Every
 replay is compared with the eager fused path on the same seeds (identical
 kernels and arguments, so bit-identical results are expected), with the
 program's own eager work (estimate copies, synchronisations) between
-replays, for the Lorenz model, the FH-N model, a mixed batch, and a reset
-of the interval counter in the middle of a run.
+replays, for the Lorenz model, the FH-N model, a mixed batch, the paper's
+network with bootstrap and auxiliary ensembles, the other resampling schemes
+with the ESS schedule, and a reset of the interval counter in the middle of
+a run.
 """
 import numpy as np
 import pytest
@@ -41,8 +43,8 @@ def _snap(f, n_ens):
 def _compare_runs(pf, orc, torch_mod, specs, ens, T):
     models = [orc.Model(s) for s in specs]
     ys = []
-    for e, (mi, M, N, seed) in enumerate(ens):
-        _, y = orc.simulate(models[mi], 300 + e, T)
+    for e, en in enumerate(ens):
+        _, y = orc.simulate(models[en[0]], 300 + e, T)
         ys.append(y.astype(np.float32))
     y_all = torch_mod.from_numpy(np.ascontiguousarray(np.concatenate(ys, axis=1))).cuda()
     eager = pf.ParticleFilter(specs, ens, fused=True)
@@ -70,6 +72,24 @@ def test_graph_matches_eager_mixed_batch(pf, orc, torch_mod):
     specs = [pf_inputs.lorenz63(), pf_inputs.fhn(20),
              pf_inputs.ou1d(theta=1.0, sd=1.0, h=0.01, S=10, obs_var=0.3)]
     ens = [(0, 2, 3000, 1), (1, 2, 128, 2), (0, 5, 64, 3), (2, 4, 100, 4), (0, 1, 9000, 5)]
+    _compare_runs(pf, orc, torch_mod, specs, ens, T=5)
+
+
+def test_graph_matches_eager_network_and_auxiliary(pf, orc, torch_mod):
+    # the paper's FH-N network (events drawn often), a bootstrap and an
+    # auxiliary ensemble, several particles per workgroup
+    spec = pf_inputs.fhn_paper(32, eps=0.3)
+    ens = [(0, 2, 1500, 7), (0, 2, 700, 8, pf.ENS_AUXILIARY)]
+    _compare_runs(pf, orc, torch_mod, [spec], ens, T=4)
+
+
+def test_graph_matches_eager_schemes_and_schedule(pf, orc, torch_mod):
+    # the other resampling schemes and the ESS-triggered schedule (the
+    # per-filter resampler's second variant) beside a plain ensemble
+    specs = [pf_inputs.lorenz63(), pf_inputs.fhn(20)]
+    ens = [(0, 3, 2000, 1, 0, "systematic"), (0, 2, 700, 2, 0, "residual", 0.5),
+           (0, 2, 4096, 3, 0, "stratified"), (1, 2, 64, 4, 0, "multinomial", 0.7),
+           (0, 4, 300, 5)]
     _compare_runs(pf, orc, torch_mod, specs, ens, T=5)
 
 
