@@ -7,8 +7,8 @@ kernels and arguments, so bit-identical results are expected), with the
 program's own eager work (estimate copies, synchronisations) between
 replays, for the Lorenz model, the FH-N model, a mixed batch, the paper's
 network with bootstrap and auxiliary ensembles, the other resampling schemes
-with the ESS schedule, and a reset of the interval counter in the middle of
-a run.
+with the ESS schedule, a learned-proposal ensemble, and a reset of the
+interval counter in the middle of a run.
 """
 import numpy as np
 import pytest
@@ -91,6 +91,30 @@ def test_graph_matches_eager_schemes_and_schedule(pf, orc, torch_mod):
            (0, 2, 4096, 3, 0, "stratified"), (1, 2, 64, 4, 0, "multinomial", 0.7),
            (0, 4, 300, 5)]
     _compare_runs(pf, orc, torch_mod, specs, ens, T=5)
+
+
+def test_graph_matches_eager_learned_proposal(pf, orc, torch_mod):
+    # a learned-proposal FH-N ensemble (random network) beside a bootstrap one
+    spec = pf_inputs.fhn(20)
+    T = 3
+    _, y = orc.simulate(orc.Model(spec), 301, T)
+    y2 = np.concatenate([y, y], axis=1).astype(np.float32)
+    y_all = torch_mod.from_numpy(np.ascontiguousarray(y2)).cuda()
+    rng = np.random.default_rng(11)
+    params = torch_mod.from_numpy(
+        (rng.standard_normal(orc.mlp_nparams(22, 2)) * 0.05).astype(np.float32)).cuda()
+    ens = [(0, 2, 96, 6, pf.ENS_LEARNED), (0, 2, 64, 7)]
+    eager = pf.ParticleFilter([spec], ens, fused=True)
+    graph = pf.ParticleFilter([spec], ens, graph=True)
+    for f in (eager, graph):
+        f.set_proposal(0, params)
+    graph.set_observations(y_all)
+    for t in range(T):
+        eager.step(y_all[t])
+        graph.step()
+        graph.sync()
+        for x, z in zip(_snap(eager, 2), _snap(graph, 2)):
+            assert np.array_equal(x, z, equal_nan=True), f"interval {t + 1} differs"
 
 
 def test_graph_interval_reset(pf, orc, torch_mod):
