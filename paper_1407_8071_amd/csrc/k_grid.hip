@@ -14,8 +14,11 @@
 //   - k_grid_stream_step: one Euler step per launch, state read from and
 //     written to HBM (16 bytes per node-step).
 // Both share grid_euler(): drift v(v-a)(1-v) - w + D lap(v), eps (v - gam w),
-// Euler-Maruyama with compensated FP32 sums, the noise of nodes 2p, 2p+1 from
-// the Philox call of node pair p at step n.
+// Euler-Maruyama with the increments of an interval summed in an FP32 offset
+// from its start state (the blocked and the simulation kernels; compensated
+// sums where several particles share a workgroup, whose registers are
+// fewer; a plain update for the streaming kernel's single step), the noise
+// of nodes 2p, 2p+1 from the Philox call of node pair p at step n.
 #include <algorithm>
 #include <atomic>
 #include <type_traits>
@@ -42,7 +45,15 @@ __device__ __forceinline__ void st_stream(float4 *p, const float4 &a) {
 }
 
 struct Slot4 {
-  float4 v, w, cv, cw;  // state of 4 nodes and the compensation terms
+  // state of 4 nodes, the sums of their increments since the interval's
+  // start (or the compensation terms of compensated sums), and the start
+  // state
+  float4 v, w, dv, dw, v0, w0;
+  __device__ void start(float4 a, float4 b) {
+    v = v0 = a;
+    w = w0 = b;
+    dv = dw = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
 };
 
 __device__ __forceinline__ float get(const float4 &a, int e) {
@@ -112,8 +123,12 @@ __device__ __forceinline__ void fetch_nbrs(const Row4 &nb, const float *vs, cons
 
 // One Euler-Maruyama step of the 4 nodes of slot s (nodes 4s .. 4s+3), reading
 // neighbour v values from the LDS plane vs (which holds S.v for this slot).
-// Returns the new state in S.
-template <class NB>
+// Returns the new state in S.  MODE: the increments summed in an offset from
+// the interval's start state S.v0, S.w0 (EULER_OFFSET), compensated sums
+// with S.dv, S.dw the compensation terms (EULER_KAHAN), or a single step
+// from S.v, S.w (EULER_SINGLE).
+constexpr int EULER_OFFSET = 0, EULER_KAHAN = 1, EULER_SINGLE = 2;
+template <int MODE, class NB>
 __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t purpose,
                                            uint32_t c0, uint32_t c1, uint32_t n, int s,
                                            const NB &nb, const float *vs, Slot4 &S) {
@@ -131,11 +146,21 @@ __device__ __forceinline__ void grid_euler(const ModelDev &md, Key key, uint32_t
   for (int e = 0; e < 4; ++e) {
     const float c = get(S.v, e), w = get(S.w, e);
     const float lap = (((vu[e] - c) + (vd[e] - c)) + (vl[e] - c)) + (vr[e] - c);
-    float nv, nw, cv = get(S.cv, e), cw = get(S.cw, e);
-    fhn_node_step<false>(md, c, w, lap, zv[e], zw[e], 0.f, 0.f, nv, nw, cv, cw);
-    set(S.cv, e, cv);
+    float nv, nw;
+    if constexpr (MODE == EULER_SINGLE) {
+      float dv = 0.f, dw = 0.f;
+      fhn_node_step_off<false>(md, c, w, lap, zv[e], zw[e], 0.f, 0.f, c, w, nv, nw, dv, dw);
+    } else {
+      float dv = get(S.dv, e), dw = get(S.dw, e);
+      if constexpr (MODE == EULER_OFFSET)
+        fhn_node_step_off<false>(md, c, w, lap, zv[e], zw[e], 0.f, 0.f, get(S.v0, e),
+                                 get(S.w0, e), nv, nw, dv, dw);
+      else
+        fhn_node_step<false>(md, c, w, lap, zv[e], zw[e], 0.f, 0.f, nv, nw, dv, dw);
+      set(S.dv, e, dv);
+      set(S.dw, e, dw);
+    }
     set(S.v, e, nv);
-    set(S.cw, e, cw);
     set(S.w, e, nw);
   }
 }
@@ -224,15 +249,15 @@ __device__ __forceinline__ void grid_steps(const int4 *__restrict__ ptab, int n_
       const int src = thru ? min(max(gptr(E.A)[(size_t)m * N + i], 0), N - 1) : i;
       const gmem<f4v> *in = gptr((const f4v *)(Xin + ((size_t)m * N + src) * dx));
       const f4v a = in[sl], b = in[slots + sl];
-      S.v = make_float4(a.x, a.y, a.z, a.w);
-      S.w = make_float4(b.x, b.y, b.z, b.w);
-      S.cv = S.cw = make_float4(0.f, 0.f, 0.f, 0.f);
+      S.start(make_float4(a.x, a.y, a.z, a.w), make_float4(b.x, b.y, b.z, b.w));
       *(float4 *)(vs + 4 * sl) = S.v;
     }
     __syncthreads();
     const int n0 = (t - 1) * md.S;
     for (int st = 0; st < md.S; ++st) {
-      if (on) grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)(n0 + st), sl, nb, vs, S);
+      if (on)
+        grid_euler<MULTI ? EULER_KAHAN : EULER_OFFSET>(md, key, P_PROP, (uint32_t)i, (uint32_t)m,
+                                                       (uint32_t)(n0 + st), sl, nb, vs, S);
       __syncthreads();
       if (on) *(float4 *)(vs + 4 * sl) = S.v;
       __syncthreads();
@@ -315,9 +340,7 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
     for (int q = 0; q < SPT; ++q) {
       const int s = threadIdx.x + q * blockDim.x;
       if (s < slots) {
-        S[q].v = nv[q];
-        S[q].w = nw[q];
-        S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
+        S[q].start(nv[q], nw[q]);
         *(float4 *)(vs + 4 * s) = S[q].v;
       }
     }
@@ -328,7 +351,8 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
     for (int q = 0; q < SPT; ++q) {
       const int s = threadIdx.x + q * blockDim.x;
       if (s < slots) {
-        grid_euler(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)n, s, nb[q], vs, S[q]);
+        grid_euler<EULER_SINGLE>(md, key, P_PROP, (uint32_t)i, (uint32_t)m, (uint32_t)n, s, nb[q], vs,
+                                 S[q]);
         st_stream(out + s, S[q].v);
         st_stream(out + slots + s, S[q].w);
       }
@@ -653,9 +677,7 @@ k_grid_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
       normals4(philox(0u, TRUTH_STREAM, 0u, (P_TRUTH_INIT << 24) | (uint32_t)(slots + s), key), z);
       for (int l = 0; l < 4; ++l)
         w[l] = md.prior_mean[nn + 4 * s + l] + md.prior_sd[nn + 4 * s + l] * z[l];
-      S[q].v = make_float4(v[0], v[1], v[2], v[3]);
-      S[q].w = make_float4(w[0], w[1], w[2], w[3]);
-      S[q].cv = S[q].cw = make_float4(0.f, 0.f, 0.f, 0.f);
+      S[q].start(make_float4(v[0], v[1], v[2], v[3]), make_float4(w[0], w[1], w[2], w[3]));
       *(float4 *)(vs + 4 * s) = S[q].v;
       ((float4 *)xtrue)[s] = S[q].v;
       ((float4 *)xtrue)[slots + s] = S[q].w;
@@ -668,7 +690,8 @@ k_grid_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int s = threadIdx.x + q * blockDim.x;
-        if (s < slots) grid_euler(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, n, s, nb[q], vs, S[q]);
+        if (s < slots)
+          grid_euler<EULER_OFFSET>(md, key, P_TRUTH_NOISE, 0u, TRUTH_STREAM, n, s, nb[q], vs, S[q]);
       }
       __syncthreads();
 #pragma unroll
@@ -685,6 +708,7 @@ k_grid_simulate(ModelDev md, Key key, int T, float *__restrict__ xtrue, float *_
       if (s < slots) {
         xt[s] = S[q].v;
         xt[slots + s] = S[q].w;
+        S[q].start(S[q].v, S[q].w);  // the next interval's offsets from here
       }
     }
     for (int k4 = threadIdx.x; 4 * k4 < md.dy; k4 += GB) {
