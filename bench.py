@@ -101,7 +101,7 @@ FHN_FP32_FLOP_PER_NODE_STEP = 25.0
 # units; profiles/valu_instruction_mix.md): instructions per unit, and slots
 # = instructions + 3 per transcendental + 1 per 64-bit multiply-add.
 L63_ISSUED = {"valu": 60.33, "trans": 6.00, "int64": 11.85}
-FHN_ISSUED = {"valu": 62.01, "trans": 4.48, "int64": 8.50}
+FHN_ISSUED = {"valu": 55.93, "trans": 4.48, "int64": 8.50}
 # 64 lanes per CU per clock: the basis of the plain instruction-issue fraction
 VALU_LANE_OPS_64_PER_S = 256 * 64 * 2.4e9
 
@@ -125,7 +125,7 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # are now.
 MEASURED_TRAFFIC_BYTES = {
     ("lorenz63", "fused", 256, 4096): (2 * 2368.0 + 16384) * 1024,
-    ("fhn", "plain", 64, 512): (2 * 204841.5 + 409609) * 1024,
+    ("fhn", "plain", 64, 512): (2 * 204843 + 409612.8) * 1024,
     ("fhn_paper", "fused", 10, 5000): (2 * 202242.7 + 421123.3) * 1024,
 }
 
