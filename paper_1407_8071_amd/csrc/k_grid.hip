@@ -503,7 +503,7 @@ k_grid_estimate_part(int N, int dx4, const float4 *__restrict__ Xb,
   double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
 #pragma unroll 4
   for (int i = i0; i < i1; ++i) {
-    const float4 x = Xb[((size_t)m * N + i) * dx4 + g];
+    const float4 x = ld_stream(Xb + ((size_t)m * N + i) * dx4 + g);
     const double n = nsh[i - i0], w = wsh[i - i0];
     pv[0] += n * x.x; pv[1] += n * x.y; pv[2] += n * x.z; pv[3] += n * x.w;
     wv[0] += w * x.x; wv[1] += w * x.y; wv[2] += w * x.z; wv[3] += w * x.w;
@@ -608,7 +608,7 @@ k_grid_estimate_part_b(const int4 *__restrict__ jobs, const FusedEns *__restrict
   double pv[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
 #pragma unroll 4
   for (int i = i0; i < i1; ++i) {
-    const f4v x = Xb[((size_t)m * N + i) * dx4 + g];
+    const f4v x = __builtin_nontemporal_load(Xb + ((size_t)m * N + i) * dx4 + g);
     const double n = nsh[i - i0], w = wsh[i - i0];
     pv[0] += n * x.x; pv[1] += n * x.y; pv[2] += n * x.z; pv[3] += n * x.w;
     wv[0] += w * x.x; wv[1] += w * x.y; wv[2] += w * x.z; wv[3] += w * x.w;
