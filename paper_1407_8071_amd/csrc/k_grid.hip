@@ -310,16 +310,18 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
                    const int32_t *__restrict__ anc, float *Xout,
                    float *__restrict__ lw, const float *__restrict__ y) {
   // Xin may equal Xout (in-place step): each workgroup reads its whole
-  // particle before the barrier and writes it after.  The next particle of
-  // the workgroup is loaded into registers while the current one computes.
+  // particle before the barrier and writes it after.  The workgroup's next
+  // two particles are in flight into registers (two sets, alternating) while
+  // the current one computes: a particle's load is issued two particles
+  // ahead, as soon as its register set has been taken.
   extern __shared__ float vs[];
-  const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn;
+  const int J = md.J, nn = J * J, slots = nn / 4, dx = 2 * nn, MN = M * N, G = gridDim.x;
   float *shf = vs + nn;
   Nbr4 nb[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) nb[q] = neighbours(J, min((int)(threadIdx.x + q * blockDim.x), slots - 1));
-  float4 nv[SPT], nw[SPT];
-  auto load = [&](int p) {
+  float4 av[SPT], aw[SPT], bv[SPT], bw[SPT];
+  auto load = [&](int p, float4 (&nv)[SPT], float4 (&nw)[SPT]) {
     const int m = p / N, i = p - m * N;
     const int src = anc ? min(max(anc[(size_t)m * N + i], 0), N - 1) : i;
     const float4 *in = (const float4 *)(Xin + ((size_t)m * N + src) * dx);
@@ -332,8 +334,7 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
       }
     }
   };
-  if (blockIdx.x < M * N) load(blockIdx.x);
-  for (int p = blockIdx.x; p < M * N; p += gridDim.x) {
+  auto particle = [&](int p, float4 (&nv)[SPT], float4 (&nw)[SPT]) {
     const int m = p / N, i = p - m * N;
     Slot4 S[SPT];
 #pragma unroll
@@ -345,7 +346,7 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
       }
     }
     __syncthreads();
-    if (p + (int)gridDim.x < M * N) load(p + gridDim.x);
+    if (p + 2 * G < MN) load(p + 2 * G, nv, nw);
     float4 *out = (float4 *)(Xout + ((size_t)m * N + i) * dx);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
@@ -369,6 +370,13 @@ k_grid_stream_step(ModelDev md, Key key, int M, int N, int n, const float *Xin,
       if (threadIdx.x == 0) lw[(size_t)m * N + i] = l;
     }
     __syncthreads();
+  };
+  const int p0 = blockIdx.x;
+  if (p0 < MN) load(p0, av, aw);
+  if (p0 + G < MN) load(p0 + G, bv, bw);
+  for (int p = p0; p < MN; p += 2 * G) {
+    particle(p, av, aw);
+    if (p + G < MN) particle(p + G, bv, bw);
   }
 }
 
