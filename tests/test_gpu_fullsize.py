@@ -3,9 +3,9 @@
 The FH-N 40 x 40 ensemble of 64 filters x 512 particles and the learned
 ensemble of 64 x 128 run in the launch configurations the benchmark times:
 every stepping kernel loops over many particles per workgroup there (the
-blocked kernel's particle groups, the streaming kernel's prefetch of the next
-particle while it steps the current one in place, the learned kernel's
-particle loop), which small parity cases never reach.  A sample of particles
+blocked kernel's particle groups, the streaming kernel's two register sets
+that hold the next two particles while it steps the current one in place, the
+learned kernel's particle loop), which small parity cases never reach.  A sample of particles
 spread over the whole index range -- the last ones included -- is checked
 against the oracle, which propagates each particle on its own from the
 particles the GPU holds:
@@ -135,8 +135,10 @@ def test_fhn40_64x512_fused_two_intervals(pf, orc, torch_mod):
 
 def test_fhn40_64x512_plain_stream_steps(pf, orc, torch_mod):
     """The streaming one-step kernel, 20 launches per interval: each
-    workgroup prefetches particle p + gridDim while it steps p in place; the
-    second interval reads the particles the gather kernel wrote."""
+    workgroup has particles p + gridDim and p + 2 gridDim in flight while it
+    steps p in place (32768 particles over 768 workgroups: both register sets,
+    and workgroups with an odd and with an even particle count); the second
+    interval reads the particles the gather kernel wrote."""
     _two_intervals(pf, orc, torch_mod, fused=False)
 
 
