@@ -85,13 +85,13 @@ def _propagate_rows(orc, m, seed, fil, idx, t, X_in):
         return np.array(list(pool.map(one, range(len(fil)))))
 
 
-def _two_intervals(pf, orc, torch_mod, fused):
-    spec, M, N, seed = F40, 64, 512, 1
+def _two_intervals(pf, orc, torch_mod, fused, M=64, N=512, n_sample=96):
+    spec, seed = F40, 1
     m = orc.Model(spec)
     _, y = orc.simulate(m, 61, 2)
     y32 = y.astype(np.float32)
     f = pf.ParticleFilter([spec], [(0, M, N, seed)], fused=fused)
-    fil, idx = _sample(M, N, 96, 5)
+    fil, idx = _sample(M, N, n_sample, 5)
     print(f"FH-N 40x40 {M}x{N} {'fused' if fused else 'plain'}: {len(fil)} sampled particles",
           flush=True)
     x0 = _rows(f.get_particles(0), fil, idx)
@@ -140,6 +140,14 @@ def test_fhn40_64x512_plain_stream_steps(pf, orc, torch_mod):
     and workgroups with an odd and with an even particle count); the second
     interval reads the particles the gather kernel wrote."""
     _two_intervals(pf, orc, torch_mod, fused=False)
+
+
+def test_fhn40_plain_stream_steps_between_one_and_two_rounds(pf, orc, torch_mod):
+    """The streaming kernel where the particles number between one and two
+    per resident workgroup (2 x 500 = 1000 particles over 768 workgroups on
+    the MI355X): the first workgroups step a second particle from their
+    second register set, the others stop after one."""
+    _two_intervals(pf, orc, torch_mod, fused=False, M=2, N=500, n_sample=48)
 
 
 def _learned_interval(pf, orc, torch_mod, p, n_sample, seed_sample):
