@@ -205,6 +205,11 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
       // (the read of the next tile is unconditional -- the last one repeats
       // a valid tile -- so that it stays in the MFMA block and its LDS
       // latency hides under the MFMAs)
+      // The tiles run at a raised wave priority: where the other workgroup
+      // on the CU is in its Euler phase, the SIMD then issues this wave's
+      // MFMAs and their packing first and fills the matrix pipe's gaps with
+      // the other wave's VALU work, instead of taking both in turn.
+      __builtin_amdgcn_s_setprio(2);
       bf16x8 Fc[2], Fn[2];
       int no_n = NO[tile_node(min(wid + nwaves, ntiles - 1))];
       if (wid < ntiles) inputs(wid, NO[tile_node(wid)], Fc);
@@ -217,6 +222,7 @@ k_grid_steps_learned(ModelDev md, Key key, int M, int N, IvArg iv, int yoff,
         Fc[1] = Fn[1];
         no_n = no_nn;
       }
+      __builtin_amdgcn_s_setprio(0);
       __syncthreads();
       // (B) Euler-Maruyama with the corrected drift; the compensation terms
       // of the sums stay in LDS
